@@ -1,0 +1,323 @@
+"""Python binding of libadl (include/adl.h): the Leja exponential integrator
+for 2D anisotropic diffusion with advection on MI355X (gfx950).
+
+This module only marshals arguments: every step of the computation runs in
+the HIP kernels of libadl.so.  PyTorch provides device memory (tensors) and
+the current stream; nothing here computes on tensors.  If the library is not
+built, every entry point raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadl.so")
+
+OK, EINVAL, ENOCONV, EBOUND, ENAN, EHIP, ENOWORKSPACE = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC, BC_DIRICHLET = 0, 1
+STORAGE_FP64, STORAGE_FP32_FIELDS, STORAGE_FP32_FIELDS_Y = 0, 1, 2
+BOUND_GERSHGORIN, BOUND_POWER = 0, 1
+QUAD2_AUGMENTED, QUAD2_TWO_SWEEP = 0, 1
+MLP_PARAMS, MLP_IN, MLP_OUT, MLP_CACHE_PER_ROW = 9155, 9, 3, 201
+
+_ERRNAMES = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EBOUND: "EBOUND", ENAN: "ENAN",
+             EHIP: "EHIP", ENOWORKSPACE: "ENOWORKSPACE"}
+
+
+class AdlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("matvecs", ctypes.c_int), ("sweeps", ctypes.c_int),
+                ("max_degree", ctypes.c_int), ("last_degree", ctypes.c_int),
+                ("substeps", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("status", ctypes.c_int), ("reserved_i", ctypes.c_int),
+                ("alpha", ctypes.c_double), ("reserved", ctypes.c_double * 3)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k in ("matvecs", "sweeps", "max_degree", "last_degree",
+                                              "substeps", "fallback", "status", "alpha")}
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_F = ctypes.c_float
+_SZ = ctypes.c_size_t
+_SIG = {
+    "adl_last_error": (ctypes.c_char_p, []),
+    "adl_workspace_bytes": (_SZ, [_I, _I, _I, _I]),
+    "adl_op_create": (_I, [_I, _I, _D, _D, _I, _I, _P, _P, _P, _P, _P, _D, _D, _P, _SZ, _P,
+                           ctypes.POINTER(_P)]),
+    "adl_op_destroy": (_I, [_P]),
+    "adl_op_set_limits": (_I, [_P, _I, _D]),
+    "adl_op_set_quad2_mode": (_I, [_P, _I]),
+    "adl_apply": (_I, [_P, _P, _P, _P]),
+    "adl_spectral_bound": (_I, [_P, _I, _I, _D, ctypes.c_uint64, ctypes.POINTER(_D),
+                                ctypes.POINTER(_I), _P]),
+    "adl_set_bound": (_I, [_P, _D]),
+    "adl_get_bound": (_I, [_P, ctypes.POINTER(_D)]),
+    "adl_leja_phi": (_I, [_P, _I, _D, _P, _P, _D, _I, ctypes.POINTER(Stats), _P]),
+    "adl_exp_midpoint_step": (_I, [_P, _P, _P, _D, _D, ctypes.POINTER(Stats), _P]),
+    "adl_exp_quad2_step": (_I, [_P, _P, _P, _P, _D, _D, _D, _D, ctypes.POINTER(Stats), _P]),
+    "adl_batch_workspace_bytes": (_SZ, [_I, ctypes.POINTER(_P), _I]),
+    "adl_batch_create": (_I, [_I, ctypes.POINTER(_P), _P, _SZ, _I, ctypes.POINTER(_P)]),
+    "adl_batch_destroy": (_I, [_P]),
+    "adl_batch_midpoint_step": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, _I,
+                                     ctypes.POINTER(Stats), _P]),
+    "adl_field_stats": (_I, [_P, _D, _P, _P]),
+    "adl_mlp_forward": (_I, [_P, _P, _P, _P, _I, _P]),
+    "adl_mlp_backward": (_I, [_P, _P, _P, _P, _I, _P]),
+    "adl_mlp_adam_step": (_I, [_P, _P, _P, _P, _I, _F, _F, _F, _F, _P]),
+    "adl_leja_points": (_I, [_I, ctypes.POINTER(_D)]),
+    "adl_newton_coefficients": (_I, [_I, _D, _D, _I, ctypes.POINTER(_D)]),
+}
+
+
+def lib():
+    """The loaded libadl.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libadl.so is not built (run paper_2307_12276_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIG.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> Sequence[str]:
+    return list(_SIG.keys())
+
+
+def _check(code: int):
+    if code != OK:
+        raise AdlError(code, lib().adl_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype=None, shape=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def leja_points(n: int = 501):
+    out = (ctypes.c_double * n)()
+    _check(lib().adl_leja_points(n, out))
+    return list(out)
+
+
+def newton_coefficients(l: int, alpha: float, h: float, n: int):
+    out = (ctypes.c_double * n)()
+    _check(lib().adl_newton_coefficients(l, alpha, h, n, out))
+    return list(out)
+
+
+def workspace_bytes(nx: int, ny: int, storage: int = STORAGE_FP64, max_degree: int = 0) -> int:
+    return int(lib().adl_workspace_bytes(nx, ny, storage, max_degree))
+
+
+class Op:
+    """The operator A of one grid: owns the device workspace (a torch tensor)
+    and the library handle."""
+
+    def __init__(self, Dxx, Dxy, Dyy, hx: float, hy: float, bc: int = BC_PERIODIC,
+                 storage: int = STORAGE_FP64, ax=None, ay=None, ax_c: float = 0.0,
+                 ay_c: float = 0.0, stream=None):
+        import torch
+        ny, nx = Dxx.shape
+        self.nx, self.ny, self.shape = nx, ny, (ny, nx)
+        self.storage = storage
+        dev = Dxx.device
+        nbytes = workspace_bytes(nx, ny, storage)
+        if nbytes == 0:
+            raise AdlError(EINVAL, "invalid grid size or storage")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._ws_ptr = ctypes.c_void_p(aligned)
+        self._ws_bytes = nbytes
+        h = ctypes.c_void_p()
+        f64 = torch.float64
+        _check(lib().adl_op_create(nx, ny, float(hx), float(hy), int(bc), int(storage),
+                                   _ptr(Dxx, f64, self.shape, "Dxx"), _ptr(Dxy, f64, self.shape, "Dxy"),
+                                   _ptr(Dyy, f64, self.shape, "Dyy"), _ptr(ax, f64, self.shape, "ax"),
+                                   _ptr(ay, f64, self.shape, "ay"), float(ax_c), float(ay_c),
+                                   self._ws_ptr, nbytes, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.hx, self.hy, self.bc = hx, hy, bc
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().adl_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _v(self, t, name):
+        import torch
+        return _ptr(t, torch.float64, self.shape, name)
+
+    def set_limits(self, max_degree: int = 500, rho_max: float = 1600.0):
+        _check(lib().adl_op_set_limits(self.handle, int(max_degree), float(rho_max)))
+
+    def set_quad2_mode(self, mode: int):
+        _check(lib().adl_op_set_quad2_mode(self.handle, int(mode)))
+
+    def apply(self, x, y, stream=None):
+        _check(lib().adl_apply(self.handle, self._v(x, "x"), self._v(y, "y"), _stream(stream)))
+        return y
+
+    def spectral_bound(self, method: int = BOUND_GERSHGORIN, max_iter: int = 2000, rtol: float = 1e-3,
+                       seed: int = 0, stream=None):
+        a = ctypes.c_double()
+        it = ctypes.c_int()
+        _check(lib().adl_spectral_bound(self.handle, int(method), int(max_iter), float(rtol),
+                                        int(seed) % (1 << 64), ctypes.byref(a), ctypes.byref(it),
+                                        _stream(stream)))
+        return a.value, it.value
+
+    def set_bound(self, alpha: float):
+        _check(lib().adl_set_bound(self.handle, float(alpha)))
+
+    def get_bound(self) -> float:
+        a = ctypes.c_double()
+        _check(lib().adl_get_bound(self.handle, ctypes.byref(a)))
+        return a.value
+
+    def leja_phi(self, l: int, dt: float, v, out, tol: float, max_degree: int = 0, stream=None):
+        st = Stats()
+        _check(lib().adl_leja_phi(self.handle, int(l), float(dt), self._v(v, "v"), self._v(out, "out"),
+                                  float(tol), int(max_degree), ctypes.byref(st), _stream(stream)))
+        return st.as_dict()
+
+    def midpoint_step(self, u, S_half, dt: float, tol: float, stream=None):
+        st = Stats()
+        _check(lib().adl_exp_midpoint_step(self.handle, self._v(u, "u"),
+                                           self._v(S_half, "S_half") if S_half is not None else None,
+                                           float(dt), float(tol), ctypes.byref(st), _stream(stream)))
+        return st.as_dict()
+
+    def quad2_step(self, u, S1, S2, c1: float, c2: float, dt: float, tol: float, stream=None):
+        st = Stats()
+        _check(lib().adl_exp_quad2_step(self.handle, self._v(u, "u"),
+                                        self._v(S1, "S1") if S1 is not None else None,
+                                        self._v(S2, "S2") if S2 is not None else None,
+                                        float(c1), float(c2), float(dt), float(tol), ctypes.byref(st),
+                                        _stream(stream)))
+        return st.as_dict()
+
+    def field_stats(self, dt: float, feats, stream=None):
+        import torch
+        _check(lib().adl_field_stats(self.handle, float(dt), _ptr(feats, torch.float32, (9,), "feats"),
+                                     _stream(stream)))
+        return feats
+
+
+class Batch:
+    """Many ops advanced together by one persistent launch per step."""
+
+    def __init__(self, ops: Sequence[Op], tile_rows: int = 0):
+        import torch
+        self.ops = list(ops)
+        n = len(self.ops)
+        arr = (ctypes.c_void_p * n)(*[o.handle.value for o in self.ops])
+        self._arr = arr
+        nbytes = int(lib().adl_batch_workspace_bytes(n, arr, 0))
+        if nbytes == 0:
+            raise AdlError(EINVAL, "invalid batch")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p()
+        _check(lib().adl_batch_create(n, arr, ctypes.c_void_p(aligned), nbytes, int(tile_rows),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().adl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def midpoint_step(self, us, S_halfs, dt: float, tol: float, use_graph: bool = True,
+                      stream=None):
+        import torch
+        n = len(self.ops)
+        up = (ctypes.c_void_p * n)(*[_ptr(u, torch.float64, o.shape, "u").value
+                                     for u, o in zip(us, self.ops)])
+        if S_halfs is None:
+            sp = None
+        else:
+            sp = (ctypes.c_void_p * n)(*[(_ptr(s, torch.float64, o.shape, "S").value if s is not None else None)
+                                         for s, o in zip(S_halfs, self.ops)])
+        stats = (Stats * n)()
+        _check(lib().adl_batch_midpoint_step(self.handle, up, sp, float(dt), float(tol), int(bool(use_graph)),
+                                             stats, _stream(stream)))
+        return [s.as_dict() for s in stats]
+
+
+def mlp_forward(W, X, Y, cache=None, stream=None):
+    import torch
+    B = X.shape[0]
+    _check(lib().adl_mlp_forward(_ptr(W, torch.float32, (MLP_PARAMS,), "W"),
+                                 _ptr(X, torch.float32, (B, MLP_IN), "X"),
+                                 _ptr(Y, torch.float32, (B, MLP_OUT), "Y"),
+                                 _ptr(cache, torch.float32, (B, MLP_CACHE_PER_ROW), "cache") if cache is not None else None,
+                                 int(B), _stream(stream)))
+    return Y
+
+
+def mlp_backward(W, cache, dY, dW, stream=None):
+    import torch
+    B = dY.shape[0]
+    _check(lib().adl_mlp_backward(_ptr(W, torch.float32, (MLP_PARAMS,), "W"),
+                                  _ptr(cache, torch.float32, (B, MLP_CACHE_PER_ROW), "cache"),
+                                  _ptr(dY, torch.float32, (B, MLP_OUT), "dY"),
+                                  _ptr(dW, torch.float32, (MLP_PARAMS,), "dW"), int(B), _stream(stream)))
+    return dW
+
+
+def mlp_adam_step(W, dW, m1, m2, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    import torch
+    f = torch.float32
+    _check(lib().adl_mlp_adam_step(_ptr(W, f, (MLP_PARAMS,), "W"), _ptr(dW, f, (MLP_PARAMS,), "dW"),
+                                   _ptr(m1, f, (MLP_PARAMS,), "m1"), _ptr(m2, f, (MLP_PARAMS,), "m2"),
+                                   int(t), float(lr), float(beta1), float(beta2), float(eps),
+                                   _stream(stream)))

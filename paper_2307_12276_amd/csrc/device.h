@@ -1,0 +1,219 @@
+// Device helpers shared by the HIP translation units of libadl:
+// tile remapping across XCDs, row loads with boundary rules, and the
+// fixed-order grid reduction with a last-block ticket.
+#pragma once
+
+#include "internal.h"
+
+#include <cmath>
+
+namespace adl {
+
+enum { MODE_ZERO = 0, MODE_EDGE = 1 };
+
+__device__ __forceinline__ int remap_xcd(int b, int nb) {
+  const int x = b & 7, local = b >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + local;
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_c(const T* __restrict__ a, long off, double (&c)[VEC]) {
+  if constexpr (VEC == 1) {
+    c[0] = (double)a[off];
+  } else if constexpr (sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = *reinterpret_cast<const d2*>(a + off);
+    c[0] = v.x;
+    c[1] = v.y;
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = *reinterpret_cast<const f2*>(a + off);
+    c[0] = (double)v.x;
+    c[1] = (double)v.y;
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_c(T* __restrict__ a, long off, const double (&c)[VEC]) {
+  if constexpr (VEC == 1) {
+    a[off] = (T)c[0];
+  } else if constexpr (sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 v;
+    v.x = c[0];
+    v.y = c[1];
+    *reinterpret_cast<d2*>(a + off) = v;
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 v;
+    v.x = (float)c[0];
+    v.y = (float)c[1];
+    *reinterpret_cast<f2*>(a + off) = v;
+  }
+}
+
+struct LaneGeom {
+  int col0;
+  int lane;
+  bool inside;
+  bool needL, needR;
+};
+
+// Row index after the boundary rule; zero = the whole row is a zero ghost row.
+__device__ __forceinline__ int map_row(int r, int ny, int bc, int mode, bool& zero) {
+  zero = false;
+  if (r >= 0 && r < ny) return r;
+  if (bc == BC_PERIODIC) return r < 0 ? r + ny : r - ny;
+  if (mode == MODE_EDGE) return r < 0 ? 0 : ny - 1;
+  zero = true;
+  return 0;
+}
+
+// Centre values only.
+template <typename T, int VEC>
+__device__ __forceinline__ void load_row(const T* __restrict__ a, int r, int mode, int nx, int ny,
+                                         int bc, const LaneGeom& g, double (&c)[VEC]) {
+  bool zero;
+  const int row = map_row(r, ny, bc, mode, zero);
+  if (!zero && g.inside) {
+    load_c<T, VEC>(a, (long)row * nx + g.col0, c);
+  } else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) c[v] = 0.0;
+  }
+}
+
+// Centre values and the x-neighbours col0-1 (l) and col0+VEC (r).
+template <typename T, int VEC>
+__device__ __forceinline__ void load_row_n(const T* __restrict__ a, int r, int mode, int nx, int ny,
+                                           int bc, const LaneGeom& g, double (&c)[VEC], double& l,
+                                           double& rr) {
+  bool zero;
+  const int row = map_row(r, ny, bc, mode, zero);
+  if (!zero && g.inside) {
+    load_c<T, VEC>(a, (long)row * nx + g.col0, c);
+  } else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) c[v] = 0.0;
+  }
+  l = __shfl_up(c[VEC - 1], 1);
+  rr = __shfl_down(c[0], 1);
+  if (g.needL) {
+    const int cl = g.col0 - 1;
+    double v;
+    if (zero) v = 0.0;
+    else if (cl >= 0) v = (double)a[(long)row * nx + cl];
+    else if (bc == BC_PERIODIC) v = (double)a[(long)row * nx + nx - 1];
+    else v = (mode == MODE_EDGE) ? c[0] : 0.0;
+    l = v;
+  }
+  if (g.needR) {
+    const int cr = g.col0 + VEC;
+    double v;
+    if (zero) v = 0.0;
+    else if (cr < nx) v = (double)a[(long)row * nx + cr];
+    else if (bc == BC_PERIODIC) v = (double)a[(long)row * nx];
+    else v = (mode == MODE_EDGE) ? c[VEC - 1] : 0.0;
+    rr = v;
+  }
+}
+
+template <int VEC>
+struct RowN {
+  double c[VEC];
+  double l, r;
+  __device__ __forceinline__ double at(int v) const { return c[v]; }
+  __device__ __forceinline__ double west(int v) const { return v == 0 ? l : c[v - 1]; }
+  __device__ __forceinline__ double east(int v) const { return v == VEC - 1 ? r : c[v + 1]; }
+};
+
+template <int VEC>
+struct RowC {
+  double c[VEC];
+};
+
+__device__ __forceinline__ double nanmax(double a, double b) {
+  // max that propagates NaN
+  return (a != a || b != b) ? (a + b) : (a > b ? a : b);
+}
+
+// Block partials -> last block sums them in fixed order -> fin(totals).
+// Sums for the first NS values, NaN-propagating max for the rest.
+template <int NA, int NS, class Fin>
+__device__ __forceinline__ void grid_reduce(double (&acc)[NA], double* partials, Ctl* ctl, Fin fin) {
+  __shared__ double sh[NA * 16];
+  __shared__ int last;
+  // block reduce: sums for k < NS, max for k >= NS
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double t = __shfl_xor(acc[k], o);
+      acc[k] = (k < NS) ? acc[k] + t : nanmax(acc[k], t);
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) sh[wave * NA + k] = acc[k];
+  }
+  __syncthreads();
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      double s = sh[k];
+      for (int w = 1; w < nw; ++w) s = (k < NS) ? s + sh[w * NA + k] : nanmax(s, sh[w * NA + k]);
+      partials[(long)k * nb + blockIdx.x] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned int t = atomicAdd(&ctl->ticket, 1u);
+    last = (t == (unsigned)(nb - 1));
+  }
+  __syncthreads();
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double tot[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    double s = (k < NS) ? 0.0 : 0.0;
+    bool any = false;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      const double v = __builtin_nontemporal_load(&partials[(long)k * nb + i]);
+      if (k < NS) s += v;
+      else s = any ? nanmax(s, v) : v;
+      any = true;
+    }
+    tot[k] = s;
+  }
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double t = __shfl_xor(tot[k], o);
+      tot[k] = (k < NS) ? tot[k] + t : nanmax(tot[k], t);
+    }
+  }
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) sh[wave * NA + k] = tot[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      double s = sh[k];
+      for (int w = 1; w < nw; ++w) s = (k < NS) ? s + sh[w * NA + k] : nanmax(s, sh[w * NA + k]);
+      tot[k] = s;
+    }
+    fin(tot);
+    ctl->ticket = 0u;
+  }
+}
+
+
+
+}  // namespace adl

@@ -1,0 +1,887 @@
+// Host runtime of libadl: Leja points, divided differences, sweep driver,
+// exponential integrators and the C ABI (include/adl.h).
+//
+// Method (Deka, Kissmann, Einkemmer, ICRC 2023, Sec. 2): phi_l(A dt) v is
+// approximated by Newton interpolation of phi_l((c + gamma xi) dt) at Leja
+// points xi in [-2, 2], c = alpha/2, gamma = -alpha/4, applied term by term:
+//   y_{k+1} = ((A - c I)/gamma - xi_k I) y_k,   p_{k+1} = p_k + d_{k+1} y_{k+1}.
+// One GPU launch per term (fused stencil + axpy + norms); the last block of
+// each launch sets a device stop flag so that launches enqueued after
+// convergence are no-ops, and the host reads the flag once per chunk.
+#include "internal.h"
+#include "../../include/adl.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace adl {
+
+// --------------------------------------------------------------------------
+// error reporting
+// --------------------------------------------------------------------------
+static thread_local std::string g_err = "";
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ADL_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define RETCHK(expr)        \
+  do {                      \
+    int r_ = (expr);        \
+    if (r_ != ADL_OK) return r_; \
+  } while (0)
+
+// --------------------------------------------------------------------------
+// Leja points on [-2, 2]: xi_0 = 2, then xi_k maximises prod_{j<k} |x - xi_j|.
+// On each gap between consecutive sorted points log|prod| is strictly concave,
+// so its maximiser is the zero of f'(x) = sum 1/(x - xi_j); it is tracked per
+// gap by safeguarded Newton iteration.  Ties (equal products within 1e-12
+// relative) go to the smaller point.
+// --------------------------------------------------------------------------
+constexpr int kMaxDegreeDefault = 500;
+constexpr double kRhoMaxDefault = 1600.0;
+constexpr int kMaxDoublings = 6;
+
+static double gap_root(const std::vector<double>& pts, double a, double b, double x0) {
+  double lo = a, hi = b;
+  double x = (x0 > a && x0 < b) ? x0 : 0.5 * (a + b);
+  for (int it = 0; it < 200; ++it) {
+    double f1 = 0.0, f2 = 0.0;
+    for (double p : pts) {
+      const double r = 1.0 / (x - p);
+      f1 += r;
+      f2 -= r * r;
+    }
+    if (f1 > 0.0) lo = x; else hi = x;
+    double xn = x - f1 / f2;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    if (std::fabs(xn - x) <= 2e-16 * std::fabs(x) + 1e-300 || hi - lo <= 4e-16 * std::fabs(x) + 1e-300) {
+      x = xn;
+      break;
+    }
+    x = xn;
+  }
+  return x;
+}
+
+static const std::vector<double>& leja_table() {
+  static std::vector<double> pts;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int M = kMaxDegreeDefault + 1;
+    pts = {2.0, -2.0, 0.0};
+    std::vector<double> sorted = {-2.0, 0.0, 2.0};
+    std::vector<double> guess = {-1.0, 1.0};  // maximiser guess per gap
+    while ((int)pts.size() < M) {
+      const int ng = (int)sorted.size() - 1;
+      double best_f = -INFINITY, best_x = 0.0;
+      std::vector<double> xs(ng), fs(ng);
+      for (int g = 0; g < ng; ++g) {
+        const double x = gap_root(pts, sorted[g], sorted[g + 1], guess[g]);
+        double f = 0.0;
+        for (double p : pts) f += std::log(std::fabs(x - p));
+        xs[g] = x;
+        fs[g] = f;
+        if (f > best_f) best_f = f;
+      }
+      const double thr = best_f - 1e-12 * std::max(1.0, std::fabs(best_f));
+      int pick = -1;
+      for (int g = 0; g < ng; ++g)
+        if (fs[g] >= thr && (pick < 0 || xs[g] < xs[pick])) pick = g;
+      best_x = xs[pick];
+      pts.push_back(best_x);
+      // split the chosen gap
+      std::vector<double> ns, ng2;
+      ns.reserve(sorted.size() + 1);
+      ng2.reserve(guess.size() + 1);
+      for (int g = 0; g < ng; ++g) {
+        ns.push_back(sorted[g]);
+        if (g == pick) {
+          ns.push_back(best_x);
+          ng2.push_back(0.5 * (sorted[g] + best_x));
+          ng2.push_back(0.5 * (best_x + sorted[g + 1]));
+        } else {
+          ng2.push_back(xs[g]);
+        }
+      }
+      ns.push_back(sorted.back());
+      sorted.swap(ns);
+      guess.swap(ng2);
+    }
+  });
+  return pts;
+}
+
+// --------------------------------------------------------------------------
+// phi_l scalars: phi_0 = exp, phi_1 = (e^z - 1)/z, phi_2 = (e^z - 1 - z)/z^2;
+// Taylor series sum_k z^k/(k+l)! for |z| < 1.
+// --------------------------------------------------------------------------
+static double phi_scalar(int l, double z) {
+  if (l == 0) return std::exp(z);
+  if (std::fabs(z) < 1.0) {
+    double fact = 1.0;
+    for (int i = 2; i <= l; ++i) fact *= i;  // l!
+    double term = 1.0 / fact, s = 0.0;
+    for (int k = 0; k < 30; ++k) {
+      s += term;
+      term *= z / (double)(k + l + 1);
+    }
+    return s;
+  }
+  const double e = std::expm1(z);
+  if (l == 1) return e / z;
+  return (e - z) / (z * z);
+}
+
+// --------------------------------------------------------------------------
+// Plans: divided differences of g(xi) = phi_l((c + gamma xi) h)
+// --------------------------------------------------------------------------
+struct Plan {
+  int l = -1;
+  double alpha = 0.0, h = 0.0;
+  int M = 0;
+  std::vector<double> d;      // d_0 .. d_{M-1}
+  std::vector<double> shift;  // c + gamma xi_k
+  std::vector<double> s;      // augmented scalars s_k
+  double invg = 0.0;
+  int last_degree = -1;
+};
+
+static void build_plan(Plan& P, int l, double alpha, double h, int M) {
+  const std::vector<double>& xi = leja_table();
+  P.l = l;
+  P.alpha = alpha;
+  P.h = h;
+  P.M = M;
+  const double c = alpha / 2.0, gamma = -alpha / 4.0;
+  P.d.resize(M);
+  for (int k = 0; k < M; ++k) P.d[k] = phi_scalar(l, (c + gamma * xi[k]) * h);
+  for (int j = 1; j < M; ++j)
+    for (int k = M - 1; k >= j; --k) P.d[k] = (P.d[k] - P.d[k - 1]) / (xi[k] - xi[k - j]);
+  P.shift.resize(M);
+  P.s.resize(M);
+  P.s[0] = 1.0;
+  for (int k = 0; k < M; ++k) {
+    P.shift[k] = c + gamma * xi[k];
+    if (k + 1 < M) P.s[k + 1] = (2.0 - xi[k]) * P.s[k];
+  }
+  P.invg = 1.0 / gamma;
+  P.last_degree = -1;
+}
+
+}  // namespace adl
+
+using namespace adl;
+
+// --------------------------------------------------------------------------
+// opaque handle
+// --------------------------------------------------------------------------
+struct adl_op {
+  FieldView f{};
+  Tiling t{};   // preferred tiling (two columns per lane when nx is even)
+  Tiling t1{};  // one column per lane: used when a caller's vector is not 16-byte aligned
+  int nx = 0, ny = 0, bc = 0, storage = 0;
+  double hx = 0, hy = 0;
+  long n = 0;
+  int ws_max_degree = kMaxDegreeDefault;
+  int max_degree = kMaxDegreeDefault;
+  double rho_max = kRhoMaxDefault;
+  int quad2_mode = ADL_QUAD2_AUGMENTED;
+  bool has_bound = false;
+  double alpha = 0.0;
+  double gersh = NAN;  // cached Gershgorin bound
+  // workspace slices
+  void* ybuf[2] = {nullptr, nullptr};
+  double* p = nullptr;
+  double* w1 = nullptr;
+  double* w2 = nullptr;
+  double* yacc = nullptr;
+  double* tmp = nullptr;
+  double* tmp2 = nullptr;
+  double* partials = nullptr;
+  Ctl* ctl = nullptr;
+  Ctl* host_ctl = nullptr;  // pinned
+  std::vector<Plan> plans;  // small cache
+  int plan_next = 0;
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+  size_t kxx, kxy, kyy, ax, ay, y0, y1, p, w1, w2, yacc, tmp, tmp2, partials, ctl, total;
+};
+
+static size_t max_partial_blocks(int nx, int ny) {
+  // upper bound over tilings with rows >= 1 and vec >= 1
+  const long ncb = (nx + kBlock - 1) / kBlock;
+  long nb = ncb * ny;
+  if (nb < 4096) nb = 4096;  // elementwise reductions use <= 1024 blocks
+  return (size_t)nb;
+}
+
+static WsLayout ws_layout(int nx, int ny, int storage) {
+  const size_t n = (size_t)nx * ny;
+  const size_t fs = storage == ADL_STORAGE_FP64 ? 8 : 4;
+  const size_t ys = storage == ADL_STORAGE_FP32_FIELDS_Y ? 4 : 8;
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.kxx = take(n * fs);
+  L.kxy = take(n * fs);
+  L.kyy = take(n * fs);
+  L.ax = take(n * fs);
+  L.ay = take(n * fs);
+  L.y0 = take(n * ys);
+  L.y1 = take(n * ys);
+  L.p = take(n * 8);
+  L.w1 = take(n * 8);
+  L.w2 = take(n * 8);
+  L.yacc = take(n * 8);
+  L.tmp = take(n * 8);
+  L.tmp2 = take(n * 8);
+  L.partials = take(3 * max_partial_blocks(nx, ny) * 8);
+  L.ctl = take(4 * 128);
+  L.total = o;
+  return L;
+}
+
+static hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+static bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// tiling usable with these caller vectors (two-column loads need 16-byte alignment)
+static const Tiling& tiling_for(const adl_op* op, const void* a, const void* b = nullptr,
+                                const void* c = nullptr) {
+  return (al16(a) && al16(b) && al16(c)) ? op->t : op->t1;
+}
+
+// --------------------------------------------------------------------------
+// sweep: one Newton interpolation with a device stop flag
+// --------------------------------------------------------------------------
+struct SweepOut {
+  int degree = 0;
+  int status = 0;  // 1 converged, 2 non-finite, 3 degree cap
+};
+
+static int read_ctl(adl_op* op, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(op->host_ctl, op->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return ADL_OK;
+}
+
+static Plan& get_plan(adl_op* op, int l, double alpha, double h) {
+  for (Plan& P : op->plans)
+    if (P.l == l && P.alpha == alpha && P.h == h && P.M == op->max_degree + 1) return P;
+  if (op->plans.size() < 8) {
+    op->plans.emplace_back();
+    build_plan(op->plans.back(), l, alpha, h, op->max_degree + 1);
+    return op->plans.back();
+  }
+  Plan& P = op->plans[op->plan_next];
+  op->plan_next = (op->plan_next + 1) % (int)op->plans.size();
+  build_plan(P, l, alpha, h, op->max_degree + 1);
+  return P;
+}
+
+// p_out = g(A) v (top block of the augmented form when w2 != null; the
+// augmented column enters with coefficient s_k * w2scale).
+static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
+                 double tol, int maxdeg, hipStream_t st, SweepOut& out) {
+  HIPCHK(launch_ctl_reset(op->ctl, 1, st));
+  const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
+  int predicted = P.last_degree > 0 ? P.last_degree + 2
+                                    : (int)(5.0 * std::sqrt(std::fabs(P.alpha) * P.h) + 8.0);
+  if (predicted > maxdeg) predicted = maxdeg;
+  int launched = 0;
+  while (true) {
+    int chunk = launched == 0 ? predicted : std::max(8, launched / 4);
+    if (launched + chunk > maxdeg) chunk = maxdeg - launched;
+    for (int i = 0; i < chunk; ++i) {
+      const int k = launched + i;
+      LejaArgs a{};
+      a.yin = k == 0 ? (const void*)v : op->ybuf[k & 1];
+      a.yout = op->ybuf[(k + 1) & 1];
+      a.p = p_out;
+      a.w2 = (w2 && P.s[k] != 0.0) ? w2 : nullptr;
+      a.w2c = P.s[k] * w2scale;
+      a.shift = P.shift[k];
+      a.invg = P.invg;
+      a.d0 = P.d[0];
+      a.dk1 = P.d[k + 1];
+      a.tol2 = tol * tol;
+      a.k = k;
+      a.max_degree = maxdeg;
+      a.first = k == 0;
+      a.ystore_f32 = ys32;
+      a.yin_f32 = (k > 0) && ys32;
+      a.partials = op->partials;
+      a.ctl = op->ctl;
+      HIPCHK(launch_leja_step(op->f, tiling_for(op, v, p_out), a, st));
+    }
+    launched += chunk;
+    RETCHK(read_ctl(op, st));
+    if (op->host_ctl->stop || launched >= maxdeg) break;
+  }
+  out.degree = op->host_ctl->degree;
+  out.status = op->host_ctl->stop ? op->host_ctl->status : 3;
+  if (out.status == 1) P.last_degree = out.degree;
+  return ADL_OK;
+}
+
+static int substeps_for(double alpha, double dt, double rho_max) {
+  const double r = std::fabs(alpha) * dt / rho_max;
+  const double K = std::ceil(r);
+  if (!(K < 1e6)) return 1 << 20;
+  return std::max(1, (int)K);
+}
+
+struct Acc {
+  int matvecs = 0, sweeps = 0, maxdeg = 0, lastdeg = 0, substeps = 0;
+};
+
+static void account(Acc& a, const SweepOut& o) {
+  a.matvecs += o.degree;
+  a.sweeps += 1;
+  a.maxdeg = std::max(a.maxdeg, o.degree);
+  a.lastdeg = o.degree;
+}
+
+static int status_to_code(int status) {
+  if (status == 2) return fail(ADL_ENAN, "non-finite value in a Leja sweep (NaN/Inf input or overflow)");
+  return fail(ADL_ENOCONV, "Leja sweep reached the degree cap without converging");
+}
+
+// y_acc = dt [phi_1(A dt) w1 + phi_2(A dt) w2] with K fixed substeps.
+// Returns ADL_OK and ok = false if a sweep hit the degree cap.
+static int combo_fixed(adl_op* op, const double* w1, const double* w2, double dt, double tol, int K, Acc& acc,
+                       bool& ok, hipStream_t st) {
+  const double h = dt / K;
+  Plan& P = get_plan(op, 1, op->alpha, h);
+  ok = true;
+  for (int j = 0; j < K; ++j) {
+    const double* f = w1;
+    if (j > 0) {
+      // f = A y + w1 + (j h/dt) w2
+      HIPCHK(launch_apply(op->f, tiling_for(op, w1, w2), op->yacc, op->tmp, w1, 1.0, w2, (double)j * h / dt, st));
+      acc.matvecs += 1;
+      f = op->tmp;
+    }
+    SweepOut so;
+    RETCHK(sweep(op, P, f, w2, 1.0 / dt, op->p, tol, op->max_degree, st, so));
+    account(acc, so);
+    if (so.status != 1) {
+      if (so.status == 2) return status_to_code(2);
+      ok = false;
+      return ADL_OK;
+    }
+    if (j == 0) HIPCHK(launch_axpby(op->n, op->yacc, h, op->p, 0.0, nullptr, st));
+    else HIPCHK(launch_axpby(op->n, op->yacc, 1.0, op->yacc, h, op->p, st));
+  }
+  return ADL_OK;
+}
+
+// y_acc = dt [phi_1(A dt) w1 + phi_2(A dt) w2]  (w2 may be null)
+static int phi_combo(adl_op* op, const double* w1, const double* w2, double dt, double tol, Acc& acc,
+                     hipStream_t st) {
+  if (op->alpha == 0.0) {
+    HIPCHK(launch_axpby(op->n, op->yacc, dt, w1, w2 ? 0.5 * dt : 0.0, w2, st));
+    acc.substeps = 0;
+    return ADL_OK;
+  }
+  int K = substeps_for(op->alpha, dt, op->rho_max);
+  for (int d = 0; d <= kMaxDoublings; ++d) {
+    bool ok;
+    RETCHK(combo_fixed(op, w1, w2, dt, tol, K, acc, ok, st));
+    if (ok) {
+      acc.substeps = K;
+      return ADL_OK;
+    }
+    K *= 2;
+  }
+  return status_to_code(3);
+}
+
+static void fill_stats(adl_stats* st, const Acc& a, adl_op* op, int code) {
+  if (!st) return;
+  st->matvecs = a.matvecs;
+  st->sweeps = a.sweeps;
+  st->max_degree = a.maxdeg;
+  st->last_degree = a.lastdeg;
+  st->substeps = a.substeps;
+  st->status = code;
+  st->alpha = op ? op->alpha : 0.0;
+}
+
+static int check_op(const adl_op* op) {
+  if (!op) return fail(ADL_EINVAL, "null op");
+  return ADL_OK;
+}
+
+static int check_bound(const adl_op* op) {
+  if (!op->has_bound) return fail(ADL_EBOUND, "no spectral bound installed (adl_spectral_bound / adl_set_bound)");
+  return ADL_OK;
+}
+
+static int check_tol(double tol) {
+  if (!(tol > 0.0 && tol < 1.0)) return fail(ADL_EINVAL, "tol must be in (0, 1), got %g", tol);
+  return ADL_OK;
+}
+
+static int check_dt(double dt) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ADL_EINVAL, "dt must be finite and > 0, got %g", dt);
+  return ADL_OK;
+}
+
+static int gershgorin(adl_op* op, hipStream_t st, double& out) {
+  HIPCHK(launch_ctl_reset(op->ctl, 1, st));
+  HIPCHK(launch_gershgorin(op->f, op->partials, op->ctl, st));
+  RETCHK(read_ctl(op, st));
+  out = op->host_ctl->gmin;
+  op->gersh = out;
+  return ADL_OK;
+}
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char* adl_last_error(void) { return g_err.c_str(); }
+
+int adl_leja_points(int n, double* out) {
+  if (!out || n < 1 || n > kMaxDegreeDefault + 1) return fail(ADL_EINVAL, "n must be in [1, %d]", kMaxDegreeDefault + 1);
+  const std::vector<double>& xi = leja_table();
+  std::copy(xi.begin(), xi.begin() + n, out);
+  return ADL_OK;
+}
+
+int adl_newton_coefficients(int l, double alpha, double h, int n, double* out) {
+  if (!out || n < 1 || n > kMaxDegreeDefault + 1) return fail(ADL_EINVAL, "n must be in [1, %d]", kMaxDegreeDefault + 1);
+  if (l < 0 || l > 2) return fail(ADL_EINVAL, "l must be 0, 1 or 2");
+  if (!(alpha < 0.0) || !std::isfinite(alpha) || !(h > 0.0)) return fail(ADL_EINVAL, "need alpha < 0, h > 0");
+  Plan P;
+  build_plan(P, l, alpha, h, n);
+  std::copy(P.d.begin(), P.d.end(), out);
+  return ADL_OK;
+}
+
+size_t adl_workspace_bytes(int nx, int ny, int storage, int max_degree) {
+  (void)max_degree;
+  if (nx < 3 || ny < 3 || storage < 0 || storage > 2) return 0;
+  return ws_layout(nx, ny, storage).total;
+}
+
+int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, const double* Dxx,
+                  const double* Dxy, const double* Dyy, const double* ax, const double* ay, double ax_c,
+                  double ay_c, void* workspace, size_t ws_bytes, void* stream, adl_op** out) {
+  if (!out) return fail(ADL_EINVAL, "out is null");
+  *out = nullptr;
+  if (nx < 3 || ny < 3) return fail(ADL_EINVAL, "nx, ny must be >= 3 (got %d, %d)", nx, ny);
+  if ((long)nx * ny > (1L << 31)) return fail(ADL_EINVAL, "grid too large");
+  if (!(hx > 0.0) || !(hy > 0.0) || !std::isfinite(hx) || !std::isfinite(hy))
+    return fail(ADL_EINVAL, "hx, hy must be finite and > 0");
+  if (bc != ADL_BC_PERIODIC && bc != ADL_BC_DIRICHLET) return fail(ADL_EINVAL, "bad bc %d", bc);
+  if (storage < 0 || storage > 2) return fail(ADL_EINVAL, "bad storage %d", storage);
+  if (!Dxx || !Dxy || !Dyy) return fail(ADL_EINVAL, "null tensor field");
+  if ((ax == nullptr) != (ay == nullptr)) return fail(ADL_EINVAL, "ax and ay must both be given or both NULL");
+  if (!std::isfinite(ax_c) || !std::isfinite(ay_c)) return fail(ADL_EINVAL, "advection constants not finite");
+  const WsLayout L = ws_layout(nx, ny, storage);
+  if (!workspace) return fail(ADL_ENOWORKSPACE, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(ADL_ENOWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(ADL_ENOWORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.total);
+
+  adl_op* op = new (std::nothrow) adl_op();
+  if (!op) return fail(ADL_EINVAL, "out of host memory");
+  char* base = reinterpret_cast<char*>(workspace);
+  op->nx = nx;
+  op->ny = ny;
+  op->bc = bc;
+  op->storage = storage;
+  op->hx = hx;
+  op->hy = hy;
+  op->n = (long)nx * ny;
+  const int f32 = storage != ADL_STORAGE_FP64;
+  op->f.kxx = base + L.kxx;
+  op->f.kxy = base + L.kxy;
+  op->f.kyy = base + L.kyy;
+  op->f.ax = ax ? base + L.ax : nullptr;
+  op->f.ay = ay ? base + L.ay : nullptr;
+  op->f.axc = ax_c / (2.0 * hx);
+  op->f.ayc = ay_c / (2.0 * hy);
+  op->f.nx = nx;
+  op->f.ny = ny;
+  op->f.bc = bc;
+  op->f.f32 = f32;
+  op->t = make_tiling(nx, ny, 0);
+  op->t1 = op->t;
+  if (op->t.vec == 2) {
+    op->t1 = make_tiling(nx, ny, op->t.rows);
+    op->t1.vec = 1;
+    op->t1.ncb = (nx + kBlock - 1) / kBlock;
+    op->t1.nblocks = op->t1.ncb * op->t1.nrb;
+  }
+  op->ybuf[0] = base + L.y0;
+  op->ybuf[1] = base + L.y1;
+  op->p = reinterpret_cast<double*>(base + L.p);
+  op->w1 = reinterpret_cast<double*>(base + L.w1);
+  op->w2 = reinterpret_cast<double*>(base + L.w2);
+  op->yacc = reinterpret_cast<double*>(base + L.yacc);
+  op->tmp = reinterpret_cast<double*>(base + L.tmp);
+  op->tmp2 = reinterpret_cast<double*>(base + L.tmp2);
+  op->partials = reinterpret_cast<double*>(base + L.partials);
+  op->ctl = reinterpret_cast<Ctl*>(base + L.ctl);
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&op->host_ctl), 4 * sizeof(Ctl), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete op;
+    return fail(ADL_EHIP, "hipHostMalloc failed: %s", hipGetErrorString(e));
+  }
+  hipStream_t st = S(stream);
+  const long n = op->n;
+  int rc = ADL_OK;
+  auto prep = [&](const double* src, double scale, const void* dst) -> int {
+    HIPCHK(launch_prepare_field(n, src, scale, const_cast<void*>(dst), f32, st));
+    return ADL_OK;
+  };
+  rc = prep(Dxx, 1.0 / (hx * hx), op->f.kxx);
+  if (rc == ADL_OK) rc = prep(Dyy, 1.0 / (hy * hy), op->f.kyy);
+  if (rc == ADL_OK) rc = prep(Dxy, 1.0 / (4.0 * hx * hy), op->f.kxy);
+  if (rc == ADL_OK && ax) rc = prep(ax, 1.0 / (2.0 * hx), op->f.ax);
+  if (rc == ADL_OK && ay) rc = prep(ay, 1.0 / (2.0 * hy), op->f.ay);
+  if (rc == ADL_OK) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(ADL_EHIP, "field preparation failed: %s", hipGetErrorString(e));
+  }
+  if (rc != ADL_OK) {
+    hipHostFree(op->host_ctl);
+    delete op;
+    return rc;
+  }
+  (void)leja_table();
+  *out = op;
+  return ADL_OK;
+}
+
+int adl_op_destroy(adl_op* op) {
+  if (!op) return ADL_OK;
+  if (op->host_ctl) hipHostFree(op->host_ctl);
+  delete op;
+  return ADL_OK;
+}
+
+int adl_op_set_limits(adl_op* op, int max_degree, double rho_max) {
+  RETCHK(check_op(op));
+  if (max_degree < 1 || max_degree > op->ws_max_degree)
+    return fail(ADL_EINVAL, "max_degree must be in [1, %d]", op->ws_max_degree);
+  if (!(rho_max > 0.0) || !std::isfinite(rho_max)) return fail(ADL_EINVAL, "rho_max must be > 0");
+  op->max_degree = max_degree;
+  op->rho_max = rho_max;
+  return ADL_OK;
+}
+
+int adl_op_set_quad2_mode(adl_op* op, int mode) {
+  RETCHK(check_op(op));
+  if (mode != ADL_QUAD2_AUGMENTED && mode != ADL_QUAD2_TWO_SWEEP) return fail(ADL_EINVAL, "bad quad2 mode");
+  op->quad2_mode = mode;
+  return ADL_OK;
+}
+
+int adl_apply(adl_op* op, const double* x, double* y, void* stream) {
+  RETCHK(check_op(op));
+  if (!x || !y) return fail(ADL_EINVAL, "null vector");
+  if (x == y) return fail(ADL_EINVAL, "x and y must not alias");
+  HIPCHK(launch_apply(op->f, tiling_for(op, x, y), x, y, nullptr, 0.0, nullptr, 0.0, S(stream)));
+  return ADL_OK;
+}
+
+int adl_spectral_bound(adl_op* op, int method, int max_iter, double rtol, uint64_t seed, double* alpha_out,
+                       int* iters_out, void* stream) {
+  RETCHK(check_op(op));
+  if (method != ADL_BOUND_GERSHGORIN && method != ADL_BOUND_POWER) return fail(ADL_EINVAL, "bad method");
+  hipStream_t st = S(stream);
+  double ag;
+  RETCHK(gershgorin(op, st, ag));
+  if (!std::isfinite(ag)) return fail(ADL_ENAN, "non-finite Gershgorin bound (fields contain NaN/Inf?)");
+  double alpha = ag;
+  int iters = 0;
+  if (method == ADL_BOUND_POWER) {
+    if (max_iter < 1) return fail(ADL_EINVAL, "max_iter must be >= 1");
+    if (!(rtol > 0.0)) return fail(ADL_EINVAL, "rtol must be > 0");
+    HIPCHK(launch_ctl_reset(op->ctl, 1, st));
+    HIPCHK(launch_power_init((int)op->n, seed, op->tmp, op->partials, 0, op->ctl, st));
+    double* bufs[2] = {op->tmp, op->tmp2};
+    int launched = 0;
+    while (launched < max_iter) {
+      const int chunk = std::min(max_iter - launched, launched == 0 ? 64 : 128);
+      for (int i = 0; i < chunk; ++i) {
+        const int k = launched + i;
+        HIPCHK(launch_power_step(op->f, op->t, bufs[k & 1], bufs[(k + 1) & 1], rtol, max_iter, op->partials,
+                                 op->ctl, st));
+      }
+      launched += chunk;
+      RETCHK(read_ctl(op, st));
+      if (op->host_ctl->stop) break;
+    }
+    const Ctl& c = *op->host_ctl;
+    if (c.status == 2) return fail(ADL_ENAN, "non-finite value in power iteration");
+    iters = c.iters;
+    const double lam = c.lam;
+    alpha = -std::min(1.1 * lam, std::fabs(ag));
+  }
+  if (alpha == 0.0 && ag != 0.0) return fail(ADL_EBOUND, "power iteration gave lambda = 0");
+  op->alpha = alpha;
+  op->has_bound = true;
+  if (alpha_out) *alpha_out = alpha;
+  if (iters_out) *iters_out = iters;
+  return ADL_OK;
+}
+
+int adl_set_bound(adl_op* op, double alpha) {
+  RETCHK(check_op(op));
+  if (!std::isfinite(alpha) || alpha > 0.0) return fail(ADL_EBOUND, "alpha must be finite and < 0 (got %g)", alpha);
+  if (alpha == 0.0) {
+    double ag = op->gersh;
+    if (std::isnan(ag)) RETCHK(gershgorin(op, nullptr, ag));
+    if (ag != 0.0) return fail(ADL_EBOUND, "alpha = 0 is only valid for the zero operator");
+  }
+  op->alpha = alpha;
+  op->has_bound = true;
+  return ADL_OK;
+}
+
+int adl_get_bound(const adl_op* op, double* alpha) {
+  RETCHK(check_op(op));
+  if (!alpha) return fail(ADL_EINVAL, "null alpha");
+  if (!op->has_bound) return fail(ADL_EBOUND, "no bound installed");
+  *alpha = op->alpha;
+  return ADL_OK;
+}
+
+int adl_leja_phi(adl_op* op, int l, double dt, const double* v, double* out, double tol, int max_degree,
+                 adl_stats* stp, void* stream) {
+  RETCHK(check_op(op));
+  if (l < 0 || l > 2) return fail(ADL_EINVAL, "l must be 0, 1 or 2");
+  if (!v || !out) return fail(ADL_EINVAL, "null vector");
+  if (v == out) return fail(ADL_EINVAL, "out must not alias v");
+  RETCHK(check_dt(dt));
+  RETCHK(check_tol(tol));
+  RETCHK(check_bound(op));
+  const int saved = op->max_degree;
+  if (max_degree > 0) {
+    if (max_degree > op->ws_max_degree) return fail(ADL_EINVAL, "max_degree too large");
+    op->max_degree = max_degree;
+  }
+  hipStream_t st = S(stream);
+  Acc acc;
+  int code = ADL_OK;
+  auto run = [&]() -> int {
+    if (op->alpha == 0.0) {
+      const double f = l == 0 ? 1.0 : (l == 1 ? 1.0 : 0.5);
+      HIPCHK(launch_axpby(op->n, out, f, v, 0.0, nullptr, st));
+      acc.substeps = 0;
+      return ADL_OK;
+    }
+    int K = substeps_for(op->alpha, dt, op->rho_max);
+    for (int dbl = 0; dbl <= kMaxDoublings; ++dbl) {
+      if (K == 1) {
+        Plan& P = get_plan(op, l, op->alpha, dt);
+        SweepOut so;
+        RETCHK(sweep(op, P, v, nullptr, 0.0, out, tol, op->max_degree, st, so));
+        account(acc, so);
+        if (so.status == 1) {
+          acc.substeps = 1;
+          return ADL_OK;
+        }
+        if (so.status == 2) return status_to_code(2);
+      } else if (l == 0) {
+        const double h = dt / K;
+        Plan& P = get_plan(op, 0, op->alpha, h);
+        const double* src = v;
+        double* bufs[2] = {op->tmp, op->tmp2};
+        bool ok = true;
+        for (int j = 0; j < K; ++j) {
+          double* dst = (j == K - 1) ? out : bufs[j & 1];
+          SweepOut so;
+          RETCHK(sweep(op, P, src, nullptr, 0.0, dst, tol, op->max_degree, st, so));
+          account(acc, so);
+          if (so.status == 2) return status_to_code(2);
+          if (so.status != 1) {
+            ok = false;
+            break;
+          }
+          src = dst;
+        }
+        if (ok) {
+          acc.substeps = K;
+          return ADL_OK;
+        }
+      } else {
+        bool ok;
+        if (l == 1) {
+          RETCHK(combo_fixed(op, v, nullptr, dt, tol, K, acc, ok, st));
+        } else {
+          HIPCHK(launch_fill(op->n, op->w1, 0.0, st));
+          RETCHK(combo_fixed(op, op->w1, v, dt, tol, K, acc, ok, st));
+        }
+        if (ok) {
+          HIPCHK(launch_axpby(op->n, out, 1.0 / dt, op->yacc, 0.0, nullptr, st));
+          acc.substeps = K;
+          return ADL_OK;
+        }
+      }
+      K *= 2;
+    }
+    return status_to_code(3);
+  };
+  code = run();
+  op->max_degree = saved;
+  fill_stats(stp, acc, op, code);
+  return code;
+}
+
+int adl_exp_midpoint_step(adl_op* op, double* u, const double* S_half, double dt, double tol, adl_stats* stp,
+                          void* stream) {
+  RETCHK(check_op(op));
+  if (!u) return fail(ADL_EINVAL, "null u");
+  RETCHK(check_dt(dt));
+  RETCHK(check_tol(tol));
+  RETCHK(check_bound(op));
+  hipStream_t st = S(stream);
+  Acc acc;
+  // w = A u + S(t + dt/2)
+  HIPCHK(launch_apply(op->f, tiling_for(op, u, S_half), u, op->w1, S_half, 1.0, nullptr, 0.0, st));
+  acc.matvecs += 1;
+  int code = phi_combo(op, op->w1, nullptr, dt, tol, acc, st);
+  if (code == ADL_OK) {
+    hipError_t e = launch_axpby(op->n, u, 1.0, u, 1.0, op->yacc, st);
+    if (e != hipSuccess) code = fail(ADL_EHIP, "update failed: %s", hipGetErrorString(e));
+  }
+  fill_stats(stp, acc, op, code);
+  return code;
+}
+
+int adl_exp_quad2_step(adl_op* op, double* u, const double* S1, const double* S2, double c1, double c2, double dt,
+                       double tol, adl_stats* stp, void* stream) {
+  RETCHK(check_op(op));
+  if (!u) return fail(ADL_EINVAL, "null u");
+  if (!std::isfinite(c1) || !std::isfinite(c2) || c1 == c2) return fail(ADL_EINVAL, "need finite c1 != c2");
+  RETCHK(check_dt(dt));
+  RETCHK(check_tol(tol));
+  RETCHK(check_bound(op));
+  hipStream_t st = S(stream);
+  Acc acc;
+  const double inv = 1.0 / (c2 - c1);
+  // w1 = A u + (c2 S1 - c1 S2)/(c2 - c1),  w2 = (S2 - S1)/(c2 - c1)
+  HIPCHK(launch_apply(op->f, tiling_for(op, u, S1, S2), u, op->w1, S1, c2 * inv, S2, -c1 * inv, st));
+  acc.matvecs += 1;
+  const double* w2 = nullptr;
+  if (S1 || S2) {
+    if (S1 && S2) HIPCHK(launch_diff_scale(op->n, op->w2, S2, S1, inv, st));
+    else if (S2) HIPCHK(launch_axpby(op->n, op->w2, inv, S2, 0.0, nullptr, st));
+    else HIPCHK(launch_axpby(op->n, op->w2, -inv, S1, 0.0, nullptr, st));
+    w2 = op->w2;
+  }
+  int code = ADL_OK;
+  if (op->quad2_mode == ADL_QUAD2_AUGMENTED || op->alpha == 0.0) {
+    code = phi_combo(op, op->w1, w2, dt, tol, acc, st);
+  } else {
+    // two sweeps: dt (phi_1 w1 + phi_2 w2)
+    adl_stats s1{}, s2{};
+    code = adl_leja_phi(op, 1, dt, op->w1, op->tmp2, tol, 0, &s1, stream);
+    if (code == ADL_OK) {
+      acc.matvecs += s1.matvecs;
+      acc.sweeps += s1.sweeps;
+      acc.maxdeg = std::max(acc.maxdeg, s1.max_degree);
+      acc.lastdeg = s1.last_degree;
+      acc.substeps = s1.substeps;
+      if (w2) {
+        // phi_2 result into w1 (w1 is no longer needed)
+        code = adl_leja_phi(op, 2, dt, w2, op->w1, tol, 0, &s2, stream);
+        if (code == ADL_OK) {
+          acc.matvecs += s2.matvecs;
+          acc.sweeps += s2.sweeps;
+          acc.maxdeg = std::max(acc.maxdeg, s2.max_degree);
+          acc.lastdeg = s2.last_degree;
+          hipError_t e = launch_axpby(op->n, op->tmp2, 1.0, op->tmp2, 1.0, op->w1, st);
+          if (e != hipSuccess) code = fail(ADL_EHIP, "combine failed");
+        }
+      }
+      if (code == ADL_OK) {
+        hipError_t e = launch_axpby(op->n, op->yacc, dt, op->tmp2, 0.0, nullptr, st);
+        if (e != hipSuccess) code = fail(ADL_EHIP, "scale failed");
+      }
+    }
+  }
+  if (code == ADL_OK) {
+    hipError_t e = launch_axpby(op->n, u, 1.0, u, 1.0, op->yacc, st);
+    if (e != hipSuccess) code = fail(ADL_EHIP, "update failed: %s", hipGetErrorString(e));
+  }
+  fill_stats(stp, acc, op, code);
+  return code;
+}
+
+
+// ---------------------------------------------------------------------------
+// learned bound: statistics and MLP
+// ---------------------------------------------------------------------------
+int adl_field_stats(adl_op* op, double dt, float* feats, void* stream) {
+  RETCHK(check_op(op));
+  if (!feats) return fail(ADL_EINVAL, "null feats");
+  RETCHK(check_dt(dt));
+  hipStream_t st = S(stream);
+  HIPCHK(launch_ctl_reset(op->ctl, 1, st));
+  HIPCHK(launch_field_stats(op->f, op->hx, op->hy, dt, feats, op->partials, op->ctl, st));
+  return ADL_OK;
+}
+
+int adl_mlp_forward(const float* W, const float* X, float* Y, float* act_cache, int B, void* stream) {
+  if (!W || !X || !Y) return fail(ADL_EINVAL, "null pointer");
+  if (B < 1) return fail(ADL_EINVAL, "B must be >= 1");
+  HIPCHK(launch_mlp_forward(W, X, Y, act_cache, B, S(stream)));
+  return ADL_OK;
+}
+
+int adl_mlp_backward(const float* W, const float* act_cache, const float* dY, float* dW, int B, void* stream) {
+  if (!W || !act_cache || !dY || !dW) return fail(ADL_EINVAL, "null pointer");
+  if (B < 1) return fail(ADL_EINVAL, "B must be >= 1");
+  HIPCHK(launch_mlp_backward(W, act_cache, dY, dW, B, S(stream)));
+  return ADL_OK;
+}
+
+int adl_mlp_adam_step(float* W, const float* dW, float* m1, float* m2, int t, float lr, float beta1, float beta2,
+                      float eps, void* stream) {
+  if (!W || !dW || !m1 || !m2) return fail(ADL_EINVAL, "null pointer");
+  if (t < 1) return fail(ADL_EINVAL, "t must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+    return fail(ADL_EINVAL, "bad Adam hyper-parameters");
+  HIPCHK(launch_mlp_adam(W, dW, m1, m2, t, lr, beta1, beta2, eps, S(stream)));
+  return ADL_OK;
+}
+
+}  // extern "C"

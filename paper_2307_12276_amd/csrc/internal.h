@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP translation units of libadl.
+// Nothing here is part of the public C ABI (include/adl.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace adl {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;             // 4 waves, side by side in x
+constexpr int kWavesX = kBlock / kWave;
+
+enum { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
+
+// Per-sweep control block in device memory.  Written only by the last block
+// of a launch (fixed-order reduction), read by the next launch and the host.
+struct Ctl {
+  int stop;             // 1: every later launch of this sweep returns at once
+  int status;           // 0 running, 1 converged, 2 non-finite, 3 degree cap
+  int degree;           // Newton terms (matrix applications) so far
+  unsigned int ticket;  // arrival counter of the running launch (reset by last block)
+  double tn2, pn2;      // ||d y||^2, ||p||^2 of the last term
+  double scale;         // power iteration: 1 / lambda_k
+  double lam, lam_prev; // power iteration estimates
+  double gmin;          // Gershgorin result
+  int iters;
+  int pad[3];
+};
+static_assert(sizeof(Ctl) <= 128, "ctl size");
+
+// The stored operator.  Coefficients are pre-scaled:
+//   kxx = Dxx / hx^2, kyy = Dyy / hy^2, kxy = Dxy / (4 hx hy),
+//   ax' = ax / (2 hx), ay' = ay / (2 hy)
+struct FieldView {
+  const void* kxx;
+  const void* kxy;
+  const void* kyy;
+  const void* ax;   // nullptr: constant axc
+  const void* ay;   // nullptr: constant ayc
+  double axc, ayc;
+  int nx, ny, bc;
+  int f32;          // fields stored as float
+};
+
+// Tiling of one grid for the row-marching stencil kernels.
+struct Tiling {
+  int vec;      // columns per lane (1 or 2; 2 needs even nx)
+  int rows;     // rows per block
+  int ncb, nrb; // column / row blocks
+  int nblocks;
+};
+
+Tiling make_tiling(int nx, int ny, int rows_hint);
+
+// ---- launches (stencil.hip) ----------------------------------------------
+// y = A x + a1 s1 + a2 s2   (s1 / s2 may be null)
+hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, double* y,
+                        const double* s1, double a1, const double* s2, double a2,
+                        hipStream_t st);
+
+struct LejaArgs {
+  const void* yin;   // y_k (double at k = 0, else the y storage type)
+  void* yout;        // y_{k+1}
+  double* p;         // Newton polynomial (FP64)
+  const double* w2;  // augmented column (k with s_k != 0 only), or null
+  double w2c;        // s_k / h
+  double shift;      // c + gamma xi_k
+  double invg;       // 1 / gamma
+  double d0, dk1;    // d_0 (first launch), d_{k+1}
+  double tol2;
+  int k;
+  int max_degree;
+  int first;         // k == 0: p = d0 y0 + d1 y1, zero-vector test
+  int ystore_f32;    // y_{k+1} stored as float
+  int yin_f32;       // y_k stored as float
+  double* partials;  // 3 * nblocks
+  Ctl* ctl;
+};
+hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
+
+// power iteration: w = scale * A x ; lambda = ||w|| ; see Ctl
+hipError_t launch_power_init(int n, uint64_t seed, double* w, double* partials, int nblocks,
+                             Ctl* ctl, hipStream_t st);
+hipError_t launch_power_step(const FieldView& f, const Tiling& t, const double* x, double* w,
+                             double rtol, int max_iter, double* partials, Ctl* ctl,
+                             hipStream_t st);
+hipError_t launch_gershgorin(const FieldView& f, double* partials, Ctl* ctl, hipStream_t st);
+
+// ---- elementwise (stencil.hip) --------------------------------------------
+hipError_t launch_ctl_reset(Ctl* ctl, int n, hipStream_t st);
+// y = a * x + b * z  (z may be null; y may alias x or z)
+hipError_t launch_axpby(long n, double* y, double a, const double* x, double b, const double* z,
+                        hipStream_t st);
+hipError_t launch_fill(long n, double* y, double v, hipStream_t st);
+// y = (x - z) * s   (the difference is formed first, so equal x and z give exact zeros)
+hipError_t launch_diff_scale(long n, double* y, const double* x, const double* z, double s, hipStream_t st);
+// out_f = (double or float) scale * in   for field preparation
+hipError_t launch_prepare_field(long n, const double* in, double scale, void* out, int f32,
+                                hipStream_t st);
+
+// ---- learned bound (mlp.hip) -----------------------------------------------
+hipError_t launch_field_stats(const FieldView& f, double hx, double hy, double dt, float* feats,
+                              double* partials, Ctl* ctl, hipStream_t st);
+hipError_t launch_mlp_forward(const float* W, const float* X, float* Y, float* cache, int B,
+                              hipStream_t st);
+hipError_t launch_mlp_backward(const float* W, const float* cache, const float* dY, float* dW,
+                               int B, hipStream_t st);
+hipError_t launch_mlp_adam(float* W, const float* dW, float* m1, float* m2, int t, float lr,
+                           float b1, float b2, float eps, hipStream_t st);
+
+}  // namespace adl

@@ -1,0 +1,264 @@
+// Learned spectral-interval predictor: field statistics and a 9-64-64-64-3
+// tanh MLP in FP32 with hand-written forward, backward and Adam kernels.
+//
+// Packed parameters: for each layer l, W_l [in][out] row-major then b_l[out].
+// Activation cache per row: X (9) | H1 (64) | H2 (64) | H3 (64).
+//
+// These networks are tiny (9155 parameters) and latency-bound: the forward
+// kernel gives each sample one wave64 (one lane per hidden unit, activations
+// in LDS); the backward kernel runs in a single block and walks the batch in
+// chunks so that every parameter gradient is a fixed-order sum over samples
+// (bitwise reproducible, no atomics).
+#include "device.h"
+
+namespace adl {
+
+constexpr int kIn = 9, kH = 64, kOut = 3;
+constexpr int oW1 = 0, oB1 = oW1 + kIn * kH;
+constexpr int oW2 = oB1 + kH, oB2 = oW2 + kH * kH;
+constexpr int oW3 = oB2 + kH, oB3 = oW3 + kH * kH;
+constexpr int oW4 = oB3 + kH, oB4 = oW4 + kH * kOut;
+constexpr int kParams = oB4 + kOut;
+static_assert(kParams == 9155, "parameter count");
+constexpr int kCache = kIn + 3 * kH;  // 201
+
+// ---------------------------------------------------------------------------
+// forward: one wave per sample
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restrict__ W, const float* __restrict__ X,
+                                                          float* __restrict__ Y, float* __restrict__ cache, int B) {
+  __shared__ float act[4][kH];
+  __shared__ float xin[4][kIn];
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + w;
+  const bool valid = b < B;
+  if (valid && t < kIn) {
+    const float v = X[(long)b * kIn + t];
+    xin[w][t] = v;
+    if (cache) cache[(long)b * kCache + t] = v;
+  }
+  __syncthreads();
+  // layer 1
+  float z = W[oB1 + t];
+  for (int i = 0; i < kIn; ++i) z += xin[w][i] * W[oW1 + i * kH + t];
+  float h = tanhf(z);
+  if (valid && cache) cache[(long)b * kCache + kIn + t] = h;
+  act[w][t] = h;
+  __syncthreads();
+  // layers 2 and 3
+  for (int layer = 0; layer < 2; ++layer) {
+    const int oW = layer == 0 ? oW2 : oW3, oB = layer == 0 ? oB2 : oB3;
+    z = W[oB + t];
+    for (int k = 0; k < kH; ++k) z += act[w][k] * W[oW + k * kH + t];
+    h = tanhf(z);
+    __syncthreads();
+    act[w][t] = h;
+    if (valid && cache) cache[(long)b * kCache + kIn + (layer + 1) * kH + t] = h;
+    __syncthreads();
+  }
+  // output layer (linear)
+  if (valid && t < kOut) {
+    float y = W[oB4 + t];
+    for (int k = 0; k < kH; ++k) y += act[w][k] * W[oW4 + k * kOut + t];
+    Y[(long)b * kOut + t] = y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward: single block, batch walked in chunks of kChunk samples.
+//   G4 = dY;  G3 = (G4 W4^T) (1 - H3^2);  G2 = (G3 W3^T)(1 - H2^2);  G1 = ...
+//   dW_l[i][o] = sum_b Hin_l[b][i] G_l[b][o],   db_l[o] = sum_b G_l[b][o]
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 32;
+constexpr int kBwdThreads = 1024;
+constexpr int kPerThread = (kParams + kBwdThreads - 1) / kBwdThreads;  // 9
+
+__global__ __launch_bounds__(kBwdThreads) void mlp_backward_kernel(const float* __restrict__ W,
+                                                                   const float* __restrict__ cache,
+                                                                   const float* __restrict__ dY,
+                                                                   float* __restrict__ dW, int B) {
+  __shared__ float G4[kChunk][kOut];
+  __shared__ float G3[kChunk][kH];
+  __shared__ float G2[kChunk][kH];
+  __shared__ float G1[kChunk][kH];
+  __shared__ float Hc[kChunk][kCache];
+  const int tid = threadIdx.x;
+  float acc[kPerThread];
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) acc[q] = 0.0f;
+
+  for (int b0 = 0; b0 < B; b0 += kChunk) {
+    const int nb = min(kChunk, B - b0);
+    __syncthreads();
+    for (int e = tid; e < nb * kCache; e += kBwdThreads) Hc[e / kCache][e % kCache] = cache[(long)b0 * kCache + e];
+    for (int e = tid; e < nb * kOut; e += kBwdThreads) G4[e / kOut][e % kOut] = dY[(long)b0 * kOut + e];
+    __syncthreads();
+    // G3: thread -> (sample, unit)
+    for (int e = tid; e < nb * kH; e += kBwdThreads) {
+      const int s = e / kH, k = e % kH;
+      float g = 0.0f;
+      for (int o = 0; o < kOut; ++o) g += G4[s][o] * W[oW4 + k * kOut + o];
+      const float hv = Hc[s][kIn + 2 * kH + k];
+      G3[s][k] = g * (1.0f - hv * hv);
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * kH; e += kBwdThreads) {
+      const int s = e / kH, k = e % kH;
+      float g = 0.0f;
+      for (int o = 0; o < kH; ++o) g += G3[s][o] * W[oW3 + k * kH + o];
+      const float hv = Hc[s][kIn + kH + k];
+      G2[s][k] = g * (1.0f - hv * hv);
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * kH; e += kBwdThreads) {
+      const int s = e / kH, k = e % kH;
+      float g = 0.0f;
+      for (int o = 0; o < kH; ++o) g += G2[s][o] * W[oW2 + k * kH + o];
+      const float hv = Hc[s][kIn + k];
+      G1[s][k] = g * (1.0f - hv * hv);
+    }
+    __syncthreads();
+    // accumulate parameter gradients, samples in order
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+      const int idx = tid + q * kBwdThreads;
+      if (idx >= kParams) continue;
+      float a = acc[q];
+      if (idx < oB1) {
+        const int i = (idx - oW1) / kH, o = (idx - oW1) % kH;
+        for (int s = 0; s < nb; ++s) a += Hc[s][i] * G1[s][o];
+      } else if (idx < oW2) {
+        const int o = idx - oB1;
+        for (int s = 0; s < nb; ++s) a += G1[s][o];
+      } else if (idx < oB2) {
+        const int i = (idx - oW2) / kH, o = (idx - oW2) % kH;
+        for (int s = 0; s < nb; ++s) a += Hc[s][kIn + i] * G2[s][o];
+      } else if (idx < oW3) {
+        const int o = idx - oB2;
+        for (int s = 0; s < nb; ++s) a += G2[s][o];
+      } else if (idx < oB3) {
+        const int i = (idx - oW3) / kH, o = (idx - oW3) % kH;
+        for (int s = 0; s < nb; ++s) a += Hc[s][kIn + kH + i] * G3[s][o];
+      } else if (idx < oW4) {
+        const int o = idx - oB3;
+        for (int s = 0; s < nb; ++s) a += G3[s][o];
+      } else if (idx < oB4) {
+        const int i = (idx - oW4) / kOut, o = (idx - oW4) % kOut;
+        for (int s = 0; s < nb; ++s) a += Hc[s][kIn + 2 * kH + i] * G4[s][o];
+      } else {
+        const int o = idx - oB4;
+        for (int s = 0; s < nb; ++s) a += G4[s][o];
+      }
+      acc[q] = a;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int idx = tid + q * kBwdThreads;
+    if (idx < kParams) dW[idx] = acc[q];
+  }
+}
+
+// Adam (Kingma & Ba 2015): bias corrections bc1 = 1 - b1^t, bc2 = 1 - b2^t.
+__global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ W, const float* __restrict__ dW,
+                                                       float* __restrict__ m1, float* __restrict__ m2, float lr,
+                                                       float b1, float b2, float eps, float bc1, float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kParams) return;
+  const float g = dW[i];
+  const float m = b1 * m1[i] + (1.0f - b1) * g;
+  const float v = b2 * m2[i] + (1.0f - b2) * g * g;
+  m1[i] = m;
+  m2[i] = v;
+  const float mh = m / bc1, vh = v / bc2;
+  W[i] = W[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// field statistics: per-node eigenvalues of [[Dxx, Dxy], [Dxy, Dyy]] and |a|
+// ---------------------------------------------------------------------------
+template <typename TF, bool ADVF>
+__global__ __launch_bounds__(kBlock) void field_stats_kernel(FieldView F, double hx, double hy, double dt,
+                                                             float* __restrict__ feats, double* partials,
+                                                             Ctl* ctl) {
+  const TF* kxx = reinterpret_cast<const TF*>(F.kxx);
+  const TF* kxy = reinterpret_cast<const TF*>(F.kxy);
+  const TF* kyy = reinterpret_cast<const TF*>(F.kyy);
+  const TF* fax = reinterpret_cast<const TF*>(F.ax);
+  const TF* fay = reinterpret_cast<const TF*>(F.ay);
+  const double sxx = hx * hx, syy = hy * hy, sxy = 4.0 * hx * hy, sax = 2.0 * hx, say = 2.0 * hy;
+  const long n = (long)F.nx * F.ny;
+  // sums: kpar, kperp', |a|; maxima: kpar, kperp', |a|
+  double acc[6] = {0.0, 0.0, 0.0, -INFINITY, -INFINITY, -INFINITY};
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double dxx = (double)kxx[i] * sxx, dyy = (double)kyy[i] * syy, dxy = (double)kxy[i] * sxy;
+    const double m = 0.5 * (dxx + dyy);
+    const double r = sqrt(0.25 * (dxx - dyy) * (dxx - dyy) + dxy * dxy);
+    const double kp = m + r;
+    const double kq = fmax(m - r, 0.0) + 1e-30;
+    double ax = F.axc * sax, ay = F.ayc * say;
+    if constexpr (ADVF) {
+      ax = (double)fax[i] * sax;
+      ay = (double)fay[i] * say;
+    }
+    const double am = sqrt(ax * ax + ay * ay);
+    acc[0] += kp;
+    acc[1] += kq;
+    acc[2] += am;
+    acc[3] = nanmax(acc[3], kp);
+    acc[4] = nanmax(acc[4], kq);
+    acc[5] = nanmax(acc[5], am);
+  }
+  const double nn = (double)n;
+  grid_reduce<6, 3>(acc, partials, ctl, [=](const double (&tot)[6]) {
+    feats[0] = (float)log10(fmax(tot[3], 1e-30));
+    feats[1] = (float)log10(fmax(tot[0] / nn, 1e-30));
+    feats[2] = (float)log10(tot[4]);
+    feats[3] = (float)log10(tot[1] / nn);
+    feats[4] = (float)tot[5];
+    feats[5] = (float)(tot[2] / nn);
+    feats[6] = (float)log10(hx);
+    feats[7] = (float)log10(hy);
+    feats[8] = (float)log10(dt);
+  });
+}
+
+hipError_t launch_field_stats(const FieldView& f, double hx, double hy, double dt, float* feats, double* partials,
+                              Ctl* ctl, hipStream_t st) {
+  const long n = (long)f.nx * f.ny;
+  long nb = (n + kBlock - 1) / kBlock;
+  if (nb > 1024) nb = 1024;
+  const bool advf = f.ax != nullptr;
+  if (f.f32) {
+    if (advf)
+      hipLaunchKernelGGL((field_stats_kernel<float, true>), dim3(nb), dim3(kBlock), 0, st, f, hx, hy, dt, feats, partials, ctl);
+    else
+      hipLaunchKernelGGL((field_stats_kernel<float, false>), dim3(nb), dim3(kBlock), 0, st, f, hx, hy, dt, feats, partials, ctl);
+  } else {
+    if (advf)
+      hipLaunchKernelGGL((field_stats_kernel<double, true>), dim3(nb), dim3(kBlock), 0, st, f, hx, hy, dt, feats, partials, ctl);
+    else
+      hipLaunchKernelGGL((field_stats_kernel<double, false>), dim3(nb), dim3(kBlock), 0, st, f, hx, hy, dt, feats, partials, ctl);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* W, const float* X, float* Y, float* cache, int B, hipStream_t st) {
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((B + 3) / 4), dim3(256), 0, st, W, X, Y, cache, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const float* W, const float* cache, const float* dY, float* dW, int B, hipStream_t st) {
+  hipLaunchKernelGGL(mlp_backward_kernel, dim3(1), dim3(kBwdThreads), 0, st, W, cache, dY, dW, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* W, const float* dW, float* m1, float* m2, int t, float lr, float b1, float b2,
+                           float eps, hipStream_t st) {
+  const double bc1 = 1.0 - pow((double)b1, (double)t), bc2 = 1.0 - pow((double)b2, (double)t);
+  hipLaunchKernelGGL(mlp_adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, st, W, dW, m1, m2, lr, b1, b2, eps,
+                     (float)bc1, (float)bc2);
+  return hipGetLastError();
+}
+
+}  // namespace adl

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  FP64 results must agree to 1e-10 relative L2 with the
+same Leja degrees."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bounds, integrators, leja
+from oracle import operator as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2307_12276_amd as A  # noqa: E402
+from gpu_util import make_pair, rel, to_dev, to_np, workload_pair  # noqa: E402
+
+SHAPES = [(3, 3), (5, 7), (64, 64), (130, 70), (257, 33), (256, 9), (300, 129), (128, 128)]
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
+@pytest.mark.parametrize("adv", ["const", "field"])
+def test_apply_matches_oracle(nx, ny, bc, adv):
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=nx * 31 + ny, field_advection=(adv == "field"))
+    hx, hy = 1.0 / nx, 0.7 / ny
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, hx, hy, bc)
+    x = W.random_vector((ny, nx), 5)
+    y = torch.empty_like(to_dev(x))
+    gop.apply(to_dev(x), y)
+    ref = O.apply(oop, x)
+    assert rel(to_np(y), ref) < 1e-13
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_apply_fp32_fields(storage):
+    nx, ny = 300, 77
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=3, field_advection=True)
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, 1 / nx, 1 / ny, O.PERIODIC, storage)
+    x = W.random_vector((ny, nx), 1)
+    y = torch.empty_like(to_dev(x))
+    gop.apply(to_dev(x), y)
+    assert rel(to_np(y), O.apply(oop, x)) < 1e-13
+
+
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
+def test_tile_corner_impulses(bc):
+    """Unit impulses at tile corners and strip / band edges."""
+    nx, ny = 520, 200
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=8, field_advection=True)
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, 1 / nx, 1 / ny, bc)
+    t = gop_tiling_guess = None  # noqa: F841
+    x = np.zeros((ny, nx))
+    for j in (0, 1, 3, 4, 15, 16, 31, 32, 63, 64, ny - 2, ny - 1):
+        for i in (0, 1, 63, 64, 127, 128, 255, 256, 511, 512, nx - 1):
+            x[j, i] += 1.0 + 0.001 * (i + j)
+    y = torch.empty_like(to_dev(x))
+    gop.apply(to_dev(x), y)
+    ref = O.apply(oop, x)
+    assert np.max(np.abs(to_np(y) - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
+def test_gershgorin(bc):
+    nx, ny = 131, 66
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=2, field_advection=True)
+    oop, gop = make_pair(Dxx, Dxy, Dyy, 5 * ax, 5 * ay, 1 / nx, 1 / ny, bc)
+    a, _ = gop.spectral_bound(A.BOUND_GERSHGORIN)
+    assert a == pytest.approx(bounds.gershgorin(oop), rel=1e-13)
+
+
+def test_power_iteration():
+    w = W.c2_dirichlet_circular(n=48)
+    oop, gop = workload_pair(w)
+    a, its = gop.spectral_bound(A.BOUND_POWER, max_iter=3000, rtol=1e-6, seed=7)
+    ao, itso = bounds.spectral_bound(oop, 1, max_iter=3000, rtol=1e-6, seed=7)
+    assert its == itso
+    assert a == pytest.approx(ao, rel=1e-10)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2])
+@pytest.mark.parametrize("rho_max", [1600.0, 30.0])
+def test_leja_phi(l, rho_max):
+    w = W.c2_dirichlet_circular(n=40)
+    oop, gop = workload_pair(w)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    gop.set_limits(500, rho_max)
+    v = W.random_vector(oop.shape, 4)
+    out = torch.empty_like(to_dev(v))
+    st = gop.leja_phi(l, w.dt, to_dev(v), out, 1e-10)
+    ost = {}
+    ref = leja.phi_apply(lambda x: O.apply(oop, x), l, w.dt, v, alpha, 1e-10, rho_max=rho_max, stats=ost)
+    assert st["substeps"] == ost["substeps"]
+    assert st["matvecs"] == ost["matvecs"]
+    assert rel(to_np(out), ref) < 1e-12
+
+
+def run_workload(w, steps, storage=None, quad2_mode=A.QUAD2_AUGMENTED):
+    oop, gop = workload_pair(w, storage)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    gop.set_quad2_mode(quad2_mode)
+    u = w.u0.copy()
+    ug = to_dev(w.u0)
+    A_ = lambda x: O.apply(oop, x)
+    for n in range(steps):
+        S1, S2 = w.stage_sources(n)
+        ost = {}
+        if w.scheme == "midpoint":
+            u = integrators.exp_midpoint_step(A_, u, S1, w.dt, alpha, w.tol, stats=ost)
+            st = gop.midpoint_step(ug, to_dev(S1) if S1 is not None else None, w.dt, w.tol)
+        else:
+            mode = "augmented" if quad2_mode == A.QUAD2_AUGMENTED else "two_sweep"
+            u = integrators.exp_quad2_step(A_, u, S1, S2, w.c1, w.c2, w.dt, alpha, w.tol, stats=ost, mode=mode)
+            st = gop.quad2_step(ug, to_dev(S1) if S1 is not None else None,
+                                to_dev(S2) if S2 is not None else None, w.c1, w.c2, w.dt, w.tol)
+        assert st["matvecs"] == ost["matvecs"], (n, st, ost)
+    return to_np(ug), u
+
+
+def test_periodic_constant_midpoint_full_config():
+    """64x64 periodic constant tensor, exponential midpoint, 10 steps."""
+    w = W.c1_periodic_constant(n=64, steps=10)
+    g, o = run_workload(w, w.steps)
+    assert rel(g, o) < 1e-10
+
+
+@pytest.mark.parametrize("mode", [A.QUAD2_AUGMENTED, A.QUAD2_TWO_SWEEP])
+def test_dirichlet_circular_quad2_small(mode):
+    w = W.c2_dirichlet_circular(n=96, steps=4)
+    g, o = run_workload(w, w.steps, quad2_mode=mode)
+    assert rel(g, o) < 1e-10
+
+
+def test_dirichlet_circular_quad2_full_size_two_steps():
+    """512x512 Dirichlet circular field, two-stage quadrature (1/3, 2/3),
+    dt = 200 dt_CFL: the first two of its steps against the oracle."""
+    w = W.c2_dirichlet_circular(n=512)
+    g, o = run_workload(w, 2)
+    assert rel(g, o) < 1e-10
+
+
+def test_stream_function_fp32_storage_parity():
+    """Stream-function field with FP32 fields (mode 1) and FP32 Newton vectors
+    (mode 2): mode 1 equals the oracle run on the FP32-rounded fields to
+    1e-10; mode 2 is within 1e-5 of it."""
+    w = W.c3_stream_function(n=128, steps=3, storage=1)
+    g1, o1 = run_workload(w, 3, storage=1)
+    assert rel(g1, o1) < 1e-10
+    g2, _ = run_workload(w, 3, storage=2)
+    assert rel(g2, o1) < 1e-5
+
+
+def test_gauss_quad2_and_time_dependent_source():
+    """Exponential Gauss nodes with the time-dependent sources of eq. 9."""
+    X, Y, hx, hy = W.grid_2d(70, 60, W.DIRICHLET, box=(-1, 1, -1, 1))
+    Dxx, Dxy, Dyy = W.spiral_tensor(X, Y, 2)
+    oop, gop = make_pair(Dxx + 1e-4, Dxy, Dyy + 1e-4, 1.0, 2.0, hx, hy, W.DIRICHLET)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    c1, c2 = 0.5 - math.sqrt(3) / 6, 0.5 + math.sqrt(3) / 6
+    u = W.gaussian(X, Y, 0.2, 0.1, 0.2)
+    ug = to_dev(u)
+    dt = 2e-3
+    A_ = lambda x: O.apply(oop, x)
+    for n in range(3):
+        t = 0.08 + n * dt
+        S1, S2 = W.source_tds(X, Y, t + c1 * dt), W.source_tds(X, Y, t + c2 * dt)
+        u = integrators.exp_quad2_step(A_, u, S1, S2, c1, c2, dt, alpha, 1e-10)
+        gop.quad2_step(ug, to_dev(S1), to_dev(S2), c1, c2, dt, 1e-10)
+    assert rel(to_np(ug), u) < 1e-10
+
+
+def test_zero_vector_degree_zero():
+    w = W.c1_periodic_constant(n=64)
+    oop, gop = workload_pair(w)
+    gop.set_bound(-1000.0)
+    z = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    out = torch.full_like(z, 7.0)
+    st = gop.leja_phi(1, 1e-3, z, out, 1e-10)
+    assert st["matvecs"] == 0 and float(out.abs().max()) == 0.0
+
+
+def test_nan_input_is_reported_and_u_untouched():
+    w = W.c1_periodic_constant(n=64)
+    oop, gop = workload_pair(w)
+    gop.spectral_bound(A.BOUND_GERSHGORIN)
+    u = to_dev(w.u0)
+    S = torch.zeros_like(u)
+    S[3, 5] = float("nan")
+    before = u.clone()
+    with pytest.raises(A.AdlError) as e:
+        gop.midpoint_step(u, S, w.dt, 1e-10)
+    assert e.value.code == A.ENAN
+    assert torch.equal(u, before)
+
+
+def test_degree_cap_triggers_substeps_then_enoconv():
+    w = W.c1_periodic_constant(n=64)
+    oop, gop = workload_pair(w)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    gop.set_limits(12, 1600.0)
+    v = W.random_vector(oop.shape, 2)
+    out = torch.empty_like(to_dev(v))
+    st = gop.leja_phi(1, w.dt, to_dev(v), out, 1e-10)
+    ost = {}
+    ref = leja.phi_apply(lambda x: O.apply(oop, x), 1, w.dt, v, alpha, 1e-10, max_degree=12, stats=ost)
+    assert st["substeps"] == ost["substeps"] > 1
+    assert rel(to_np(out), ref) < 1e-12
+    gop.set_limits(2, 1600.0)
+    with pytest.raises(A.AdlError) as e:
+        gop.leja_phi(1, 100 * w.dt, to_dev(v), out, 1e-10)
+    assert e.value.code == A.ENOCONV
+
+
+def test_invalid_arguments():
+    w = W.c1_periodic_constant(n=64)
+    oop, gop = workload_pair(w)
+    u = to_dev(w.u0)
+    with pytest.raises(A.AdlError) as e:
+        gop.midpoint_step(u, None, w.dt, 1e-10)  # no bound yet
+    assert e.value.code == A.EBOUND
+    gop.set_bound(-100.0)
+    for dt, tol in [(0.0, 1e-10), (-1.0, 1e-10), (1e-3, 0.0), (1e-3, 1.0)]:
+        with pytest.raises(A.AdlError) as e:
+            gop.midpoint_step(u, None, dt, tol)
+        assert e.value.code == A.EINVAL
+    with pytest.raises(A.AdlError):
+        gop.quad2_step(u, None, None, 0.5, 0.5, 1e-3, 1e-10)
+    with pytest.raises(A.AdlError) as e:
+        gop.set_bound(1.0)
+    assert e.value.code == A.EBOUND
+
+
+def test_deterministic_bitwise():
+    w = W.c2_dirichlet_circular(n=200, steps=2)
+    oop, gop = workload_pair(w)
+    gop.spectral_bound(A.BOUND_GERSHGORIN)
+    outs = []
+    for _ in range(2):
+        u = to_dev(w.u0)
+        S = to_dev(w.S(0))
+        for n in range(2):
+            gop.quad2_step(u, S, S, w.c1, w.c2, w.dt, w.tol)
+        outs.append(to_np(u))
+    assert np.array_equal(outs[0], outs[1])
