@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the Leja exponential integrator on one MI355X.
+
+Workload (one "step" = one pass of the hot path: stage vectors, the Newton-
+Leja sweep with its fused norm reductions, and the update): 512 x 512
+Dirichlet grid, circular field about the centre, k_par = 1, k_par/k_perp =
+1e3, a = (0.2, 0), centred time-independent Gaussian source, two-stage
+exponential quadrature c = (1/3, 2/3), dt = 200 dt_CFL, tol 1e-10, FP64.
+Operator setup and the Gershgorin bound happen once, before timing.
+
+Prints one JSON line.  `value` = time steps per second on one GPU.
+`roofline` = the Newton-Leja iteration kernel (the dominant kernel):
+algorithmic bytes per launch / average dispatch-timed duration, against
+8 TB/s.  `cpu_baseline` = the FP64 NumPy oracle, single-threaded, on a
+bounded sample of the same workload.  Extra legs: the same kernel on a
+4096 x 4096 grid (working set far beyond the caches).
+"""
+import os
+
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import math  # noqa: E402
+import sys  # noqa: E402
+import time  # noqa: E402
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "stencil GB/s (%HBM peak), Leja steps/s; chosen vs plain at fixed rel. error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev_tensor(a):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def make_op(w, storage=None):
+    import paper_2307_12276_amd as A
+    st = w.storage if storage is None else storage
+    return A.Op(dev_tensor(w.Dxx), dev_tensor(w.Dxy), dev_tensor(w.Dyy), w.hx, w.hy, w.bc, st,
+                ax_c=w.ax_c, ay_c=w.ay_c)
+
+
+def gpu_step(op, w, u, n, srcs):
+    S1, S2 = srcs(n)
+    if w.scheme == "midpoint":
+        return op.midpoint_step(u, S1, w.dt, w.tol)
+    return op.quad2_step(u, S1, S2, w.c1, w.c2, w.dt, w.tol)
+
+
+def device_sources(w):
+    """Source arrays at the quadrature nodes, moved to the device once per
+    distinct array (the time-independent source is one array)."""
+    cache = {}
+
+    def get(a):
+        if a is None:
+            return None
+        k = id(a)
+        if k not in cache:
+            cache[k] = (a, dev_tensor(a))
+        return cache[k][1]
+
+    def srcs(n):
+        S1, S2 = w.stage_sources(n)
+        return get(S1), get(S2)
+    return srcs
+
+
+def kernel_roofline(op_ms, launches, nbytes):
+    avg_ms = op_ms / max(launches, 1)
+    per_launch = nbytes / max(launches, 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return avg_ms, per_launch, achieved
+
+
+def run_roofline_leg(w, storage):
+    """One midpoint step of the stream-function field at n x n: the Leja
+    kernel's dispatch-timed bandwidth on a working set far beyond the caches."""
+    import torch
+    import paper_2307_12276_amd as A
+    n = w.nx
+    op = make_op(w, storage)
+    op.spectral_bound(A.BOUND_GERSHGORIN)
+    u = dev_tensor(w.u0)
+    srcs = device_sources(w)
+    gpu_step(op, w, u, 0, srcs)  # warm-up (plan, predicted degree)
+    torch.cuda.synchronize()
+    op.profile(True)
+    t0 = time.perf_counter()
+    st = gpu_step(op, w, u, 1, srcs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, launches, nbytes = op.profile_read()
+    op.profile(False)
+    avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)
+    res = {"workload": w.name, "storage": ["fp64", "fp32-fields", "fp32-fields+y"][storage],
+           "nx": n, "ny": n, "kernel": "leja_kernel", "launches": launches,
+           "bytes_per_launch": per_launch, "avg_kernel_us": avg_ms * 1e3,
+           "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
+           "matvecs_per_step": st["matvecs"], "step_ms": wall * 1e3}
+    del op
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle, single-threaded, on the first steps of the same
+    workload until budget_s seconds of CPU work have been spent."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bounds, integrators
+    from oracle import operator as O
+    oop = O.make_operator(w.Dxx, w.Dxy, w.Dyy, w.ax_c, w.ay_c, w.hx, w.hy, w.bc)
+    A_ = lambda x: O.apply(oop, x)
+    alpha = bounds.gershgorin(oop)
+    u = w.u0.copy()
+    steps = 0
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        while True:
+            S1, S2 = w.stage_sources(steps)
+            if w.scheme == "midpoint":
+                u = integrators.exp_midpoint_step(A_, u, S1, w.dt, alpha, w.tol)
+            else:
+                u = integrators.exp_quad2_step(A_, u, S1, S2, w.c1, w.c2, w.dt, alpha, w.tol)
+            steps += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    el = time.perf_counter() - t0
+    return steps / el, steps, el, u
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(bins and row slabs would shard across GPUs; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2307_12276_amd as A
+    import workloads as W
+
+    torch.cuda.init()
+    w = W.c2_dirichlet_circular(n=512, steps=args.steps)
+    t0 = time.perf_counter()
+    op = make_op(w, A.STORAGE_FP64)
+    alpha, _ = op.spectral_bound(A.BOUND_GERSHGORIN)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    u = dev_tensor(w.u0)
+    srcs = device_sources(w)
+    for n in range(args.warmup):
+        gpu_step(op, w, u, n, srcs)
+    torch.cuda.synchronize()
+
+    op.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mv = 0
+    for n in range(args.warmup, args.warmup + args.steps):
+        st = gpu_step(op, w, u, n, srcs)
+        mv += st["matvecs"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, launches, nbytes = op.profile_read()
+    op.profile(False)
+    avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)
+    value = args.steps / el
+    log("timed %d steps in %.3fs: %.1f steps/s, %.1f matvecs/step, leja kernel %.2f us avg, %.0f GB/s"
+        % (args.steps, el, value, mv / args.steps, avg_ms * 1e3, achieved))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded analytic fields)",
+        "config": {"workload": "dirichlet-circular-512: Dirichlet 512x512, circular b, k_par/k_perp=1e3, "
+                               "a=(0.2,0), time-independent Gaussian source, two-stage exp. quadrature "
+                               "c=(1/3,2/3), dt=200 dt_CFL, tol=1e-10",
+                   "nx": 512, "ny": 512, "dt": w.dt, "tol": w.tol, "alpha": alpha,
+                   "matvecs_per_step": mv / args.steps, "setup_s": setup_s},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "leja_kernel", "bytes_per_launch": per_launch,
+                     "avg_kernel_us": avg_ms * 1e3, "launches": launches,
+                     "note": "512^2 FP64 working set (~15 MB/iteration) stays in L2/MALL"},
+    }
+
+    if not args.no_cpu:
+        # same workload, first steps, oracle single-threaded
+        cw = W.c2_dirichlet_circular(n=512, steps=args.steps)
+        rate, nst, el_cpu, u_cpu = cpu_baseline(cw, args.cpu_budget)
+        # parity of the GPU on exactly those steps
+        op2 = make_op(cw, A.STORAGE_FP64)
+        op2.set_bound(alpha)
+        ug = dev_tensor(cw.u0)
+        s2 = device_sources(cw)
+        for n in range(nst):
+            gpu_step(op2, cw, ug, n, s2)
+        torch.cuda.synchronize()
+        err = float(np.linalg.norm(ug.cpu().numpy() - u_cpu) / np.linalg.norm(u_cpu))
+        out["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                               "sample": "first %d steps of the same 512^2 workload (%.1fs), NumPy FP64, "
+                                         "single-threaded" % (nst, el_cpu)}
+        out["parity"] = {"steps": nst, "rel_l2_vs_oracle": err}
+        log("cpu oracle: %.3f steps/s over %d steps; GPU rel err on those steps %.2e" % (rate, nst, err))
+        del op2
+
+    if not args.no_extra:
+        del op
+        torch.cuda.empty_cache()
+        legs = []
+        t0 = time.time()
+        rw = W.roofline_shape(n=4096)
+        log("roofline leg: 4096^2 fields built in %.1fs" % (time.time() - t0))
+        for storage in (A.STORAGE_FP64, A.STORAGE_FP32_FIELDS):
+            legs.append(run_roofline_leg(rw, storage))
+            log("roofline leg %s: %.1f us/iter, %.0f GB/s (%.1f%% of 8 TB/s)" % (
+                legs[-1]["storage"], legs[-1]["avg_kernel_us"], legs[-1]["achieved_GBs"],
+                100 * legs[-1]["frac_of_8TBs"]))
+        out["roofline_4096"] = legs
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -123,6 +123,23 @@ int adl_op_set_limits(adl_op* op, int max_degree, double rho_max);
 /* ADL_QUAD2_AUGMENTED (default) or ADL_QUAD2_TWO_SWEEP. */
 int adl_op_set_quad2_mode(adl_op* op, int mode);
 
+/* Kernel-time profiling of the Newton-Leja iteration kernel (the hot loop).
+ * With enable != 0 every productive iteration launch (not the no-op launches
+ * enqueued past the stopping index) is timed with HIP events attached to its
+ * dispatch.  adl_op_profile_read returns the summed kernel time in ms, the
+ * number of timed launches and the algorithmic bytes they moved (read y_k,
+ * tensor and advection fields, p, w2 when present; write y_{k+1}, p), then
+ * resets the counters.  adl_op_profile resets them too. */
+int adl_op_profile(adl_op* op, int enable);
+int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, double* bytes);
+
+/* Tiling of the stencil kernels: rows = height of the row band each block
+ * marches down (0 = built-in default; the autotuner sets it).  Two columns per
+ * lane are used when nx is even.  adl_op_get_tiling reports the tiling in use
+ * (any output pointer may be NULL). */
+int adl_op_set_tiling(adl_op* op, int rows);
+int adl_op_get_tiling(const adl_op* op, int* vec, int* rows, int* nblocks);
+
 /* y = A x (one stencil application).  x, y: device [ny][nx] FP64, not
  * overlapping. */
 int adl_apply(adl_op* op, const double* x, double* y, void* stream);

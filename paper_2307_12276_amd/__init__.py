@@ -59,6 +59,11 @@ _SIG = {
     "adl_op_destroy": (_I, [_P]),
     "adl_op_set_limits": (_I, [_P, _I, _D]),
     "adl_op_set_quad2_mode": (_I, [_P, _I]),
+    "adl_op_profile": (_I, [_P, _I]),
+    "adl_op_set_tiling": (_I, [_P, _I]),
+    "adl_op_get_tiling": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "adl_op_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
+                                 ctypes.POINTER(_D)]),
     "adl_apply": (_I, [_P, _P, _P, _P]),
     "adl_spectral_bound": (_I, [_P, _I, _I, _D, ctypes.c_uint64, ctypes.POINTER(_D),
                                 ctypes.POINTER(_I), _P]),
@@ -191,6 +196,25 @@ class Op:
 
     def set_limits(self, max_degree: int = 500, rho_max: float = 1600.0):
         _check(lib().adl_op_set_limits(self.handle, int(max_degree), float(rho_max)))
+
+    def set_tiling(self, rows: int):
+        _check(lib().adl_op_set_tiling(self.handle, int(rows)))
+
+    def get_tiling(self):
+        v, r, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().adl_op_get_tiling(self.handle, ctypes.byref(v), ctypes.byref(r), ctypes.byref(nb)))
+        return {"vec": v.value, "rows": r.value, "nblocks": nb.value}
+
+    def profile(self, enable: bool = True):
+        _check(lib().adl_op_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self):
+        """(kernel ms, launches, algorithmic bytes) of the timed Leja launches."""
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        b = ctypes.c_double()
+        _check(lib().adl_op_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
 
     def set_quad2_mode(self, mode: int):
         _check(lib().adl_op_set_quad2_mode(self.handle, int(mode)))

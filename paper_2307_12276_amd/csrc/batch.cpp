@@ -1,7 +1,7 @@
 // Batched momentum bins (first version): every bin advanced by its own
 // exponential midpoint step, one after the other.
 #include "internal.h"
-#include "../../include/adl.h"
+#include "adl.h"
 
 #include <new>
 #include <vector>

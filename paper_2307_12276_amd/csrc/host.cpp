@@ -9,7 +9,7 @@
 // each launch sets a device stop flag so that launches enqueued after
 // convergence are no-ops, and the host reads the flag once per chunk.
 #include "internal.h"
-#include "../../include/adl.h"
+#include "adl.h"
 
 #include <algorithm>
 #include <cmath>
@@ -225,6 +225,11 @@ struct adl_op {
   Ctl* host_ctl = nullptr;  // pinned
   std::vector<Plan> plans;  // small cache
   int plan_next = 0;
+  // kernel profiling of the Newton-Leja iteration kernel
+  bool prof = false;
+  double prof_ms = 0.0, prof_bytes = 0.0;
+  long long prof_launches = 0;
+  std::vector<hipEvent_t> evs;
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -309,6 +314,17 @@ static Plan& get_plan(adl_op* op, int l, double alpha, double h) {
   return P;
 }
 
+// Algorithmic HBM bytes of one Newton-Leja iteration launch: read y_k, the
+// three tensor fields (+ two advection fields), p (not at k = 0), w2 (when
+// the augmented column enters); write y_{k+1} and p.
+static double leja_bytes(const adl_op* op, int k, bool with_w2) {
+  const double fs = op->f.f32 ? 4.0 : 8.0;
+  const double ys = op->storage == ADL_STORAGE_FP32_FIELDS_Y ? 4.0 : 8.0;
+  double b = (k == 0 ? 8.0 : ys) + 3.0 * fs + (k == 0 ? 0.0 : 8.0) + (with_w2 ? 8.0 : 0.0) + ys + 8.0;
+  if (op->f.ax) b += 2.0 * fs;
+  return b * (double)op->n;
+}
+
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
@@ -322,9 +338,20 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   while (true) {
     int chunk = launched == 0 ? predicted : std::max(8, launched / 4);
     if (launched + chunk > maxdeg) chunk = maxdeg - launched;
+    if (op->prof) {
+      while ((int)op->evs.size() < 2 * chunk) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        op->evs.push_back(e);
+      }
+    }
     for (int i = 0; i < chunk; ++i) {
       const int k = launched + i;
       LejaArgs a{};
+      if (op->prof) {
+        a.ev_start = op->evs[2 * i];
+        a.ev_stop = op->evs[2 * i + 1];
+      }
       a.yin = k == 0 ? (const void*)v : op->ybuf[k & 1];
       a.yout = op->ybuf[(k + 1) & 1];
       a.p = p_out;
@@ -344,8 +371,19 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.ctl = op->ctl;
       HIPCHK(launch_leja_step(op->f, tiling_for(op, v, p_out), a, st));
     }
-    launched += chunk;
     RETCHK(read_ctl(op, st));
+    if (op->prof) {
+      // launches past the stopping index returned at once: time only the productive ones
+      const int productive = op->host_ctl->stop ? std::max(op->host_ctl->degree, 1) - launched : chunk;
+      for (int i = 0; i < chunk && i < productive; ++i) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * i], op->evs[2 * i + 1]));
+        op->prof_ms += ms;
+        op->prof_launches += 1;
+        op->prof_bytes += leja_bytes(op, launched + i, w2 != nullptr && P.s[launched + i] != 0.0);
+      }
+    }
+    launched += chunk;
     if (op->host_ctl->stop || launched >= maxdeg) break;
   }
   out.degree = op->host_ctl->degree;
@@ -542,7 +580,6 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->t = make_tiling(nx, ny, 0);
   op->t1 = op->t;
   if (op->t.vec == 2) {
-    op->t1 = make_tiling(nx, ny, op->t.rows);
     op->t1.vec = 1;
     op->t1.ncb = (nx + kBlock - 1) / kBlock;
     op->t1.nblocks = op->t1.ncb * op->t1.nrb;
@@ -590,6 +627,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
 
 int adl_op_destroy(adl_op* op) {
   if (!op) return ADL_OK;
+  for (hipEvent_t e : op->evs) hipEventDestroy(e);
   if (op->host_ctl) hipHostFree(op->host_ctl);
   delete op;
   return ADL_OK;
@@ -602,6 +640,47 @@ int adl_op_set_limits(adl_op* op, int max_degree, double rho_max) {
   if (!(rho_max > 0.0) || !std::isfinite(rho_max)) return fail(ADL_EINVAL, "rho_max must be > 0");
   op->max_degree = max_degree;
   op->rho_max = rho_max;
+  return ADL_OK;
+}
+
+int adl_op_profile(adl_op* op, int enable) {
+  RETCHK(check_op(op));
+  op->prof = enable != 0;
+  op->prof_ms = 0.0;
+  op->prof_bytes = 0.0;
+  op->prof_launches = 0;
+  return ADL_OK;
+}
+
+int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, double* bytes) {
+  RETCHK(check_op(op));
+  if (kernel_ms) *kernel_ms = op->prof_ms;
+  if (launches) *launches = op->prof_launches;
+  if (bytes) *bytes = op->prof_bytes;
+  op->prof_ms = 0.0;
+  op->prof_bytes = 0.0;
+  op->prof_launches = 0;
+  return ADL_OK;
+}
+
+int adl_op_set_tiling(adl_op* op, int rows) {
+  RETCHK(check_op(op));
+  if (rows < 0 || rows > op->ny) return fail(ADL_EINVAL, "rows must be in [0, ny]");
+  op->t = make_tiling(op->nx, op->ny, rows);
+  op->t1 = op->t;
+  if (op->t.vec == 2) {
+    op->t1.vec = 1;
+    op->t1.ncb = (op->nx + kBlock - 1) / kBlock;
+    op->t1.nblocks = op->t1.ncb * op->t1.nrb;
+  }
+  return ADL_OK;
+}
+
+int adl_op_get_tiling(const adl_op* op, int* vec, int* rows, int* nblocks) {
+  RETCHK(check_op(op));
+  if (vec) *vec = op->t.vec;
+  if (rows) *rows = op->t.rows;
+  if (nblocks) *nblocks = op->t.nblocks;
   return ADL_OK;
 }
 

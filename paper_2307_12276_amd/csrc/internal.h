@@ -78,6 +78,8 @@ struct LejaArgs {
   int yin_f32;       // y_k stored as float
   double* partials;  // 3 * nblocks
   Ctl* ctl;
+  hipEvent_t ev_start;  // optional: dispatch-attached timing events
+  hipEvent_t ev_stop;
 };
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 

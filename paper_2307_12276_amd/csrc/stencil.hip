@@ -26,6 +26,8 @@
 // fixed order.  Results are bitwise reproducible for a given tiling.
 #include "device.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 namespace adl {
@@ -506,19 +508,24 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
   return hipGetLastError();
 }
 
+template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF>
+static void leja_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  const dim3 grid(t.nblocks), blk(kBlock);
+  if (a.ev_start)
+    hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF>), grid, blk, 0, st, a.ev_start, a.ev_stop, 0, f, t,
+                          a);
+  else
+    hipLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF>), grid, blk, 0, st, f, t, a);
+}
+
 template <typename TF, int VEC, bool ADVF>
 static void leja_dispatch_y(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  const dim3 grid(t.nblocks), blk(kBlock);
   if (a.yin_f32) {
-    if (a.ystore_f32)
-      hipLaunchKernelGGL((leja_kernel<TF, float, float, VEC, ADVF>), grid, blk, 0, st, f, t, a);
-    else
-      hipLaunchKernelGGL((leja_kernel<TF, float, double, VEC, ADVF>), grid, blk, 0, st, f, t, a);
+    if (a.ystore_f32) leja_launch<TF, float, float, VEC, ADVF>(f, t, a, st);
+    else leja_launch<TF, float, double, VEC, ADVF>(f, t, a, st);
   } else {
-    if (a.ystore_f32)
-      hipLaunchKernelGGL((leja_kernel<TF, double, float, VEC, ADVF>), grid, blk, 0, st, f, t, a);
-    else
-      hipLaunchKernelGGL((leja_kernel<TF, double, double, VEC, ADVF>), grid, blk, 0, st, f, t, a);
+    if (a.ystore_f32) leja_launch<TF, double, float, VEC, ADVF>(f, t, a, st);
+    else leja_launch<TF, double, double, VEC, ADVF>(f, t, a, st);
   }
 }
 

@@ -91,14 +91,19 @@ def stream_function_direction(X, Y, seed: int, n_modes: int = 32,
     idx = rng.integers(0, len(ks), size=n_modes)
     amp = rng.standard_normal(n_modes)
     phase = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
+    # X, Y are tensor-product grids: cos(a + b) = cos a cos b - sin a sin b
+    # with a = 2 pi kx x + phi (along x) and b = 2 pi ky y (along y)
+    x = X[0, :]
+    y = Y[:, 0]
     gx = np.zeros_like(X)
     gy = np.zeros_like(X)
     for m in range(n_modes):
         kx, ky = ks[idx[m]]
         kn = math.hypot(kx, ky)
         A = amp[m] / kn
-        arg = 2.0 * math.pi * (kx * X + ky * Y) + phase[m]
-        c = np.cos(arg) * (2.0 * math.pi * A)
+        a = 2.0 * math.pi * kx * x + phase[m]
+        b = 2.0 * math.pi * ky * y
+        c = (np.outer(np.cos(b), np.cos(a)) - np.outer(np.sin(b), np.sin(a))) * (2.0 * math.pi * A)
         gx += c * kx
         gy += c * ky
     gnorm = np.hypot(gx, gy)
