@@ -60,7 +60,7 @@ _SIG = {
     "adl_op_set_limits": (_I, [_P, _I, _D]),
     "adl_op_set_quad2_mode": (_I, [_P, _I]),
     "adl_op_profile": (_I, [_P, _I]),
-    "adl_op_set_tiling": (_I, [_P, _I]),
+    "adl_op_set_tiling": (_I, [_P, _I, _I]),
     "adl_op_get_tiling": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "adl_op_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(_D)]),
@@ -197,13 +197,13 @@ class Op:
     def set_limits(self, max_degree: int = 500, rho_max: float = 1600.0):
         _check(lib().adl_op_set_limits(self.handle, int(max_degree), float(rho_max)))
 
-    def set_tiling(self, rows: int):
-        _check(lib().adl_op_set_tiling(self.handle, int(rows)))
+    def set_tiling(self, rows: int = 0, cols_per_lane: int = 0):
+        _check(lib().adl_op_set_tiling(self.handle, int(rows), int(cols_per_lane)))
 
     def get_tiling(self):
         v, r, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().adl_op_get_tiling(self.handle, ctypes.byref(v), ctypes.byref(r), ctypes.byref(nb)))
-        return {"vec": v.value, "rows": r.value, "nblocks": nb.value}
+        return {"cols_per_lane": v.value, "rows": r.value, "nblocks": nb.value}
 
     def profile(self, enable: bool = True):
         _check(lib().adl_op_profile(self.handle, int(bool(enable))))

@@ -53,13 +53,6 @@ __device__ __forceinline__ void store_c(T* __restrict__ a, long off, const doubl
   }
 }
 
-struct LaneGeom {
-  int col0;
-  int lane;
-  bool inside;
-  bool needL, needR;
-};
-
 // Row index after the boundary rule; zero = the whole row is a zero ghost row.
 __device__ __forceinline__ int map_row(int r, int ny, int bc, int mode, bool& zero) {
   zero = false;
@@ -68,55 +61,6 @@ __device__ __forceinline__ int map_row(int r, int ny, int bc, int mode, bool& ze
   if (mode == MODE_EDGE) return r < 0 ? 0 : ny - 1;
   zero = true;
   return 0;
-}
-
-// Centre values only.
-template <typename T, int VEC>
-__device__ __forceinline__ void load_row(const T* __restrict__ a, int r, int mode, int nx, int ny,
-                                         int bc, const LaneGeom& g, double (&c)[VEC]) {
-  bool zero;
-  const int row = map_row(r, ny, bc, mode, zero);
-  if (!zero && g.inside) {
-    load_c<T, VEC>(a, (long)row * nx + g.col0, c);
-  } else {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) c[v] = 0.0;
-  }
-}
-
-// Centre values and the x-neighbours col0-1 (l) and col0+VEC (r).
-template <typename T, int VEC>
-__device__ __forceinline__ void load_row_n(const T* __restrict__ a, int r, int mode, int nx, int ny,
-                                           int bc, const LaneGeom& g, double (&c)[VEC], double& l,
-                                           double& rr) {
-  bool zero;
-  const int row = map_row(r, ny, bc, mode, zero);
-  if (!zero && g.inside) {
-    load_c<T, VEC>(a, (long)row * nx + g.col0, c);
-  } else {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) c[v] = 0.0;
-  }
-  l = __shfl_up(c[VEC - 1], 1);
-  rr = __shfl_down(c[0], 1);
-  if (g.needL) {
-    const int cl = g.col0 - 1;
-    double v;
-    if (zero) v = 0.0;
-    else if (cl >= 0) v = (double)a[(long)row * nx + cl];
-    else if (bc == BC_PERIODIC) v = (double)a[(long)row * nx + nx - 1];
-    else v = (mode == MODE_EDGE) ? c[0] : 0.0;
-    l = v;
-  }
-  if (g.needR) {
-    const int cr = g.col0 + VEC;
-    double v;
-    if (zero) v = 0.0;
-    else if (cr < nx) v = (double)a[(long)row * nx + cr];
-    else if (bc == BC_PERIODIC) v = (double)a[(long)row * nx];
-    else v = (mode == MODE_EDGE) ? c[VEC - 1] : 0.0;
-    rr = v;
-  }
 }
 
 template <int VEC>

@@ -8,8 +8,7 @@
 // One GPU launch per term (fused stencil + axpy + norms); the last block of
 // each launch sets a device stop flag so that launches enqueued after
 // convergence are no-ops, and the host reads the flag once per chunk.
-#include "internal.h"
-#include "adl.h"
+#include "op.h"
 
 #include <algorithm>
 #include <cmath>
@@ -60,9 +59,6 @@ static int fail(int code, const char* fmt, ...) {
 // gap by safeguarded Newton iteration.  Ties (equal products within 1e-12
 // relative) go to the smaller point.
 // --------------------------------------------------------------------------
-constexpr int kMaxDegreeDefault = 500;
-constexpr double kRhoMaxDefault = 1600.0;
-constexpr int kMaxDoublings = 6;
 
 static double gap_root(const std::vector<double>& pts, double a, double b, double x0) {
   double lo = a, hi = b;
@@ -158,18 +154,7 @@ static double phi_scalar(int l, double z) {
 // --------------------------------------------------------------------------
 // Plans: divided differences of g(xi) = phi_l((c + gamma xi) h)
 // --------------------------------------------------------------------------
-struct Plan {
-  int l = -1;
-  double alpha = 0.0, h = 0.0;
-  int M = 0;
-  std::vector<double> d;      // d_0 .. d_{M-1}
-  std::vector<double> shift;  // c + gamma xi_k
-  std::vector<double> s;      // augmented scalars s_k
-  double invg = 0.0;
-  int last_degree = -1;
-};
-
-static void build_plan(Plan& P, int l, double alpha, double h, int M) {
+void build_plan(Plan& P, int l, double alpha, double h, int M) {
   const std::vector<double>& xi = leja_table();
   P.l = l;
   P.alpha = alpha;
@@ -194,43 +179,6 @@ static void build_plan(Plan& P, int l, double alpha, double h, int M) {
 }  // namespace adl
 
 using namespace adl;
-
-// --------------------------------------------------------------------------
-// opaque handle
-// --------------------------------------------------------------------------
-struct adl_op {
-  FieldView f{};
-  Tiling t{};   // preferred tiling (two columns per lane when nx is even)
-  Tiling t1{};  // one column per lane: used when a caller's vector is not 16-byte aligned
-  int nx = 0, ny = 0, bc = 0, storage = 0;
-  double hx = 0, hy = 0;
-  long n = 0;
-  int ws_max_degree = kMaxDegreeDefault;
-  int max_degree = kMaxDegreeDefault;
-  double rho_max = kRhoMaxDefault;
-  int quad2_mode = ADL_QUAD2_AUGMENTED;
-  bool has_bound = false;
-  double alpha = 0.0;
-  double gersh = NAN;  // cached Gershgorin bound
-  // workspace slices
-  void* ybuf[2] = {nullptr, nullptr};
-  double* p = nullptr;
-  double* w1 = nullptr;
-  double* w2 = nullptr;
-  double* yacc = nullptr;
-  double* tmp = nullptr;
-  double* tmp2 = nullptr;
-  double* partials = nullptr;
-  Ctl* ctl = nullptr;
-  Ctl* host_ctl = nullptr;  // pinned
-  std::vector<Plan> plans;  // small cache
-  int plan_next = 0;
-  // kernel profiling of the Newton-Leja iteration kernel
-  bool prof = false;
-  double prof_ms = 0.0, prof_bytes = 0.0;
-  long long prof_launches = 0;
-  std::vector<hipEvent_t> evs;
-};
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -270,7 +218,7 @@ static WsLayout ws_layout(int nx, int ny, int storage) {
   L.yacc = take(n * 8);
   L.tmp = take(n * 8);
   L.tmp2 = take(n * 8);
-  L.partials = take(3 * max_partial_blocks(nx, ny) * 8);
+  L.partials = take(6 * max_partial_blocks(nx, ny) * 8);
   L.ctl = take(4 * 128);
   L.total = o;
   return L;
@@ -300,7 +248,7 @@ static int read_ctl(adl_op* op, hipStream_t st) {
   return ADL_OK;
 }
 
-static Plan& get_plan(adl_op* op, int l, double alpha, double h) {
+Plan& adl::get_plan(adl_op* op, int l, double alpha, double h) {
   for (Plan& P : op->plans)
     if (P.l == l && P.alpha == alpha && P.h == h && P.M == op->max_degree + 1) return P;
   if (op->plans.size() < 8) {
@@ -327,14 +275,27 @@ static double leja_bytes(const adl_op* op, int k, bool with_w2) {
 
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
+// Launch k computes term k+1 and, at its start, takes the stopping decision
+// of term k from the block partials of launch k-1; a one-block launch at the
+// end of every chunk takes the decision of the chunk's last term.
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
                  double tol, int maxdeg, hipStream_t st, SweepOut& out) {
   HIPCHK(launch_ctl_reset(op->ctl, 1, st));
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
-  int predicted = P.last_degree > 0 ? P.last_degree + 2
+  const Tiling& T = tiling_for(op, v, p_out);
+  int predicted = P.last_degree > 0 ? P.last_degree + 1
                                     : (int)(5.0 * std::sqrt(std::fabs(P.alpha) * P.h) + 8.0);
   if (predicted > maxdeg) predicted = maxdeg;
   int launched = 0;
+  LejaArgs a{};
+  a.invg = P.invg;
+  a.d0 = P.d[0];
+  a.tol2 = tol * tol;
+  a.max_degree = maxdeg;
+  a.ystore_f32 = ys32;
+  a.partials = op->partials;
+  a.nb_prev = T.nblocks;
+  a.ctl = op->ctl;
   while (true) {
     int chunk = launched == 0 ? predicted : std::max(8, launched / 4);
     if (launched + chunk > maxdeg) chunk = maxdeg - launched;
@@ -347,43 +308,41 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     }
     for (int i = 0; i < chunk; ++i) {
       const int k = launched + i;
-      LejaArgs a{};
-      if (op->prof) {
-        a.ev_start = op->evs[2 * i];
-        a.ev_stop = op->evs[2 * i + 1];
-      }
+      a.ev_start = op->prof ? op->evs[2 * i] : nullptr;
+      a.ev_stop = op->prof ? op->evs[2 * i + 1] : nullptr;
       a.yin = k == 0 ? (const void*)v : op->ybuf[k & 1];
       a.yout = op->ybuf[(k + 1) & 1];
       a.p = p_out;
       a.w2 = (w2 && P.s[k] != 0.0) ? w2 : nullptr;
       a.w2c = P.s[k] * w2scale;
       a.shift = P.shift[k];
-      a.invg = P.invg;
-      a.d0 = P.d[0];
       a.dk1 = P.d[k + 1];
-      a.tol2 = tol * tol;
       a.k = k;
-      a.max_degree = maxdeg;
       a.first = k == 0;
-      a.ystore_f32 = ys32;
       a.yin_f32 = (k > 0) && ys32;
-      a.partials = op->partials;
-      a.ctl = op->ctl;
-      HIPCHK(launch_leja_step(op->f, tiling_for(op, v, p_out), a, st));
+      a.decide_only = 0;
+      HIPCHK(launch_leja_step(op->f, T, a, st));
     }
+    launched += chunk;
+    // decision of the last term of the chunk
+    a.ev_start = a.ev_stop = nullptr;
+    a.k = launched;
+    a.first = 0;
+    a.decide_only = 1;
+    HIPCHK(launch_leja_step(op->f, T, a, st));
     RETCHK(read_ctl(op, st));
     if (op->prof) {
       // launches past the stopping index returned at once: time only the productive ones
-      const int productive = op->host_ctl->stop ? std::max(op->host_ctl->degree, 1) - launched : chunk;
+      const int first_k = launched - chunk;
+      const int productive = op->host_ctl->stop ? std::max(op->host_ctl->degree, 1) - first_k : chunk;
       for (int i = 0; i < chunk && i < productive; ++i) {
         float ms = 0.0f;
         HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * i], op->evs[2 * i + 1]));
         op->prof_ms += ms;
         op->prof_launches += 1;
-        op->prof_bytes += leja_bytes(op, launched + i, w2 != nullptr && P.s[launched + i] != 0.0);
+        op->prof_bytes += leja_bytes(op, first_k + i, w2 != nullptr && P.s[first_k + i] != 0.0);
       }
     }
-    launched += chunk;
     if (op->host_ctl->stop || launched >= maxdeg) break;
   }
   out.degree = op->host_ctl->degree;
@@ -392,7 +351,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   return ADL_OK;
 }
 
-static int substeps_for(double alpha, double dt, double rho_max) {
+int adl::substeps_for(double alpha, double dt, double rho_max) {
   const double r = std::fabs(alpha) * dt / rho_max;
   const double K = std::ceil(r);
   if (!(K < 1e6)) return 1 << 20;
@@ -663,12 +622,20 @@ int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, doub
   return ADL_OK;
 }
 
-int adl_op_set_tiling(adl_op* op, int rows) {
+int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
   RETCHK(check_op(op));
   if (rows < 0 || rows > op->ny) return fail(ADL_EINVAL, "rows must be in [0, ny]");
-  op->t = make_tiling(op->nx, op->ny, rows);
-  op->t1 = op->t;
-  if (op->t.vec == 2) {
+  if (cols_per_lane < 0 || cols_per_lane > 2) return fail(ADL_EINVAL, "cols_per_lane must be 0, 1 or 2");
+  Tiling t = make_tiling(op->nx, op->ny, rows);
+  if (cols_per_lane == 2 && t.vec != 2) return fail(ADL_EINVAL, "two columns per lane need an even nx >= 128");
+  if (cols_per_lane == 1) {
+    t.vec = 1;
+    t.ncb = (op->nx + kBlock - 1) / kBlock;
+    t.nblocks = t.ncb * t.nrb;
+  }
+  op->t = t;
+  op->t1 = t;
+  if (t.vec == 2) {
     op->t1.vec = 1;
     op->t1.ncb = (op->nx + kBlock - 1) / kBlock;
     op->t1.nblocks = op->t1.ncb * op->t1.nrb;
@@ -713,19 +680,32 @@ int adl_spectral_bound(adl_op* op, int method, int max_iter, double rtol, uint64
     if (max_iter < 1) return fail(ADL_EINVAL, "max_iter must be >= 1");
     if (!(rtol > 0.0)) return fail(ADL_EINVAL, "rtol must be > 0");
     HIPCHK(launch_ctl_reset(op->ctl, 1, st));
-    HIPCHK(launch_power_init((int)op->n, seed, op->tmp, op->partials, 0, op->ctl, st));
+    const Tiling& T = op->t;
+    HIPCHK(launch_power_init(T, op->n, seed, op->tmp, op->partials, st));
     double* bufs[2] = {op->tmp, op->tmp2};
+    PowerArgs pa{};
+    pa.rtol = rtol;
+    pa.max_iter = max_iter;
+    pa.nb = T.nblocks;
+    pa.partials = op->partials;
+    pa.ctl = op->ctl;
     int launched = 0;
-    while (launched < max_iter) {
+    while (true) {
       const int chunk = std::min(max_iter - launched, launched == 0 ? 64 : 128);
       for (int i = 0; i < chunk; ++i) {
         const int k = launched + i;
-        HIPCHK(launch_power_step(op->f, op->t, bufs[k & 1], bufs[(k + 1) & 1], rtol, max_iter, op->partials,
-                                 op->ctl, st));
+        pa.x = bufs[k & 1];
+        pa.w = bufs[(k + 1) & 1];
+        pa.k = k;
+        pa.decide_only = 0;
+        HIPCHK(launch_power_step(op->f, T, pa, st));
       }
       launched += chunk;
+      pa.k = launched;
+      pa.decide_only = 1;
+      HIPCHK(launch_power_step(op->f, T, pa, st));
       RETCHK(read_ctl(op, st));
-      if (op->host_ctl->stop) break;
+      if (op->host_ctl->stop || launched >= max_iter) break;
     }
     const Ctl& c = *op->host_ctl;
     if (c.status == 2) return fail(ADL_ENAN, "non-finite value in power iteration");

@@ -76,19 +76,30 @@ struct LejaArgs {
   int first;         // k == 0: p = d0 y0 + d1 y1, zero-vector test
   int ystore_f32;    // y_{k+1} stored as float
   int yin_f32;       // y_k stored as float
-  double* partials;  // 3 * nblocks
+  double* partials;  // 2 parities x 3 accumulators x nblocks
+  int nb_prev;       // block count of the previous launch (its partials)
+  int decide_only;   // only take the stopping decision of term k (1-block launch)
   Ctl* ctl;
   hipEvent_t ev_start;  // optional: dispatch-attached timing events
   hipEvent_t ev_stop;
 };
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 
-// power iteration: w = scale * A x ; lambda = ||w|| ; see Ctl
-hipError_t launch_power_init(int n, uint64_t seed, double* w, double* partials, int nblocks,
-                             Ctl* ctl, hipStream_t st);
-hipError_t launch_power_step(const FieldView& f, const Tiling& t, const double* x, double* w,
-                             double rtol, int max_iter, double* partials, Ctl* ctl,
+// power iteration launch k: w = A(x) / ||x||, stopping test of iteration k
+struct PowerArgs {
+  const double* x;
+  double* w;
+  double rtol;
+  int max_iter;
+  int k;
+  int nb;            // block count of every power launch (and of the start-vector kernel)
+  int decide_only;
+  double* partials;  // 3 slots x nb
+  Ctl* ctl;
+};
+hipError_t launch_power_init(const Tiling& t, long n, uint64_t seed, double* w, double* partials,
                              hipStream_t st);
+hipError_t launch_power_step(const FieldView& f, const Tiling& t, const PowerArgs& a, hipStream_t st);
 hipError_t launch_gershgorin(const FieldView& f, double* partials, Ctl* ctl, hipStream_t st);
 
 // ---- elementwise (stencil.hip) --------------------------------------------

@@ -1,0 +1,83 @@
+// Internal definition of the op handle and Leja plans, shared by the host
+// translation units of libadl (host.cpp, batch.hip).
+#pragma once
+
+#include "internal.h"
+#include "adl.h"
+
+#include <cmath>
+#include <vector>
+
+namespace adl {
+
+constexpr int kMaxDegreeDefault = 500;
+constexpr double kRhoMaxDefault = 1600.0;
+constexpr int kMaxDoublings = 6;
+
+struct Plan {
+  int l = -1;
+  double alpha = 0.0, h = 0.0;
+  int M = 0;
+  std::vector<double> d;      // d_0 .. d_{M-1}
+  std::vector<double> shift;  // c + gamma xi_k
+  std::vector<double> s;      // augmented scalars s_k
+  double invg = 0.0;
+  int last_degree = -1;
+};
+
+
+// Plan for phi_l on [alpha, 0] with step h and M coefficients.
+void build_plan(Plan& P, int l, double alpha, double h, int M);
+
+}  // namespace adl
+
+// --------------------------------------------------------------------------
+// opaque handle
+// --------------------------------------------------------------------------
+using adl::FieldView;
+using adl::Tiling;
+using adl::Ctl;
+using adl::Plan;
+using adl::kMaxDegreeDefault;
+using adl::kRhoMaxDefault;
+
+struct adl_op {
+  FieldView f{};
+  Tiling t{};   // preferred tiling (two columns per lane when nx is even)
+  Tiling t1{};  // one column per lane: used when a caller's vector is not 16-byte aligned
+  int nx = 0, ny = 0, bc = 0, storage = 0;
+  double hx = 0, hy = 0;
+  long n = 0;
+  int ws_max_degree = kMaxDegreeDefault;
+  int max_degree = kMaxDegreeDefault;
+  double rho_max = kRhoMaxDefault;
+  int quad2_mode = ADL_QUAD2_AUGMENTED;
+  bool has_bound = false;
+  double alpha = 0.0;
+  double gersh = NAN;  // cached Gershgorin bound
+  // workspace slices
+  void* ybuf[2] = {nullptr, nullptr};
+  double* p = nullptr;
+  double* w1 = nullptr;
+  double* w2 = nullptr;
+  double* yacc = nullptr;
+  double* tmp = nullptr;
+  double* tmp2 = nullptr;
+  double* partials = nullptr;
+  Ctl* ctl = nullptr;
+  Ctl* host_ctl = nullptr;  // pinned
+  std::vector<Plan> plans;  // small cache
+  int plan_next = 0;
+  // kernel profiling of the Newton-Leja iteration kernel
+  bool prof = false;
+  double prof_ms = 0.0, prof_bytes = 0.0;
+  long long prof_launches = 0;
+  std::vector<hipEvent_t> evs;
+};
+
+
+namespace adl {
+// cached plan of the op (l, alpha, h)
+Plan& get_plan(adl_op* op, int l, double alpha, double h);
+int substeps_for(double alpha, double dt, double rho_max);
+}  // namespace adl

@@ -24,7 +24,7 @@
 // order: shuffle tree per wave, waves in order, block partials written to
 // memory, and the last block to arrive (ticket counter) sums the partials in a
 // fixed order.  Results are bitwise reproducible for a given tiling.
-#include "device.h"
+#include "march.h"
 
 #include <hip/hip_ext.h>
 
@@ -33,116 +33,74 @@
 namespace adl {
 
 // ---------------------------------------------------------------------------
-// Generic row-marching core.  Ep supplies the per-row extra loads (Extra) and
-// the per-row epilogue finish(j, g, Ax, xc, extra).
+// Block-wide fixed-order reduction (sums for k < NS, NaN-propagating max for
+// the rest); every thread receives the totals.
 // ---------------------------------------------------------------------------
+template <int NA, int NS>
+__device__ __forceinline__ void block_allreduce(double (&v)[NA]) {
+  __shared__ double sh[NA * 16];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double t = __shfl_xor(v[k], o);
+      v[k] = (k < NS) ? v[k] + t : nanmax(v[k], t);
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) sh[wave * NA + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    double s = sh[k];
+    for (int w = 1; w < nw; ++w) s = (k < NS) ? s + sh[w * NA + k] : nanmax(s, sh[w * NA + k]);
+    v[k] = s;
+  }
+}
+
+// Totals of the block partials written by an earlier launch: part[k * nb + b].
+template <int NA, int NS>
+__device__ __forceinline__ void partial_totals(const double* __restrict__ part, int nb, double (&tot)[NA]) {
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    double s = 0.0;
+    bool any = false;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      const double v = part[(long)k * nb + i];
+      s = (k < NS) ? s + v : (any ? nanmax(s, v) : v);
+      any = true;
+    }
+    tot[k] = s;
+  }
+  block_allreduce<NA, NS>(tot);
+}
+
+// block partial of this launch -> part[k * nb + blockIdx.x]
+template <int NA, int NS>
+__device__ __forceinline__ void write_partials(double (&acc)[NA], double* __restrict__ part) {
+  block_allreduce<NA, NS>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) part[(long)k * gridDim.x + blockIdx.x] = acc[k];
+  }
+}
+
 template <typename TF, typename TX, int VEC, bool ADVF, class Ep>
-__device__ __forceinline__ void march(const FieldView& F, const Tiling& T, const TX* __restrict__ x,
-                                      Ep& ep) {
-  const int nx = F.nx, ny = F.ny, bc = F.bc;
+__device__ __forceinline__ void march_block(const FieldView& F, const Tiling& T, const TX* __restrict__ x, Ep& ep) {
   const int b = remap_xcd(blockIdx.x, gridDim.x);
   const int rb = b / T.ncb, cb = b - rb * T.ncb;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  LaneGeom g;
-  g.lane = lane;
-  g.col0 = ((cb * kWavesX + wave) * kWave + lane) * VEC;
-  g.inside = g.col0 < nx;
-  g.needL = g.inside && lane == 0;
-  g.needR = g.inside && (lane == kWave - 1 || g.col0 + VEC >= nx);
   const int j0 = rb * T.rows;
-  const int j1 = min(j0 + T.rows, ny);
-
-  const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
-  const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
-  const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
-  const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
-  const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
-
-  // three-row windows (m = j-1, c = j, p = j+1)
-  RowN<VEC> um, uc, up;   // x
-  RowC<VEC> gm, gc, gp;   // kyy
-  RowN<VEC> mm, mc, mp;   // kxy (x-neighbours are used on the centre row)
-  RowC<VEC> ym, yc, yp;   // ay' field
-  RowN<VEC> kc, ac;       // kxx, ax' field (centre row only)
-  typename Ep::Extra ec;
-
-  load_row_n<TX, VEC>(x, j0 - 1, MODE_ZERO, nx, ny, bc, g, um.c, um.l, um.r);
-  load_row_n<TX, VEC>(x, j0, MODE_ZERO, nx, ny, bc, g, uc.c, uc.l, uc.r);
-  load_row_n<TX, VEC>(x, j0 + 1, MODE_ZERO, nx, ny, bc, g, up.c, up.l, up.r);
-  load_row<TF, VEC>(kyy, j0 - 1, MODE_EDGE, nx, ny, bc, g, gm.c);
-  load_row<TF, VEC>(kyy, j0, MODE_EDGE, nx, ny, bc, g, gc.c);
-  load_row<TF, VEC>(kyy, j0 + 1, MODE_EDGE, nx, ny, bc, g, gp.c);
-  load_row_n<TF, VEC>(kxy, j0 - 1, MODE_ZERO, nx, ny, bc, g, mm.c, mm.l, mm.r);
-  load_row_n<TF, VEC>(kxy, j0, MODE_ZERO, nx, ny, bc, g, mc.c, mc.l, mc.r);
-  load_row_n<TF, VEC>(kxy, j0 + 1, MODE_ZERO, nx, ny, bc, g, mp.c, mp.l, mp.r);
-  load_row_n<TF, VEC>(kxx, j0, MODE_EDGE, nx, ny, bc, g, kc.c, kc.l, kc.r);
-  if constexpr (ADVF) {
-    load_row<TF, VEC>(fay, j0 - 1, MODE_ZERO, nx, ny, bc, g, ym.c);
-    load_row<TF, VEC>(fay, j0, MODE_ZERO, nx, ny, bc, g, yc.c);
-    load_row<TF, VEC>(fay, j0 + 1, MODE_ZERO, nx, ny, bc, g, yp.c);
-    load_row_n<TF, VEC>(fax, j0, MODE_ZERO, nx, ny, bc, g, ac.c, ac.l, ac.r);
-  }
-  ep.load(j0, g, ec);
-
-  for (int j = j0; j < j1; ++j) {
-    const bool more = (j + 1 < j1);
-    RowN<VEC> un, mn, kn, an;
-    RowC<VEC> gn, yn;
-    typename Ep::Extra en;
-    if (more) {  // uniform across the block
-      load_row_n<TX, VEC>(x, j + 2, MODE_ZERO, nx, ny, bc, g, un.c, un.l, un.r);
-      load_row<TF, VEC>(kyy, j + 2, MODE_EDGE, nx, ny, bc, g, gn.c);
-      load_row_n<TF, VEC>(kxy, j + 2, MODE_ZERO, nx, ny, bc, g, mn.c, mn.l, mn.r);
-      load_row_n<TF, VEC>(kxx, j + 1, MODE_EDGE, nx, ny, bc, g, kn.c, kn.l, kn.r);
-      if constexpr (ADVF) {
-        load_row<TF, VEC>(fay, j + 2, MODE_ZERO, nx, ny, bc, g, yn.c);
-        load_row_n<TF, VEC>(fax, j + 1, MODE_ZERO, nx, ny, bc, g, an.c, an.l, an.r);
-      }
-      ep.load(j + 1, g, en);
-    }
-
-    double Ax[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      const double uC = uc.at(v), uW = uc.west(v), uE = uc.east(v);
-      const double uN = up.at(v), uS = um.at(v);
-      const double uNW = up.west(v), uNE = up.east(v);
-      const double uSW = um.west(v), uSE = um.east(v);
-      const double kC = kc.at(v), kW = kc.west(v), kE = kc.east(v);
-      const double gC = gc.c[v], gN = gp.c[v], gS = gm.c[v];
-      const double mE = mc.east(v), mW = mc.west(v), mN = mp.at(v), mS = mm.at(v);
-      double r = 0.5 * (kC + kE) * (uE - uC) - 0.5 * (kC + kW) * (uC - uW);
-      r += 0.5 * (gC + gN) * (uN - uC) - 0.5 * (gC + gS) * (uC - uS);
-      r += mE * (uNE - uSE) - mW * (uNW - uSW);
-      r += mN * (uNE - uNW) - mS * (uSE - uSW);
-      if constexpr (ADVF) {
-        r += ac.east(v) * uE - ac.west(v) * uW + yp.c[v] * uN - ym.c[v] * uS;
-      } else {
-        r += F.axc * (uE - uW) + F.ayc * (uN - uS);
-      }
-      Ax[v] = r;
-    }
-    ep.finish(j, g, Ax, uc.c, ec);
-
-    if (more) {
-      um = uc; uc = up; up = un;
-      gm = gc; gc = gp; gp = gn;
-      mm = mc; mc = mp; mp = mn;
-      kc = kn;
-      if constexpr (ADVF) {
-        ym = yc; yc = yp; yp = yn;
-        ac = an;
-      }
-      ec = en;
-    }
-  }
+  const int j1 = min(j0 + T.rows, F.ny);
+  march_tile<TF, TX, VEC, ADVF>(F, x, ep, cb, j0, j1, kWavesX, threadIdx.x >> 6);
 }
 
 // ---------------------------------------------------------------------------
 // Epilogues
 // ---------------------------------------------------------------------------
-struct NoExtra {};
-
 // out = A x + a1 s1 + a2 s2
 template <int VEC>
 struct ApplyEp {
@@ -152,10 +110,12 @@ struct ApplyEp {
   const double* __restrict__ s1;
   const double* __restrict__ s2;
   double a1, a2;
-  __device__ __forceinline__ void load(int, const LaneGeom&, Extra&) {}
-  __device__ __forceinline__ void finish(int j, const LaneGeom& g, const double (&Ax)[VEC],
-                                         const double (&)[VEC], const Extra&) {
-    if (!g.inside) return;
+  template <bool CHECK>
+  __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
+  template <bool CHECK>
+  __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&)[VEC],
+                                         const Extra&) {
+    if (CHECK && !g.inside) return;
     const long off = (long)j * nx + g.col0;
     double r[VEC];
 #pragma unroll
@@ -179,12 +139,12 @@ struct ApplyEp {
 template <typename TF, int VEC, bool ADVF>
 __global__ __launch_bounds__(kBlock) void apply_kernel(FieldView F, Tiling T, const double* __restrict__ x,
                                                        ApplyEp<VEC> ep) {
-  march<TF, double, VEC, ADVF>(F, T, x, ep);
+  march_block<TF, double, VEC, ADVF>(F, T, x, ep);
 }
 
-// One Newton-Leja iteration (fused): y' = (A y + w2c w2 - shift y) invg,
-// p' = p + d_{k+1} y'  (p = d_0 y at k = 0); norms of d y' and p'.
-template <typename TYO, int VEC>
+// One Newton-Leja term (fused): y' = (A y + w2c w2 - shift y) invg,
+// p' = p + d_{k+1} y'  (p = d_0 y at k = 0); partial norms of d y' and p'.
+template <typename TYO, int VEC, bool FIRST>
 struct LejaEp {
   struct Extra {
     double p[VEC];
@@ -193,33 +153,39 @@ struct LejaEp {
   int nx;
   TYO* __restrict__ yout;
   double* __restrict__ p;
-  const double* __restrict__ w2;
+  const double* __restrict__ w2;  // only on the first term
   double w2c, shift, invg, d0, dk1;
-  bool first;
   double acc[3];  // ||d y'||^2, ||p'||^2, max(|y0|, |w2|)
-  __device__ __forceinline__ void load(int j, const LaneGeom& g, Extra& e) {
-    if (!g.inside) return;
+  template <bool CHECK>
+  __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
+    if (CHECK && !g.inside) return;
     const long off = (long)j * nx + g.col0;
-    if (!first) load_c<double, VEC>(p, off, e.p);
-    if (w2) load_c<double, VEC>(w2, off, e.w);
+    if constexpr (FIRST) {
+      if (w2) load_c<double, VEC>(w2, off, e.w);
+    } else {
+      load_c<double, VEC>(p, off, e.p);
+    }
   }
-  __device__ __forceinline__ void finish(int j, const LaneGeom& g, const double (&Ax)[VEC],
-                                         const double (&yc)[VEC], const Extra& e) {
-    if (!g.inside) return;
+  template <bool CHECK>
+  __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&yc)[VEC],
+                                         const Extra& e) {
+    if (CHECK && !g.inside) return;
     const long off = (long)j * nx + g.col0;
     double yn[VEC], pn[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       double a = Ax[v];
-      if (w2) a += w2c * e.w[v];
+      if constexpr (FIRST) {
+        if (w2) a += w2c * e.w[v];
+      }
       const double y1 = (a - shift * yc[v]) * invg;
       const double t = dk1 * y1;
-      const double pv = (first ? d0 * yc[v] : e.p[v]) + t;
+      const double pv = (FIRST ? d0 * yc[v] : e.p[v]) + t;
       yn[v] = y1;
       pn[v] = pv;
       acc[0] += t * t;
       acc[1] += pv * pv;
-      if (first) {
+      if constexpr (FIRST) {
         acc[2] = nanmax(acc[2], fabs(yc[v]));
         if (w2) acc[2] = nanmax(acc[2], fabs(e.w[v]));
       }
@@ -229,48 +195,88 @@ struct LejaEp {
   }
 };
 
-template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF>
-__global__ __launch_bounds__(kBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
-  if (A.ctl->stop) return;  // the sweep has already stopped: no-op launch
-  LejaEp<TYO, VEC> ep;
-  ep.nx = F.nx;
-  ep.yout = reinterpret_cast<TYO*>(A.yout);
-  ep.p = A.p;
-  ep.w2 = A.w2;
-  ep.w2c = A.w2c;
-  ep.shift = A.shift;
-  ep.invg = A.invg;
-  ep.d0 = A.d0;
-  ep.dk1 = A.dk1;
-  ep.first = A.first != 0;
-  ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
-  march<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep);
-  const double tol2 = A.tol2;
-  const int k = A.k, maxdeg = A.max_degree;
-  const bool first = A.first != 0;
-  Ctl* ctl = A.ctl;
-  grid_reduce<3, 2>(ep.acc, A.partials, ctl, [=](const double (&tot)[3]) {
-    const double tn2 = tot[0], pn2 = tot[1];
-    const int deg = k + 1;
-    int stop = 0, status = 0, degree = deg;
-    if (!isfinite(tn2) || !isfinite(pn2)) {
-      stop = 1; status = 2;
-    } else if (first && tot[2] == 0.0) {
-      stop = 1; status = 1; degree = 0;
-    } else if (tn2 <= tol2 * pn2) {
-      stop = 1; status = 1;
-    } else if (deg >= maxdeg) {
-      stop = 1; status = 3;
-    }
-    ctl->tn2 = tn2;
-    ctl->pn2 = pn2;
-    ctl->degree = degree;
-    ctl->status = status;
-    ctl->stop = stop;
-  });
+// Stopping test of term kprev+1 from the partials of launch kprev (every block
+// computes the same fixed-order totals, block 0 records the decision).
+// Returns true when the sweep is over.
+__device__ __forceinline__ bool leja_decide(const LejaArgs& A, int kprev) {
+  double tot[3];
+  partial_totals<3, 2>(A.partials + (long)(kprev & 1) * 3 * A.nb_prev, A.nb_prev, tot);
+  const double tn2 = tot[0], pn2 = tot[1];
+  const int deg = kprev + 1;
+  int stop = 0, status = 0, degree = deg;
+  if (!isfinite(tn2) || !isfinite(pn2)) {
+    stop = 1; status = 2;
+  } else if (kprev == 0 && tot[2] == 0.0) {
+    stop = 1; status = 1; degree = 0;
+  } else if (tn2 <= A.tol2 * pn2) {
+    stop = 1; status = 1;
+  } else if (deg >= A.max_degree) {
+    stop = 1; status = 3;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl* c = A.ctl;
+    c->tn2 = tn2;
+    c->pn2 = pn2;
+    c->degree = degree;
+    c->status = status;
+    __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return stop != 0;
 }
 
-// Power iteration step: w = scale * A x, lambda = ||w||.
+// The sweep's stop flag, read once per block (thread 0) and broadcast, so that
+// a concurrent update by block 0 of the same launch cannot split a block.
+__device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return s_stop != 0;
+}
+
+template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF>
+__global__ __launch_bounds__(kBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
+  if (block_stopped(A.ctl)) return;
+  if (A.k > 0 && leja_decide(A, A.k - 1)) return;
+  if (A.decide_only) return;
+  double acc[3];
+  if (A.first) {
+    LejaEp<TYO, VEC, true> ep;
+    ep.nx = F.nx;
+    ep.yout = reinterpret_cast<TYO*>(A.yout);
+    ep.p = A.p;
+    ep.w2 = A.w2;
+    ep.w2c = A.w2c;
+    ep.shift = A.shift;
+    ep.invg = A.invg;
+    ep.d0 = A.d0;
+    ep.dk1 = A.dk1;
+    ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
+    march_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep);
+    acc[0] = ep.acc[0];
+    acc[1] = ep.acc[1];
+    acc[2] = ep.acc[2];
+  } else {
+    LejaEp<TYO, VEC, false> ep;
+    ep.nx = F.nx;
+    ep.yout = reinterpret_cast<TYO*>(A.yout);
+    ep.p = A.p;
+    ep.w2 = nullptr;
+    ep.w2c = 0.0;
+    ep.shift = A.shift;
+    ep.invg = A.invg;
+    ep.d0 = A.d0;
+    ep.dk1 = A.dk1;
+    ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
+    march_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep);
+    acc[0] = ep.acc[0];
+    acc[1] = ep.acc[1];
+    acc[2] = ep.acc[2];
+  }
+  write_partials<3, 2>(acc, A.partials + (long)(A.k & 1) * 3 * gridDim.x);
+}
+
+// Power iteration term: w_{k+1} = A(w_k) / lambda_k, lambda_k = ||w_k|| from
+// the partials of the launch that wrote w_k.
 template <int VEC>
 struct PowerEp {
   struct Extra {};
@@ -278,10 +284,12 @@ struct PowerEp {
   double* __restrict__ w;
   double scale;
   double acc[1];
-  __device__ __forceinline__ void load(int, const LaneGeom&, Extra&) {}
-  __device__ __forceinline__ void finish(int j, const LaneGeom& g, const double (&Ax)[VEC],
-                                         const double (&)[VEC], const Extra&) {
-    if (!g.inside) return;
+  template <bool CHECK>
+  __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
+  template <bool CHECK>
+  __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&)[VEC],
+                                         const Extra&) {
+    if (CHECK && !g.inside) return;
     double r[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -292,37 +300,52 @@ struct PowerEp {
   }
 };
 
+// Partials of power launch k live in slot k mod 3; the start vector's in slot 2.
+// At the start of launch k (k >= 1) lambda_k = ||w_k|| is tested against
+// lambda_{k-1} (0 for k = 1), the test of iteration k of the power method.
 template <typename TF, int VEC, bool ADVF>
-__global__ __launch_bounds__(kBlock) void power_kernel(FieldView F, Tiling T, const double* __restrict__ x,
-                                                       double* __restrict__ w, double rtol, int max_iter,
-                                                       double* partials, Ctl* ctl) {
-  if (ctl->stop) return;
-  PowerEp<VEC> ep;
-  ep.nx = F.nx;
-  ep.w = w;
-  ep.scale = ctl->scale;
-  ep.acc[0] = 0.0;
-  march<TF, double, VEC, ADVF>(F, T, x, ep);
-  grid_reduce<1, 1>(ep.acc, partials, ctl, [=](const double (&tot)[1]) {
-    const double lam = sqrt(tot[0]);
-    const int it = ctl->iters + 1;
+__global__ __launch_bounds__(kBlock) void power_kernel(FieldView F, Tiling T, PowerArgs P) {
+  Ctl* ctl = P.ctl;
+  if (block_stopped(ctl)) return;
+  const int k = P.k;
+  const long slot = (long)P.nb;
+  double t1[1];
+  partial_totals<1, 1>(P.partials + ((k + 2) % 3) * slot, P.nb, t1);
+  const double lam = sqrt(t1[0]);
+  if (k >= 1) {
+    double lam_prev = 0.0;
+    if (k >= 2) {
+      double t0[1];
+      partial_totals<1, 1>(P.partials + ((k + 1) % 3) * slot, P.nb, t0);
+      lam_prev = sqrt(t0[0]);
+    }
     int stop = 0, status = 0;
     if (!isfinite(lam)) {
       stop = 1; status = 2;
     } else if (lam == 0.0) {
       stop = 1; status = 1;
-    } else if (fabs(lam - ctl->lam_prev) <= rtol * lam) {
+    } else if (fabs(lam - lam_prev) <= P.rtol * lam) {
       stop = 1; status = 1;
-    } else if (it >= max_iter) {
+    } else if (k >= P.max_iter) {
       stop = 1; status = 3;
     }
-    ctl->lam = lam;
-    ctl->lam_prev = lam;
-    ctl->scale = lam > 0.0 ? 1.0 / lam : 0.0;
-    ctl->iters = it;
-    ctl->status = status;
-    ctl->stop = stop;
-  });
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctl->lam = lam;
+      ctl->lam_prev = lam_prev;
+      ctl->iters = k;
+      ctl->status = status;
+      __hip_atomic_store(&ctl->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (stop) return;
+  }
+  if (P.decide_only) return;
+  PowerEp<VEC> ep;
+  ep.nx = F.nx;
+  ep.w = P.w;
+  ep.scale = lam > 0.0 ? 1.0 / lam : 0.0;
+  ep.acc[0] = 0.0;
+  march_block<TF, double, VEC, ADVF>(F, T, P.x, ep);
+  write_partials<1, 1>(ep.acc, P.partials + (k % 3) * slot);
 }
 
 // splitmix64 output k of the stream seeded with s (Steele, Lea, Flood 2014):
@@ -334,9 +357,9 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
   return z ^ (z >> 31);
 }
 
-// w = uniform(-1, 1) start vector; lambda_0 = ||w|| -> scale = 1/lambda_0.
+// Start vector w_0 = uniform(-1, 1) (splitmix64); its partial norms go to slot 2.
 __global__ __launch_bounds__(kBlock) void power_init_kernel(long n, uint64_t seed, double* __restrict__ w,
-                                                            double* partials, Ctl* ctl) {
+                                                            double* __restrict__ partials) {
   double acc[1] = {0.0};
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const uint64_t z = splitmix64_at(seed, (uint64_t)i);
@@ -344,15 +367,7 @@ __global__ __launch_bounds__(kBlock) void power_init_kernel(long n, uint64_t see
     w[i] = u;
     acc[0] += u * u;
   }
-  grid_reduce<1, 1>(acc, partials, ctl, [=](const double (&tot)[1]) {
-    const double lam = sqrt(tot[0]);
-    ctl->scale = lam > 0.0 ? 1.0 / lam : 0.0;
-    ctl->lam = lam;
-    ctl->lam_prev = 0.0;
-    ctl->iters = 0;
-    ctl->status = 0;
-    ctl->stop = lam > 0.0 ? 0 : 1;
-  });
+  write_partials<1, 1>(acc, partials + 2L * gridDim.x);
 }
 
 // Gershgorin: min over rows of A_ii - sum_{j != i} |A_ij| (one thread per node).
@@ -455,11 +470,13 @@ Tiling make_tiling(int nx, int ny, int rows_hint) {
   t.ncb = (nx + bw - 1) / bw;
   int rows = rows_hint;
   if (rows <= 0) {
-    // aim for >= 2048 blocks on large grids, >= 4 rows per band
+    // about 2048 blocks: 16-row bands on a 4096^2 grid (measured best on MI355X);
+    // small grids get 2-row bands for more blocks (latency-bound launches)
     const long target = 2048;
-    long nrb_want = (target + t.ncb - 1) / t.ncb;
+    const long nrb_want = (target + t.ncb - 1) / t.ncb;
     rows = (int)((ny + nrb_want - 1) / nrb_want);
-    if (rows < 4) rows = 4;
+    if (rows < 4) rows = 2;
+    else rows = (rows + 3) / 4 * 4;  // interior bands march in groups of 4 rows
     if (rows > 64) rows = 64;
   }
   if (rows > ny) rows = ny;
@@ -476,23 +493,23 @@ static inline int ew_blocks(long n) {
   return (int)b;
 }
 
-#define ADL_DISPATCH_VEC_ADV(T, F, ...)                    \
-  do {                                                     \
-    const bool advf_ = (F).ax != nullptr;                  \
-    if ((T).vec == 2) {                                    \
-      constexpr int VEC = 2;                               \
-      if (advf_) { constexpr bool ADVF = true; __VA_ARGS__; }     \
-      else { constexpr bool ADVF = false; __VA_ARGS__; }          \
-    } else {                                               \
-      constexpr int VEC = 1;                               \
-      if (advf_) { constexpr bool ADVF = true; __VA_ARGS__; }     \
-      else { constexpr bool ADVF = false; __VA_ARGS__; }          \
-    }                                                      \
+#define ADL_DISPATCH_TILE(T, F, ...)                                  \
+  do {                                                                \
+    const bool advf_ = (F).ax != nullptr;                             \
+    if ((T).vec == 2) {                                               \
+      constexpr int VEC = 2;                                          \
+      if (advf_) { constexpr bool ADVF = true; __VA_ARGS__; }         \
+      else { constexpr bool ADVF = false; __VA_ARGS__; }              \
+    } else {                                                          \
+      constexpr int VEC = 1;                                          \
+      if (advf_) { constexpr bool ADVF = true; __VA_ARGS__; }         \
+      else { constexpr bool ADVF = false; __VA_ARGS__; }              \
+    }                                                                 \
   } while (0)
 
 hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, double* y, const double* s1,
                         double a1, const double* s2, double a2, hipStream_t st) {
-  ADL_DISPATCH_VEC_ADV(t, f, {
+  ADL_DISPATCH_TILE(t, f, {
     ApplyEp<VEC> ep;
     ep.nx = f.nx;
     ep.out = y;
@@ -510,10 +527,10 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
 
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF>
 static void leja_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  const dim3 grid(t.nblocks), blk(kBlock);
+  const dim3 grid(a.decide_only ? 1 : t.nblocks), blk(kBlock);
   if (a.ev_start)
-    hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF>), grid, blk, 0, st, a.ev_start, a.ev_stop, 0, f, t,
-                          a);
+    hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF>), grid, blk, 0, st, a.ev_start, a.ev_stop, 0, f,
+                          t, a);
   else
     hipLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF>), grid, blk, 0, st, f, t, a);
 }
@@ -530,30 +547,23 @@ static void leja_dispatch_y(const FieldView& f, const Tiling& t, const LejaArgs&
 }
 
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  ADL_DISPATCH_VEC_ADV(t, f, {
+  ADL_DISPATCH_TILE(t, f, {
     if (f.f32) leja_dispatch_y<float, VEC, ADVF>(f, t, a, st);
     else leja_dispatch_y<double, VEC, ADVF>(f, t, a, st);
   });
   return hipGetLastError();
 }
 
-hipError_t launch_power_init(int n, uint64_t seed, double* w, double* partials, int nblocks, Ctl* ctl,
-                             hipStream_t st) {
-  (void)nblocks;
-  const int nb = ew_blocks(n) < 1024 ? ew_blocks(n) : 1024;
-  hipLaunchKernelGGL(power_init_kernel, dim3(nb), dim3(kBlock), 0, st, (long)n, seed, w, partials, ctl);
+hipError_t launch_power_init(const Tiling& t, long n, uint64_t seed, double* w, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(power_init_kernel, dim3(t.nblocks), dim3(kBlock), 0, st, n, seed, w, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_power_step(const FieldView& f, const Tiling& t, const double* x, double* w, double rtol,
-                             int max_iter, double* partials, Ctl* ctl, hipStream_t st) {
-  ADL_DISPATCH_VEC_ADV(t, f, {
-    if (f.f32)
-      hipLaunchKernelGGL((power_kernel<float, VEC, ADVF>), dim3(t.nblocks), dim3(kBlock), 0, st, f, t, x, w,
-                         rtol, max_iter, partials, ctl);
-    else
-      hipLaunchKernelGGL((power_kernel<double, VEC, ADVF>), dim3(t.nblocks), dim3(kBlock), 0, st, f, t, x, w,
-                         rtol, max_iter, partials, ctl);
+hipError_t launch_power_step(const FieldView& f, const Tiling& t, const PowerArgs& a, hipStream_t st) {
+  const dim3 grid(a.decide_only ? 1 : t.nblocks), blk(kBlock);
+  ADL_DISPATCH_TILE(t, f, {
+    if (f.f32) hipLaunchKernelGGL((power_kernel<float, VEC, ADVF>), grid, blk, 0, st, f, t, a);
+    else hipLaunchKernelGGL((power_kernel<double, VEC, ADVF>), grid, blk, 0, st, f, t, a);
   });
   return hipGetLastError();
 }
