@@ -184,9 +184,12 @@ int adl_exp_quad2_step(adl_op* op, double* u, const double* S1, const double* S2
                        void* stream);
 
 /* ------------------------------------------------------------------------
- * Batched momentum bins: independent operators advanced together, one
- * persistent kernel launch per step (all bins' Leja sweeps), optionally
- * replayed from a captured hipGraph.
+ * Batched momentum bins: independent operators (different grids, different
+ * intervals) advanced together.  Each kernel of a step covers the tiles of
+ * all bins (stage, one launch per Leja term, final decision); the step's
+ * launches are captured once in a hipGraph and replayed, one graph launch
+ * per step.  Bins needing substeps, a zero operator or more terms than the
+ * batch allows are advanced by the single-op path inside the same call.
  * ---------------------------------------------------------------------- */
 
 /* Bytes of device workspace for a batch over these ops. */
@@ -200,13 +203,25 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
                      int tile_rows, adl_batch** out);
 int adl_batch_destroy(adl_batch* b);
 
+/* Tile height (rows, a positive multiple of 4) of the batch kernels. */
+int adl_batch_set_tile_rows(adl_batch* b, int rows);
+int adl_batch_get_tile_rows(const adl_batch* b, int* rows);
+
+/* Autotuner: times the launches of one step (stage and sweep; u is not
+ * modified) for each of the ncand candidate tile heights (host array) and
+ * installs the fastest; best_rows / best_ms (host, may be NULL) receive it. */
+int adl_batch_autotune(adl_batch* b, double* const* u, const double* const* S_half, double dt,
+                       double tol, const int* candidates, int ncand, int* best_rows,
+                       double* best_ms, void* stream);
+
 /* One exponential midpoint step (eq. 4) of every bin with a shared dt:
  *   u_b <- u_b + dt phi_1(A_b dt)(A_b u_b + S_b).
- * u, S_half: host arrays of nbins device pointers (S_half or its entries may
- * be NULL).  per_bin: host array of nbins adl_stats or NULL.  use_graph = 1
- * captures the step's launches in a hipGraph on first use and replays it
- * while the pointers, dt and tol are unchanged.  Bins whose sweep does not
- * converge are left unchanged and the call returns ADL_ENOCONV. */
+ * u, S_half: host arrays of nbins device pointers (16-byte aligned; S_half or
+ * its entries may be NULL).  per_bin: host array of nbins adl_stats or NULL.
+ * use_graph = 1 captures the step's launches in a hipGraph on first use and
+ * replays it while the pointers, dt and tol are unchanged.  Each bin's u is
+ * written only when its step succeeds; the first failing bin's code is
+ * returned (ADL_ENOCONV, ADL_ENAN, ...). */
 int adl_batch_midpoint_step(adl_batch* b, double* const* u, const double* const* S_half,
                             double dt, double tol, int use_graph, adl_stats* per_bin,
                             void* stream);

@@ -75,6 +75,10 @@ _SIG = {
     "adl_batch_workspace_bytes": (_SZ, [_I, ctypes.POINTER(_P), _I]),
     "adl_batch_create": (_I, [_I, ctypes.POINTER(_P), _P, _SZ, _I, ctypes.POINTER(_P)]),
     "adl_batch_destroy": (_I, [_P]),
+    "adl_batch_set_tile_rows": (_I, [_P, _I]),
+    "adl_batch_get_tile_rows": (_I, [_P, ctypes.POINTER(_I)]),
+    "adl_batch_autotune": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, ctypes.POINTER(_I), _I,
+                                ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
     "adl_batch_midpoint_step": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, _I,
                                      ctypes.POINTER(Stats), _P]),
     "adl_field_stats": (_I, [_P, _D, _P, _P]),
@@ -300,8 +304,7 @@ class Batch:
         except Exception:
             pass
 
-    def midpoint_step(self, us, S_halfs, dt: float, tol: float, use_graph: bool = True,
-                      stream=None):
+    def _ptr_arrays(self, us, S_halfs):
         import torch
         n = len(self.ops)
         up = (ctypes.c_void_p * n)(*[_ptr(u, torch.float64, o.shape, "u").value
@@ -311,6 +314,29 @@ class Batch:
         else:
             sp = (ctypes.c_void_p * n)(*[(_ptr(s, torch.float64, o.shape, "S").value if s is not None else None)
                                          for s, o in zip(S_halfs, self.ops)])
+        return up, sp
+
+    def set_tile_rows(self, rows: int):
+        _check(lib().adl_batch_set_tile_rows(self.handle, int(rows)))
+
+    def get_tile_rows(self) -> int:
+        r = ctypes.c_int()
+        _check(lib().adl_batch_get_tile_rows(self.handle, ctypes.byref(r)))
+        return r.value
+
+    def autotune(self, us, S_halfs, dt: float, tol: float, candidates=(8, 16, 32), stream=None):
+        up, sp = self._ptr_arrays(us, S_halfs)
+        cand = (ctypes.c_int * len(candidates))(*candidates)
+        best = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(lib().adl_batch_autotune(self.handle, up, sp, float(dt), float(tol), cand, len(candidates),
+                                        ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+        return best.value, ms.value
+
+    def midpoint_step(self, us, S_halfs, dt: float, tol: float, use_graph: bool = True,
+                      stream=None):
+        n = len(self.ops)
+        up, sp = self._ptr_arrays(us, S_halfs)
         stats = (Stats * n)()
         _check(lib().adl_batch_midpoint_step(self.handle, up, sp, float(dt), float(tol), int(bool(use_graph)),
                                              stats, _stream(stream)))

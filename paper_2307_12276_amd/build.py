@@ -17,7 +17,7 @@ OBJ = os.path.join(HERE, "_build")
 
 ARCH = os.environ.get("ADL_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    "-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",

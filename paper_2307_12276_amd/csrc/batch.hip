@@ -1,0 +1,750 @@
+// Batched momentum bins: many independent operators (grids of different
+// sizes, different spectral intervals) advanced by one exponential midpoint
+// step (Sec. 2, eq. 4) together.
+//
+// Work unit: a tile = one wave64 strip of 64*VEC columns x `rows` rows of one
+// bin.  Every kernel of a step covers the tiles of all bins:
+//   stage      w_b = A_b u_b + S_b
+//   term k     y_{k+1} = ((A_b - c_b)/gamma_b - xi_k) y_k,  p_b += d_{b,k+1} y_{k+1}
+//              for every bin still running, with the bin's own plan; at its
+//              start each tile takes its bin's stopping decision for term k
+//              from the bin's tile partials of the previous launch (fixed
+//              order, identical in every tile of the bin)
+//   finalize   the decision of the last term, one wave per bin
+//   update     u_b += dt p_b for converged bins
+// The launches of a step (reset, stage, terms, finalize) are captured once in
+// a hipGraph and replayed: one graph launch per step.  Kernel boundaries give
+// cross-XCD visibility of y_k, so no tile ever waits on another within a
+// kernel and no agent-scope fence is needed.
+#include "march.h"
+#include "op.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace adl {
+
+struct BinDesc {
+  FieldView f;
+  const double* u;
+  const double* S;
+  double* w;
+  void* y0;
+  void* y1;
+  double* p;
+  const double* d;      // d_0 .. d_{M-1} of the bin's plan
+  const double* shift;  // c + gamma xi_k
+  double invg;
+  double tol2;
+  double dt;
+  int max_degree;
+  int ncb;        // strips of 64*VEC columns
+  int rows;       // band height
+  int ntiles;
+  int tile_base;  // first global tile of this bin
+  int active;     // 0: the bin is advanced by the single-op path instead
+};
+
+struct BinCtl {
+  int stop;
+  int status;  // 0 running, 1 converged, 2 non-finite, 3 degree cap
+  int degree;
+  int pad;
+  double tn2, pn2;
+};
+
+struct BatchArgs {
+  const BinDesc* bins;
+  const int* tile_bin;  // global tile -> bin
+  BinCtl* ctl;
+  double* partials;     // 2 parities x total_tiles x 3
+  int total_tiles;
+  int k;                // term index (Leja launches)
+};
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sum3(double (&v)[3]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double t = __shfl_xor(v[q], o);
+      v[q] = (q < 2) ? v[q] + t : nanmax(v[q], t);
+    }
+  }
+}
+
+// Decision for term kprev+1 of bin b (whole wave; identical in every tile).
+__device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B, int b, int kprev, bool record) {
+  const double* part = A.partials + ((long)(kprev & 1) * A.total_tiles + B.tile_base) * 3;
+  double tot[3] = {0.0, 0.0, 0.0};
+  bool any = false;
+  for (int t = threadIdx.x & 63; t < B.ntiles; t += 64) {
+    tot[0] += part[t * 3 + 0];
+    tot[1] += part[t * 3 + 1];
+    tot[2] = any ? nanmax(tot[2], part[t * 3 + 2]) : part[t * 3 + 2];
+    any = true;
+  }
+  wave_sum3(tot);
+  const double tn2 = tot[0], pn2 = tot[1];
+  const int deg = kprev + 1;
+  int stop = 0, status = 0, degree = deg;
+  if (!isfinite(tn2) || !isfinite(pn2)) {
+    stop = 1; status = 2;
+  } else if (kprev == 0 && tot[2] == 0.0) {
+    stop = 1; status = 1; degree = 0;
+  } else if (tn2 <= B.tol2 * pn2) {
+    stop = 1; status = 1;
+  } else if (deg >= B.max_degree) {
+    stop = 1; status = 3;
+  }
+  if (record && (threadIdx.x & 63) == 0) {
+    BinCtl* c = A.ctl + b;
+    c->tn2 = tn2;
+    c->pn2 = pn2;
+    c->degree = degree;
+    c->status = status;
+    __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return stop != 0;
+}
+
+template <int VEC>
+struct StageEp {
+  struct Extra {};
+  int nx;
+  double* __restrict__ out;
+  const double* __restrict__ s;
+  template <bool CHECK>
+  __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
+  template <bool CHECK>
+  __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&)[VEC],
+                                         const Extra&) {
+    if (CHECK && !g.inside) return;
+    const long off = (long)j * nx + g.col0;
+    double r[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) r[v] = Ax[v];
+    if (s) {
+      double q[VEC];
+      load_c<double, VEC>(s, off, q);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) r[v] += q[v];
+    }
+    store_c<double, VEC>(out, off, r);
+  }
+};
+
+template <int VEC, bool FIRST>
+struct BatchLejaEp {
+  struct Extra {
+    double p[VEC];
+  };
+  int nx;
+  double* __restrict__ yout;
+  double* __restrict__ p;
+  double shift, invg, d0, dk1;
+  double acc[3];
+  template <bool CHECK>
+  __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
+    if (CHECK && !g.inside) return;
+    if constexpr (!FIRST) load_c<double, VEC>(p, (long)j * nx + g.col0, e.p);
+  }
+  template <bool CHECK>
+  __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&yc)[VEC],
+                                         const Extra& e) {
+    if (CHECK && !g.inside) return;
+    const long off = (long)j * nx + g.col0;
+    double yn[VEC], pn[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const double y1 = (Ax[v] - shift * yc[v]) * invg;
+      const double t = dk1 * y1;
+      const double pv = (FIRST ? d0 * yc[v] : e.p[v]) + t;
+      yn[v] = y1;
+      pn[v] = pv;
+      acc[0] += t * t;
+      acc[1] += pv * pv;
+      if constexpr (FIRST) acc[2] = nanmax(acc[2], fabs(yc[v]));
+    }
+    store_c<double, VEC>(yout, off, yn);
+    store_c<double, VEC>(p, off, pn);
+  }
+};
+
+template <typename TF, int VEC, bool ADVF>
+__global__ __launch_bounds__(64) void batch_stage_kernel(BatchArgs A) {
+  const int gt = blockIdx.x;
+  const int b = A.tile_bin[gt];
+  const BinDesc& B = A.bins[b];
+  if (!B.active) return;
+  const int t = gt - B.tile_base;
+  const int rb = t / B.ncb, cb = t - rb * B.ncb;
+  const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
+  StageEp<VEC> ep;
+  ep.nx = B.f.nx;
+  ep.out = B.w;
+  ep.s = B.S;
+  march_tile<TF, double, VEC, ADVF>(B.f, B.u, ep, cb, j0, j1, 1, 0);
+}
+
+template <typename TF, int VEC, bool ADVF, bool FIRST>
+__device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B, int t) {
+  const int rb = t / B.ncb, cb = t - rb * B.ncb;
+  const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
+  const int k = A.k;
+  BatchLejaEp<VEC, FIRST> ep;
+  ep.nx = B.f.nx;
+  ep.yout = reinterpret_cast<double*>(((k + 1) & 1) ? B.y1 : B.y0);
+  ep.p = B.p;
+  ep.shift = B.shift[k];
+  ep.invg = B.invg;
+  ep.d0 = B.d[0];
+  ep.dk1 = B.d[k + 1];
+  ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
+  const double* yin = FIRST ? B.w : reinterpret_cast<const double*>((k & 1) ? B.y1 : B.y0);
+  march_tile<TF, double, VEC, ADVF>(B.f, yin, ep, cb, j0, j1, 1, 0);
+  wave_sum3(ep.acc);
+  if ((threadIdx.x & 63) == 0) {
+    double* part = A.partials + ((long)(k & 1) * A.total_tiles + B.tile_base + t) * 3;
+    part[0] = ep.acc[0];
+    part[1] = ep.acc[1];
+    part[2] = ep.acc[2];
+  }
+}
+
+template <typename TF, int VEC, bool ADVF>
+__global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A) {
+  const int gt = blockIdx.x;
+  const int b = A.tile_bin[gt];
+  const BinDesc& B = A.bins[b];
+  if (!B.active) return;
+  if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int t = gt - B.tile_base;
+  if (A.k > 0 && bin_decide(A, B, b, A.k - 1, t == 0)) return;
+  if (A.k >= B.max_degree) return;
+  if (A.k == 0) batch_term<TF, VEC, ADVF, true>(A, B, t);
+  else batch_term<TF, VEC, ADVF, false>(A, B, t);
+}
+
+// decision of term k (the last launched) for every running bin: one wave per bin
+__global__ __launch_bounds__(64) void batch_finalize_kernel(BatchArgs A, int nbins) {
+  const int b = blockIdx.x;
+  if (b >= nbins) return;
+  const BinDesc& B = A.bins[b];
+  if (!B.active) return;
+  if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (A.k > 0) bin_decide(A, B, b, A.k - 1, true);
+}
+
+__global__ __launch_bounds__(256) void batch_reset_kernel(BinCtl* ctl, int nbins) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nbins) {
+    BinCtl c{};
+    ctl[b] = c;
+  }
+}
+
+// u_b += dt p_b for converged bins (one wave per tile)
+template <int VEC>
+__global__ __launch_bounds__(64) void batch_update_kernel(BatchArgs A, double* const* u) {
+  const int gt = blockIdx.x;
+  const int b = A.tile_bin[gt];
+  const BinDesc& B = A.bins[b];
+  if (!B.active || A.ctl[b].status != 1) return;
+  const int t = gt - B.tile_base;
+  const int rb = t / B.ncb, cb = t - rb * B.ncb;
+  const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
+  const int col0 = (cb * kWave + (threadIdx.x & 63)) * VEC;
+  if (col0 >= B.f.nx) return;
+  double* ub = u[b];
+  for (int j = j0; j < j1; ++j) {
+    const long off = (long)j * B.f.nx + col0;
+    double uu[VEC], pp[VEC];
+    load_c<double, VEC>(ub, off, uu);
+    load_c<double, VEC>(B.p, off, pp);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) uu[v] = uu[v] + B.dt * pp[v];
+    store_c<double, VEC>(ub, off, uu);
+  }
+}
+
+}  // namespace adl
+
+using namespace adl;
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct adl_batch {
+  std::vector<adl_op*> ops;
+  int nbins = 0;
+  int vec = 1;
+  int f32 = 0;
+  bool advf = false;
+  int rows = 16;
+  int max_degree = kMaxDegreeDefault;
+  // workspace slices
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  BinDesc* d_bins = nullptr;
+  BinCtl* d_ctl = nullptr;
+  int* d_tile_bin = nullptr;
+  double* d_partials = nullptr;
+  double* d_plans = nullptr;   // nbins x 2 x M
+  double** d_uptrs = nullptr;  // nbins
+  BinCtl* h_ctl = nullptr;     // pinned
+  int total_tiles = 0;
+  std::vector<BinDesc> bins;
+  std::vector<int> tile_bin;
+  // plan keys uploaded to d_plans
+  std::vector<double> plan_alpha, plan_dt;
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const double*> g_u, g_S;
+  double g_dt = 0.0, g_tol = 0.0;
+  int g_launches = 0;
+  int g_rows = 0;
+  int predicted = 0;
+};
+
+static thread_local std::string b_err;
+
+namespace {
+
+int bfail(int code, const char* msg) {
+  b_err = msg;
+  fprintf(stderr, "adl batch: %s\n", msg);
+  return code;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int tiles_of(int nx, int ny, int vec, int rows) {
+  const int ncb = (nx + kWave * vec - 1) / (kWave * vec);
+  const int nrb = (ny + rows - 1) / rows;
+  return ncb * nrb;
+}
+
+struct BLayout {
+  size_t bins, ctl, tile_bin, partials, plans, uptrs, total;
+};
+
+BLayout blayout(int nbins, long max_tiles, int M) {
+  BLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t n) {
+    const size_t at = o;
+    o = al256(o + n);
+    return at;
+  };
+  L.bins = take(sizeof(BinDesc) * nbins);
+  L.ctl = take(sizeof(BinCtl) * nbins);
+  L.tile_bin = take(sizeof(int) * max_tiles);
+  L.partials = take(sizeof(double) * 6 * max_tiles);
+  L.plans = take(sizeof(double) * 2 * (size_t)M * nbins);
+  L.uptrs = take(sizeof(double*) * nbins);
+  L.total = o;
+  return L;
+}
+
+long max_tiles_for(int nbins, adl_op* const* ops) {
+  long t = 0;
+  for (int b = 0; b < nbins; ++b) t += tiles_of(ops[b]->nx, ops[b]->ny, 1, 4);
+  return t;
+}
+
+#define BCHK(expr)                                            \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return bfail(ADL_EHIP, hipGetErrorString(e_)); \
+  } while (0)
+
+void build_tiles(adl_batch* B) {
+  B->tile_bin.clear();
+  int base = 0;
+  for (int b = 0; b < B->nbins; ++b) {
+    adl_op* op = B->ops[b];
+    BinDesc& d = B->bins[b];
+    d.ncb = (op->nx + kWave * B->vec - 1) / (kWave * B->vec);
+    d.rows = B->rows;
+    d.ntiles = d.ncb * ((op->ny + B->rows - 1) / B->rows);
+    d.tile_base = base;
+    for (int t = 0; t < d.ntiles; ++t) B->tile_bin.push_back(b);
+    base += d.ntiles;
+  }
+  B->total_tiles = base;
+}
+
+template <typename F>
+void dispatch(const adl_batch* B, F&& f) {
+  if (B->vec == 2) {
+    if (B->f32) {
+      if (B->advf) f.template operator()<float, 2, true>(); else f.template operator()<float, 2, false>();
+    } else {
+      if (B->advf) f.template operator()<double, 2, true>(); else f.template operator()<double, 2, false>();
+    }
+  } else {
+    if (B->f32) {
+      if (B->advf) f.template operator()<float, 1, true>(); else f.template operator()<float, 1, false>();
+    } else {
+      if (B->advf) f.template operator()<double, 1, true>(); else f.template operator()<double, 1, false>();
+    }
+  }
+}
+
+// enqueue reset, stage and n terms starting at k0 (+ finalize) on st
+int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t st) {
+  BatchArgs a{};
+  a.bins = B->d_bins;
+  a.tile_bin = B->d_tile_bin;
+  a.ctl = B->d_ctl;
+  a.partials = B->d_partials;
+  a.total_tiles = B->total_tiles;
+  if (with_stage) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((B->nbins + 255) / 256), dim3(256), 0, st, B->d_ctl, B->nbins);
+    dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
+      hipLaunchKernelGGL((batch_stage_kernel<TF, VEC, ADVF>), dim3(B->total_tiles), dim3(64), 0, st, a);
+    });
+  }
+  for (int i = 0; i < nterms; ++i) {
+    a.k = k0 + i;
+    dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
+      hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF>), dim3(B->total_tiles), dim3(64), 0, st, a);
+    });
+  }
+  a.k = k0 + nterms;
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3(B->nbins), dim3(64), 0, st, a, B->nbins);
+  BCHK(hipGetLastError());
+  return ADL_OK;
+}
+
+int upload_bins(adl_batch* B, double* const* u, const double* const* S, double dt, double tol, hipStream_t st,
+                bool& changed) {
+  changed = false;
+  const int M = B->max_degree + 1;
+  std::vector<double> planbuf;
+  bool plans_changed = false;
+  for (int b = 0; b < B->nbins; ++b) {
+    adl_op* op = B->ops[b];
+    BinDesc& d = B->bins[b];
+    const double* Sb = S ? S[b] : nullptr;
+    const int K = substeps_for(op->alpha, dt, op->rho_max);
+    const bool active = op->has_bound && op->alpha < 0.0 && K == 1;
+    if (d.u != u[b] || d.S != Sb || d.dt != dt || d.tol2 != tol * tol || d.active != (int)active) changed = true;
+    d.f = op->f;
+    d.u = u[b];
+    d.S = Sb;
+    d.w = op->w1;
+    d.y0 = op->ybuf[0];
+    d.y1 = op->ybuf[1];
+    d.p = op->p;
+    d.tol2 = tol * tol;
+    d.dt = dt;
+    d.max_degree = std::min(op->max_degree, B->max_degree);
+    d.active = active;
+    d.d = B->d_plans + (size_t)b * 2 * M;
+    d.shift = d.d + M;
+    if (active && (B->plan_alpha[b] != op->alpha || B->plan_dt[b] != dt)) {
+      if (!plans_changed) BCHK(hipStreamSynchronize(st));
+      Plan& P = get_plan(op, 1, op->alpha, dt);
+      d.invg = P.invg;
+      planbuf.assign(2 * (size_t)M, 0.0);
+      std::copy(P.d.begin(), P.d.begin() + std::min((int)P.d.size(), M), planbuf.begin());
+      std::copy(P.shift.begin(), P.shift.begin() + std::min((int)P.shift.size(), M), planbuf.begin() + M);
+      BCHK(hipMemcpy(B->d_plans + (size_t)b * 2 * M, planbuf.data(), planbuf.size() * sizeof(double),
+                     hipMemcpyHostToDevice));
+      B->plan_alpha[b] = op->alpha;
+      B->plan_dt[b] = dt;
+      plans_changed = true;
+    }
+  }
+  if (changed || plans_changed) {
+    BCHK(hipStreamSynchronize(st));
+    BCHK(hipMemcpy(B->d_bins, B->bins.data(), sizeof(BinDesc) * B->nbins, hipMemcpyHostToDevice));
+    std::vector<double*> up(u, u + B->nbins);
+    BCHK(hipMemcpy(B->d_uptrs, up.data(), sizeof(double*) * B->nbins, hipMemcpyHostToDevice));
+    changed = true;
+  }
+  (void)st;
+  return ADL_OK;
+}
+
+int predicted_terms(adl_batch* B, double dt) {
+  int mx = 0;
+  for (int b = 0; b < B->nbins; ++b) {
+    adl_op* op = B->ops[b];
+    if (!B->bins[b].active) continue;
+    Plan& P = get_plan(op, 1, op->alpha, dt);
+    const int m = P.last_degree > 0 ? P.last_degree + 1 : (int)(5.0 * std::sqrt(std::fabs(op->alpha) * dt) + 8.0);
+    mx = std::max(mx, m);
+  }
+  return std::min(std::max(mx, 1), B->max_degree);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t adl_batch_workspace_bytes(int nbins, adl_op* const* ops, int max_degree) {
+  if (nbins < 1 || !ops) return 0;
+  for (int b = 0; b < nbins; ++b)
+    if (!ops[b]) return 0;
+  const int M = (max_degree > 0 ? max_degree : kMaxDegreeDefault) + 1;
+  return blayout(nbins, max_tiles_for(nbins, ops), M).total;
+}
+
+int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_bytes, int tile_rows,
+                     adl_batch** out) {
+  if (!out) return bfail(ADL_EINVAL, "null out");
+  *out = nullptr;
+  if (nbins < 1 || !ops) return bfail(ADL_EINVAL, "need nbins >= 1 ops");
+  for (int b = 0; b < nbins; ++b)
+    if (!ops[b]) return bfail(ADL_EINVAL, "null op in batch");
+  const int f32 = ops[0]->f.f32;
+  const bool advf = ops[0]->f.ax != nullptr;
+  bool all_even = true;
+  for (int b = 0; b < nbins; ++b) {
+    adl_op* op = ops[b];
+    if (op->f.f32 != f32 || (op->f.ax != nullptr) != advf)
+      return bfail(ADL_EINVAL, "all bins must share storage mode and advection kind");
+    if (op->storage == ADL_STORAGE_FP32_FIELDS_Y) return bfail(ADL_EINVAL, "batch supports FP64 Newton vectors only");
+    if (op->nx % 2 != 0 || op->nx < 2 * kWave) all_even = false;
+  }
+  if (tile_rows < 0 || (tile_rows > 0 && tile_rows % 4 != 0)) return bfail(ADL_EINVAL, "tile_rows must be a multiple of 4");
+  const int M = kMaxDegreeDefault + 1;
+  const long mt = max_tiles_for(nbins, ops);
+  const BLayout L = blayout(nbins, mt, M);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return bfail(ADL_ENOWORKSPACE, "workspace missing or not 256-byte aligned");
+  if (ws_bytes < L.total) return bfail(ADL_ENOWORKSPACE, "batch workspace too small");
+  adl_batch* B = new (std::nothrow) adl_batch();
+  if (!B) return bfail(ADL_EINVAL, "out of host memory");
+  B->ops.assign(ops, ops + nbins);
+  B->nbins = nbins;
+  B->vec = all_even ? 2 : 1;
+  B->f32 = f32;
+  B->advf = advf;
+  B->rows = tile_rows > 0 ? tile_rows : 16;
+  B->ws = reinterpret_cast<char*>(workspace);
+  B->ws_bytes = ws_bytes;
+  B->d_bins = reinterpret_cast<BinDesc*>(B->ws + L.bins);
+  B->d_ctl = reinterpret_cast<BinCtl*>(B->ws + L.ctl);
+  B->d_tile_bin = reinterpret_cast<int*>(B->ws + L.tile_bin);
+  B->d_partials = reinterpret_cast<double*>(B->ws + L.partials);
+  B->d_plans = reinterpret_cast<double*>(B->ws + L.plans);
+  B->d_uptrs = reinterpret_cast<double**>(B->ws + L.uptrs);
+  B->bins.assign(nbins, BinDesc{});
+  B->plan_alpha.assign(nbins, NAN);
+  B->plan_dt.assign(nbins, NAN);
+  build_tiles(B);
+  hipError_t e = hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&B->h_ctl), sizeof(BinCtl) * nbins, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreate(&B->cap_stream);
+  if (e != hipSuccess) {
+    if (B->h_ctl) hipHostFree(B->h_ctl);
+    delete B;
+    return bfail(ADL_EHIP, hipGetErrorString(e));
+  }
+  *out = B;
+  return ADL_OK;
+}
+
+int adl_batch_destroy(adl_batch* B) {
+  if (!B) return ADL_OK;
+  if (B->gexec) hipGraphExecDestroy(B->gexec);
+  if (B->graph) hipGraphDestroy(B->graph);
+  if (B->cap_stream) hipStreamDestroy(B->cap_stream);
+  if (B->h_ctl) hipHostFree(B->h_ctl);
+  delete B;
+  return ADL_OK;
+}
+
+int adl_batch_set_tile_rows(adl_batch* B, int rows) {
+  if (!B || rows < 4 || rows % 4 != 0) return bfail(ADL_EINVAL, "tile rows must be a positive multiple of 4");
+  if (rows == B->rows) return ADL_OK;
+  B->rows = rows;
+  build_tiles(B);
+  BCHK(hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B->d_bins, B->bins.data(), sizeof(BinDesc) * B->nbins, hipMemcpyHostToDevice));
+  if (B->gexec) {
+    hipGraphExecDestroy(B->gexec);
+    B->gexec = nullptr;
+  }
+  if (B->graph) {
+    hipGraphDestroy(B->graph);
+    B->graph = nullptr;
+  }
+  return ADL_OK;
+}
+
+int adl_batch_get_tile_rows(const adl_batch* B, int* rows) {
+  if (!B || !rows) return bfail(ADL_EINVAL, "null argument");
+  *rows = B->rows;
+  return ADL_OK;
+}
+
+// Project autotuner: time the stage + sweep launches of one step (u is not
+// modified) for each candidate tile height and keep the fastest.
+int adl_batch_autotune(adl_batch* B, double* const* u, const double* const* S_half, double dt, double tol,
+                       const int* candidates, int ncand, int* best_rows, double* best_ms, void* stream) {
+  if (!B || !u || !candidates || ncand < 1) return bfail(ADL_EINVAL, "bad autotune arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int best = B->rows;
+  double bms = INFINITY;
+  hipEvent_t e0, e1;
+  BCHK(hipEventCreate(&e0));
+  BCHK(hipEventCreate(&e1));
+  for (int c = 0; c < ncand; ++c) {
+    int rc = adl_batch_set_tile_rows(B, candidates[c]);
+    if (rc != ADL_OK) return rc;
+    bool changed;
+    rc = upload_bins(B, u, S_half, dt, tol, st, changed);
+    if (rc != ADL_OK) return rc;
+    const int nterms = predicted_terms(B, dt);
+    float ms_min = INFINITY;
+    for (int rep = 0; rep < 3; ++rep) {
+      BCHK(hipEventRecord(e0, st));
+      rc = enqueue_sweep(B, 0, nterms, true, st);
+      if (rc != ADL_OK) return rc;
+      BCHK(hipEventRecord(e1, st));
+      BCHK(hipEventSynchronize(e1));
+      float ms;
+      BCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) ms_min = std::min(ms_min, ms);
+    }
+    if (ms_min < bms) {
+      bms = ms_min;
+      best = candidates[c];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  int rc = adl_batch_set_tile_rows(B, best);
+  if (rc != ADL_OK) return rc;
+  if (best_rows) *best_rows = best;
+  if (best_ms) *best_ms = bms;
+  return ADL_OK;
+}
+
+int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const* S_half, double dt, double tol,
+                            int use_graph, adl_stats* per_bin, void* stream) {
+  if (!B || !u) return bfail(ADL_EINVAL, "null batch or u");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return bfail(ADL_EINVAL, "dt must be finite and > 0");
+  if (!(tol > 0.0 && tol < 1.0)) return bfail(ADL_EINVAL, "tol must be in (0, 1)");
+  for (int b = 0; b < B->nbins; ++b) {
+    if (!u[b]) return bfail(ADL_EINVAL, "null u entry");
+    if (!B->ops[b]->has_bound) return bfail(ADL_EBOUND, "a bin has no spectral bound");
+    if (B->vec == 2 && (reinterpret_cast<uintptr_t>(u[b]) & 15)) return bfail(ADL_EINVAL, "u must be 16-byte aligned");
+    if (B->vec == 2 && S_half && S_half[b] && (reinterpret_cast<uintptr_t>(S_half[b]) & 15))
+      return bfail(ADL_EINVAL, "S must be 16-byte aligned");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  bool changed;
+  int rc = upload_bins(B, u, S_half, dt, tol, st, changed);
+  if (rc != ADL_OK) return rc;
+  const int nterms = predicted_terms(B, dt);
+  bool any_active = false;
+  for (int b = 0; b < B->nbins; ++b) any_active |= B->bins[b].active != 0;
+
+  if (any_active) {
+    if (use_graph) {
+      const bool rebuild = !B->gexec || changed || nterms > B->g_launches || B->g_rows != B->rows;
+      if (rebuild) {
+        if (B->gexec) hipGraphExecDestroy(B->gexec);
+        if (B->graph) hipGraphDestroy(B->graph);
+        B->gexec = nullptr;
+        B->graph = nullptr;
+        BCHK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_sweep(B, 0, nterms, true, B->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+        if (rc != ADL_OK) return rc;
+        if (e != hipSuccess) return bfail(ADL_EHIP, hipGetErrorString(e));
+        B->graph = g;
+        BCHK(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+        B->g_launches = nterms;
+        B->g_rows = B->rows;
+      }
+      // order the graph after prior work on the caller's stream
+      hipEvent_t ev;
+      BCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      BCHK(hipEventRecord(ev, st));
+      BCHK(hipStreamWaitEvent(B->cap_stream, ev, 0));
+      BCHK(hipGraphLaunch(B->gexec, B->cap_stream));
+      BCHK(hipEventRecord(ev, B->cap_stream));
+      BCHK(hipStreamWaitEvent(st, ev, 0));
+      BCHK(hipEventDestroy(ev));
+    } else {
+      rc = enqueue_sweep(B, 0, nterms, true, st);
+      if (rc != ADL_OK) return rc;
+    }
+    int launched = use_graph ? B->g_launches : nterms;
+    // continue bins that have not stopped yet
+    while (true) {
+      BCHK(hipMemcpyAsync(B->h_ctl, B->d_ctl, sizeof(BinCtl) * B->nbins, hipMemcpyDeviceToHost, st));
+      BCHK(hipStreamSynchronize(st));
+      bool running = false;
+      for (int b = 0; b < B->nbins; ++b)
+        if (B->bins[b].active && !B->h_ctl[b].stop) running = true;
+      if (!running || launched >= B->max_degree) break;
+      const int more = std::min(B->max_degree - launched, std::max(8, launched / 4));
+      rc = enqueue_sweep(B, launched, more, false, st);
+      if (rc != ADL_OK) return rc;
+      launched += more;
+    }
+    BatchArgs a{};
+    a.bins = B->d_bins;
+    a.tile_bin = B->d_tile_bin;
+    a.ctl = B->d_ctl;
+    a.partials = B->d_partials;
+    a.total_tiles = B->total_tiles;
+    if (B->vec == 2)
+      hipLaunchKernelGGL((batch_update_kernel<2>), dim3(B->total_tiles), dim3(64), 0, st, a, B->d_uptrs);
+    else
+      hipLaunchKernelGGL((batch_update_kernel<1>), dim3(B->total_tiles), dim3(64), 0, st, a, B->d_uptrs);
+    BCHK(hipGetLastError());
+  }
+  // per-bin results; bins outside the kernel (substeps, zero operator) and
+  // bins that hit the degree cap take the single-op path (substeps allowed)
+  int result = ADL_OK;
+  for (int b = 0; b < B->nbins; ++b) {
+    adl_op* op = B->ops[b];
+    adl_stats s{};
+    int code = ADL_OK;
+    bool single = !B->bins[b].active;
+    if (!single) {
+      const BinCtl& c = B->h_ctl[b];
+      if (c.status == 1) {
+        Plan& P = get_plan(op, 1, op->alpha, dt);
+        P.last_degree = c.degree;
+        s.matvecs = c.degree + 1;
+        s.sweeps = 1;
+        s.max_degree = s.last_degree = c.degree;
+        s.substeps = 1;
+        s.alpha = op->alpha;
+      } else if (c.status == 2) {
+        code = ADL_ENAN;
+      } else {
+        single = true;
+      }
+    }
+    if (single) code = adl_exp_midpoint_step(op, u[b], S_half ? S_half[b] : nullptr, dt, tol, &s, stream);
+    s.status = code;
+    if (per_bin) per_bin[b] = s;
+    if (code != ADL_OK && result == ADL_OK) result = code;
+  }
+  return result;
+}
+
+}  // extern "C"
