@@ -113,6 +113,116 @@ def run_roofline_leg(w, storage):
     return res
 
 
+def chosen_vs_plain(steps=10, tol=1e-9):
+    """Momentum-bin workload (256 bins, grids from {128,...,512}^2, k_par =
+    p^0.5, shared circular field, midpoint, shared dt).
+    plain  = per-bin FP64 operators, power-iteration interval per bin,
+             per-bin exponential midpoint steps;
+    chosen = FP32 fields, learned interval per bin (field statistics + MLP
+             + Gershgorin cap, power-iteration fallback), all bins advanced by
+             one hipGraph launch per step.
+    Both at the same tolerance; reported: steps/s of the steps, time to
+    solution including the interval estimation, and the relative difference
+    of the chosen result from the plain FP64 result (max over bins)."""
+    import numpy as np
+    import torch
+    import paper_2307_12276_amd as A
+    from paper_2307_12276_amd import learned
+    import workloads as W
+    t0 = time.time()
+    bins = W.c4_bins(steps=steps)
+    log("chosen-vs-plain: 256 bins built in %.1fs (sum N = %.1fM)" % (time.time() - t0, sum(b.nx * b.ny for b in bins) / 1e6))
+    dt = bins[0].dt
+    S = [dev_tensor(b.S(0)) for b in bins]
+    res = {"workload": "256 momentum bins, grids {128..512}^2, k_par=p^0.5, p=10^(4b/255), midpoint, "
+                       "dt=50 min dt_CFL, %d steps" % steps, "tol": tol}
+    # plain
+    ops_p = [make_op(b, A.STORAGE_FP64) for b in bins]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pits = 0
+    for op in ops_p:
+        _, it = op.spectral_bound(A.BOUND_POWER, max_iter=2000, rtol=1e-3, seed=1)
+        pits += it
+    torch.cuda.synchronize()
+    t_bound_p = time.perf_counter() - t0
+    up = [dev_tensor(b.u0) for b in bins]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mv_p = 0
+    for n in range(steps):
+        for op, u, s in zip(ops_p, up, S):
+            mv_p += op.midpoint_step(u, s, dt, tol)["matvecs"]
+    torch.cuda.synchronize()
+    t_steps_p = time.perf_counter() - t0
+    # chosen
+    ops_c = [make_op(b, A.STORAGE_FP32_FIELDS) for b in bins]
+    Wd = torch.from_numpy(learned.load()).cuda()
+    scratch = torch.empty(64, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op in ops_c:
+        op.learned_bound(dt, Wd, scratch)
+    torch.cuda.synchronize()
+    t_bound_c = time.perf_counter() - t0
+    batch = A.Batch(ops_c)
+    uc = [dev_tensor(b.u0) for b in bins]
+    best_rows, _ = batch.autotune(uc, S, dt, tol, candidates=(8, 16, 32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mv_c = 0
+    fb = 0
+    for n in range(steps):
+        st = batch.midpoint_step(uc, S, dt, tol, use_graph=True)
+        mv_c += sum(x["matvecs"] for x in st)
+        fb += sum(x["fallback"] for x in st)
+    torch.cuda.synchronize()
+    t_steps_c = time.perf_counter() - t0
+    diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(uc, up))
+    res.update({
+        "plain": {"steps_per_s": steps / t_steps_p, "bound_s": t_bound_p, "power_iterations": pits,
+                  "time_to_solution_s": t_bound_p + t_steps_p, "matvecs": mv_p},
+        "chosen": {"steps_per_s": steps / t_steps_c, "bound_s": t_bound_c, "tile_rows": best_rows,
+                   "time_to_solution_s": t_bound_c + t_steps_c, "matvecs": mv_c, "fallbacks": fb},
+        "speedup_steps": t_steps_p / t_steps_c,
+        "speedup_time_to_solution": (t_bound_p + t_steps_p) / (t_bound_c + t_steps_c),
+        "max_rel_diff_chosen_vs_plain_fp64": diff})
+    log("chosen-vs-plain: plain %.2f steps/s (bound %.2fs), chosen %.2f steps/s (bound %.3fs), "
+        "speedup %.1fx steps, %.1fx time-to-solution, max rel diff %.2e"
+        % (res["plain"]["steps_per_s"], t_bound_p, res["chosen"]["steps_per_s"], t_bound_c,
+           res["speedup_steps"], res["speedup_time_to_solution"], diff))
+    del batch, ops_c, ops_p
+    torch.cuda.empty_cache()
+    return res
+
+
+def profile_leja(n):
+    """One phi_1 sweep on the n x n stream-function field (profiler driver)."""
+    import torch
+    import paper_2307_12276_amd as A
+    import workloads as W
+    w = W.roofline_shape(n=n)
+    op = make_op(w, A.STORAGE_FP64)
+    op.spectral_bound(A.BOUND_GERSHGORIN)
+    v = dev_tensor(w.u0)
+    out = torch.empty_like(v)
+    st = op.leja_phi(1, w.dt, v, out, w.tol)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_leja": n, "terms": st["matvecs"]}), flush=True)
+
+
+def calibrate_copy():
+    """A plain 1 GiB device copy (read 1 GiB, write 1 GiB): the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.zeros(128 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": a.numel() * 8}), flush=True)
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle, single-threaded, on the first steps of the same
     workload until budget_s seconds of CPU work have been spent."""
@@ -146,8 +256,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline and bins legs")
+    ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
     args = ap.parse_args()
+    if args.profile_leja:
+        profile_leja(args.profile_leja)
+        return
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(bins and row slabs would shard across GPUs; see the design notes). "
@@ -238,6 +356,7 @@ def main():
                 legs[-1]["storage"], legs[-1]["avg_kernel_us"], legs[-1]["achieved_GBs"],
                 100 * legs[-1]["frac_of_8TBs"]))
         out["roofline_4096"] = legs
+        out["chosen_vs_plain"] = chosen_vs_plain()
 
     print(json.dumps(out), flush=True)
 

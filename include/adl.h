@@ -154,6 +154,10 @@ int adl_apply(adl_op* op, const double* x, double* y, void* stream);
 int adl_spectral_bound(adl_op* op, int method, int max_iter, double rtol, uint64_t seed,
                        double* alpha_out, int* iters_out, void* stream);
 
+/* The raw estimate lambda (before the safety factor and the Gershgorin cap)
+ * of the op's last power iteration; ADL_EBOUND if none has run. */
+int adl_last_power_estimate(const adl_op* op, double* lambda);
+
 /* Install an interval end directly (alpha < 0 and finite, else ADL_EBOUND),
  * e.g. from the learned predictor.  alpha == 0 is accepted only for an
  * operator whose Gershgorin bound is 0 (A = 0). */
@@ -252,6 +256,10 @@ int adl_mlp_forward(const float* W, const float* X, float* Y, float* act_cache, 
 int adl_mlp_backward(const float* W, const float* act_cache, const float* dY, float* dW,
                      int B, void* stream);
 
+/* Mean squared error of a batch: loss (device, 1 float, may be NULL) =
+ * mean((Y - T)^2) over B x 3, dY = 2 (Y - T) / (3 B) (device [B][3]). */
+int adl_mlp_mse_grad(const float* Y, const float* T, float* dY, float* loss, int B, void* stream);
+
 /* One Adam update of W (device) with moments m1, m2 (device, zero at t = 1),
  * step t >= 1. */
 int adl_mlp_adam_step(float* W, const float* dW, float* m1, float* m2, int t, float lr,
@@ -270,6 +278,38 @@ int adl_leja_points(int n, double* out);
  * phi_l((c + gamma xi) h) at the Leja points, c = alpha/2, gamma = -alpha/4
  * (Sec. 2: divided differences), l in {0,1,2}, alpha < 0, h > 0. */
 int adl_newton_coefficients(int l, double alpha, double h, int n, double* out);
+
+/* ------------------------------------------------------------------------
+ * Learned spectral interval.  The predictor maps dimensionless inputs built
+ * from the raw statistics f (adl_field_stats) and g = |alpha_Gershgorin| to
+ * dimensionless targets
+ *   y0 = 10 log10(rho / g), y1 = m / sqrt(rho dt / K + 1), y2 = log2 K
+ * with rho the spectral radius (power iteration), m the phi_1 Leja degree and
+ * K the substeps.  Host helpers (no GPU): */
+int adl_learned_features(const float* raw9, double g, float* x9);
+int adl_learned_targets(const float* raw9, double g, double rho, int degree, int substeps, float* y3);
+int adl_learned_decode(const float* raw9, double g, const float* y3, double* rho, int* degree,
+                       int* substeps);
+
+typedef struct adl_learned_info {
+  double rho_hat;     /* predicted spectral radius */
+  double alpha;       /* installed interval end -min(1.2 rho_hat, |alpha_Gershgorin|) */
+  double gershgorin;
+  int degree_hat;     /* predicted Leja degree */
+  int substeps_hat;   /* predicted substeps */
+  float feats[9], x[9], y[3];
+} adl_learned_info;
+
+/* Predict and install the op's interval for step size dt with the trained
+ * network W (device, ADL_MLP_PARAMS floats): field statistics, the network's
+ * forward pass and the Gershgorin cap run on the GPU.  scratch: device, >= 32
+ * floats.  Power iteration stays the fallback and the judge: while the learned
+ * interval is installed, a sweep needing more than 1.5 degree_hat + 10 terms,
+ * or producing a non-finite value, makes adl_exp_midpoint_step /
+ * adl_exp_quad2_step replace the interval by power iteration's and redo the
+ * step (adl_stats.fallback = 1).  info (host) may be NULL. */
+int adl_learned_bound(adl_op* op, double dt, const float* W, float* scratch, adl_learned_info* info,
+                      void* stream);
 
 /* Thread-local message of the last error (never NULL). */
 const char* adl_last_error(void);

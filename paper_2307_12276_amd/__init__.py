@@ -32,6 +32,17 @@ class AdlError(RuntimeError):
         self.code = code
 
 
+class LearnedInfo(ctypes.Structure):
+    _fields_ = [("rho_hat", ctypes.c_double), ("alpha", ctypes.c_double), ("gershgorin", ctypes.c_double),
+                ("degree_hat", ctypes.c_int), ("substeps_hat", ctypes.c_int),
+                ("feats", ctypes.c_float * 9), ("x", ctypes.c_float * 9), ("y", ctypes.c_float * 3)]
+
+    def as_dict(self):
+        return {"rho_hat": self.rho_hat, "alpha": self.alpha, "gershgorin": self.gershgorin,
+                "degree_hat": self.degree_hat, "substeps_hat": self.substeps_hat,
+                "feats": list(self.feats), "x": list(self.x), "y": list(self.y)}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("matvecs", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("max_degree", ctypes.c_int), ("last_degree", ctypes.c_int),
@@ -68,6 +79,7 @@ _SIG = {
     "adl_spectral_bound": (_I, [_P, _I, _I, _D, ctypes.c_uint64, ctypes.POINTER(_D),
                                 ctypes.POINTER(_I), _P]),
     "adl_set_bound": (_I, [_P, _D]),
+    "adl_last_power_estimate": (_I, [_P, ctypes.POINTER(_D)]),
     "adl_get_bound": (_I, [_P, ctypes.POINTER(_D)]),
     "adl_leja_phi": (_I, [_P, _I, _D, _P, _P, _D, _I, ctypes.POINTER(Stats), _P]),
     "adl_exp_midpoint_step": (_I, [_P, _P, _P, _D, _D, ctypes.POINTER(Stats), _P]),
@@ -85,6 +97,12 @@ _SIG = {
     "adl_mlp_forward": (_I, [_P, _P, _P, _P, _I, _P]),
     "adl_mlp_backward": (_I, [_P, _P, _P, _P, _I, _P]),
     "adl_mlp_adam_step": (_I, [_P, _P, _P, _P, _I, _F, _F, _F, _F, _P]),
+    "adl_mlp_mse_grad": (_I, [_P, _P, _P, _P, _I, _P]),
+    "adl_learned_features": (_I, [ctypes.POINTER(_F), _D, ctypes.POINTER(_F)]),
+    "adl_learned_targets": (_I, [ctypes.POINTER(_F), _D, _D, _I, _I, ctypes.POINTER(_F)]),
+    "adl_learned_decode": (_I, [ctypes.POINTER(_F), _D, ctypes.POINTER(_F), ctypes.POINTER(_D), ctypes.POINTER(_I),
+                                ctypes.POINTER(_I)]),
+    "adl_learned_bound": (_I, [_P, _D, _P, _P, ctypes.POINTER(LearnedInfo), _P]),
     "adl_leja_points": (_I, [_I, ctypes.POINTER(_D)]),
     "adl_newton_coefficients": (_I, [_I, _D, _D, _I, ctypes.POINTER(_D)]),
 }
@@ -236,6 +254,11 @@ class Op:
                                         _stream(stream)))
         return a.value, it.value
 
+    def last_power_estimate(self) -> float:
+        lam = ctypes.c_double()
+        _check(lib().adl_last_power_estimate(self.handle, ctypes.byref(lam)))
+        return lam.value
+
     def set_bound(self, alpha: float):
         _check(lib().adl_set_bound(self.handle, float(alpha)))
 
@@ -265,6 +288,14 @@ class Op:
                                         float(c1), float(c2), float(dt), float(tol), ctypes.byref(st),
                                         _stream(stream)))
         return st.as_dict()
+
+    def learned_bound(self, dt: float, W, scratch, stream=None):
+        import torch
+        info = LearnedInfo()
+        _check(lib().adl_learned_bound(self.handle, float(dt), _ptr(W, torch.float32, (MLP_PARAMS,), "W"),
+                                       _ptr(scratch, torch.float32, None, "scratch"), ctypes.byref(info),
+                                       _stream(stream)))
+        return info.as_dict()
 
     def field_stats(self, dt: float, feats, stream=None):
         import torch
@@ -362,6 +393,40 @@ def mlp_backward(W, cache, dY, dW, stream=None):
                                   _ptr(dY, torch.float32, (B, MLP_OUT), "dY"),
                                   _ptr(dW, torch.float32, (MLP_PARAMS,), "dW"), int(B), _stream(stream)))
     return dW
+
+
+def mlp_mse_grad(Y, T, dY, loss=None, stream=None):
+    import torch
+    B = Y.shape[0]
+    f = torch.float32
+    _check(lib().adl_mlp_mse_grad(_ptr(Y, f, (B, MLP_OUT), "Y"), _ptr(T, f, (B, MLP_OUT), "T"),
+                                  _ptr(dY, f, (B, MLP_OUT), "dY"), _ptr(loss, f, (1,), "loss") if loss is not None else None,
+                                  int(B), _stream(stream)))
+    return dY
+
+
+def _f9(a):
+    return (ctypes.c_float * len(a))(*[float(v) for v in a])
+
+
+def learned_features(raw, g: float):
+    x = (ctypes.c_float * 9)()
+    _check(lib().adl_learned_features(_f9(raw), float(g), x))
+    return list(x)
+
+
+def learned_targets(raw, g: float, rho: float, degree: int, substeps: int):
+    y = (ctypes.c_float * 3)()
+    _check(lib().adl_learned_targets(_f9(raw), float(g), float(rho), int(degree), int(substeps), y))
+    return list(y)
+
+
+def learned_decode(raw, g: float, y):
+    r = ctypes.c_double()
+    m = ctypes.c_int()
+    K = ctypes.c_int()
+    _check(lib().adl_learned_decode(_f9(raw), float(g), _f9(y), ctypes.byref(r), ctypes.byref(m), ctypes.byref(K)))
+    return r.value, m.value, K.value
 
 
 def mlp_adam_step(W, dW, m1, m2, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -27,6 +27,8 @@ namespace adl {
 // --------------------------------------------------------------------------
 static thread_local std::string g_err = "";
 
+constexpr double kLearnedSafety = 1.2;  // learned rho is widened by this factor (capped by Gershgorin)
+
 static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 static int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -280,6 +282,7 @@ static double leja_bytes(const adl_op* op, int k, bool with_w2) {
 // end of every chunk takes the decision of the chunk's last term.
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
                  double tol, int maxdeg, hipStream_t st, SweepOut& out) {
+  if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;
   HIPCHK(launch_ctl_reset(op->ctl, 1, st));
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
   const Tiling& T = tiling_for(op, v, p_out);
@@ -412,6 +415,7 @@ static int phi_combo(adl_op* op, const double* w1, const double* w2, double dt, 
     return ADL_OK;
   }
   int K = substeps_for(op->alpha, dt, op->rho_max);
+  if (op->learned) K = std::max(K, op->substeps_hint);
   for (int d = 0; d <= kMaxDoublings; ++d) {
     bool ok;
     RETCHK(combo_fixed(op, w1, w2, dt, tol, K, acc, ok, st));
@@ -419,6 +423,9 @@ static int phi_combo(adl_op* op, const double* w1, const double* w2, double dt, 
       acc.substeps = K;
       return ADL_OK;
     }
+    // a learned interval that needs more terms than predicted is suspect:
+    // report it so that the caller falls back to power iteration
+    if (op->learned) return status_to_code(3);
     K *= 2;
   }
   return status_to_code(3);
@@ -711,13 +718,23 @@ int adl_spectral_bound(adl_op* op, int method, int max_iter, double rtol, uint64
     if (c.status == 2) return fail(ADL_ENAN, "non-finite value in power iteration");
     iters = c.iters;
     const double lam = c.lam;
+    op->last_lambda = lam;
     alpha = -std::min(1.1 * lam, std::fabs(ag));
   }
   if (alpha == 0.0 && ag != 0.0) return fail(ADL_EBOUND, "power iteration gave lambda = 0");
   op->alpha = alpha;
   op->has_bound = true;
+  op->learned = false;
   if (alpha_out) *alpha_out = alpha;
   if (iters_out) *iters_out = iters;
+  return ADL_OK;
+}
+
+int adl_last_power_estimate(const adl_op* op, double* lambda) {
+  RETCHK(check_op(op));
+  if (!lambda) return fail(ADL_EINVAL, "null lambda");
+  if (std::isnan(op->last_lambda)) return fail(ADL_EBOUND, "no power iteration has run on this op");
+  *lambda = op->last_lambda;
   return ADL_OK;
 }
 
@@ -731,6 +748,7 @@ int adl_set_bound(adl_op* op, double alpha) {
   }
   op->alpha = alpha;
   op->has_bound = true;
+  op->learned = false;
   return ADL_OK;
 }
 
@@ -824,8 +842,8 @@ int adl_leja_phi(adl_op* op, int l, double dt, const double* v, double* out, dou
   return code;
 }
 
-int adl_exp_midpoint_step(adl_op* op, double* u, const double* S_half, double dt, double tol, adl_stats* stp,
-                          void* stream) {
+static int midpoint_impl(adl_op* op, double* u, const double* S_half, double dt, double tol, adl_stats* stp,
+                         void* stream) {
   RETCHK(check_op(op));
   if (!u) return fail(ADL_EINVAL, "null u");
   RETCHK(check_dt(dt));
@@ -845,8 +863,8 @@ int adl_exp_midpoint_step(adl_op* op, double* u, const double* S_half, double dt
   return code;
 }
 
-int adl_exp_quad2_step(adl_op* op, double* u, const double* S1, const double* S2, double c1, double c2, double dt,
-                       double tol, adl_stats* stp, void* stream) {
+static int quad2_impl(adl_op* op, double* u, const double* S1, const double* S2, double c1, double c2, double dt,
+                      double tol, adl_stats* stp, void* stream) {
   RETCHK(check_op(op));
   if (!u) return fail(ADL_EINVAL, "null u");
   if (!std::isfinite(c1) || !std::isfinite(c2) || c1 == c2) return fail(ADL_EINVAL, "need finite c1 != c2");
@@ -940,6 +958,168 @@ int adl_mlp_adam_step(float* W, const float* dW, float* m1, float* m2, int t, fl
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
     return fail(ADL_EINVAL, "bad Adam hyper-parameters");
   HIPCHK(launch_mlp_adam(W, dW, m1, m2, t, lr, beta1, beta2, eps, S(stream)));
+  return ADL_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// steps with the learned-bound fallback
+// ---------------------------------------------------------------------------
+static int fallback_to_power(adl_op* op, void* stream) {
+  op->learned = false;
+  double a;
+  return adl_spectral_bound(op, ADL_BOUND_POWER, 2000, 1e-3, 0, &a, nullptr, stream);
+}
+
+int adl_exp_midpoint_step(adl_op* op, double* u, const double* S_half, double dt, double tol, adl_stats* stp,
+                          void* stream) {
+  RETCHK(check_op(op));
+  const bool learned = op->learned;
+  int rc = midpoint_impl(op, u, S_half, dt, tol, stp, stream);
+  if (learned && (rc == ADL_ENOCONV || rc == ADL_ENAN)) {
+    adl_stats first{};
+    if (stp) first = *stp;
+    RETCHK(fallback_to_power(op, stream));
+    rc = midpoint_impl(op, u, S_half, dt, tol, stp, stream);
+    if (stp) {
+      stp->matvecs += first.matvecs;
+      stp->sweeps += first.sweeps;
+      stp->fallback = 1;
+    }
+  }
+  return rc;
+}
+
+int adl_exp_quad2_step(adl_op* op, double* u, const double* S1, const double* S2, double c1, double c2, double dt,
+                       double tol, adl_stats* stp, void* stream) {
+  RETCHK(check_op(op));
+  const bool learned = op->learned;
+  int rc = quad2_impl(op, u, S1, S2, c1, c2, dt, tol, stp, stream);
+  if (learned && (rc == ADL_ENOCONV || rc == ADL_ENAN)) {
+    adl_stats first{};
+    if (stp) first = *stp;
+    RETCHK(fallback_to_power(op, stream));
+    rc = quad2_impl(op, u, S1, S2, c1, c2, dt, tol, stp, stream);
+    if (stp) {
+      stp->matvecs += first.matvecs;
+      stp->sweeps += first.sweeps;
+      stp->fallback = 1;
+    }
+  }
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// learned bound: dimensionless inputs and targets of the predictor
+// ---------------------------------------------------------------------------
+// raw statistics (adl_field_stats): log10 kpar_max, log10 kpar_mean,
+// log10 kperp_max, log10 kperp_mean, a_max, a_mean, log10 hx, log10 hy, log10 dt;
+// g = |alpha_G|, the Gershgorin bound, sets the scale of the spectrum and
+// rho_ref = 4 kpar_max (1/hx^2 + 1/hy^2) the diffusive scale.
+static double rho_ref_of(const float* f) {
+  const double kmax = std::pow(10.0, (double)f[0]);
+  const double hx = std::pow(10.0, (double)f[6]), hy = std::pow(10.0, (double)f[7]);
+  return 4.0 * kmax * (1.0 / (hx * hx) + 1.0 / (hy * hy));
+}
+
+int adl_learned_features(const float* f, double g, float* x) {
+  if (!f || !x) return fail(ADL_EINVAL, "null pointer");
+  if (!(g > 0.0) || !std::isfinite(g)) return fail(ADL_EINVAL, "Gershgorin bound must be > 0");
+  const double kmax = std::pow(10.0, (double)f[0]);
+  const double hx = std::pow(10.0, (double)f[6]), hy = std::pow(10.0, (double)f[7]);
+  const double dt = std::pow(10.0, (double)f[8]);
+  const double hmin = std::min(hx, hy);
+  x[0] = (float)(f[1] - f[0]);                                 // mean / max k_par
+  x[1] = (float)(f[2] - f[0]);                                 // max k_perp / max k_par
+  x[2] = (float)(f[3] - f[0]);                                 // mean k_perp / max k_par
+  x[3] = (float)std::log10(1.0 + (double)f[4] * hmin / kmax);  // cell Peclet (max)
+  x[4] = (float)std::log10(1.0 + (double)f[5] * hmin / kmax);  // cell Peclet (mean)
+  x[5] = (float)(f[6] - f[7]);                                 // hx / hy
+  x[6] = (float)(std::log10(g * dt) / 4.0);                    // stiffness of the step
+  x[7] = (float)std::log10(1.0 + (double)f[4] * dt / hmin);    // advective Courant number
+  x[8] = (float)std::log10(g / rho_ref_of(f));                 // Gershgorin / diffusive scale
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(x[i])) return fail(ADL_EINVAL, "non-finite feature");
+  return ADL_OK;
+}
+
+int adl_learned_targets(const float* f, double g, double rho, int degree, int substeps, float* y) {
+  if (!f || !y) return fail(ADL_EINVAL, "null pointer");
+  if (!(rho > 0.0) || !(g > 0.0) || degree < 0 || substeps < 1) return fail(ADL_EINVAL, "bad label");
+  const double dt = std::pow(10.0, (double)f[8]);
+  y[0] = (float)(10.0 * std::log10(rho / g));
+  y[1] = (float)((double)degree / std::sqrt(rho * dt / substeps + 1.0));
+  y[2] = (float)std::log2((double)substeps);
+  return ADL_OK;
+}
+
+int adl_learned_decode(const float* f, double g, const float* y, double* rho, int* degree, int* substeps) {
+  if (!f || !y) return fail(ADL_EINVAL, "null pointer");
+  if (!(g > 0.0)) return fail(ADL_EINVAL, "Gershgorin bound must be > 0");
+  const double dt = std::pow(10.0, (double)f[8]);
+  const double r = g * std::pow(10.0, (double)y[0] / 10.0);
+  int K = (int)std::lround(std::pow(2.0, (double)y[2]));
+  if (K < 1) K = 1;
+  const double m = std::max(1.0, (double)y[1] * std::sqrt(r * dt / K + 1.0));
+  if (rho) *rho = r;
+  if (degree) *degree = (int)std::ceil(m);
+  if (substeps) *substeps = K;
+  return ADL_OK;
+}
+
+int adl_learned_bound(adl_op* op, double dt, const float* W, float* scratch, adl_learned_info* info, void* stream) {
+  RETCHK(check_op(op));
+  if (!W || !scratch) return fail(ADL_EINVAL, "null W or scratch");
+  RETCHK(check_dt(dt));
+  hipStream_t st = S(stream);
+  float* d_feat = scratch;        // 9
+  float* d_x = scratch + 12;      // 9
+  float* d_y = scratch + 24;      // 3
+  RETCHK(adl_field_stats(op, dt, d_feat, stream));
+  float f[9], x[9], y[3];
+  HIPCHK(hipMemcpyAsync(f, d_feat, sizeof f, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double ag = op->gersh;
+  if (std::isnan(ag)) RETCHK(gershgorin(op, st, ag));
+  if (!(ag < 0.0)) return fail(ADL_EBOUND, "zero operator: no learned interval");
+  RETCHK(adl_learned_features(f, -ag, x));
+  HIPCHK(hipMemcpyAsync(d_x, x, sizeof x, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_mlp_forward(W, d_x, d_y, nullptr, 1, st));
+  HIPCHK(hipMemcpyAsync(y, d_y, sizeof y, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double rho;
+  int m, K;
+  RETCHK(adl_learned_decode(f, -ag, y, &rho, &m, &K));
+  const double alpha = -std::min(kLearnedSafety * rho, std::fabs(ag));
+  if (!(alpha < 0.0) || !std::isfinite(alpha)) return fail(ADL_EBOUND, "learned bound unusable");
+  op->alpha = alpha;
+  op->has_bound = true;
+  op->learned = true;
+  op->budget = std::min(op->max_degree, (int)std::ceil(1.5 * m) + 10);
+  op->substeps_hint = K;
+  // seed the plan's predicted degree so the first chunk is sized right
+  const int Kp = std::max(K, substeps_for(alpha, dt, op->rho_max));
+  Plan& P = get_plan(op, 1, alpha, dt / Kp);
+  if (P.last_degree <= 0) P.last_degree = m;
+  if (info) {
+    info->rho_hat = rho;
+    info->alpha = alpha;
+    info->gershgorin = ag;
+    info->degree_hat = m;
+    info->substeps_hat = K;
+    for (int i = 0; i < 9; ++i) {
+      info->feats[i] = f[i];
+      info->x[i] = x[i];
+    }
+    for (int i = 0; i < 3; ++i) info->y[i] = y[i];
+  }
+  return ADL_OK;
+}
+
+int adl_mlp_mse_grad(const float* Y, const float* T, float* dY, float* loss, int B, void* stream) {
+  if (!Y || !T || !dY) return fail(ADL_EINVAL, "null pointer");
+  if (B < 1) return fail(ADL_EINVAL, "B must be >= 1");
+  HIPCHK(launch_mlp_mse_grad(Y, T, dY, loss, B, S(stream)));
   return ADL_OK;
 }
 

@@ -121,6 +121,7 @@ hipError_t launch_mlp_forward(const float* W, const float* X, float* Y, float* c
                               hipStream_t st);
 hipError_t launch_mlp_backward(const float* W, const float* cache, const float* dY, float* dW,
                                int B, hipStream_t st);
+hipError_t launch_mlp_mse_grad(const float* Y, const float* T, float* dY, float* loss, int B, hipStream_t st);
 hipError_t launch_mlp_adam(float* W, const float* dW, float* m1, float* m2, int t, float lr,
                            float b1, float b2, float eps, hipStream_t st);
 

@@ -159,6 +159,28 @@ __global__ __launch_bounds__(kBwdThreads) void mlp_backward_kernel(const float* 
   }
 }
 
+// Mean squared error L = mean((Y - T)^2) over B x 3 and dL/dY = 2 (Y - T) / (3 B);
+// one block, fixed-order sum.
+__global__ __launch_bounds__(256) void mlp_mse_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                                           float* __restrict__ dY, float* __restrict__ loss, int B) {
+  __shared__ float sh[256];
+  const int n = B * kOut;
+  const float sc = 2.0f / (float)n;
+  float acc = 0.0f;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const float d = Y[i] - T[i];
+    dY[i] = sc * d;
+    acc += d * d;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) loss[0] = sh[0] / (float)n;
+}
+
 // Adam (Kingma & Ba 2015): bias corrections bc1 = 1 - b1^t, bc2 = 1 - b2^t.
 __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ W, const float* __restrict__ dW,
                                                        float* __restrict__ m1, float* __restrict__ m2, float lr,
@@ -250,6 +272,11 @@ hipError_t launch_mlp_forward(const float* W, const float* X, float* Y, float* c
 
 hipError_t launch_mlp_backward(const float* W, const float* cache, const float* dY, float* dW, int B, hipStream_t st) {
   hipLaunchKernelGGL(mlp_backward_kernel, dim3(1), dim3(kBwdThreads), 0, st, W, cache, dY, dW, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_mse_grad(const float* Y, const float* T, float* dY, float* loss, int B, hipStream_t st) {
+  hipLaunchKernelGGL(mlp_mse_grad_kernel, dim3(1), dim3(256), 0, st, Y, T, dY, loss, B);
   return hipGetLastError();
 }
 

@@ -54,6 +54,12 @@ struct adl_op {
   int quad2_mode = ADL_QUAD2_AUGMENTED;
   bool has_bound = false;
   double alpha = 0.0;
+  // learned bound: the interval came from the predictor; sweeps are capped at
+  // `budget` terms and a failure falls back to power iteration
+  double last_lambda = NAN;  // last power-iteration estimate of the spectral radius
+  bool learned = false;
+  int budget = 0;
+  int substeps_hint = 0;
   double gersh = NAN;  // cached Gershgorin bound
   // workspace slices
   void* ybuf[2] = {nullptr, nullptr};

@@ -1,0 +1,138 @@
+"""GPU checks of the learned-bound kernels against the FP64 oracle, and the
+gain of the trained predictor over the method without it."""
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bounds, features, integrators, mlp
+from oracle import operator as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2307_12276_amd as A  # noqa: E402
+from gpu_util import rel, to_dev, to_np, workload_pair  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+@pytest.mark.parametrize("B", [1, 7, 64, 257])
+def test_mlp_forward_backward_against_oracle(B):
+    Wh = mlp.init_params(5).astype(np.float32)
+    X = np.random.default_rng(B).standard_normal((B, 9)).astype(np.float32)
+    T = np.random.default_rng(B + 1).standard_normal((B, 3)).astype(np.float32)
+    Wd, Xd, Td = f32(Wh), f32(X), f32(T)
+    Y = torch.empty((B, 3), dtype=torch.float32, device=DEV)
+    cache = torch.empty((B, A.MLP_CACHE_PER_ROW), dtype=torch.float32, device=DEV)
+    A.mlp_forward(Wd, Xd, Y, cache)
+    Yo, co = mlp.forward(Wh.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(Y.cpu().numpy() - Yo)) <= 1e-5 * max(1.0, np.max(np.abs(Yo)))
+    assert np.allclose(cache.cpu().numpy(), np.concatenate(co, axis=1), atol=2e-6)
+    dY = torch.empty_like(Y)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    A.mlp_mse_grad(Y, Td, dY, loss)
+    Lo, dYo = mlp.mse_loss(Yo, T.astype(np.float64))
+    assert float(loss.item()) == pytest.approx(Lo, rel=1e-5)
+    assert np.allclose(dY.cpu().numpy(), dYo, rtol=1e-4, atol=1e-7)
+    dW = torch.empty_like(Wd)
+    A.mlp_backward(Wd, cache, dY, dW)
+    go = mlp.backward(Wh.astype(np.float64), co, dYo)
+    g = dW.cpu().numpy()
+    assert np.max(np.abs(g - go)) <= 1e-4 * np.max(np.abs(go))
+
+
+def test_adam_against_oracle():
+    rng = np.random.default_rng(3)
+    Wh = rng.standard_normal(9155).astype(np.float32)
+    m1 = np.zeros(9155, np.float32)
+    m2 = np.zeros(9155, np.float32)
+    Wd, m1d, m2d = f32(Wh), f32(m1), f32(m2)
+    Wo, m1o, m2o = Wh.astype(np.float64), m1.astype(np.float64), m2.astype(np.float64)
+    for t in range(1, 6):
+        g = rng.standard_normal(9155).astype(np.float32)
+        A.mlp_adam_step(Wd, f32(g), m1d, m2d, t, 1e-2)
+        Wo, m1o, m2o = mlp.adam_step(Wo, g.astype(np.float64), m1o, m2o, t, 1e-2)
+    assert np.max(np.abs(Wd.cpu().numpy() - Wo)) < 1e-5
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_field_stats_against_oracle(storage):
+    w = W.c3_stream_function(n=200, storage=storage)
+    oop, gop = workload_pair(w)
+    feats = torch.empty(9, dtype=torch.float32, device=DEV)
+    gop.field_stats(w.dt, feats)
+    Dxx, Dxy, Dyy = w.Dxx, w.Dxy, w.Dyy
+    if storage:
+        r = lambda a: a.astype(np.float32).astype(np.float64)
+        Dxx, Dxy, Dyy = oop.Dxx, oop.Dxy, oop.Dyy  # the FP32-rounded fields the GPU op holds
+    ref = features.field_features(Dxx, Dxy, Dyy, w.ax_c, w.ay_c, w.hx, w.hy, w.dt)
+    got = feats.cpu().numpy().astype(np.float64)
+    assert np.allclose(got, ref, rtol=2e-6, atol=2e-6), (got, ref)
+
+
+def test_learned_training_decreases_loss():
+    """A few hundred Adam steps of the library's kernels on synthetic
+    targets reduce the loss (training machinery works end to end)."""
+    from paper_2307_12276_amd import learned
+    rng = np.random.default_rng(0)
+    X = rng.uniform(-1, 1, (1024, 9)).astype(np.float32)
+    Y = np.stack([np.sin(X[:, 0]) + 0.5 * X[:, 6], X[:, 1] * X[:, 2], np.tanh(X[:, 3])], 1).astype(np.float32)
+    Wt, hist = learned.train(X, Y, epochs=40, batch=128, lr=3e-3, log=lambda *a: None)
+    assert hist[-1] < 0.2 * hist[0]
+
+
+WEIGHTS = os.path.join(os.path.dirname(A.__file__), "learned_bound_weights.f32")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_learned_bound_gain_and_accuracy():
+    """Held-out field (seed outside the training range, 1024^2, FP32 fields):
+    the learned interval replaces power iteration.  The predicted spectral
+    radius is within 25% of the power estimate, the step result matches the
+    power-bound step to ~tol, and the bound costs far fewer matrix
+    applications (and less time) than power iteration."""
+    from paper_2307_12276_amd import learned
+    d = W.learned_sample(99_999, sizes=(1024,))
+    dev = DEV
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Wd = f32(learned.load())
+    scratch = torch.empty(64, dtype=torch.float32, device=dev)
+    mk = lambda: A.Op(t(d["Dxx"]), t(d["Dxy"]), t(d["Dyy"]), d["hx"], d["hy"], d["bc"], A.STORAGE_FP32_FIELDS,
+                      ax_c=d["ax_c"], ay_c=d["ay_c"])
+    opL, opP = mk(), mk()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = opL.learned_bound(d["dt"], Wd, scratch)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    aP, its = opP.spectral_bound(A.BOUND_POWER, max_iter=1000, rtol=1e-6, seed=1)
+    torch.cuda.synchronize()
+    t_power = time.perf_counter() - t0
+    lam = opP.last_power_estimate()
+    assert abs(info["rho_hat"] / lam - 1) < 0.25, (info, lam)
+    u0 = np.random.default_rng(1).standard_normal((d["ny"], d["nx"]))
+    opR = mk()
+    opR.set_bound(aP)
+    uL, uP, uR = t(u0), t(u0), t(u0)
+    sL = opL.midpoint_step(uL, None, d["dt"], 1e-9)
+    sP = opP.midpoint_step(uP, None, d["dt"], 1e-9)
+    opR.midpoint_step(uR, None, d["dt"], 1e-13)
+    eL, eP = rel(to_np(uL), to_np(uR)), rel(to_np(uP), to_np(uR))
+    assert eL < 1e-8 and eP < 1e-8, (eL, eP)
+    # gain: the bound itself (power iteration = its matrix applications)
+    assert its > 20 and t_learned < t_power
+    print("learned bound %.2f ms vs power iteration %.2f ms (%d matvecs); step matvecs %d vs %d; "
+          "errors %.2e vs %.2e; fallback %d"
+          % (1e3 * t_learned, 1e3 * t_power, its, sL["matvecs"], sP["matvecs"], eL, eP, sL["fallback"]))
