@@ -16,7 +16,7 @@
 // a hipGraph and replayed: one graph launch per step.  Kernel boundaries give
 // cross-XCD visibility of y_k, so no tile ever waits on another within a
 // kernel and no agent-scope fence is needed.
-#include "march.h"
+#include "tile.h"
 #include "op.h"
 
 #include <hip/hip_runtime.h>
@@ -124,23 +124,22 @@ struct StageEp {
   int nx;
   double* __restrict__ out;
   const double* __restrict__ s;
-  template <bool CHECK>
+  __device__ __forceinline__ bool go() const { return true; }
   __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
-  template <bool CHECK>
   __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&)[VEC],
                                          const Extra&) {
-    if (CHECK && !g.inside) return;
-    const long off = (long)j * nx + g.col0;
+    if (!g.inside) return;
+    const long ro = (long)j * nx;
     double r[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) r[v] = Ax[v];
     if (s) {
       double q[VEC];
-      load_c<double, VEC>(s, off, q);
+      ldr<double, VEC>(s + ro, g.col0, q);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) r[v] += q[v];
     }
-    store_c<double, VEC>(out, off, r);
+    str<double, VEC>(out + ro, g.col0, r);
   }
 };
 
@@ -154,16 +153,15 @@ struct BatchLejaEp {
   double* __restrict__ p;
   double shift, invg, d0, dk1;
   double acc[3];
-  template <bool CHECK>
+  __device__ __forceinline__ bool go() const { return true; }
   __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
-    if (CHECK && !g.inside) return;
-    if constexpr (!FIRST) load_c<double, VEC>(p, (long)j * nx + g.col0, e.p);
+    if (!g.inside) return;
+    if constexpr (!FIRST) ldr<double, VEC>(p + (long)j * nx, g.col0, e.p);
   }
-  template <bool CHECK>
   __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&yc)[VEC],
                                          const Extra& e) {
-    if (CHECK && !g.inside) return;
-    const long off = (long)j * nx + g.col0;
+    if (!g.inside) return;
+    const long ro = (long)j * nx;
     double yn[VEC], pn[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -176,8 +174,8 @@ struct BatchLejaEp {
       acc[1] += pv * pv;
       if constexpr (FIRST) acc[2] = nanmax(acc[2], fabs(yc[v]));
     }
-    store_c<double, VEC>(yout, off, yn);
-    store_c<double, VEC>(p, off, pn);
+    str<double, VEC>(yout + ro, g.col0, yn);
+    str<double, VEC>(p + ro, g.col0, pn);
   }
 };
 
@@ -194,7 +192,7 @@ __global__ __launch_bounds__(64) void batch_stage_kernel(BatchArgs A) {
   ep.nx = B.f.nx;
   ep.out = B.w;
   ep.s = B.S;
-  march_tile<TF, double, VEC, ADVF>(B.f, B.u, ep, cb, j0, j1, 1, 0);
+  stencil_tile<TF, double, VEC, ADVF>(B.f, B.u, ep, cb, j0, j1);
 }
 
 template <typename TF, int VEC, bool ADVF, bool FIRST>
@@ -212,7 +210,7 @@ __device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B,
   ep.dk1 = B.d[k + 1];
   ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
   const double* yin = FIRST ? B.w : reinterpret_cast<const double*>((k & 1) ? B.y1 : B.y0);
-  march_tile<TF, double, VEC, ADVF>(B.f, yin, ep, cb, j0, j1, 1, 0);
+  stencil_tile<TF, double, VEC, ADVF>(B.f, yin, ep, cb, j0, j1);
   wave_sum3(ep.acc);
   if ((threadIdx.x & 63) == 0) {
     double* part = A.partials + ((long)(k & 1) * A.total_tiles + B.tile_base + t) * 3;
@@ -268,13 +266,13 @@ __global__ __launch_bounds__(64) void batch_update_kernel(BatchArgs A, double* c
   if (col0 >= B.f.nx) return;
   double* ub = u[b];
   for (int j = j0; j < j1; ++j) {
-    const long off = (long)j * B.f.nx + col0;
+    const long ro = (long)j * B.f.nx;
     double uu[VEC], pp[VEC];
-    load_c<double, VEC>(ub, off, uu);
-    load_c<double, VEC>(B.p, off, pp);
+    ldr<double, VEC>(ub + ro, col0, uu);
+    ldr<double, VEC>(B.p + ro, col0, pp);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) uu[v] = uu[v] + B.dt * pp[v];
-    store_c<double, VEC>(ub, off, uu);
+    str<double, VEC>(ub + ro, col0, uu);
   }
 }
 

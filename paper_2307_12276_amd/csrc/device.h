@@ -53,6 +53,31 @@ __device__ __forceinline__ void store_c(T* __restrict__ a, long off, const doubl
   }
 }
 
+// Element addressing as (row start, column): the row start is wave-uniform
+// (kept in SGPRs), the column part a 32-bit byte offset, which is the
+// global load/store form with a scalar base and a 32-bit vector offset; no
+// 64-bit address is held in VGPRs.
+template <typename T>
+__device__ __forceinline__ const T* at_col(const T* rowp, int col) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(rowp) + (unsigned)(col * (int)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T* at_col(T* rowp, int col) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(rowp) + (unsigned)(col * (int)sizeof(T)));
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void ldr(const T* rowp, int col, double (&c)[VEC]) {
+  load_c<T, VEC>(at_col(rowp, col), 0, c);
+}
+template <typename T>
+__device__ __forceinline__ double ld1(const T* rowp, int col) {
+  return (double)*at_col(rowp, col);
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void str(T* rowp, int col, const double (&c)[VEC]) {
+  store_c<T, VEC>(at_col(rowp, col), 0, c);
+}
+
 // Row index after the boundary rule; zero = the whole row is a zero ghost row.
 __device__ __forceinline__ int map_row(int r, int ny, int bc, int mode, bool& zero) {
   zero = false;

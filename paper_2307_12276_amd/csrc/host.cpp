@@ -185,15 +185,15 @@ using namespace adl;
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-  size_t kxx, kxy, kyy, ax, ay, y0, y1, p, w1, w2, yacc, tmp, tmp2, partials, ctl, total;
+  size_t kxx, kxy, kyy, ax, ay, y0, y1, p, p2, w1, w2, yacc, tmp, tmp2, partials, ctl, total;
 };
 
 static size_t max_partial_blocks(int nx, int ny) {
-  // upper bound over tilings with rows >= 1 and vec >= 1
-  const long ncb = (nx + kBlock - 1) / kBlock;
-  long nb = ncb * ny;
-  if (nb < 4096) nb = 4096;  // elementwise reductions use <= 1024 blocks
-  return (size_t)nb;
+  // stencil launches: <= min(tiles, kMaxGrid) blocks, the most tiles with one
+  // column per lane and one row per wave; elementwise reductions <= 1024
+  const size_t tiles = (size_t)((nx + kWave - 1) / kWave) * (size_t)((ny + kWavesY - 1) / kWavesY);
+  size_t nb = tiles < (size_t)kMaxGrid ? tiles : (size_t)kMaxGrid;
+  return nb > 4096 ? nb : 4096;
 }
 
 static WsLayout ws_layout(int nx, int ny, int storage) {
@@ -220,6 +220,7 @@ static WsLayout ws_layout(int nx, int ny, int storage) {
   L.yacc = take(n * 8);
   L.tmp = take(n * 8);
   L.tmp2 = take(n * 8);
+  L.p2 = take(n * 8);
   L.partials = take(6 * max_partial_blocks(nx, ny) * 8);
   L.ctl = take(4 * 128);
   L.total = o;
@@ -277,18 +278,28 @@ static double leja_bytes(const adl_op* op, int k, bool with_w2) {
 
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
-// Launch k computes term k+1 and, at its start, takes the stopping decision
-// of term k from the block partials of launch k-1; a one-block launch at the
-// end of every chunk takes the decision of the chunk's last term.
+// Launch k computes term k+1 into one of two p buffers (p_out and the
+// workspace buffer p2, alternating) while an extra block of the same launch
+// takes the stopping decision of term k from the block partials of launch
+// k-1; a one-block launch at the end of every chunk takes the decision of the
+// chunk's last term.  The buffers are assigned so that the predicted degree
+// ends in p_out; otherwise the result is copied there.
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
                  double tol, int maxdeg, hipStream_t st, SweepOut& out) {
   if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;
   HIPCHK(launch_ctl_reset(op->ctl, 1, st));
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
   const Tiling& T = tiling_for(op, v, p_out);
-  int predicted = P.last_degree > 0 ? P.last_degree + 1
+  // launches of the first chunk = the predicted degree: with a right guess the
+  // chunk's closing decision launch finds the sweep converged and no term is wasted
+  int predicted = P.last_degree > 0 ? P.last_degree
                                     : (int)(5.0 * std::sqrt(std::fabs(P.alpha) * P.h) + 8.0);
   if (predicted > maxdeg) predicted = maxdeg;
+  if (predicted < 1) predicted = 1;
+  // p_m (degree m) is written by launch m-1 into pbuf[m & 1]
+  double* pbuf[2];
+  pbuf[predicted & 1] = p_out;
+  pbuf[(predicted + 1) & 1] = op->p2;
   int launched = 0;
   LejaArgs a{};
   a.invg = P.invg;
@@ -315,7 +326,8 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.ev_stop = op->prof ? op->evs[2 * i + 1] : nullptr;
       a.yin = k == 0 ? (const void*)v : op->ybuf[k & 1];
       a.yout = op->ybuf[(k + 1) & 1];
-      a.p = p_out;
+      a.pin = k == 0 ? nullptr : pbuf[k & 1];
+      a.p = pbuf[(k + 1) & 1];
       a.w2 = (w2 && P.s[k] != 0.0) ? w2 : nullptr;
       a.w2c = P.s[k] * w2scale;
       a.shift = P.shift[k];
@@ -331,14 +343,17 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     a.ev_start = a.ev_stop = nullptr;
     a.k = launched;
     a.first = 0;
+    a.w2 = nullptr;
+    a.yin_f32 = ys32;
     a.decide_only = 1;
     HIPCHK(launch_leja_step(op->f, T, a, st));
     RETCHK(read_ctl(op, st));
     if (op->prof) {
-      // launches past the stopping index returned at once: time only the productive ones
+      // launches past the stopping index skipped their work: time the others
+      // (up to and including the one that ran while term m was being decided)
       const int first_k = launched - chunk;
-      const int productive = op->host_ctl->stop ? std::max(op->host_ctl->degree, 1) - first_k : chunk;
-      for (int i = 0; i < chunk && i < productive; ++i) {
+      const int worked = op->host_ctl->stop ? op->host_ctl->degree + 1 - first_k : chunk;
+      for (int i = 0; i < chunk && i < worked; ++i) {
         float ms = 0.0f;
         HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * i], op->evs[2 * i + 1]));
         op->prof_ms += ms;
@@ -350,7 +365,12 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   }
   out.degree = op->host_ctl->degree;
   out.status = op->host_ctl->stop ? op->host_ctl->status : 3;
-  if (out.status == 1) P.last_degree = out.degree;
+  if (out.status == 1) {
+    P.last_degree = out.degree;
+    if (out.degree == 0) HIPCHK(launch_fill(op->n, p_out, 0.0, st));
+    else if (pbuf[out.degree & 1] != p_out)
+      HIPCHK(launch_axpby(op->n, p_out, 1.0, pbuf[out.degree & 1], 0.0, nullptr, st));
+  }
   return ADL_OK;
 }
 
@@ -544,12 +564,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->f.bc = bc;
   op->f.f32 = f32;
   op->t = make_tiling(nx, ny, 0);
-  op->t1 = op->t;
-  if (op->t.vec == 2) {
-    op->t1.vec = 1;
-    op->t1.ncb = (nx + kBlock - 1) / kBlock;
-    op->t1.nblocks = op->t1.ncb * op->t1.nrb;
-  }
+  op->t1 = make_tiling(nx, ny, 0, 1);
   op->ybuf[0] = base + L.y0;
   op->ybuf[1] = base + L.y1;
   op->p = reinterpret_cast<double*>(base + L.p);
@@ -558,6 +573,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->yacc = reinterpret_cast<double*>(base + L.yacc);
   op->tmp = reinterpret_cast<double*>(base + L.tmp);
   op->tmp2 = reinterpret_cast<double*>(base + L.tmp2);
+  op->p2 = reinterpret_cast<double*>(base + L.p2);
   op->partials = reinterpret_cast<double*>(base + L.partials);
   op->ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&op->host_ctl), 4 * sizeof(Ctl), hipHostMallocDefault);
@@ -633,20 +649,10 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
   RETCHK(check_op(op));
   if (rows < 0 || rows > op->ny) return fail(ADL_EINVAL, "rows must be in [0, ny]");
   if (cols_per_lane < 0 || cols_per_lane > 2) return fail(ADL_EINVAL, "cols_per_lane must be 0, 1 or 2");
-  Tiling t = make_tiling(op->nx, op->ny, rows);
+  const Tiling t = make_tiling(op->nx, op->ny, rows, cols_per_lane);
   if (cols_per_lane == 2 && t.vec != 2) return fail(ADL_EINVAL, "two columns per lane need an even nx >= 128");
-  if (cols_per_lane == 1) {
-    t.vec = 1;
-    t.ncb = (op->nx + kBlock - 1) / kBlock;
-    t.nblocks = t.ncb * t.nrb;
-  }
   op->t = t;
-  op->t1 = t;
-  if (t.vec == 2) {
-    op->t1.vec = 1;
-    op->t1.ncb = (op->nx + kBlock - 1) / kBlock;
-    op->t1.nblocks = op->t1.ncb * op->t1.nrb;
-  }
+  op->t1 = make_tiling(op->nx, op->ny, rows, 1);
   return ADL_OK;
 }
 

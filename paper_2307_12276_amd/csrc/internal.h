@@ -10,8 +10,12 @@
 namespace adl {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;             // 4 waves, side by side in x
-constexpr int kWavesX = kBlock / kWave;
+constexpr int kBlock = 256;             // 4 waves, stacked in y (one strip, 4 row bands)
+constexpr int kWavesY = kBlock / kWave;
+#ifndef ADL_MAX_GRID
+#define ADL_MAX_GRID 16384
+#endif
+constexpr int kMaxGrid = ADL_MAX_GRID;  // blocks of a stencil launch (grid-stride over tiles)
 
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
 
@@ -45,15 +49,20 @@ struct FieldView {
   int f32;          // fields stored as float
 };
 
-// Tiling of one grid for the row-marching stencil kernels.
+// Tiling of one grid for the stencil kernels.  A tile = one strip of
+// 64*vec columns x kWavesY*rows rows, one block's unit of work; wave w of the
+// block computes rows [w*rows, (w+1)*rows) of the tile.  Blocks loop over the
+// tiles with a grid stride.
 struct Tiling {
   int vec;      // columns per lane (1 or 2; 2 needs even nx)
-  int rows;     // rows per block
-  int ncb, nrb; // column / row blocks
-  int nblocks;
+  int rows;     // rows per wave and tile
+  int ncb, nrb; // strips / row bands
+  int ntiles;   // ncb * nrb
+  int nblocks;  // grid size: min(ntiles, kMaxGrid)
 };
 
-Tiling make_tiling(int nx, int ny, int rows_hint);
+// rows_hint <= 0: default rows; vec_hint 0: widest usable, 1 or 2: forced
+Tiling make_tiling(int nx, int ny, int rows_hint, int vec_hint = 0);
 
 // ---- launches (stencil.hip) ----------------------------------------------
 // y = A x + a1 s1 + a2 s2   (s1 / s2 may be null)
@@ -64,7 +73,8 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
 struct LejaArgs {
   const void* yin;   // y_k (double at k = 0, else the y storage type)
   void* yout;        // y_{k+1}
-  double* p;         // Newton polynomial (FP64)
+  const double* pin; // p_k (k >= 1; FP64)
+  double* p;         // p_{k+1} (FP64; a different buffer from pin)
   const double* w2;  // augmented column (k with s_k != 0 only), or null
   double w2c;        // s_k / h
   double shift;      // c + gamma xi_k

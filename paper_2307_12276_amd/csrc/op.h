@@ -69,6 +69,7 @@ struct adl_op {
   double* yacc = nullptr;
   double* tmp = nullptr;
   double* tmp2 = nullptr;
+  double* p2 = nullptr;     // second Newton polynomial buffer (sweeps alternate)
   double* partials = nullptr;
   Ctl* ctl = nullptr;
   Ctl* host_ctl = nullptr;  // pinned

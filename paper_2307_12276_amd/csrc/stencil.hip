@@ -1,4 +1,5 @@
-// Row-marching nine-point stencil kernels for gfx950.
+// Nine-point stencil kernels for gfx950: operator application, the fused
+// Newton-Leja term, power iteration, Gershgorin bound, elementwise helpers.
 //
 // The operator is A = div(D grad .) + div(a .) (Sec. 1 eq. 2, Sec. 2), in the
 // conservative central nine-point form
@@ -9,22 +10,20 @@
 // with face coefficients kf_E = (kxx_C + kxx_E)/2 etc. and pre-scaled
 // coefficient fields (kxx = Dxx/hx^2, kxy = Dxy/(4 hx hy), ax' = ax/(2 hx)).
 //
-// Layout and mapping.  Arrays are [ny][nx], x contiguous.  A block of four
-// wave64s covers 4 * 64 * VEC adjacent columns and a band of `rows` rows;
-// each lane owns VEC adjacent columns and marches down the band keeping the
-// three rows j-1, j, j+1 of every input in registers, so each element is read
-// from HBM once per sweep (plus one halo row per band edge).  x-neighbours come
-// from the adjacent lane by cross-lane shuffle; only the strip-edge lanes load
-// a halo element.  Loads of row j+2 are issued before row j is computed.
-// Block ids are remapped so that each XCD (blocks are dealt round-robin to the
-// 8 XCDs) works on a contiguous range of tiles, keeping band-edge halo rows in
-// that XCD's L2.
+// Layout and mapping.  Arrays are [ny][nx], x contiguous.  A tile is one strip
+// of 64 * VEC columns by 4 * rows rows; the four waves of a block take the
+// four row bands of a tile (stacked in y, so the rows they share are L1 hits),
+// each wave computing its rows in load groups of two (tile.h).  Blocks walk
+// the tiles in row-major order with a grid stride; with 32 strips per row
+// band (4096 columns) the tile below a tile runs on the same XCD, whose L2
+// serves the shared rows.
 //
 // Reductions (norms for the Leja stopping test, power iteration) are fixed
 // order: shuffle tree per wave, waves in order, block partials written to
-// memory, and the last block to arrive (ticket counter) sums the partials in a
-// fixed order.  Results are bitwise reproducible for a given tiling.
-#include "march.h"
+// memory.  The next launch's blocks each sum the partials in the same fixed
+// order before doing any work (no agent-scope fence; a kernel boundary makes
+// the partials visible).  Results are bitwise reproducible for a given tiling.
+#include "tile.h"
 
 #include <hip/hip_ext.h>
 
@@ -79,23 +78,27 @@ __device__ __forceinline__ void partial_totals(const double* __restrict__ part, 
   block_allreduce<NA, NS>(tot);
 }
 
-// block partial of this launch -> part[k * nb + blockIdx.x]
+// block partial of this launch -> part[k * nb + b]
 template <int NA, int NS>
-__device__ __forceinline__ void write_partials(double (&acc)[NA], double* __restrict__ part) {
+__device__ __forceinline__ void write_partials(double (&acc)[NA], double* __restrict__ part, int nb, int b) {
   block_allreduce<NA, NS>(acc);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NA; ++k) part[(long)k * gridDim.x + blockIdx.x] = acc[k];
+    for (int k = 0; k < NA; ++k) part[(long)k * nb + b] = acc[k];
   }
 }
 
+// Tiles b, b + T.nblocks, ... for worker block b.
 template <typename TF, typename TX, int VEC, bool ADVF, class Ep>
-__device__ __forceinline__ void march_block(const FieldView& F, const Tiling& T, const TX* __restrict__ x, Ep& ep) {
-  const int b = remap_xcd(blockIdx.x, gridDim.x);
-  const int rb = b / T.ncb, cb = b - rb * T.ncb;
-  const int j0 = rb * T.rows;
-  const int j1 = min(j0 + T.rows, F.ny);
-  march_tile<TF, TX, VEC, ADVF>(F, x, ep, cb, j0, j1, kWavesX, threadIdx.x >> 6);
+__device__ __forceinline__ void stencil_block(const FieldView& F, const Tiling& T, const TX* __restrict__ x,
+                                              Ep& ep, int b) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform rows
+#pragma unroll 1
+  for (int t = b; t < T.ntiles; t += T.nblocks) {
+    const int rb = t / T.ncb, cb = t - rb * T.ncb;
+    const int j0 = (rb * kWavesY + wave) * T.rows;
+    if (j0 < F.ny && !stencil_tile<TF, TX, VEC, ADVF>(F, x, ep, cb, j0, min(j0 + T.rows, F.ny))) break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -104,42 +107,41 @@ __device__ __forceinline__ void march_block(const FieldView& F, const Tiling& T,
 // out = A x + a1 s1 + a2 s2
 template <int VEC>
 struct ApplyEp {
-  struct Extra {};
+  struct Extra {
+    double s1[VEC];
+    double s2[VEC];
+  };
   int nx;
   double* __restrict__ out;
   const double* __restrict__ s1;
   const double* __restrict__ s2;
   double a1, a2;
-  template <bool CHECK>
-  __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
-  template <bool CHECK>
+  __device__ __forceinline__ bool go() const { return true; }
+  __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
+    if (!g.inside) return;
+    const long ro = (long)j * nx;
+    if (s1) ldr<double, VEC>(s1 + ro, g.col0, e.s1);
+    if (s2) ldr<double, VEC>(s2 + ro, g.col0, e.s2);
+  }
   __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&)[VEC],
-                                         const Extra&) {
-    if (CHECK && !g.inside) return;
-    const long off = (long)j * nx + g.col0;
+                                         const Extra& e) {
+    if (!g.inside) return;
+    const long ro = (long)j * nx;
     double r[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) r[v] = Ax[v];
-    if (s1) {
-      double s[VEC];
-      load_c<double, VEC>(s1, off, s);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) r[v] += a1 * s[v];
+    for (int v = 0; v < VEC; ++v) {
+      r[v] = Ax[v];
+      if (s1) r[v] += a1 * e.s1[v];
+      if (s2) r[v] += a2 * e.s2[v];
     }
-    if (s2) {
-      double s[VEC];
-      load_c<double, VEC>(s2, off, s);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) r[v] += a2 * s[v];
-    }
-    store_c<double, VEC>(out, off, r);
+    str<double, VEC>(out + ro, g.col0, r);
   }
 };
 
 template <typename TF, int VEC, bool ADVF>
 __global__ __launch_bounds__(kBlock) void apply_kernel(FieldView F, Tiling T, const double* __restrict__ x,
                                                        ApplyEp<VEC> ep) {
-  march_block<TF, double, VEC, ADVF>(F, T, x, ep);
+  stencil_block<TF, double, VEC, ADVF>(F, T, x, ep, blockIdx.x);
 }
 
 // One Newton-Leja term (fused): y' = (A y + w2c w2 - shift y) invg,
@@ -152,25 +154,25 @@ struct LejaEp {
   };
   int nx;
   TYO* __restrict__ yout;
-  double* __restrict__ p;
-  const double* __restrict__ w2;  // only on the first term
+  const double* __restrict__ pin;  // p_k (not on the first term)
+  double* __restrict__ p;          // p_{k+1}
+  const double* __restrict__ w2;   // only on the first term
   double w2c, shift, invg, d0, dk1;
   double acc[3];  // ||d y'||^2, ||p'||^2, max(|y0|, |w2|)
-  template <bool CHECK>
+  __device__ __forceinline__ bool go() const { return true; }
   __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
-    if (CHECK && !g.inside) return;
-    const long off = (long)j * nx + g.col0;
+    if (!g.inside) return;
+    const long ro = (long)j * nx;
     if constexpr (FIRST) {
-      if (w2) load_c<double, VEC>(w2, off, e.w);
+      if (w2) ldr<double, VEC>(w2 + ro, g.col0, e.w);
     } else {
-      load_c<double, VEC>(p, off, e.p);
+      ldr<double, VEC>(pin + ro, g.col0, e.p);
     }
   }
-  template <bool CHECK>
   __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&yc)[VEC],
                                          const Extra& e) {
-    if (CHECK && !g.inside) return;
-    const long off = (long)j * nx + g.col0;
+    if (!g.inside) return;
+    const long ro = (long)j * nx;
     double yn[VEC], pn[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -190,13 +192,13 @@ struct LejaEp {
         if (w2) acc[2] = nanmax(acc[2], fabs(e.w[v]));
       }
     }
-    store_c<TYO, VEC>(yout, off, yn);
-    store_c<double, VEC>(p, off, pn);
+    str<TYO, VEC>(yout + ro, g.col0, yn);
+    str<double, VEC>(p + ro, g.col0, pn);
   }
 };
 
-// Stopping test of term kprev+1 from the partials of launch kprev (every block
-// computes the same fixed-order totals, block 0 records the decision).
+// Stopping test of term kprev+1 from the partials of launch kprev, taken by
+// one block (fixed-order totals) and recorded in the control block.
 // Returns true when the sweep is over.
 __device__ __forceinline__ bool leja_decide(const LejaArgs& A, int kprev) {
   double tot[3];
@@ -213,7 +215,7 @@ __device__ __forceinline__ bool leja_decide(const LejaArgs& A, int kprev) {
   } else if (deg >= A.max_degree) {
     stop = 1; status = 3;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (threadIdx.x == 0) {
     Ctl* c = A.ctl;
     c->tn2 = tn2;
     c->pn2 = pn2;
@@ -225,7 +227,7 @@ __device__ __forceinline__ bool leja_decide(const LejaArgs& A, int kprev) {
 }
 
 // The sweep's stop flag, read once per block (thread 0) and broadcast, so that
-// a concurrent update by block 0 of the same launch cannot split a block.
+// a concurrent update of the flag cannot split a block.
 __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
   __shared__ int s_stop;
   if (threadIdx.x == 0) s_stop = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -233,46 +235,52 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
   return s_stop != 0;
 }
 
-template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF>
+// The sweep's stop flag as one wave sees it (no barrier).
+__device__ __forceinline__ bool wave_stopped(const Ctl* ctl) {
+  const int s = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_amdgcn_readfirstlane(s) != 0;
+}
+
+// One Newton-Leja term, launch k: y_{k+1} from y_k, p_{k+1} = p_k + d_{k+1} y_{k+1}
+// into the other p buffer, block partials of the norms.
+//
+// The stopping decision lags one launch behind the work: an extra block
+// (block 0, dispatched first) takes the decision of term k from the partials
+// of launch k-1 and records it, while the worker blocks 1 .. nblocks compute
+// term k+1 without waiting for it.  A worker wave only checks the stop flag,
+// which launches before this one have set.  If term k turns out to be the
+// last, the term computed by this launch is discarded: p_k is still intact in the other p
+// buffer, and every later launch sees the flag and skips its work.  No store
+// of a worker depends on a reduction, so the launch starts loading at once.
+// Waves that skip their work still join the partial-sum barriers, and a wave
+// that sees the flag set while its block's other waves did not only leaves
+// its part of a discarded term unwritten.
+//
+// The first term of a sweep (y_0 = v in FP64, the augmented column w2, the
+// zero-vector check) is a kernel of its own, so that the other terms'
+// register allocation does not carry its extra state.
+template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
 __global__ __launch_bounds__(kBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
-  if (block_stopped(A.ctl)) return;
-  if (A.k > 0 && leja_decide(A, A.k - 1)) return;
-  if (A.decide_only) return;
-  double acc[3];
-  if (A.first) {
-    LejaEp<TYO, VEC, true> ep;
-    ep.nx = F.nx;
-    ep.yout = reinterpret_cast<TYO*>(A.yout);
-    ep.p = A.p;
-    ep.w2 = A.w2;
-    ep.w2c = A.w2c;
-    ep.shift = A.shift;
-    ep.invg = A.invg;
-    ep.d0 = A.d0;
-    ep.dk1 = A.dk1;
-    ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
-    march_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep);
-    acc[0] = ep.acc[0];
-    acc[1] = ep.acc[1];
-    acc[2] = ep.acc[2];
-  } else {
-    LejaEp<TYO, VEC, false> ep;
-    ep.nx = F.nx;
-    ep.yout = reinterpret_cast<TYO*>(A.yout);
-    ep.p = A.p;
-    ep.w2 = nullptr;
-    ep.w2c = 0.0;
-    ep.shift = A.shift;
-    ep.invg = A.invg;
-    ep.d0 = A.d0;
-    ep.dk1 = A.dk1;
-    ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
-    march_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep);
-    acc[0] = ep.acc[0];
-    acc[1] = ep.acc[1];
-    acc[2] = ep.acc[2];
+  if (A.decide_only || blockIdx.x == 0) {
+    if (!FIRST && !block_stopped(A.ctl)) leja_decide(A, A.k - 1);
+    return;
   }
-  write_partials<3, 2>(acc, A.partials + (long)(A.k & 1) * 3 * gridDim.x);
+  const int b = blockIdx.x - 1;
+  LejaEp<TYO, VEC, FIRST> ep;
+  ep.nx = F.nx;
+  ep.yout = reinterpret_cast<TYO*>(A.yout);
+  ep.pin = FIRST ? nullptr : A.pin;
+  ep.p = A.p;
+  ep.w2 = FIRST ? A.w2 : nullptr;
+  ep.w2c = FIRST ? A.w2c : 0.0;
+  ep.shift = A.shift;
+  ep.invg = A.invg;
+  ep.d0 = A.d0;
+  ep.dk1 = A.dk1;
+  ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
+  if (FIRST || !wave_stopped(A.ctl))
+    stencil_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep, b);
+  write_partials<3, 2>(ep.acc, A.partials + (long)(A.k & 1) * 3 * T.nblocks, T.nblocks, b);
 }
 
 // Power iteration term: w_{k+1} = A(w_k) / lambda_k, lambda_k = ||w_k|| from
@@ -284,19 +292,18 @@ struct PowerEp {
   double* __restrict__ w;
   double scale;
   double acc[1];
-  template <bool CHECK>
+  __device__ __forceinline__ bool go() const { return true; }
   __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
-  template <bool CHECK>
   __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&)[VEC],
                                          const Extra&) {
-    if (CHECK && !g.inside) return;
+    if (!g.inside) return;
     double r[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       r[v] = Ax[v] * scale;
       acc[0] += r[v] * r[v];
     }
-    store_c<double, VEC>(w, (long)j * nx + g.col0, r);
+    str<double, VEC>(w + (long)j * nx, g.col0, r);
   }
 };
 
@@ -344,8 +351,8 @@ __global__ __launch_bounds__(kBlock) void power_kernel(FieldView F, Tiling T, Po
   ep.w = P.w;
   ep.scale = lam > 0.0 ? 1.0 / lam : 0.0;
   ep.acc[0] = 0.0;
-  march_block<TF, double, VEC, ADVF>(F, T, P.x, ep);
-  write_partials<1, 1>(ep.acc, P.partials + (k % 3) * slot);
+  stencil_block<TF, double, VEC, ADVF>(F, T, P.x, ep, blockIdx.x);
+  write_partials<1, 1>(ep.acc, P.partials + (k % 3) * slot, gridDim.x, blockIdx.x);
 }
 
 // splitmix64 output k of the stream seeded with s (Steele, Lea, Flood 2014):
@@ -367,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void power_init_kernel(long n, uint64_t see
     w[i] = u;
     acc[0] += u * u;
   }
-  write_partials<1, 1>(acc, partials + 2L * gridDim.x);
+  write_partials<1, 1>(acc, partials + 2L * gridDim.x, gridDim.x, blockIdx.x);
 }
 
 // Gershgorin: min over rows of A_ii - sum_{j != i} |A_ij| (one thread per node).
@@ -463,26 +470,19 @@ __global__ __launch_bounds__(kBlock) void prepare_kernel(long n, const double* _
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-Tiling make_tiling(int nx, int ny, int rows_hint) {
+Tiling make_tiling(int nx, int ny, int rows_hint, int vec_hint) {
   Tiling t;
-  t.vec = (nx % 2 == 0 && nx >= 2 * kWave) ? 2 : 1;
-  const int bw = kBlock * t.vec;
-  t.ncb = (nx + bw - 1) / bw;
-  int rows = rows_hint;
-  if (rows <= 0) {
-    // about 2048 blocks: 16-row bands on a 4096^2 grid (measured best on MI355X);
-    // small grids get 2-row bands for more blocks (latency-bound launches)
-    const long target = 2048;
-    const long nrb_want = (target + t.ncb - 1) / t.ncb;
-    rows = (int)((ny + nrb_want - 1) / nrb_want);
-    if (rows < 4) rows = 2;
-    else rows = (rows + 3) / 4 * 4;  // interior bands march in groups of 4 rows
-    if (rows > 64) rows = 64;
-  }
+  const bool two = nx % 2 == 0 && nx >= 2 * kWave;
+  t.vec = (vec_hint == 1 || !two) ? 1 : 2;
+  t.ncb = (nx + kWave * t.vec - 1) / (kWave * t.vec);
+  // one row per wave unless asked otherwise (measured best on MI355X from 512^2 to 4096^2)
+  int rows = rows_hint > 0 ? rows_hint : kGroupRows;
   if (rows > ny) rows = ny;
   t.rows = rows;
-  t.nrb = (ny + rows - 1) / rows;
-  t.nblocks = t.ncb * t.nrb;
+  const int band = kWavesY * rows;
+  t.nrb = (ny + band - 1) / band;
+  t.ntiles = t.ncb * t.nrb;
+  t.nblocks = t.ntiles < kMaxGrid ? t.ntiles : kMaxGrid;
   return t;
 }
 
@@ -525,28 +525,33 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
   return hipGetLastError();
 }
 
-template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF>
+template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
 static void leja_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  const dim3 grid(a.decide_only ? 1 : t.nblocks), blk(kBlock);
+  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kBlock);
   if (a.ev_start)
-    hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF>), grid, blk, 0, st, a.ev_start, a.ev_stop, 0, f,
-                          t, a);
+    hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF, FIRST>), grid, blk, 0, st, a.ev_start, a.ev_stop,
+                          0, f, t, a);
   else
-    hipLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF>), grid, blk, 0, st, f, t, a);
+    hipLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF, FIRST>), grid, blk, 0, st, f, t, a);
 }
 
 template <typename TF, int VEC, bool ADVF>
 static void leja_dispatch_y(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  if (a.yin_f32) {
-    if (a.ystore_f32) leja_launch<TF, float, float, VEC, ADVF>(f, t, a, st);
-    else leja_launch<TF, float, double, VEC, ADVF>(f, t, a, st);
+  if (a.first) {  // y_0 = v, FP64
+    if (a.ystore_f32) leja_launch<TF, double, float, VEC, ADVF, true>(f, t, a, st);
+    else leja_launch<TF, double, double, VEC, ADVF, true>(f, t, a, st);
+  } else if (a.ystore_f32) {
+    leja_launch<TF, float, float, VEC, ADVF, false>(f, t, a, st);
   } else {
-    if (a.ystore_f32) leja_launch<TF, double, float, VEC, ADVF>(f, t, a, st);
-    else leja_launch<TF, double, double, VEC, ADVF>(f, t, a, st);
+    leja_launch<TF, double, double, VEC, ADVF, false>(f, t, a, st);
   }
 }
 
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  // later terms read y_k in the storage type and never the augmented column
+  if (!a.first && (a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || a.k < 1)) return hipErrorInvalidValue;
+  if (!a.first && !a.decide_only && (a.pin == nullptr || a.pin == a.p)) return hipErrorInvalidValue;
+  if (a.first && (a.yin_f32 || a.k != 0)) return hipErrorInvalidValue;
   ADL_DISPATCH_TILE(t, f, {
     if (f.f32) leja_dispatch_y<float, VEC, ADVF>(f, t, a, st);
     else leja_dispatch_y<double, VEC, ADVF>(f, t, a, st);
