@@ -278,7 +278,7 @@ def main():
     import workloads as W
 
     torch.cuda.init()
-    w = W.c2_dirichlet_circular(n=512, steps=args.steps)
+    w = W.c2_dirichlet_circular(n=512, steps=args.warmup + 2 * args.steps)
     t0 = time.perf_counter()
     op = make_op(w, A.STORAGE_FP64)
     alpha, _ = op.spectral_bound(A.BOUND_GERSHGORIN)
@@ -290,7 +290,7 @@ def main():
         gpu_step(op, w, u, n, srcs)
     torch.cuda.synchronize()
 
-    op.profile(True)
+    # timed region: K steps, no per-launch instrumentation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mv = 0
@@ -299,12 +299,21 @@ def main():
         mv += st["matvecs"]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    value = args.steps / el
+    # kernel timing pass: the next K steps again, every Newton-Leja launch
+    # timed by HIP events attached to its dispatch on the op's stream
+    # (per-launch events slow the host loop, so they stay out of the timed region)
+    op.profile(True)
+    t1 = time.perf_counter()
+    for n in range(args.warmup + args.steps, args.warmup + 2 * args.steps):
+        gpu_step(op, w, u, n, srcs)
+    torch.cuda.synchronize()
+    el_prof = time.perf_counter() - t1
     ms, launches, nbytes = op.profile_read()
     op.profile(False)
     avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)
-    value = args.steps / el
-    log("timed %d steps in %.3fs: %.1f steps/s, %.1f matvecs/step, leja kernel %.2f us avg, %.0f GB/s"
-        % (args.steps, el, value, mv / args.steps, avg_ms * 1e3, achieved))
+    log("timed %d steps in %.3fs: %.1f steps/s, %.1f matvecs/step; kernel pass: leja kernel %.2f us avg "
+        "over %d launches, %.0f GB/s" % (args.steps, el, value, mv / args.steps, avg_ms * 1e3, launches, achieved))
 
     out = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
@@ -320,6 +329,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "leja_kernel", "bytes_per_launch": per_launch,
                      "avg_kernel_us": avg_ms * 1e3, "launches": launches,
+                     "timing": "HIP events on each Newton-Leja dispatch, second pass of %d steps "
+                               "(%.3fs)" % (args.steps, el_prof),
                      "note": "512^2 FP64 working set (~15 MB/iteration) stays in L2/MALL"},
     }
 

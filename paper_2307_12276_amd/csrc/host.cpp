@@ -290,16 +290,18 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   HIPCHK(launch_ctl_reset(op->ctl, 1, st));
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
   const Tiling& T = tiling_for(op, v, p_out);
-  // launches of the first chunk = the predicted degree: with a right guess the
-  // chunk's closing decision launch finds the sweep converged and no term is wasted
-  int predicted = P.last_degree > 0 ? P.last_degree
+  // launches of the first chunk: the last degree of this plan plus one (the
+  // degree moves by about one from step to step; one launch too many costs a
+  // term, one too few a second chunk and host round trip)
+  int predicted = P.last_degree > 0 ? P.last_degree + 1
                                     : (int)(5.0 * std::sqrt(std::fabs(P.alpha) * P.h) + 8.0);
   if (predicted > maxdeg) predicted = maxdeg;
   if (predicted < 1) predicted = 1;
-  // p_m (degree m) is written by launch m-1 into pbuf[m & 1]
+  // p_m (degree m) is written by launch m-1 into pbuf[m & 1]; expect m = predicted - 1
   double* pbuf[2];
-  pbuf[predicted & 1] = p_out;
-  pbuf[(predicted + 1) & 1] = op->p2;
+  const int mexp = P.last_degree > 0 ? P.last_degree : predicted;
+  pbuf[mexp & 1] = p_out;
+  pbuf[(mexp + 1) & 1] = op->p2;
   int launched = 0;
   LejaArgs a{};
   a.invg = P.invg;

@@ -159,7 +159,8 @@ struct LejaEp {
   const double* __restrict__ w2;   // only on the first term
   double w2c, shift, invg, d0, dk1;
   double acc[3];  // ||d y'||^2, ||p'||^2, max(|y0|, |w2|)
-  __device__ __forceinline__ bool go() const { return true; }
+  int stopflag;   // the sweep's stop flag as loaded at the start of the wave
+  __device__ __forceinline__ bool go() const { return __builtin_amdgcn_readfirstlane(stopflag) == 0; }
   __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
     if (!g.inside) return;
     const long ro = (long)j * nx;
@@ -235,12 +236,6 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
   return s_stop != 0;
 }
 
-// The sweep's stop flag as one wave sees it (no barrier).
-__device__ __forceinline__ bool wave_stopped(const Ctl* ctl) {
-  const int s = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_amdgcn_readfirstlane(s) != 0;
-}
-
 // One Newton-Leja term, launch k: y_{k+1} from y_k, p_{k+1} = p_k + d_{k+1} y_{k+1}
 // into the other p buffer, block partials of the norms.
 //
@@ -248,8 +243,9 @@ __device__ __forceinline__ bool wave_stopped(const Ctl* ctl) {
 // (block 0, dispatched first) takes the decision of term k from the partials
 // of launch k-1 and records it, while the worker blocks 1 .. nblocks compute
 // term k+1 without waiting for it.  A worker wave only checks the stop flag,
-// which launches before this one have set.  If term k turns out to be the
-// last, the term computed by this launch is discarded: p_k is still intact in the other p
+// which launches before this one have set, and only after its first loads
+// are issued.  If term k turns out to be the last, the term computed by this
+// launch is discarded: p_k is still intact in the other p
 // buffer, and every later launch sees the flag and skips its work.  No store
 // of a worker depends on a reduction, so the launch starts loading at once.
 // Waves that skip their work still join the partial-sum barriers, and a wave
@@ -278,8 +274,8 @@ __global__ __launch_bounds__(kBlock) void leja_kernel(FieldView F, Tiling T, Lej
   ep.d0 = A.d0;
   ep.dk1 = A.dk1;
   ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
-  if (FIRST || !wave_stopped(A.ctl))
-    stencil_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep, b);
+  ep.stopflag = FIRST ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  stencil_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep, b);
   write_partials<3, 2>(ep.acc, A.partials + (long)(A.k & 1) * 3 * T.nblocks, T.nblocks, b);
 }
 
