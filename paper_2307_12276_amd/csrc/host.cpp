@@ -189,10 +189,11 @@ struct WsLayout {
 };
 
 static size_t max_partial_blocks(int nx, int ny) {
-  // stencil launches: <= min(tiles, kMaxGrid) blocks, the most tiles with one
-  // column per lane and one row per wave; elementwise reductions <= 1024
-  const size_t tiles = (size_t)((nx + kWave - 1) / kWave) * (size_t)((ny + kWavesY - 1) / kWavesY);
-  size_t nb = tiles < (size_t)kMaxGrid ? tiles : (size_t)kMaxGrid;
+  // stencil launches: at most max(kMaxGrid, number of strips) blocks (one
+  // column per lane: the most strips); elementwise reductions <= 1024
+  const size_t strips = (size_t)((nx + kWave - 1) / kWave);
+  size_t nb = strips > (size_t)kMaxGrid ? strips : (size_t)kMaxGrid;
+  (void)ny;
   return nb > 4096 ? nb : 4096;
 }
 
@@ -293,8 +294,10 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   // launches of the first chunk: the last degree of this plan plus one (the
   // degree moves by about one from step to step; one launch too many costs a
   // term, one too few a second chunk and host round trip)
+  // (first sweep of a plan: a guess from rho h that stays below the degrees
+  // measured at tol 1e-10, since launches past the stop still load a group)
   int predicted = P.last_degree > 0 ? P.last_degree + 1
-                                    : (int)(5.0 * std::sqrt(std::fabs(P.alpha) * P.h) + 8.0);
+                                    : (int)(3.5 * std::sqrt(std::fabs(P.alpha) * P.h) + 4.0);
   if (predicted > maxdeg) predicted = maxdeg;
   if (predicted < 1) predicted = 1;
   // p_m (degree m) is written by launch m-1 into pbuf[m & 1]; expect m = predicted - 1

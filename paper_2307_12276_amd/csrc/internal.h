@@ -10,8 +10,12 @@
 namespace adl {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;             // 4 waves, stacked in y (one strip, 4 row bands)
-constexpr int kWavesY = kBlock / kWave;
+constexpr int kBlock = 256;             // elementwise and reduction kernels
+#ifndef ADL_WAVES_Y
+#define ADL_WAVES_Y 4
+#endif
+constexpr int kWavesY = ADL_WAVES_Y;     // stencil blocks: waves stacked in y (one strip)
+constexpr int kTileBlock = kWave * kWavesY;
 #ifndef ADL_MAX_GRID
 #define ADL_MAX_GRID 16384
 #endif
@@ -50,15 +54,16 @@ struct FieldView {
 };
 
 // Tiling of one grid for the stencil kernels.  A tile = one strip of
-// 64*vec columns x kWavesY*rows rows, one block's unit of work; wave w of the
-// block computes rows [w*rows, (w+1)*rows) of the tile.  Blocks loop over the
-// tiles with a grid stride.
+// 64*vec columns x kWavesY*rows rows (a row band), one block's unit of work;
+// wave w of the block computes rows [w*rows, (w+1)*rows) of the tile.  Block b
+// takes strip b mod ncb and the run of `bands` consecutive row bands number
+// b / ncb, so the rows shared by consecutive bands are re-read from cache.
 struct Tiling {
   int vec;      // columns per lane (1 or 2; 2 needs even nx)
   int rows;     // rows per wave and tile
   int ncb, nrb; // strips / row bands
-  int ntiles;   // ncb * nrb
-  int nblocks;  // grid size: min(ntiles, kMaxGrid)
+  int bands;    // consecutive row bands per block
+  int nblocks;  // ncb * ceil(nrb / bands)
 };
 
 // rows_hint <= 0: default rows; vec_hint 0: widest usable, 1 or 2: forced

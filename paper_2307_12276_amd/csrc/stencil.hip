@@ -88,14 +88,17 @@ __device__ __forceinline__ void write_partials(double (&acc)[NA], double* __rest
   }
 }
 
-// Tiles b, b + T.nblocks, ... for worker block b.
+// The tiles of worker block b: strip b mod ncb, row bands
+// [(b / ncb) * bands, (b / ncb + 1) * bands).
 template <typename TF, typename TX, int VEC, bool ADVF, class Ep>
 __device__ __forceinline__ void stencil_block(const FieldView& F, const Tiling& T, const TX* __restrict__ x,
                                               Ep& ep, int b) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform rows
+  const int cb = b % T.ncb;
+  const int rb0 = (b / T.ncb) * T.bands;
+  const int rb1 = min(rb0 + T.bands, T.nrb);
 #pragma unroll 1
-  for (int t = b; t < T.ntiles; t += T.nblocks) {
-    const int rb = t / T.ncb, cb = t - rb * T.ncb;
+  for (int rb = rb0; rb < rb1; ++rb) {
     const int j0 = (rb * kWavesY + wave) * T.rows;
     if (j0 < F.ny && !stencil_tile<TF, TX, VEC, ADVF>(F, x, ep, cb, j0, min(j0 + T.rows, F.ny))) break;
   }
@@ -139,7 +142,7 @@ struct ApplyEp {
 };
 
 template <typename TF, int VEC, bool ADVF>
-__global__ __launch_bounds__(kBlock) void apply_kernel(FieldView F, Tiling T, const double* __restrict__ x,
+__global__ __launch_bounds__(kTileBlock) void apply_kernel(FieldView F, Tiling T, const double* __restrict__ x,
                                                        ApplyEp<VEC> ep) {
   stencil_block<TF, double, VEC, ADVF>(F, T, x, ep, blockIdx.x);
 }
@@ -256,7 +259,7 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
 // zero-vector check) is a kernel of its own, so that the other terms'
 // register allocation does not carry its extra state.
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
-__global__ __launch_bounds__(kBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
+__global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
   if (A.decide_only || blockIdx.x == 0) {
     if (!FIRST && !block_stopped(A.ctl)) leja_decide(A, A.k - 1);
     return;
@@ -307,7 +310,7 @@ struct PowerEp {
 // At the start of launch k (k >= 1) lambda_k = ||w_k|| is tested against
 // lambda_{k-1} (0 for k = 1), the test of iteration k of the power method.
 template <typename TF, int VEC, bool ADVF>
-__global__ __launch_bounds__(kBlock) void power_kernel(FieldView F, Tiling T, PowerArgs P) {
+__global__ __launch_bounds__(kTileBlock) void power_kernel(FieldView F, Tiling T, PowerArgs P) {
   Ctl* ctl = P.ctl;
   if (block_stopped(ctl)) return;
   const int k = P.k;
@@ -472,13 +475,15 @@ Tiling make_tiling(int nx, int ny, int rows_hint, int vec_hint) {
   t.vec = (vec_hint == 1 || !two) ? 1 : 2;
   t.ncb = (nx + kWave * t.vec - 1) / (kWave * t.vec);
   // one row per wave unless asked otherwise (measured best on MI355X from 512^2 to 4096^2)
-  int rows = rows_hint > 0 ? rows_hint : kGroupRows;
+  int rows = rows_hint > 0 ? rows_hint : 1;
   if (rows > ny) rows = ny;
   t.rows = rows;
   const int band = kWavesY * rows;
   t.nrb = (ny + band - 1) / band;
-  t.ntiles = t.ncb * t.nrb;
-  t.nblocks = t.ntiles < kMaxGrid ? t.ntiles : kMaxGrid;
+  // bands per block: the fewest that keep the grid within kMaxGrid blocks
+  const long per_strip = kMaxGrid / t.ncb > 0 ? kMaxGrid / t.ncb : 1;
+  t.bands = (int)((t.nrb + per_strip - 1) / per_strip);
+  t.nblocks = t.ncb * ((t.nrb + t.bands - 1) / t.bands);
   return t;
 }
 
@@ -514,16 +519,16 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
     ep.a1 = a1;
     ep.a2 = a2;
     if (f.f32)
-      hipLaunchKernelGGL((apply_kernel<float, VEC, ADVF>), dim3(t.nblocks), dim3(kBlock), 0, st, f, t, x, ep);
+      hipLaunchKernelGGL((apply_kernel<float, VEC, ADVF>), dim3(t.nblocks), dim3(kTileBlock), 0, st, f, t, x, ep);
     else
-      hipLaunchKernelGGL((apply_kernel<double, VEC, ADVF>), dim3(t.nblocks), dim3(kBlock), 0, st, f, t, x, ep);
+      hipLaunchKernelGGL((apply_kernel<double, VEC, ADVF>), dim3(t.nblocks), dim3(kTileBlock), 0, st, f, t, x, ep);
   });
   return hipGetLastError();
 }
 
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
 static void leja_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kBlock);
+  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock);
   if (a.ev_start)
     hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF, FIRST>), grid, blk, 0, st, a.ev_start, a.ev_stop,
                           0, f, t, a);
@@ -561,7 +566,7 @@ hipError_t launch_power_init(const Tiling& t, long n, uint64_t seed, double* w, 
 }
 
 hipError_t launch_power_step(const FieldView& f, const Tiling& t, const PowerArgs& a, hipStream_t st) {
-  const dim3 grid(a.decide_only ? 1 : t.nblocks), blk(kBlock);
+  const dim3 grid(a.decide_only ? 1 : t.nblocks), blk(kTileBlock);
   ADL_DISPATCH_TILE(t, f, {
     if (f.f32) hipLaunchKernelGGL((power_kernel<float, VEC, ADVF>), grid, blk, 0, st, f, t, a);
     else hipLaunchKernelGGL((power_kernel<double, VEC, ADVF>), grid, blk, 0, st, f, t, a);
