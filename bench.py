@@ -76,6 +76,33 @@ def device_sources(w):
     return srcs
 
 
+KERNEL_SOURCES = ("device.h", "internal.h", "stencil.hip", "tile.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_kernel_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per Newton-Leja launch of the 512^2 workload from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the
+    kernel sources have changed since those counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, "paper_2307_12276_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv.get("kernel_sources_sha256"):
+            return None
+        return float(kv["traffic_bytes_per_launch_dirichlet512"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def kernel_roofline(op_ms, launches, nbytes):
     avg_ms = op_ms / max(launches, 1)
     per_launch = nbytes / max(launches, 1)
@@ -326,11 +353,13 @@ def main():
                    "nx": 512, "ny": 512, "dt": w.dt, "tol": w.tol, "alpha": alpha,
                    "matvecs_per_step": mv / args.steps, "setup_s": setup_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "leja_kernel", "bytes_per_launch": per_launch,
                      "avg_kernel_us": avg_ms * 1e3, "launches": launches,
                      "timing": "HIP events on each Newton-Leja dispatch, second pass of %d steps "
                                "(%.3fs)" % (args.steps, el_prof),
+                     "traffic_source": "profiles/leja_kernel_traffic.txt (rocprofv3 FETCH_SIZE x2.0 + "
+                                       "WRITE_SIZE x1.0, calibrated on a 1 GiB copy), bytes per launch",
                      "note": "512^2 FP64 working set (~15 MB/iteration) stays in L2/MALL"},
     }
 

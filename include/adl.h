@@ -133,12 +133,12 @@ int adl_op_set_quad2_mode(adl_op* op, int mode);
 int adl_op_profile(adl_op* op, int enable);
 int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, double* bytes);
 
-/* Tiling of the stencil kernels (the autotuner's knobs): rows = height of the
- * row band each block marches down (rounded up to a multiple of 4 for the
- * interior fast path by the default only), cols_per_lane = columns per lane
- * (1, or 2 for even nx >= 128); 0 selects the built-in default for each.
- * adl_op_get_tiling reports the tiling in use (any output pointer may be
- * NULL). */
+/* Tiling of the stencil kernels (the autotuner's knobs): rows = rows each
+ * wave computes per tile (a block of four waves covers 4 * rows rows of one
+ * strip; default 1), cols_per_lane = columns per lane (1, or 2 for even
+ * nx >= 128); 0 selects the built-in default for each.  adl_op_get_tiling
+ * reports the tiling in use and the worker block count of a launch (any
+ * output pointer may be NULL). */
 int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
 int adl_op_get_tiling(const adl_op* op, int* cols_per_lane, int* rows, int* nblocks);
 
