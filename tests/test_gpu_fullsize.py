@@ -1,0 +1,138 @@
+"""Full-size runs: the 2048^2 FP32-storage workload (20 steps) and the 4096^2
+learned-interval evaluation.  The oracle cannot run these sizes inside a
+test, so they are checked against properties that hold at any size and
+against the FP64 GPU path, whose parity with the oracle is established on the
+same fields at smaller sizes (test_gpu_parity.py):
+
+- mass: on a periodic grid the columns of A sum to zero (conservative fluxes,
+  pinned in the oracle tests), so sum(A v) = 0 and the Newton recurrence maps
+  sum(y_k) to (2 - xi_k) sum(y_k).  With xi_0 = 2 the polynomial is exact at
+  the eigenvalue 0: a midpoint step changes sum(u) by exactly dt * sum(S) up
+  to rounding; the two-stage quadrature adds the w2 column, whose phi_2 part
+  at the eigenvalue 0 is interpolated, so the step's mass change matches
+  dt * (sum(w1) + sum(w2) / 2) to the interpolation tolerance;
+- the FP32-storage error against the FP64 path, bounded by 1e-5.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2307_12276_amd as A  # noqa: E402
+from paper_2307_12276_amd import learned  # noqa: E402
+from gpu_util import rel, to_dev, to_np  # noqa: E402
+
+
+def make_op(w, storage):
+    return A.Op(to_dev(w.Dxx), to_dev(w.Dxy), to_dev(w.Dyy), w.hx, w.hy, w.bc, storage,
+                ax_c=w.ax_c, ay_c=w.ay_c)
+
+
+def run_quad2(w, storage, steps):
+    """u after `steps` two-stage steps and, per step, the mass-change defect
+    |dM - dt (sum w1 + sum w2 / 2)| relative to the step's source input
+    dt (sum|w1| + sum|w2|) and relative to sum|u|."""
+    op = make_op(w, storage)
+    op.spectral_bound(A.BOUND_GERSHGORIN)
+    u = to_dev(w.u0)
+    defects, defects_u, degrees = [], [], []
+    inv = 1.0 / (w.c2 - w.c1)
+    for n in range(steps):
+        S1, S2 = w.stage_sources(n)
+        m0 = float(u.sum())
+        st = op.quad2_step(u, to_dev(S1), to_dev(S2), w.c1, w.c2, w.dt, w.tol)
+        m1 = float(u.sum())
+        w1 = (w.c2 * S1 - w.c1 * S2) * inv
+        w2 = (S2 - S1) * inv
+        expect = w.dt * (w1.sum() + 0.5 * w2.sum())
+        scale = w.dt * (np.abs(w1).sum() + np.abs(w2).sum())
+        defects.append(abs((m1 - m0) - expect) / scale)
+        defects_u.append(abs((m1 - m0) - expect) / float(u.abs().sum()))
+        degrees.append(st["max_degree"])
+    out = to_np(u)
+    del op
+    torch.cuda.empty_cache()
+    return out, defects, defects_u, degrees
+
+
+def test_stream_function_2048_fp32_storage_20_steps():
+    """2048^2 periodic stream-function field, k_par/k_perp = 1e4, pulsed
+    source, two-stage quadrature, 100 dt_CFL, tol 1e-10, 20 steps: FP32
+    fields (storage 1) and FP32 fields + Newton vectors (storage 2) against
+    the FP64 path; mass balance of every step."""
+    w = W.c3_stream_function(n=2048, steps=20)
+    u0, d0, _, deg0 = run_quad2(w, A.STORAGE_FP64, w.steps)
+    u1, d1, _, deg1 = run_quad2(w, A.STORAGE_FP32_FIELDS, w.steps)
+    u2, _, d2u, deg2 = run_quad2(w, A.STORAGE_FP32_FIELDS_Y, w.steps)
+    e1, e2 = rel(u1, u0), rel(u2, u0)
+    print("2048^2, 20 steps: rel. error vs FP64 path: FP32 fields %.2e, FP32 fields + y %.2e; "
+          "mass defect (of the source input) max %.1e / %.1e, FP32 y (of sum|u|) %.1e; degrees %s"
+          % (e1, e2, max(d0), max(d1), max(d2u), deg0[:3]))
+    assert np.isfinite(u0).all() and np.abs(u0).max() > 0
+    assert e1 <= 1e-5 and e2 <= 1e-5
+    # FP64 vectors: only the interpolated phi_2 slope at the eigenvalue 0 is
+    # inexact (observed 5e-9 of the source input at tol 1e-10)
+    assert max(d0) < 3e-8 and max(d1) < 3e-8
+    # FP32 Newton vectors: each y_k is rounded to FP32 (2^-24 relative)
+    assert max(d2u) < 1e-9
+    # the storage changes the coefficients only: the polynomial degrees agree to a term or two
+    assert all(abs(a - b) <= 2 for a, b in zip(deg0, deg1))
+
+
+def test_learned_interval_4096_fp32_storage():
+    """4096^2 stream-function field with FP32 storage, k_par/k_perp = 1e4:
+    the learned interval (field statistics + MLP, Gershgorin cap, power
+    iteration as fallback) against power iteration, 5 midpoint steps at tol
+    1e-8 each, both against an FP64 run at tol 1e-10; mass of every step."""
+    w = W.roofline_shape(n=4096, steps=5)
+    Wd = torch.from_numpy(learned.load()).cuda()
+    scratch = torch.empty(64, dtype=torch.float32, device="cuda")
+    S = [to_dev(w.stage_sources(n)[0]) for n in range(w.steps)]
+
+    def run(storage, bound, tol):
+        op = make_op(w, storage)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = None
+        if bound == "learned":
+            info = op.learned_bound(w.dt, Wd, scratch)
+        elif bound == "power":
+            op.spectral_bound(A.BOUND_POWER, max_iter=2000, rtol=1e-3, seed=1)
+        else:
+            op.spectral_bound(A.BOUND_GERSHGORIN)
+        torch.cuda.synchronize()
+        t_bound = time.perf_counter() - t0
+        u = to_dev(w.u0)
+        mv, fb, defect = 0, 0, 0.0
+        for n in range(w.steps):
+            m0 = float(u.sum())
+            st = op.midpoint_step(u, S[n], w.dt, tol)
+            mv += st["matvecs"]
+            fb += st["fallback"]
+            ds = w.dt * float(S[n].sum())
+            defect = max(defect, abs(float(u.sum()) - m0 - ds) / (abs(m0) + abs(ds)))
+        out = to_np(u)
+        del op
+        torch.cuda.empty_cache()
+        return out, t_bound, mv, fb, defect, info
+
+    ref, _, mv_ref, _, d_ref, _ = run(A.STORAGE_FP64, "gershgorin", 1e-10)
+    ul, tl, mvl, fbl, dl, info = run(A.STORAGE_FP32_FIELDS, "learned", 1e-8)
+    up, tp, mvp, fbp, dp, _ = run(A.STORAGE_FP32_FIELDS, "power", 1e-8)
+    el, ep = rel(ul, ref), rel(up, ref)
+    print("4096^2 FP32 fields, 5 steps at tol 1e-8: learned bound %.3fs (rho_hat %.4g, alpha %.4g, "
+          "Gershgorin %.4g), %d matvecs, %d fallbacks, rel err %.2e; power bound %.3fs, %d matvecs, "
+          "rel err %.2e; FP64 reference %d matvecs; mass defect %.1e / %.1e / %.1e"
+          % (tl, info["rho_hat"], info["alpha"], info["gershgorin"], mvl, fbl, el, tp, mvp, ep, mv_ref,
+             dl, dp, d_ref))
+    assert el <= 1e-5 and ep <= 1e-5
+    assert tl < tp
+    assert max(dl, dp, d_ref) < 1e-10
