@@ -194,7 +194,7 @@ def chosen_vs_plain(steps=10, tol=1e-9):
     t_bound_c = time.perf_counter() - t0
     batch = A.Batch(ops_c)
     uc = [dev_tensor(b.u0) for b in bins]
-    best_rows, _ = batch.autotune(uc, S, dt, tol, candidates=(8, 16, 32))
+    best_rows, _ = batch.autotune(uc, S, dt, tol, candidates=(2, 4, 8, 16))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mv_c = 0

@@ -207,7 +207,7 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
                      int tile_rows, adl_batch** out);
 int adl_batch_destroy(adl_batch* b);
 
-/* Tile height (rows, a positive multiple of 4) of the batch kernels. */
+/* Tile height (rows per wave, >= 1) of the batch kernels. */
 int adl_batch_set_tile_rows(adl_batch* b, int rows);
 int adl_batch_get_tile_rows(const adl_batch* b, int* rows);
 

@@ -5,17 +5,22 @@
 // Work unit: a tile = one wave64 strip of 64*VEC columns x `rows` rows of one
 // bin.  Every kernel of a step covers the tiles of all bins:
 //   stage      w_b = A_b u_b + S_b
-//   term k     y_{k+1} = ((A_b - c_b)/gamma_b - xi_k) y_k,  p_b += d_{b,k+1} y_{k+1}
-//              for every bin still running, with the bin's own plan; at its
-//              start each tile takes its bin's stopping decision for term k
-//              from the bin's tile partials of the previous launch (fixed
-//              order, identical in every tile of the bin)
+//   term k     y_{k+1} = ((A_b - c_b)/gamma_b - xi_k) y_k,
+//              p_{b,k+1} = p_{b,k} + d_{b,k+1} y_{k+1} into the bin's other p buffer,
+//              for every bin still running, with the bin's own plan
 //   finalize   the decision of the last term, one wave per bin
 //   update     u_b += dt p_b for converged bins
-// The launches of a step (reset, stage, terms, finalize) are captured once in
-// a hipGraph and replayed: one graph launch per step.  Kernel boundaries give
-// cross-XCD visibility of y_k, so no tile ever waits on another within a
-// kernel and no agent-scope fence is needed.
+// The stopping decision lags one launch behind the work, as for a single
+// operator: the first nbins blocks of a term launch are one decision wave per
+// bin, which sums the bin's tile partials of the previous launch in a fixed
+// order and records the decision; the tile waves only check their bin's stop
+// flag (set by an earlier launch) and compute the next term.  When the
+// decision recorded in launch k stops a bin, the term launch k computed for it
+// is discarded (p_k is intact in the other buffer).  The launches of a step
+// (reset, stage, terms, finalize) are captured once in a hipGraph and
+// replayed: one graph launch per step.  Kernel boundaries give cross-XCD
+// visibility of y_k, so no wave ever waits on another and no agent-scope fence
+// is needed.
 #include "tile.h"
 #include "op.h"
 
@@ -40,7 +45,8 @@ struct BinDesc {
   double* w;
   void* y0;
   void* y1;
-  double* p;
+  double* p0;           // p_m of degree m lives in p0 (m even) or p1 (m odd)
+  double* p1;
   const double* d;      // d_0 .. d_{M-1} of the bin's plan
   const double* shift;  // c + gamma xi_k
   double invg;
@@ -150,13 +156,14 @@ struct BatchLejaEp {
   };
   int nx;
   double* __restrict__ yout;
-  double* __restrict__ p;
+  const double* __restrict__ pin;  // p_k (not on the first term)
+  double* __restrict__ p;          // p_{k+1}
   double shift, invg, d0, dk1;
   double acc[3];
   __device__ __forceinline__ bool go() const { return true; }
   __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
     if (!g.inside) return;
-    if constexpr (!FIRST) ldr<double, VEC>(p + (long)j * nx, g.col0, e.p);
+    if constexpr (!FIRST) ldr<double, VEC>(pin + (long)j * nx, g.col0, e.p);
   }
   __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&yc)[VEC],
                                          const Extra& e) {
@@ -203,7 +210,8 @@ __device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B,
   BatchLejaEp<VEC, FIRST> ep;
   ep.nx = B.f.nx;
   ep.yout = reinterpret_cast<double*>(((k + 1) & 1) ? B.y1 : B.y0);
-  ep.p = B.p;
+  ep.pin = FIRST ? nullptr : ((k & 1) ? B.p1 : B.p0);
+  ep.p = ((k + 1) & 1) ? B.p1 : B.p0;
   ep.shift = B.shift[k];
   ep.invg = B.invg;
   ep.d0 = B.d[0];
@@ -220,18 +228,27 @@ __device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B,
   }
 }
 
-template <typename TF, int VEC, bool ADVF>
-__global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A) {
-  const int gt = blockIdx.x;
+// Term launch k: blocks [0, nbins) decide term k-1 of their bin (from the
+// partials of launch k-1), blocks [nbins, nbins + total tiles) compute term
+// k+1 of their tile's bin unless the bin has stopped.  The first term (k = 0,
+// y_0 = w) is a kernel of its own.
+template <typename TF, int VEC, bool ADVF, bool FIRST>
+__global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A, int nbins) {
+  if ((int)blockIdx.x < nbins) {
+    const int b = blockIdx.x;
+    const BinDesc& B = A.bins[b];
+    if (FIRST || !B.active) return;
+    if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    bin_decide(A, B, b, A.k - 1, true);
+    return;
+  }
+  const int gt = blockIdx.x - nbins;
   const int b = A.tile_bin[gt];
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
   if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const int t = gt - B.tile_base;
-  if (A.k > 0 && bin_decide(A, B, b, A.k - 1, t == 0)) return;
   if (A.k >= B.max_degree) return;
-  if (A.k == 0) batch_term<TF, VEC, ADVF, true>(A, B, t);
-  else batch_term<TF, VEC, ADVF, false>(A, B, t);
+  batch_term<TF, VEC, ADVF, FIRST>(A, B, gt - B.tile_base);
 }
 
 // decision of term k (the last launched) for every running bin: one wave per bin
@@ -258,7 +275,8 @@ __global__ __launch_bounds__(64) void batch_update_kernel(BatchArgs A, double* c
   const int gt = blockIdx.x;
   const int b = A.tile_bin[gt];
   const BinDesc& B = A.bins[b];
-  if (!B.active || A.ctl[b].status != 1) return;
+  if (!B.active || A.ctl[b].status != 1 || A.ctl[b].degree == 0) return;  // degree 0: p = 0
+  const double* pb = (A.ctl[b].degree & 1) ? B.p1 : B.p0;
   const int t = gt - B.tile_base;
   const int rb = t / B.ncb, cb = t - rb * B.ncb;
   const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
@@ -269,7 +287,7 @@ __global__ __launch_bounds__(64) void batch_update_kernel(BatchArgs A, double* c
     const long ro = (long)j * B.f.nx;
     double uu[VEC], pp[VEC];
     ldr<double, VEC>(ub + ro, col0, uu);
-    ldr<double, VEC>(B.p + ro, col0, pp);
+    ldr<double, VEC>(pb + ro, col0, pp);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) uu[v] = uu[v] + B.dt * pp[v];
     str<double, VEC>(ub + ro, col0, uu);
@@ -359,7 +377,7 @@ BLayout blayout(int nbins, long max_tiles, int M) {
 
 long max_tiles_for(int nbins, adl_op* const* ops) {
   long t = 0;
-  for (int b = 0; b < nbins; ++b) t += tiles_of(ops[b]->nx, ops[b]->ny, 1, 4);
+  for (int b = 0; b < nbins; ++b) t += tiles_of(ops[b]->nx, ops[b]->ny, 1, 1);
   return t;
 }
 
@@ -418,8 +436,12 @@ int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t
   }
   for (int i = 0; i < nterms; ++i) {
     a.k = k0 + i;
+    const dim3 grid(B->nbins + B->total_tiles);
     dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
-      hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF>), dim3(B->total_tiles), dim3(64), 0, st, a);
+      if (a.k == 0)
+        hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF, true>), grid, dim3(64), 0, st, a, B->nbins);
+      else
+        hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF, false>), grid, dim3(64), 0, st, a, B->nbins);
     });
   }
   a.k = k0 + nterms;
@@ -447,7 +469,8 @@ int upload_bins(adl_batch* B, double* const* u, const double* const* S, double d
     d.w = op->w1;
     d.y0 = op->ybuf[0];
     d.y1 = op->ybuf[1];
-    d.p = op->p;
+    d.p0 = op->p2;
+    d.p1 = op->p;
     d.tol2 = tol * tol;
     d.dt = dt;
     d.max_degree = std::min(op->max_degree, B->max_degree);
@@ -520,7 +543,7 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
     if (op->storage == ADL_STORAGE_FP32_FIELDS_Y) return bfail(ADL_EINVAL, "batch supports FP64 Newton vectors only");
     if (op->nx % 2 != 0 || op->nx < 2 * kWave) all_even = false;
   }
-  if (tile_rows < 0 || (tile_rows > 0 && tile_rows % 4 != 0)) return bfail(ADL_EINVAL, "tile_rows must be a multiple of 4");
+  if (tile_rows < 0) return bfail(ADL_EINVAL, "tile_rows must be >= 0");
   const int M = kMaxDegreeDefault + 1;
   const long mt = max_tiles_for(nbins, ops);
   const BLayout L = blayout(nbins, mt, M);
@@ -569,7 +592,7 @@ int adl_batch_destroy(adl_batch* B) {
 }
 
 int adl_batch_set_tile_rows(adl_batch* B, int rows) {
-  if (!B || rows < 4 || rows % 4 != 0) return bfail(ADL_EINVAL, "tile rows must be a positive multiple of 4");
+  if (!B || rows < 1) return bfail(ADL_EINVAL, "tile rows must be positive");
   if (rows == B->rows) return ADL_OK;
   B->rows = rows;
   build_tiles(B);

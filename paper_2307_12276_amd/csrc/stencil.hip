@@ -202,17 +202,32 @@ struct LejaEp {
 };
 
 // Stopping test of term kprev+1 from the partials of launch kprev, taken by
-// one block (fixed-order totals) and recorded in the control block.
-// Returns true when the sweep is over.
-__device__ __forceinline__ bool leja_decide(const LejaArgs& A, int kprev) {
-  double tot[3];
-  partial_totals<3, 2>(A.partials + (long)(kprev & 1) * 3 * A.nb_prev, A.nb_prev, tot);
-  const double tn2 = tot[0], pn2 = tot[1];
+// one block (fixed-order totals) and recorded in the control block unless an
+// earlier launch has already stopped the sweep.
+__device__ __forceinline__ void leja_decide(const LejaArgs& A, int kprev) {
+  // the stop flag travels with the partial sums (a fourth, max-reduced
+  // value), so its load and the partial loads are in flight together
+  const double* part = A.partials + (long)(kprev & 1) * 3 * A.nb_prev;
+  const int nb = A.nb_prev;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (threadIdx.x == 0)
+    v[3] = (double)__hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  bool any = false;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    v[0] += part[i];
+    v[1] += part[(long)nb + i];
+    const double m = part[2L * nb + i];
+    v[2] = any ? nanmax(v[2], m) : m;
+    any = true;
+  }
+  block_allreduce<4, 2>(v);
+  if (v[3] != 0.0) return;  // decided by an earlier launch
+  const double tn2 = v[0], pn2 = v[1];
   const int deg = kprev + 1;
   int stop = 0, status = 0, degree = deg;
   if (!isfinite(tn2) || !isfinite(pn2)) {
     stop = 1; status = 2;
-  } else if (kprev == 0 && tot[2] == 0.0) {
+  } else if (kprev == 0 && v[2] == 0.0) {
     stop = 1; status = 1; degree = 0;
   } else if (tn2 <= A.tol2 * pn2) {
     stop = 1; status = 1;
@@ -227,7 +242,6 @@ __device__ __forceinline__ bool leja_decide(const LejaArgs& A, int kprev) {
     c->status = status;
     __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  return stop != 0;
 }
 
 // The sweep's stop flag, read once per block (thread 0) and broadcast, so that
@@ -261,7 +275,7 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
 __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
   if (A.decide_only || blockIdx.x == 0) {
-    if (!FIRST && !block_stopped(A.ctl)) leja_decide(A, A.k - 1);
+    if (!FIRST) leja_decide(A, A.k - 1);
     return;
   }
   const int b = blockIdx.x - 1;
