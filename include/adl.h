@@ -140,6 +140,14 @@ int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, doub
  * reports the tiling in use and the worker block count of a launch (any
  * output pointer may be NULL). */
 int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
+
+/* Newton terms per launch of a sweep (Sec. 2 recurrence): two_terms = 1 (the
+ * default) computes terms k+1 and k+2 in one launch, keeping y_{k+1} on chip
+ * (read y_k, the fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2});
+ * two_terms = 0 launches one kernel per term.  Results agree to rounding (the
+ * block partial sums of the norms are grouped differently).  ADL_EINVAL for
+ * other values. */
+int adl_op_set_term_fusion(adl_op* op, int two_terms);
 int adl_op_get_tiling(const adl_op* op, int* cols_per_lane, int* rows, int* nblocks);
 
 /* y = A x (one stencil application).  x, y: device [ny][nx] FP64, not

@@ -72,6 +72,7 @@ _SIG = {
     "adl_op_set_quad2_mode": (_I, [_P, _I]),
     "adl_op_profile": (_I, [_P, _I]),
     "adl_op_set_tiling": (_I, [_P, _I, _I]),
+    "adl_op_set_term_fusion": (_I, [_P, _I]),
     "adl_op_get_tiling": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "adl_op_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(_D)]),
@@ -221,6 +222,9 @@ class Op:
 
     def set_tiling(self, rows: int = 0, cols_per_lane: int = 0):
         _check(lib().adl_op_set_tiling(self.handle, int(rows), int(cols_per_lane)))
+
+    def set_term_fusion(self, two_terms: bool = True):
+        _check(lib().adl_op_set_term_fusion(self.handle, int(bool(two_terms))))
 
     def get_tiling(self):
         v, r, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -185,14 +185,16 @@ using namespace adl;
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-  size_t kxx, kxy, kyy, ax, ay, y0, y1, p, p2, w1, w2, yacc, tmp, tmp2, partials, ctl, total;
+  size_t kxx, kxy, kyy, ax, ay, y0, y1, p, p2, p3, p4, w1, w2, yacc, tmp, tmp2, partials, ctl, total;
 };
 
 static size_t max_partial_blocks(int nx, int ny) {
   // stencil launches: at most max(kMaxGrid, number of strips) blocks (one
-  // column per lane: the most strips); elementwise reductions <= 1024
-  const size_t strips = (size_t)((nx + kWave - 1) / kWave);
+  // column per lane and 62 output columns per strip in the two-term kernel:
+  // the most strips); elementwise reductions <= 1024
+  const size_t strips = (size_t)((nx + kWave - 3) / (kWave - 2));
   size_t nb = strips > (size_t)kMaxGrid ? strips : (size_t)kMaxGrid;
+  if (nb < (size_t)kMaxGrid2) nb = kMaxGrid2;
   (void)ny;
   return nb > 4096 ? nb : 4096;
 }
@@ -222,7 +224,9 @@ static WsLayout ws_layout(int nx, int ny, int storage) {
   L.tmp = take(n * 8);
   L.tmp2 = take(n * 8);
   L.p2 = take(n * 8);
-  L.partials = take(6 * max_partial_blocks(nx, ny) * 8);
+  L.p3 = take(n * 8);
+  L.p4 = take(n * 8);
+  L.partials = take(2 * 6 * max_partial_blocks(nx, ny) * 8);
   L.ctl = take(4 * 128);
   L.total = o;
   return L;
@@ -266,46 +270,79 @@ Plan& adl::get_plan(adl_op* op, int l, double alpha, double h) {
   return P;
 }
 
-// Algorithmic HBM bytes of one Newton-Leja iteration launch: read y_k, the
-// three tensor fields (+ two advection fields), p (not at k = 0), w2 (when
-// the augmented column enters); write y_{k+1} and p.
-static double leja_bytes(const adl_op* op, int k, bool with_w2) {
+// Algorithmic HBM bytes of one Newton-Leja launch of n terms: read y_k, the
+// three tensor fields (+ two advection fields), p_k (not at k = 0), w2 (when
+// the augmented column enters); write y of the last term and p of each term.
+static double leja_bytes(const adl_op* op, int k, int n, bool with_w2) {
   const double fs = op->f.f32 ? 4.0 : 8.0;
   const double ys = op->storage == ADL_STORAGE_FP32_FIELDS_Y ? 4.0 : 8.0;
-  double b = (k == 0 ? 8.0 : ys) + 3.0 * fs + (k == 0 ? 0.0 : 8.0) + (with_w2 ? 8.0 : 0.0) + ys + 8.0;
+  double b = (k == 0 ? 8.0 : ys) + 3.0 * fs + (k == 0 ? 0.0 : 8.0) + (with_w2 ? 8.0 : 0.0) + ys + 8.0 * n;
   if (op->f.ax) b += 2.0 * fs;
   return b * (double)op->n;
 }
 
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
-// Launch k computes term k+1 into one of two p buffers (p_out and the
-// workspace buffer p2, alternating) while an extra block of the same launch
-// takes the stopping decision of term k from the block partials of launch
-// k-1; a one-block launch at the end of every chunk takes the decision of the
-// chunk's last term.  The buffers are assigned so that the predicted degree
-// ends in p_out; otherwise the result is copied there.
+//
+// Launches: the first term (y_0 = v) alone, then two terms per launch while
+// the op fuses terms (one otherwise, or when one term is left before the
+// degree cap).  Each launch's block 0 takes the stopping decision of the
+// previous launch's terms from its block partials; a one-block launch at the
+// end of every chunk decides the chunk's last launch, and the host reads the
+// control block once per chunk.  p of the terms of launch L goes to the
+// buffer pair L mod 2 (the last term always to the pair's second buffer), so
+// a launch never overwrites a p that the decision it runs beside may pick.
+// The buffers are p_out and three workspace buffers, arranged so that the
+// predicted degree ends in p_out; otherwise the result is copied there.
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
                  double tol, int maxdeg, hipStream_t st, SweepOut& out) {
   if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;
   HIPCHK(launch_ctl_reset(op->ctl, 1, st));
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
   const Tiling& T = tiling_for(op, v, p_out);
-  // launches of the first chunk: the last degree of this plan plus one (the
-  // degree moves by about one from step to step; one launch too many costs a
-  // term, one too few a second chunk and host round trip)
-  // (first sweep of a plan: a guess from rho h that stays below the degrees
-  // measured at tol 1e-10, since launches past the stop still load a group)
+  const Tiling& T2 = T.vec == op->t2.vec ? op->t2 : op->t21;
+  const bool fuse = op->fuse_terms != 0;
+  // first chunk: the last degree of this plan plus one (the degree moves by
+  // about one from step to step; one launch too many costs its work, one too
+  // few a second chunk and host round trip); the first sweep of a plan
+  // guesses from rho h, below the degrees measured at tol 1e-10, since
+  // launches past the stop still load a row group per wave
   int predicted = P.last_degree > 0 ? P.last_degree + 1
                                     : (int)(3.5 * std::sqrt(std::fabs(P.alpha) * P.h) + 4.0);
   if (predicted > maxdeg) predicted = maxdeg;
   if (predicted < 1) predicted = 1;
-  // p_m (degree m) is written by launch m-1 into pbuf[m & 1]; expect m = predicted - 1
-  double* pbuf[2];
   const int mexp = P.last_degree > 0 ? P.last_degree : predicted;
-  pbuf[mexp & 1] = p_out;
-  pbuf[(mexp + 1) & 1] = op->p2;
-  int launched = 0;
+  // launch plan: launch L covers terms kL+1 .. kL+nL
+  std::vector<int> lk, ln;
+  auto plan_terms = [&](int kcov) {
+    if (kcov == 0) return 1;
+    const bool two = fuse && kcov + 2 <= maxdeg && !(w2 && (P.s[kcov] != 0.0 || P.s[kcov + 1] != 0.0));
+    return two ? 2 : 1;
+  };
+  // slot of term j in the four p buffers: pair L mod 2, last term in the second buffer
+  auto slot_of_term = [&](int j) -> int {
+    int kcov = 0, L = 0;
+    while (true) {
+      const int n = plan_terms(kcov);
+      if (j <= kcov + n) return 2 * (L & 1) + (j == kcov + n ? 1 : 0);
+      kcov += n;
+      ++L;
+    }
+  };
+  double* pbuf[4];
+  {
+    const int want = slot_of_term(std::max(mexp, 1));
+    double* ws[4] = {op->p, op->p2, op->p3, op->p4};
+    int wi = 0;
+    for (int s = 0; s < 4; ++s) {
+      if (s == want) {
+        pbuf[s] = p_out;
+      } else {
+        if (ws[wi] == p_out) ++wi;
+        pbuf[s] = ws[wi++];
+      }
+    }
+  }
   LejaArgs a{};
   a.invg = P.invg;
   a.d0 = P.d[0];
@@ -313,68 +350,101 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   a.max_degree = maxdeg;
   a.ystore_f32 = ys32;
   a.partials = op->partials;
-  a.nb_prev = T.nblocks;
+  a.slot_stride = op->slot_stride;
   a.ctl = op->ctl;
+  int kcov = 0, L = 0;
+  int prev_nb = 0, prev_k = 0, prev_n = 0, prev_slot = 0;
   while (true) {
-    int chunk = launched == 0 ? predicted : std::max(8, launched / 4);
-    if (launched + chunk > maxdeg) chunk = maxdeg - launched;
-    if (op->prof) {
-      while ((int)op->evs.size() < 2 * chunk) {
-        hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
-        op->evs.push_back(e);
+    int target = kcov == 0 ? predicted : kcov + std::max(8, kcov / 4);
+    if (target > maxdeg) target = maxdeg;
+    const int L0 = L;
+    while (kcov < target) {
+      const int n = plan_terms(kcov);
+      if (op->prof) {
+        while ((int)op->evs.size() < 2 * (L - L0 + 1)) {
+          hipEvent_t e;
+          HIPCHK(hipEventCreate(&e));
+          op->evs.push_back(e);
+        }
+        a.ev_start = op->evs[2 * (L - L0)];
+        a.ev_stop = op->evs[2 * (L - L0) + 1];
+      } else {
+        a.ev_start = a.ev_stop = nullptr;
       }
-    }
-    for (int i = 0; i < chunk; ++i) {
-      const int k = launched + i;
-      a.ev_start = op->prof ? op->evs[2 * i] : nullptr;
-      a.ev_stop = op->prof ? op->evs[2 * i + 1] : nullptr;
-      a.yin = k == 0 ? (const void*)v : op->ybuf[k & 1];
-      a.yout = op->ybuf[(k + 1) & 1];
-      a.pin = k == 0 ? nullptr : pbuf[k & 1];
-      a.p = pbuf[(k + 1) & 1];
-      a.w2 = (w2 && P.s[k] != 0.0) ? w2 : nullptr;
-      a.w2c = P.s[k] * w2scale;
-      a.shift = P.shift[k];
-      a.dk1 = P.d[k + 1];
-      a.k = k;
-      a.first = k == 0;
-      a.yin_f32 = (k > 0) && ys32;
+      a.k = kcov;
+      a.nterms = n;
+      a.first = kcov == 0;
+      a.yin = kcov == 0 ? (const void*)v : op->ybuf[L & 1];
+      a.yout = op->ybuf[(L + 1) & 1];
+      a.yin_f32 = (kcov > 0) && ys32;
+      a.pin = kcov == 0 ? nullptr : pbuf[2 * ((L + 1) & 1) + 1];
+      a.p = pbuf[2 * (L & 1) + 1];
+      a.pmid = n == 2 ? pbuf[2 * (L & 1)] : nullptr;
+      a.w2 = (kcov == 0 && w2 && P.s[0] != 0.0) ? w2 : nullptr;
+      a.w2c = P.s[kcov] * w2scale;
+      a.shift = P.shift[kcov];
+      a.shift2 = n == 2 ? P.shift[kcov + 1] : 0.0;
+      a.dk1 = P.d[kcov + 1];
+      a.dk2 = n == 2 ? P.d[kcov + 2] : 0.0;
+      a.slot = L & 1;
+      a.nb_prev = prev_nb;
+      a.k_prev = prev_k;
+      a.nterms_prev = prev_n;
+      a.slot_prev = prev_slot;
       a.decide_only = 0;
-      HIPCHK(launch_leja_step(op->f, T, a, st));
+      if (n == 2) HIPCHK(launch_leja2_step(op->f, T2, a, st));
+      else HIPCHK(launch_leja_step(op->f, T, a, st));
+      lk.push_back(kcov);
+      ln.push_back(n);
+      prev_nb = n == 2 ? T2.nblocks : T.nblocks;
+      prev_k = kcov;
+      prev_n = n;
+      prev_slot = L & 1;
+      kcov += n;
+      ++L;
     }
-    launched += chunk;
-    // decision of the last term of the chunk
+    // decision of the chunk's last launch
     a.ev_start = a.ev_stop = nullptr;
-    a.k = launched;
+    a.k = kcov;
+    a.nterms = 1;
     a.first = 0;
     a.w2 = nullptr;
     a.yin_f32 = ys32;
+    a.nb_prev = prev_nb;
+    a.k_prev = prev_k;
+    a.nterms_prev = prev_n;
+    a.slot_prev = prev_slot;
     a.decide_only = 1;
     HIPCHK(launch_leja_step(op->f, T, a, st));
     RETCHK(read_ctl(op, st));
     if (op->prof) {
-      // launches past the stopping index skipped their work: time the others
-      // (up to and including the one that ran while term m was being decided)
-      const int first_k = launched - chunk;
-      const int worked = op->host_ctl->stop ? op->host_ctl->degree + 1 - first_k : chunk;
-      for (int i = 0; i < chunk && i < worked; ++i) {
+      // launches after the one that ran beside the final decision skipped
+      // their work: time the others
+      const bool stopped = op->host_ctl->stop != 0;
+      const int m = op->host_ctl->degree;
+      bool past = false;
+      for (int l = L0; l < L; ++l) {
+        if (stopped && past) break;
         float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * i], op->evs[2 * i + 1]));
+        HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * (l - L0)], op->evs[2 * (l - L0) + 1]));
         op->prof_ms += ms;
         op->prof_launches += 1;
-        op->prof_bytes += leja_bytes(op, first_k + i, w2 != nullptr && P.s[first_k + i] != 0.0);
+        op->prof_bytes += leja_bytes(op, lk[l], ln[l], lk[l] == 0 && w2 != nullptr && P.s[0] != 0.0);
+        if (lk[l] >= m) past = true;  // this launch ran beside (or after) the final decision
       }
     }
-    if (op->host_ctl->stop || launched >= maxdeg) break;
+    if (op->host_ctl->stop || kcov >= maxdeg) break;
   }
   out.degree = op->host_ctl->degree;
   out.status = op->host_ctl->stop ? op->host_ctl->status : 3;
   if (out.status == 1) {
     P.last_degree = out.degree;
-    if (out.degree == 0) HIPCHK(launch_fill(op->n, p_out, 0.0, st));
-    else if (pbuf[out.degree & 1] != p_out)
-      HIPCHK(launch_axpby(op->n, p_out, 1.0, pbuf[out.degree & 1], 0.0, nullptr, st));
+    if (out.degree == 0) {
+      HIPCHK(launch_fill(op->n, p_out, 0.0, st));
+    } else {
+      double* res = pbuf[slot_of_term(out.degree)];
+      if (res != p_out) HIPCHK(launch_axpby(op->n, p_out, 1.0, res, 0.0, nullptr, st));
+    }
   }
   return ADL_OK;
 }
@@ -570,6 +640,8 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->f.f32 = f32;
   op->t = make_tiling(nx, ny, 0);
   op->t1 = make_tiling(nx, ny, 0, 1);
+  op->t2 = make_tiling2(nx, ny, 0);
+  op->t21 = make_tiling2(nx, ny, 0, 1);
   op->ybuf[0] = base + L.y0;
   op->ybuf[1] = base + L.y1;
   op->p = reinterpret_cast<double*>(base + L.p);
@@ -579,6 +651,9 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->tmp = reinterpret_cast<double*>(base + L.tmp);
   op->tmp2 = reinterpret_cast<double*>(base + L.tmp2);
   op->p2 = reinterpret_cast<double*>(base + L.p2);
+  op->p3 = reinterpret_cast<double*>(base + L.p3);
+  op->p4 = reinterpret_cast<double*>(base + L.p4);
+  op->slot_stride = 6 * (long)max_partial_blocks(nx, ny);
   op->partials = reinterpret_cast<double*>(base + L.partials);
   op->ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&op->host_ctl), 4 * sizeof(Ctl), hipHostMallocDefault);
@@ -658,6 +733,15 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
   if (cols_per_lane == 2 && t.vec != 2) return fail(ADL_EINVAL, "two columns per lane need an even nx >= 128");
   op->t = t;
   op->t1 = make_tiling(op->nx, op->ny, rows, 1);
+  op->t2 = make_tiling2(op->nx, op->ny, rows, cols_per_lane);
+  op->t21 = make_tiling2(op->nx, op->ny, rows, 1);
+  return ADL_OK;
+}
+
+int adl_op_set_term_fusion(adl_op* op, int two_terms) {
+  RETCHK(check_op(op));
+  if (two_terms != 0 && two_terms != 1) return fail(ADL_EINVAL, "two_terms must be 0 or 1");
+  op->fuse_terms = two_terms;
   return ADL_OK;
 }
 

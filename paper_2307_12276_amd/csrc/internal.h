@@ -14,12 +14,21 @@ constexpr int kBlock = 256;             // elementwise and reduction kernels
 #ifndef ADL_WAVES_Y
 #define ADL_WAVES_Y 4
 #endif
-constexpr int kWavesY = ADL_WAVES_Y;     // stencil blocks: waves stacked in y (one strip)
-constexpr int kTileBlock = kWave * kWavesY;
 #ifndef ADL_MAX_GRID
 #define ADL_MAX_GRID 16384
 #endif
-constexpr int kMaxGrid = ADL_MAX_GRID;  // blocks of a stencil launch (grid-stride over tiles)
+#ifndef ADL_WAVES_Y2
+#define ADL_WAVES_Y2 4
+#endif
+#ifndef ADL_MAX_GRID2
+#define ADL_MAX_GRID2 ADL_MAX_GRID
+#endif
+constexpr int kWavesY = ADL_WAVES_Y;     // stencil blocks: waves stacked in y (one strip)
+constexpr int kTileBlock = kWave * kWavesY;
+constexpr int kMaxGrid = ADL_MAX_GRID;   // blocks of a stencil launch (tiles walked per block)
+constexpr int kWavesY2 = ADL_WAVES_Y2;   // two-term kernel: waves (= output rows) per block
+constexpr int kTileBlock2 = kWave * kWavesY2;
+constexpr int kMaxGrid2 = ADL_MAX_GRID2;
 
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
 
@@ -75,30 +84,45 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
                         const double* s1, double a1, const double* s2, double a2,
                         hipStream_t st);
 
+// One launch of a Newton-Leja sweep: terms k+1 .. k+nterms (nterms = 1, or 2
+// for the two-term kernel), plus the stopping decision of the previous
+// launch's terms (taken by block 0).
 struct LejaArgs {
   const void* yin;   // y_k (double at k = 0, else the y storage type)
-  void* yout;        // y_{k+1}
+  void* yout;        // y of the launch's last term
   const double* pin; // p_k (k >= 1; FP64)
-  double* p;         // p_{k+1} (FP64; a different buffer from pin)
-  const double* w2;  // augmented column (k with s_k != 0 only), or null
-  double w2c;        // s_k / h
-  double shift;      // c + gamma xi_k
+  double* p;         // p of the launch's last term (a different buffer from pin)
+  double* pmid;      // two-term launch: p_{k+1}
+  const double* w2;  // augmented column (first term only), or null
+  double w2c;        // s_0 / h
+  double shift;      // c + gamma xi_k   (term k+1)
+  double shift2;     // c + gamma xi_{k+1} (term k+2)
   double invg;       // 1 / gamma
-  double d0, dk1;    // d_0 (first launch), d_{k+1}
+  double d0, dk1, dk2;  // d_0 (first launch), d_{k+1}, d_{k+2}
   double tol2;
-  int k;
+  int k;             // terms before this launch
+  int nterms;        // terms of this launch
   int max_degree;
   int first;         // k == 0: p = d0 y0 + d1 y1, zero-vector test
-  int ystore_f32;    // y_{k+1} stored as float
+  int ystore_f32;    // y stored as float
   int yin_f32;       // y_k stored as float
-  double* partials;  // 2 parities x 3 accumulators x nblocks
-  int nb_prev;       // block count of the previous launch (its partials)
-  int decide_only;   // only take the stopping decision of term k (1-block launch)
+  double* partials;  // two slots of 6 x (max blocks) values
+  long slot_stride;
+  int slot;          // slot written by this launch
+  int nb_prev;       // the decided launch: block count, terms before it, its terms, its slot
+  int k_prev;
+  int nterms_prev;
+  int slot_prev;
+  int decide_only;   // only take the decision of the previous launch (1-block launch)
   Ctl* ctl;
   hipEvent_t ev_start;  // optional: dispatch-attached timing events
   hipEvent_t ev_stop;
 };
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
+// two-term launch (terms k+1, k+2; k >= 1) on the two-term tiling
+hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
+// tiling of the two-term kernel: strips of 62*vec output columns, bands of kWavesY*rows rows
+Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint = 0);
 
 // power iteration launch k: w = A(x) / ||x||, stopping test of iteration k
 struct PowerArgs {

@@ -45,6 +45,9 @@ struct adl_op {
   FieldView f{};
   Tiling t{};   // preferred tiling (two columns per lane when nx is even)
   Tiling t1{};  // one column per lane: used when a caller's vector is not 16-byte aligned
+  Tiling t2{};  // two-term Newton-Leja kernel (two columns per lane when nx is even)
+  Tiling t21{}; // two-term kernel, one column per lane
+  int fuse_terms = 1;  // Newton terms two per launch
   int nx = 0, ny = 0, bc = 0, storage = 0;
   double hx = 0, hy = 0;
   long n = 0;
@@ -69,7 +72,10 @@ struct adl_op {
   double* yacc = nullptr;
   double* tmp = nullptr;
   double* tmp2 = nullptr;
-  double* p2 = nullptr;     // second Newton polynomial buffer (sweeps alternate)
+  double* p2 = nullptr;     // Newton polynomial buffers of a sweep (with the caller's p_out)
+  double* p3 = nullptr;
+  double* p4 = nullptr;
+  long slot_stride = 0;     // doubles per partials slot
   double* partials = nullptr;
   Ctl* ctl = nullptr;
   Ctl* host_ctl = nullptr;  // pinned

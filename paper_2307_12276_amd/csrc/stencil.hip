@@ -201,38 +201,49 @@ struct LejaEp {
   }
 };
 
-// Stopping test of term kprev+1 from the partials of launch kprev, taken by
-// one block (fixed-order totals) and recorded in the control block unless an
-// earlier launch has already stopped the sweep.
-__device__ __forceinline__ void leja_decide(const LejaArgs& A, int kprev) {
-  // the stop flag travels with the partial sums (a fourth, max-reduced
-  // value), so its load and the partial loads are in flight together
-  const double* part = A.partials + (long)(kprev & 1) * 3 * A.nb_prev;
+// Stopping test of the terms of the previous launch (k_prev+1 ..
+// k_prev+nterms_prev, in order) from its block partials, taken by one block
+// (fixed-order totals) and recorded in the control block unless an earlier
+// launch has already stopped the sweep.
+__device__ __forceinline__ void leja_decide(const LejaArgs& A) {
+  // the stop flag travels with the partial sums (a max-reduced value), so its
+  // load and the partial loads are in flight together
+  const double* part = A.partials + (long)A.slot_prev * A.slot_stride;
   const int nb = A.nb_prev;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool two = A.nterms_prev == 2;
+  // tn2 / pn2 of the first and second term (sums), max(|y0|, |w2|), flag (max)
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (threadIdx.x == 0)
-    v[3] = (double)__hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v[5] = (double)__hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   bool any = false;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
     v[0] += part[i];
     v[1] += part[(long)nb + i];
     const double m = part[2L * nb + i];
-    v[2] = any ? nanmax(v[2], m) : m;
+    v[4] = any ? nanmax(v[4], m) : m;
+    if (two) {
+      v[2] += part[3L * nb + i];
+      v[3] += part[4L * nb + i];
+    }
     any = true;
   }
-  block_allreduce<4, 2>(v);
-  if (v[3] != 0.0) return;  // decided by an earlier launch
-  const double tn2 = v[0], pn2 = v[1];
-  const int deg = kprev + 1;
-  int stop = 0, status = 0, degree = deg;
-  if (!isfinite(tn2) || !isfinite(pn2)) {
-    stop = 1; status = 2;
-  } else if (kprev == 0 && v[2] == 0.0) {
-    stop = 1; status = 1; degree = 0;
-  } else if (tn2 <= A.tol2 * pn2) {
-    stop = 1; status = 1;
-  } else if (deg >= A.max_degree) {
-    stop = 1; status = 3;
+  block_allreduce<6, 4>(v);
+  if (v[5] != 0.0) return;  // decided by an earlier launch
+  int stop = 0, status = 0, degree = A.k_prev + A.nterms_prev;
+  double tn2 = 0.0, pn2 = 0.0;
+  for (int t = 0; t < A.nterms_prev && !stop; ++t) {
+    tn2 = t ? v[2] : v[0];
+    pn2 = t ? v[3] : v[1];
+    const int deg = A.k_prev + t + 1;
+    if (!isfinite(tn2) || !isfinite(pn2)) {
+      stop = 1; status = 2; degree = deg;
+    } else if (deg == 1 && v[4] == 0.0) {
+      stop = 1; status = 1; degree = 0;
+    } else if (tn2 <= A.tol2 * pn2) {
+      stop = 1; status = 1; degree = deg;
+    } else if (deg >= A.max_degree) {
+      stop = 1; status = 3; degree = deg;
+    }
   }
   if (threadIdx.x == 0) {
     Ctl* c = A.ctl;
@@ -275,7 +286,7 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
 __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
   if (A.decide_only || blockIdx.x == 0) {
-    if (!FIRST) leja_decide(A, A.k - 1);
+    if (!FIRST) leja_decide(A);
     return;
   }
   const int b = blockIdx.x - 1;
@@ -293,7 +304,188 @@ __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T,
   ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
   ep.stopflag = FIRST ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   stencil_block<TF, TYI, VEC, ADVF>(F, T, reinterpret_cast<const TYI*>(A.yin), ep, b);
-  write_partials<3, 2>(ep.acc, A.partials + (long)(A.k & 1) * 3 * T.nblocks, T.nblocks, b);
+  write_partials<3, 2>(ep.acc, A.partials + (long)A.slot * A.slot_stride, T.nblocks, b);
+}
+
+// ---------------------------------------------------------------------------
+// Two Newton-Leja terms per launch (k >= 1): y_{k+1} is never written to
+// memory.  A block owns a tile of 62*VEC output columns (lanes 1..62 of a
+// wave strip that starts VEC columns to the left of the tile) by kWavesY2
+// output rows, one per wave.  Stage 1 computes y_{k+1} on the tile's rows and
+// a one-row frame above and below (done by the two middle waves) over the
+// strip's 64*VEC columns into LDS; each wave keeps the fields and p_k of its
+// own row in registers.  After a block barrier, stage 2 computes y_{k+2} on
+// the tile from LDS (x-neighbours by the same DPP shifts, the strip's lanes 0
+// and 63 being the one-column frame) and
+// updates p twice: p_{k+1} = p_k + d_{k+1} y_{k+1} (written: it is the result
+// if term k+1 is the last) and p_{k+2} = p_{k+1} + d_{k+2} y_{k+2}.  Per point
+// and pair of terms: read y_k, the fields and p_k, write y_{k+2}, p_{k+1} and
+// p_{k+2} (64 B in FP64 instead of 2 x 56 B).  Frame positions outside a
+// Dirichlet grid hold zero; periodic frames are computed from wrapped loads.
+// Stage 2 reads y_{k+1} from LDS rounded to the y storage type, exactly as
+// the one-term kernel would read it back; p and the norms use it unrounded.
+// ---------------------------------------------------------------------------
+template <typename TY>
+__device__ __forceinline__ double storage_round(double v) {
+  return (double)(TY)v;
+}
+
+// stage 1 epilogue: y_{k+1} of one strip row into LDS (all lanes)
+template <int VEC>
+struct Stage1Ep {
+  struct Extra {};
+  double* lds;   // [rows][64*VEC]
+  int r0;        // grid row of LDS row 0
+  int ny;
+  bool per;
+  double shift, invg;
+  int stopflag;
+  __device__ __forceinline__ bool go() const { return __builtin_amdgcn_readfirstlane(stopflag) == 0; }
+  __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
+  __device__ __forceinline__ void finish(int r, const Strip& g, const double (&Ax)[VEC], const double (&xc)[VEC],
+                                         const Extra&) {
+    const bool ghost = !per && (!g.inside || r < 0 || r >= ny);
+    double* row = lds + (long)(r - r0) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) row[v] = ghost ? 0.0 : (Ax[v] - shift * xc[v]) * invg;
+  }
+};
+
+// y_{k+1} row q of LDS (rounded to the storage type) with its x-neighbours
+template <typename TY, int VEC>
+__device__ __forceinline__ void lds_row_n(const double* lds, int q, RowN<VEC>& o) {
+  const double* row = lds + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = storage_round<TY>(row[v]);
+  o.l = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
+  o.r = dpp_f64<kDppWaveShl1>(o.c[0]);
+}
+
+// The loads of one output row that stage 2 needs again: the fields of rows
+// j-1 .. j+1 and p_k, kept in registers across the block barrier.
+template <int VEC>
+struct Kept {
+  RowN<VEC> m[3], k, ac;
+  RowC<VEC> gg[3], ay[3];
+  double pk[VEC];
+};
+
+// Stage 1 of an output row j (wave-uniform): y_{k+1} at row j into LDS row
+// j - r0, keeping the fields and p_k.  Returns false when the gate is closed.
+template <typename TF, typename TY, int VEC, bool ADVF>
+__device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restrict__ yin, Stage1Ep<VEC>& ep,
+                                           const Strip& g, int j, const double* __restrict__ pin, bool own,
+                                           Kept<VEC>& kp) {
+  const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
+  const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
+  const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
+  const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
+  const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
+  RowN<VEC> u[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    row_n<TY, VEC, MODE_ZERO>(yin, j - 1 + t, F, g, u[t]);
+    row_c<TF, VEC, MODE_EDGE>(kyy, j - 1 + t, F, g, kp.gg[t]);
+    row_n<TF, VEC, MODE_ZERO>(kxy, j - 1 + t, F, g, kp.m[t]);
+    if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, j - 1 + t, F, g, kp.ay[t]);
+  }
+  row_n<TF, VEC, MODE_EDGE>(kxx, j, F, g, kp.k);
+  if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, j, F, g, kp.ac);
+  if (own) ldr<double, VEC>(pin + (long)j * F.nx, g.col0, kp.pk);
+  if (!ep.go()) return false;
+  double Ax[VEC];
+  stencil_point<VEC, ADVF>(u[0], u[1], u[2], kp.gg[0], kp.gg[1], kp.gg[2], kp.m[0], kp.m[1], kp.m[2], kp.k, kp.ac,
+                           kp.ay[0], kp.ay[2], F.axc, F.ayc, Ax);
+  typename Stage1Ep<VEC>::Extra none;
+  ep.finish(j, g, Ax, u[1].c, none);
+  return true;
+}
+
+template <typename TF, typename TY, int VEC, bool ADVF>
+__global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling T, LejaArgs A) {
+  extern __shared__ double lds[];
+  if (A.decide_only || blockIdx.x == 0) {
+    leja_decide(A);
+    return;
+  }
+  const int b = blockIdx.x - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int W = kWave * VEC;
+  const TY* __restrict__ yin = reinterpret_cast<const TY*>(A.yin);
+  TY* __restrict__ yout = reinterpret_cast<TY*>(A.yout);
+  Stage1Ep<VEC> ep1;
+  ep1.lds = lds;
+  ep1.ny = F.ny;
+  ep1.per = F.bc == BC_PERIODIC;
+  ep1.shift = A.shift;
+  ep1.invg = A.invg;
+  ep1.stopflag = __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // term k+1: ||d y||^2, ||p||^2; term k+2: the same
+  bool live = true;
+  const int cb = b % T.ncb;
+  const int rb0 = (b / T.ncb) * T.bands;
+  const int rb1 = min(rb0 + T.bands, T.nrb);
+  const Strip g = strip_at<VEC>(F, cb * (kWave - 2) * VEC - VEC);
+  const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
+#pragma unroll 1
+  for (int rb = rb0; rb < rb1; ++rb) {
+    // one output row per wave: row j = j0 + wave (LDS row wave + 1); the
+    // frame rows j0 - 1 and j0 + kWavesY2 (LDS rows 0 and kWavesY2 + 1) go
+    // to two middle waves
+    const int j0 = rb * kWavesY2;
+    const int j = j0 + wave;
+    const bool has = j < F.ny;
+    ep1.r0 = j0 - 1;
+    // frame rows first, so that no kept registers are live during them
+    const int last = min(j0 + kWavesY2, F.ny);  // frame row below the tile
+    if (live && wave == kWavesY2 / 2 - 1) live = stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, j0 - 1);
+    if (live && wave == kWavesY2 / 2) live = stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, last);
+    Kept<VEC> kp;
+    if (live && has) live = stage1_own<TF, TY, VEC, ADVF>(F, yin, ep1, g, j, A.pin, own, kp);
+    __syncthreads();
+    if (live && has) {
+      RowN<VEC> u[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(lds, wave + t, u[t]);
+      double Ax[VEC];
+      stencil_point<VEC, ADVF>(u[0], u[1], u[2], kp.gg[0], kp.gg[1], kp.gg[2], kp.m[0], kp.m[1], kp.m[2], kp.k,
+                               kp.ac, kp.ay[0], kp.ay[2], F.axc, F.ayc, Ax);
+      if (own) {
+        const long ro = (long)j * F.nx;
+        const double* y1row = lds + (long)(wave + 1) * W + lane * VEC;
+        double y2[VEC], pm[VEC], p2[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double t1 = A.dk1 * y1row[v];
+          pm[v] = kp.pk[v] + t1;
+          y2[v] = (Ax[v] - A.shift2 * u[1].c[v]) * A.invg;
+          const double t2 = A.dk2 * y2[v];
+          p2[v] = pm[v] + t2;
+          acc[0] += t1 * t1;
+          acc[1] += pm[v] * pm[v];
+          acc[2] += t2 * t2;
+          acc[3] += p2[v] * p2[v];
+        }
+        str<TY, VEC>(yout + ro, g.col0, y2);
+        str<double, VEC>(A.pmid + ro, g.col0, pm);
+        str<double, VEC>(A.p + ro, g.col0, p2);
+      }
+    }
+    __syncthreads();
+  }
+  // block partials: term k+1 at (0, 1, 2), term k+2 at (3, 4, 5)
+  block_allreduce<4, 4>(acc);
+  if (threadIdx.x == 0) {
+    double* part = A.partials + (long)A.slot * A.slot_stride;
+    const int nb = T.nblocks;
+    part[0L * nb + b] = acc[0];
+    part[1L * nb + b] = acc[1];
+    part[2L * nb + b] = 0.0;
+    part[3L * nb + b] = acc[2];
+    part[4L * nb + b] = acc[3];
+    part[5L * nb + b] = 0.0;
+  }
 }
 
 // Power iteration term: w_{k+1} = A(w_k) / lambda_k, lambda_k = ||w_k|| from
@@ -501,6 +693,21 @@ Tiling make_tiling(int nx, int ny, int rows_hint, int vec_hint) {
   return t;
 }
 
+Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint) {
+  Tiling t;
+  const bool two = nx % 2 == 0 && nx >= 2 * kWave;
+  t.vec = (vec_hint == 1 || !two) ? 1 : 2;
+  const int wo = (kWave - 2) * t.vec;  // output columns of a strip
+  t.ncb = (nx + wo - 1) / wo;
+  (void)rows_hint;  // one output row per wave
+  t.rows = 1;
+  t.nrb = (ny + kWavesY2 - 1) / kWavesY2;
+  const long per_strip = kMaxGrid2 / t.ncb > 0 ? kMaxGrid2 / t.ncb : 1;
+  t.bands = (int)((t.nrb + per_strip - 1) / per_strip);
+  t.nblocks = t.ncb * ((t.nrb + t.bands - 1) / t.bands);
+  return t;
+}
+
 static inline int ew_blocks(long n) {
   long b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
@@ -570,6 +777,34 @@ hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs&
   ADL_DISPATCH_TILE(t, f, {
     if (f.f32) leja_dispatch_y<float, VEC, ADVF>(f, t, a, st);
     else leja_dispatch_y<double, VEC, ADVF>(f, t, a, st);
+  });
+  return hipGetLastError();
+}
+
+template <typename TF, typename TY, int VEC, bool ADVF>
+static void leja2_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock2);
+  const size_t lds = (size_t)(kWavesY2 + 2) * kWave * VEC * sizeof(double);
+  if (a.ev_start)
+    hipExtLaunchKernelGGL((leja2_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
+  else
+    hipLaunchKernelGGL((leja2_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, f, t, a);
+}
+
+hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if (a.first || a.k < 1 || a.nterms != 2 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32) return hipErrorInvalidValue;
+  if (!a.decide_only && (a.pin == nullptr || a.p == nullptr || a.pmid == nullptr || a.pin == a.p ||
+                         a.pin == a.pmid || a.p == a.pmid))
+    return hipErrorInvalidValue;
+  if ((size_t)(kWavesY2 + 2) * kWave * t.vec * sizeof(double) > 64 * 1024) return hipErrorInvalidValue;
+  ADL_DISPATCH_TILE(t, f, {
+    if (f.f32) {
+      if (a.ystore_f32) leja2_launch<float, float, VEC, ADVF>(f, t, a, st);
+      else leja2_launch<float, double, VEC, ADVF>(f, t, a, st);
+    } else {
+      if (a.ystore_f32) leja2_launch<double, float, VEC, ADVF>(f, t, a, st);
+      else leja2_launch<double, double, VEC, ADVF>(f, t, a, st);
+    }
   });
   return hipGetLastError();
 }

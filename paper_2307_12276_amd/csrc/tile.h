@@ -42,41 +42,53 @@ struct Strip {
   int colc;     // column of this lane's own loads (in the grid)
   int hcol;     // column of this lane's halo load (in the grid)
   bool lane0, lane63;
-  bool inside;  // col0 < nx
+  bool inside;  // 0 <= col0 < nx
   bool useL;    // left neighbour = halo element (lane 0)
-  bool useR;    // right neighbour = halo element (lane 63 inside the grid)
+  bool useR;    // right neighbour = halo element (lane 63)
   bool ghostL;  // Dirichlet: the left neighbour is a ghost column (lane 0 at column 0)
   bool ghostR;  // Dirichlet: the right neighbour is a ghost column (last inside lane)
 };
 
-// Columns and neighbour sources of one lane.  Lane 0 loads its left halo
-// element, lane 63 (when inside) its right one; the other lanes re-read their
-// own column (a cache hit), so all lanes run the same load.  A lane past the
-// right edge of the grid loads, as its own element, the periodic wrap of the
-// last inside lane's right neighbour (column 0), so that the DPP shift
-// delivers it; with Dirichlet boundaries the ghost neighbours are selects
-// (zero, or the edge value for the face averages of kxx and kyy).
+__device__ __forceinline__ int wrap_col(int c, int nx) {
+  const int m = c % nx;
+  return m < 0 ? m + nx : m;
+}
+
+// Columns and neighbour sources of one lane of the strip that starts at
+// column i0 (i0 may be negative and the strip may reach past nx: lanes
+// outside the grid load, as their own elements, the periodic wrap of their
+// columns, or a valid dummy column with Dirichlet boundaries).  Lane 0 loads
+// its left halo element, lane 63 its right one; the other lanes re-read their
+// own column (a cache hit), so all lanes run the same load.  The DPP shifts
+// then deliver every periodic neighbour, and with Dirichlet boundaries the
+// ghost neighbours of the edge columns are selects (zero, or the edge value
+// for the face averages of kxx and kyy).
 template <int VEC>
-__device__ __forceinline__ Strip make_strip(const FieldView& F, int strip) {
+__device__ __forceinline__ Strip strip_at(const FieldView& F, int i0) {
   const int nx = F.nx;
   const bool per = F.bc == BC_PERIODIC;
   Strip g;
   const int lane = threadIdx.x & (kWave - 1);
-  const int i0 = strip * kWave * VEC;
   g.col0 = i0 + lane * VEC;
-  g.inside = g.col0 < nx;
-  g.colc = g.inside ? g.col0 : (per ? 0 : nx - VEC);
+  g.inside = g.col0 >= 0 && g.col0 < nx;
+  g.colc = g.inside ? g.col0 : (per ? wrap_col(g.col0, nx) : (g.col0 < 0 ? 0 : nx - VEC));
   g.lane0 = lane == 0;
   g.lane63 = lane == kWave - 1;
   g.useL = g.lane0;
-  g.useR = g.lane63 && g.inside;
+  g.useR = g.lane63 && (g.inside || per);
   const bool lastin = g.inside && g.col0 + VEC >= nx;
   g.ghostL = !per && g.col0 == 0;
   g.ghostR = !per && lastin;
-  if (g.lane0) g.hcol = g.col0 >= 1 ? g.col0 - 1 : (per ? nx - 1 : g.colc);
-  else if (g.useR) g.hcol = g.col0 + VEC < nx ? g.col0 + VEC : (per ? g.col0 + VEC - nx : g.colc);
+  const int cl = g.col0 - 1, cr = g.col0 + VEC;
+  if (g.lane0) g.hcol = (cl >= 0 && cl < nx) ? cl : (per ? wrap_col(cl, nx) : g.colc);
+  else if (g.useR) g.hcol = (cr >= 0 && cr < nx) ? cr : (per ? wrap_col(cr, nx) : g.colc);
   else g.hcol = g.colc;
   return g;
+}
+
+template <int VEC>
+__device__ __forceinline__ Strip make_strip(const FieldView& F, int strip) {
+  return strip_at<VEC>(F, strip * kWave * VEC);
 }
 
 // ---- row loads -------------------------------------------------------------

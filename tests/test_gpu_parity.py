@@ -250,3 +250,28 @@ def test_deterministic_bitwise():
             gop.quad2_step(u, S, S, w.c1, w.c2, w.dt, w.tol)
         outs.append(to_np(u))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("nx,ny", [(33, 45), (64, 64), (130, 70), (257, 33), (300, 129), (128, 128), (250, 7)])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_two_term_launches_match_one_term_launches(nx, ny, bc, storage):
+    """Two Newton terms per launch (y_{k+1} kept on chip, one-column frames
+    recomputed) give the one-term result: same degree, same polynomial up to
+    the grouping of the norm partial sums."""
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=nx + 7 * ny, field_advection=(storage == 0))
+    hx, hy = 1.0 / nx, 0.8 / ny
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, hx, hy, bc, storage)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    v = to_dev(W.random_vector((ny, nx), 11))
+    dt = 300.0 / abs(alpha)
+    outs, degs = [], []
+    for fuse in (False, True):
+        gop.set_term_fusion(fuse)
+        out = torch.empty_like(v)
+        st = gop.leja_phi(1, dt, v, out, 1e-10)
+        outs.append(to_np(out))
+        degs.append(st["max_degree"])
+    assert degs[0] == degs[1], degs
+    assert rel(outs[1], outs[0]) < 1e-13
