@@ -9,9 +9,9 @@ exponential quadrature c = (1/3, 2/3), dt = 200 dt_CFL, tol 1e-10, FP64.
 Operator setup and the Gershgorin bound happen once, before timing.
 
 Prints one JSON line.  `value` = time steps per second on one GPU.
-`roofline` = the Newton-Leja iteration kernel (the dominant kernel):
-algorithmic bytes per launch / average dispatch-timed duration, against
-8 TB/s.  `cpu_baseline` = the FP64 NumPy oracle, single-threaded, on a
+`roofline` = the Newton-Leja launches (the dominant kernel: two terms per
+launch, the first term of a sweep alone): algorithmic bytes per launch /
+average dispatch-timed duration, against 8 TB/s.  `cpu_baseline` = the FP64 NumPy oracle, single-threaded, on a
 bounded sample of the same workload.  Extra legs: the same kernel on a
 4096 x 4096 grid (working set far beyond the caches).
 """
@@ -110,13 +110,15 @@ def kernel_roofline(op_ms, launches, nbytes):
     return avg_ms, per_launch, achieved
 
 
-def run_roofline_leg(w, storage):
-    """One midpoint step of the stream-function field at n x n: the Leja
-    kernel's dispatch-timed bandwidth on a working set far beyond the caches."""
+def run_roofline_leg(w, storage, two_terms=True):
+    """One midpoint step of the stream-function field at n x n: the
+    Newton-Leja kernels' dispatch-timed bandwidth on a working set far beyond
+    the caches, with two terms per launch (leja2_kernel) or one."""
     import torch
     import paper_2307_12276_amd as A
     n = w.nx
     op = make_op(w, storage)
+    op.set_term_fusion(two_terms)
     op.spectral_bound(A.BOUND_GERSHGORIN)
     u = dev_tensor(w.u0)
     srcs = device_sources(w)
@@ -130,9 +132,12 @@ def run_roofline_leg(w, storage):
     ms, launches, nbytes = op.profile_read()
     op.profile(False)
     avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)
+    terms = st["matvecs"] - 1  # the stage vector's matrix application is not a Newton term
     res = {"workload": w.name, "storage": ["fp64", "fp32-fields", "fp32-fields+y"][storage],
-           "nx": n, "ny": n, "kernel": "leja_kernel", "launches": launches,
-           "bytes_per_launch": per_launch, "avg_kernel_us": avg_ms * 1e3,
+           "launches_of": "two-term" if two_terms else "one-term",
+           "nx": n, "ny": n, "kernel": "leja2_kernel + leja_kernel" if two_terms else "leja_kernel",
+           "launches": launches, "bytes_per_launch": per_launch, "avg_kernel_us": avg_ms * 1e3,
+           "us_per_term": ms * 1e3 / max(terms + 1, 1),
            "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
            "matvecs_per_step": st["matvecs"], "step_ms": wall * 1e3}
     del op
@@ -223,13 +228,14 @@ def chosen_vs_plain(steps=10, tol=1e-9):
     return res
 
 
-def profile_leja(n):
+def profile_leja(n, two_terms=True):
     """One phi_1 sweep on the n x n stream-function field (profiler driver)."""
     import torch
     import paper_2307_12276_amd as A
     import workloads as W
     w = W.roofline_shape(n=n)
     op = make_op(w, A.STORAGE_FP64)
+    op.set_term_fusion(two_terms)
     op.spectral_bound(A.BOUND_GERSHGORIN)
     v = dev_tensor(w.u0)
     out = torch.empty_like(v)
@@ -286,9 +292,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline and bins legs")
     ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
+    ap.add_argument("--one-term", action="store_true", help="with --profile-leja: one Newton term per launch")
     args = ap.parse_args()
     if args.profile_leja:
-        profile_leja(args.profile_leja)
+        profile_leja(args.profile_leja, not args.one_term)
         return
     if args.calibrate_copy:
         calibrate_copy()
@@ -339,7 +346,7 @@ def main():
     ms, launches, nbytes = op.profile_read()
     op.profile(False)
     avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)
-    log("timed %d steps in %.3fs: %.1f steps/s, %.1f matvecs/step; kernel pass: leja kernel %.2f us avg "
+    log("timed %d steps in %.3fs: %.1f steps/s, %.1f matvecs/step; kernel pass: Newton-Leja launches %.2f us avg "
         "over %d launches, %.0f GB/s" % (args.steps, el, value, mv / args.steps, avg_ms * 1e3, launches, achieved))
 
     out = {
@@ -354,7 +361,8 @@ def main():
                    "matvecs_per_step": mv / args.steps, "setup_s": setup_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "leja_kernel", "bytes_per_launch": per_launch,
+                     "kernel": "leja2_kernel (two Newton terms per launch; the first term of a sweep "
+                               "runs in leja_kernel)", "bytes_per_launch": per_launch,
                      "avg_kernel_us": avg_ms * 1e3, "launches": launches,
                      "timing": "HIP events on each Newton-Leja dispatch, second pass of %d steps "
                                "(%.3fs)" % (args.steps, el_prof),
@@ -390,11 +398,11 @@ def main():
         t0 = time.time()
         rw = W.roofline_shape(n=4096)
         log("roofline leg: 4096^2 fields built in %.1fs" % (time.time() - t0))
-        for storage in (A.STORAGE_FP64, A.STORAGE_FP32_FIELDS):
-            legs.append(run_roofline_leg(rw, storage))
-            log("roofline leg %s: %.1f us/iter, %.0f GB/s (%.1f%% of 8 TB/s)" % (
-                legs[-1]["storage"], legs[-1]["avg_kernel_us"], legs[-1]["achieved_GBs"],
-                100 * legs[-1]["frac_of_8TBs"]))
+        for storage, two in ((A.STORAGE_FP64, False), (A.STORAGE_FP64, True), (A.STORAGE_FP32_FIELDS, True)):
+            legs.append(run_roofline_leg(rw, storage, two))
+            log("roofline leg %s %s: %.1f us/launch, %.1f us/term, %.0f GB/s (%.1f%% of 8 TB/s)" % (
+                legs[-1]["storage"], legs[-1]["launches_of"], legs[-1]["avg_kernel_us"],
+                legs[-1]["us_per_term"], legs[-1]["achieved_GBs"], 100 * legs[-1]["frac_of_8TBs"]))
         out["roofline_4096"] = legs
         out["chosen_vs_plain"] = chosen_vs_plain()
 
