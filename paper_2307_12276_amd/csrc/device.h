@@ -1,6 +1,7 @@
-// Device helpers shared by the HIP translation units of libadl:
-// tile remapping across XCDs, row loads with boundary rules, and the
-// fixed-order grid reduction with a last-block ticket.
+// Device helpers shared by the HIP translation units of libadl: vector
+// loads and stores with (row start, column) addressing, the boundary rule for
+// row indices, and the fixed-order grid reduction with a last-block ticket
+// (used by the one-pass kernels: Gershgorin bound, field statistics).
 #pragma once
 
 #include "internal.h"
@@ -10,12 +11,6 @@
 namespace adl {
 
 enum { MODE_ZERO = 0, MODE_EDGE = 1 };
-
-__device__ __forceinline__ int remap_xcd(int b, int nb) {
-  const int x = b & 7, local = b >> 3;
-  const int q = nb >> 3, r = nb & 7;
-  return x * q + (x < r ? x : r) + local;
-}
 
 template <typename T, int VEC>
 __device__ __forceinline__ void load_c(const T* __restrict__ a, long off, double (&c)[VEC]) {

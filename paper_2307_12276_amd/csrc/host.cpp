@@ -297,7 +297,7 @@ static double leja_bytes(const adl_op* op, int k, int n, bool with_w2) {
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
                  double tol, int maxdeg, hipStream_t st, SweepOut& out) {
   if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;
-  HIPCHK(launch_ctl_reset(op->ctl, 1, st));
+  // (the control block is cleared by block 0 of the first launch)
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
   const Tiling& T = tiling_for(op, v, p_out);
   const Tiling& T2 = T.vec == op->t2.vec ? op->t2 : op->t21;
@@ -473,9 +473,11 @@ static int status_to_code(int status) {
 }
 
 // y_acc = dt [phi_1(A dt) w1 + phi_2(A dt) w2] with K fixed substeps.
-// Returns ADL_OK and ok = false if a sweep hit the degree cap.
+// Returns ADL_OK and ok = false if a sweep hit the degree cap.  With one
+// substep and u_direct set, u_direct += dt p is applied instead (one update
+// launch fewer) and `applied` is set.
 static int combo_fixed(adl_op* op, const double* w1, const double* w2, double dt, double tol, int K, Acc& acc,
-                       bool& ok, hipStream_t st) {
+                       bool& ok, hipStream_t st, double* u_direct = nullptr, bool* applied = nullptr) {
   const double h = dt / K;
   Plan& P = get_plan(op, 1, op->alpha, h);
   ok = true;
@@ -495,15 +497,26 @@ static int combo_fixed(adl_op* op, const double* w1, const double* w2, double dt
       ok = false;
       return ADL_OK;
     }
-    if (j == 0) HIPCHK(launch_axpby(op->n, op->yacc, h, op->p, 0.0, nullptr, st));
-    else HIPCHK(launch_axpby(op->n, op->yacc, 1.0, op->yacc, h, op->p, st));
+    if (K == 1 && u_direct) {
+      HIPCHK(launch_axpby(op->n, u_direct, 1.0, u_direct, h, op->p, st));
+      *applied = true;
+    } else if (j == 0) {
+      HIPCHK(launch_axpby(op->n, op->yacc, h, op->p, 0.0, nullptr, st));
+    } else {
+      HIPCHK(launch_axpby(op->n, op->yacc, 1.0, op->yacc, h, op->p, st));
+    }
   }
   return ADL_OK;
 }
 
-// y_acc = dt [phi_1(A dt) w1 + phi_2(A dt) w2]  (w2 may be null)
+// y_acc = dt [phi_1(A dt) w1 + phi_2(A dt) w2]  (w2 may be null); with
+// u_direct set, a one-substep result may instead be added to u_direct
+// directly (`applied` tells which happened).
 static int phi_combo(adl_op* op, const double* w1, const double* w2, double dt, double tol, Acc& acc,
-                     hipStream_t st) {
+                     hipStream_t st, double* u_direct = nullptr, bool* applied = nullptr) {
+  bool dummy = false;
+  if (!applied) applied = &dummy;
+  *applied = false;
   if (op->alpha == 0.0) {
     HIPCHK(launch_axpby(op->n, op->yacc, dt, w1, w2 ? 0.5 * dt : 0.0, w2, st));
     acc.substeps = 0;
@@ -513,7 +526,7 @@ static int phi_combo(adl_op* op, const double* w1, const double* w2, double dt, 
   if (op->learned) K = std::max(K, op->substeps_hint);
   for (int d = 0; d <= kMaxDoublings; ++d) {
     bool ok;
-    RETCHK(combo_fixed(op, w1, w2, dt, tol, K, acc, ok, st));
+    RETCHK(combo_fixed(op, w1, w2, dt, tol, K, acc, ok, st, u_direct, applied));
     if (ok) {
       acc.substeps = K;
       return ADL_OK;
@@ -949,8 +962,9 @@ static int midpoint_impl(adl_op* op, double* u, const double* S_half, double dt,
   // w = A u + S(t + dt/2)
   HIPCHK(launch_apply(op->f, tiling_for(op, u, S_half), u, op->w1, S_half, 1.0, nullptr, 0.0, st));
   acc.matvecs += 1;
-  int code = phi_combo(op, op->w1, nullptr, dt, tol, acc, st);
-  if (code == ADL_OK) {
+  bool applied = false;
+  int code = phi_combo(op, op->w1, nullptr, dt, tol, acc, st, u, &applied);
+  if (code == ADL_OK && !applied) {
     hipError_t e = launch_axpby(op->n, u, 1.0, u, 1.0, op->yacc, st);
     if (e != hipSuccess) code = fail(ADL_EHIP, "update failed: %s", hipGetErrorString(e));
   }
@@ -969,19 +983,25 @@ static int quad2_impl(adl_op* op, double* u, const double* S1, const double* S2,
   hipStream_t st = S(stream);
   Acc acc;
   const double inv = 1.0 / (c2 - c1);
-  // w1 = A u + (c2 S1 - c1 S2)/(c2 - c1),  w2 = (S2 - S1)/(c2 - c1)
-  HIPCHK(launch_apply(op->f, tiling_for(op, u, S1, S2), u, op->w1, S1, c2 * inv, S2, -c1 * inv, st));
-  acc.matvecs += 1;
+  // w1 = A u + (c2 S1 - c1 S2)/(c2 - c1),  w2 = (S2 - S1)/(c2 - c1) (the
+  // difference taken first; with both sources, w2 is a second output of the
+  // stage launch)
   const double* w2 = nullptr;
-  if (S1 || S2) {
-    if (S1 && S2) HIPCHK(launch_diff_scale(op->n, op->w2, S2, S1, inv, st));
-    else if (S2) HIPCHK(launch_axpby(op->n, op->w2, inv, S2, 0.0, nullptr, st));
-    else HIPCHK(launch_axpby(op->n, op->w2, -inv, S1, 0.0, nullptr, st));
+  if (S1 && S2) {
+    HIPCHK(launch_apply2(op->f, tiling_for(op, u, S1, S2), u, op->w1, S1, c2 * inv, S2, -c1 * inv, op->w2, inv,
+                         st));
     w2 = op->w2;
+  } else {
+    HIPCHK(launch_apply(op->f, tiling_for(op, u, S1, S2), u, op->w1, S1, c2 * inv, S2, -c1 * inv, st));
+    if (S2) HIPCHK(launch_axpby(op->n, op->w2, inv, S2, 0.0, nullptr, st));
+    else if (S1) HIPCHK(launch_axpby(op->n, op->w2, -inv, S1, 0.0, nullptr, st));
+    if (S1 || S2) w2 = op->w2;
   }
+  acc.matvecs += 1;
   int code = ADL_OK;
+  bool applied = false;
   if (op->quad2_mode == ADL_QUAD2_AUGMENTED || op->alpha == 0.0) {
-    code = phi_combo(op, op->w1, w2, dt, tol, acc, st);
+    code = phi_combo(op, op->w1, w2, dt, tol, acc, st, u, &applied);
   } else {
     // two sweeps: dt (phi_1 w1 + phi_2 w2)
     adl_stats s1{}, s2{};
@@ -1010,7 +1030,7 @@ static int quad2_impl(adl_op* op, double* u, const double* S1, const double* S2,
       }
     }
   }
-  if (code == ADL_OK) {
+  if (code == ADL_OK && !applied) {
     hipError_t e = launch_axpby(op->n, u, 1.0, u, 1.0, op->yacc, st);
     if (e != hipSuccess) code = fail(ADL_EHIP, "update failed: %s", hipGetErrorString(e));
   }

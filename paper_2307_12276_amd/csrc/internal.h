@@ -83,6 +83,10 @@ Tiling make_tiling(int nx, int ny, int rows_hint, int vec_hint = 0);
 hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, double* y,
                         const double* s1, double a1, const double* s2, double a2,
                         hipStream_t st);
+// the same, and y2 = (s2 - s1) d2 as a second output (s1, s2 required)
+hipError_t launch_apply2(const FieldView& f, const Tiling& t, const double* x, double* y,
+                         const double* s1, double a1, const double* s2, double a2, double* y2, double d2,
+                         hipStream_t st);
 
 // One launch of a Newton-Leja sweep: terms k+1 .. k+nterms (nterms = 1, or 2
 // for the two-term kernel), plus the stopping decision of the previous

@@ -119,6 +119,8 @@ struct ApplyEp {
   const double* __restrict__ s1;
   const double* __restrict__ s2;
   double a1, a2;
+  double* __restrict__ out2;  // optional second output (s2 - s1) * d2, difference first
+  double d2;
   __device__ __forceinline__ bool go() const { return true; }
   __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
     if (!g.inside) return;
@@ -138,6 +140,15 @@ struct ApplyEp {
       if (s2) r[v] += a2 * e.s2[v];
     }
     str<double, VEC>(out + ro, g.col0, r);
+    if (out2) {
+      double q[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const double dlt = e.s2[v] - e.s1[v];
+        q[v] = dlt * d2;
+      }
+      str<double, VEC>(out2 + ro, g.col0, q);
+    }
   }
 };
 
@@ -286,7 +297,13 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
 __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
   if (A.decide_only || blockIdx.x == 0) {
-    if (!FIRST) leja_decide(A);
+    if (!FIRST) {
+      leja_decide(A);
+    } else if (threadIdx.x == 0) {
+      // a new sweep: clear the control block (no block of this launch reads it)
+      Ctl c{};
+      *A.ctl = c;
+    }
     return;
   }
   const int b = blockIdx.x - 1;
@@ -729,8 +746,9 @@ static inline int ew_blocks(long n) {
     }                                                                 \
   } while (0)
 
-hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, double* y, const double* s1,
-                        double a1, const double* s2, double a2, hipStream_t st) {
+hipError_t launch_apply2(const FieldView& f, const Tiling& t, const double* x, double* y, const double* s1,
+                         double a1, const double* s2, double a2, double* y2, double d2, hipStream_t st) {
+  if (y2 && (!s1 || !s2)) return hipErrorInvalidValue;
   ADL_DISPATCH_TILE(t, f, {
     ApplyEp<VEC> ep;
     ep.nx = f.nx;
@@ -739,12 +757,19 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
     ep.s2 = s2;
     ep.a1 = a1;
     ep.a2 = a2;
+    ep.out2 = y2;
+    ep.d2 = d2;
     if (f.f32)
       hipLaunchKernelGGL((apply_kernel<float, VEC, ADVF>), dim3(t.nblocks), dim3(kTileBlock), 0, st, f, t, x, ep);
     else
       hipLaunchKernelGGL((apply_kernel<double, VEC, ADVF>), dim3(t.nblocks), dim3(kTileBlock), 0, st, f, t, x, ep);
   });
   return hipGetLastError();
+}
+
+hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, double* y, const double* s1,
+                        double a1, const double* s2, double a2, hipStream_t st) {
+  return launch_apply2(f, t, x, y, s1, a1, s2, a2, nullptr, 0.0, st);
 }
 
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
