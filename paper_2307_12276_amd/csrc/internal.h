@@ -21,7 +21,7 @@ constexpr int kBlock = 256;             // elementwise and reduction kernels
 #define ADL_WAVES_Y2 4
 #endif
 #ifndef ADL_MAX_GRID2
-#define ADL_MAX_GRID2 ADL_MAX_GRID
+#define ADL_MAX_GRID2 4096
 #endif
 constexpr int kWavesY = ADL_WAVES_Y;     // stencil blocks: waves stacked in y (one strip)
 constexpr int kTileBlock = kWave * kWavesY;

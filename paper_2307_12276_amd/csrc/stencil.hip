@@ -326,14 +326,14 @@ __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T,
 
 // ---------------------------------------------------------------------------
 // Two Newton-Leja terms per launch (k >= 1): y_{k+1} is never written to
-// memory.  A block owns a tile of 62*VEC output columns (lanes 1..62 of a
-// wave strip that starts VEC columns to the left of the tile) by kWavesY2
-// output rows, one per wave.  Stage 1 computes y_{k+1} on the tile's rows and
-// a one-row frame above and below (done by the two middle waves) over the
-// strip's 64*VEC columns into LDS; each wave keeps the fields and p_k of its
-// own row in registers.  After a block barrier, stage 2 computes y_{k+2} on
-// the tile from LDS (x-neighbours by the same DPP shifts, the strip's lanes 0
-// and 63 being the one-column frame) and
+// memory.  A block owns a strip of 62*VEC output columns (lanes 1..62 of a
+// wave strip that starts VEC columns to the left; lanes 0 and 63 are the
+// one-column frame) and marches down a run of row bands, one output row per
+// wave per step.  Stage 1 computes y_{k+1} on the step's rows over the
+// strip's 64*VEC columns into an LDS ring, each wave keeping the fields and
+// p_k of its own row in registers; the one-row frame above is already in the
+// ring and one wave adds the frame row below.  After a block barrier, stage 2
+// computes y_{k+2} from the ring (x-neighbours by the same DPP shifts) and
 // updates p twice: p_{k+1} = p_k + d_{k+1} y_{k+1} (written: it is the result
 // if term k+1 is the last) and p_{k+2} = p_{k+1} + d_{k+2} y_{k+2}.  Per point
 // and pair of terms: read y_k, the fields and p_k, write y_{k+2}, p_{k+1} and
@@ -347,12 +347,15 @@ __device__ __forceinline__ double storage_round(double v) {
   return (double)(TY)v;
 }
 
-// stage 1 epilogue: y_{k+1} of one strip row into LDS (all lanes)
+// stage 1 epilogue: y_{k+1} of one strip row into the LDS ring (all lanes)
+constexpr int kRing = 8;  // slots of the LDS ring of y_{k+1} rows (a power of two)
+static_assert(kRing >= 2 * kWavesY2, "a step writes its rows and the frame below while the previous step's "
+                                     "rows are still read");
 template <int VEC>
 struct Stage1Ep {
   struct Extra {};
-  double* lds;   // [rows][64*VEC]
-  int r0;        // grid row of LDS row 0
+  double* lds;   // [kRing][64*VEC]: row r in slot (r - r0) mod kRing
+  int r0;        // grid row of slot 0 (the row above the block's first tile)
   int ny;
   bool per;
   double shift, invg;
@@ -362,7 +365,7 @@ struct Stage1Ep {
   __device__ __forceinline__ void finish(int r, const Strip& g, const double (&Ax)[VEC], const double (&xc)[VEC],
                                          const Extra&) {
     const bool ghost = !per && (!g.inside || r < 0 || r >= ny);
-    double* row = lds + (long)(r - r0) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+    double* row = lds + (long)((r - r0) & (kRing - 1)) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) row[v] = ghost ? 0.0 : (Ax[v] - shift * xc[v]) * invg;
   }
@@ -418,6 +421,12 @@ __device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restr
   return true;
 }
 
+// The block marches down its run of row bands, kWavesY2 output rows per
+// step: stage 1 of a step computes the step's own rows (keeping their fields)
+// and the frame row below them into the LDS ring; the frame row above is the
+// previous step's last own row, already in the ring (a prologue computes it
+// for the first step).  The frame row below is computed again as the next
+// step's first own row, from input rows this CU has just read.
 template <typename TF, typename TY, int VEC, bool ADVF>
 __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ double lds[];
@@ -445,32 +454,33 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
   const int rb1 = min(rb0 + T.bands, T.nrb);
   const Strip g = strip_at<VEC>(F, cb * (kWave - 2) * VEC - VEC);
   const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
+  const int J0 = rb0 * kWavesY2;
+  ep1.r0 = J0 - 1;
+  // prologue: the frame row above the run
+  constexpr int wfr = kWavesY2 / 2;  // the wave that computes frame rows
+  if (wave == wfr - 1) live = stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, J0 - 1);
 #pragma unroll 1
   for (int rb = rb0; rb < rb1; ++rb) {
-    // one output row per wave: row j = j0 + wave (LDS row wave + 1); the
-    // frame rows j0 - 1 and j0 + kWavesY2 (LDS rows 0 and kWavesY2 + 1) go
-    // to two middle waves
+    // own row j = j0 + wave; the frame row below (j0 + kWavesY2) first, so
+    // that no kept registers are live during it
     const int j0 = rb * kWavesY2;
     const int j = j0 + wave;
-    const bool has = j < F.ny;
-    ep1.r0 = j0 - 1;
-    // frame rows first, so that no kept registers are live during them
-    const int last = min(j0 + kWavesY2, F.ny);  // frame row below the tile
-    if (live && wave == kWavesY2 / 2 - 1) live = stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, j0 - 1);
-    if (live && wave == kWavesY2 / 2) live = stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, last);
+    const bool has = wave < kWavesY2 && j < F.ny;
+    const int below = min(j0 + kWavesY2, F.ny);
+    if (live && wave == wfr) live = stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, below);
     Kept<VEC> kp;
     if (live && has) live = stage1_own<TF, TY, VEC, ADVF>(F, yin, ep1, g, j, A.pin, own, kp);
     __syncthreads();
     if (live && has) {
       RowN<VEC> u[3];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(lds, wave + t, u[t]);
+      for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(lds, (j - 1 + t - ep1.r0) & (kRing - 1), u[t]);
       double Ax[VEC];
       stencil_point<VEC, ADVF>(u[0], u[1], u[2], kp.gg[0], kp.gg[1], kp.gg[2], kp.m[0], kp.m[1], kp.m[2], kp.k,
                                kp.ac, kp.ay[0], kp.ay[2], F.axc, F.ayc, Ax);
       if (own) {
         const long ro = (long)j * F.nx;
-        const double* y1row = lds + (long)(wave + 1) * W + lane * VEC;
+        const double* y1row = lds + (long)((j - ep1.r0) & (kRing - 1)) * W + lane * VEC;
         double y2[VEC], pm[VEC], p2[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
@@ -809,7 +819,7 @@ hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs&
 template <typename TF, typename TY, int VEC, bool ADVF>
 static void leja2_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
   const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock2);
-  const size_t lds = (size_t)(kWavesY2 + 2) * kWave * VEC * sizeof(double);
+  const size_t lds = (size_t)kRing * kWave * VEC * sizeof(double);
   if (a.ev_start)
     hipExtLaunchKernelGGL((leja2_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
   else
@@ -821,7 +831,6 @@ hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs
   if (!a.decide_only && (a.pin == nullptr || a.p == nullptr || a.pmid == nullptr || a.pin == a.p ||
                          a.pin == a.pmid || a.p == a.pmid))
     return hipErrorInvalidValue;
-  if ((size_t)(kWavesY2 + 2) * kWave * t.vec * sizeof(double) > 64 * 1024) return hipErrorInvalidValue;
   ADL_DISPATCH_TILE(t, f, {
     if (f.f32) {
       if (a.ystore_f32) leja2_launch<float, float, VEC, ADVF>(f, t, a, st);
