@@ -381,17 +381,45 @@ __device__ __forceinline__ void lds_row_n(const double* lds, int q, RowN<VEC>& o
   o.r = dpp_f64<kDppWaveShl1>(o.c[0]);
 }
 
-// The loads of one output row that stage 2 needs again: the fields of rows
-// j-1 .. j+1 and p_k, kept in registers across the block barrier.
+// What stage 2 of an output row j needs again from its stage-1 loads: the
+// face coefficients of the nine-point stencil at row j (0.5 (kxx_C + kxx_E)
+// etc., kxy at the four neighbours, the advection face values) and p_k, kept
+// in registers across the block barrier.
 template <int VEC>
 struct Kept {
-  RowN<VEC> m[3], k, ac;
-  RowC<VEC> gg[3], ay[3];
+  double fE[VEC], fW[VEC], fN[VEC], fS[VEC];
+  double mE[VEC], mW[VEC], mN[VEC], mS[VEC];
+  double aE[VEC], aW[VEC], aN[VEC], aS[VEC];
   double pk[VEC];
 };
 
-// Stage 1 of an output row j (wave-uniform): y_{k+1} at row j into LDS row
-// j - r0, keeping the fields and p_k.  Returns false when the gate is closed.
+// (A x) at row j from the kept coefficients and rows j-1, j, j+1 of x
+// (the operation order of stencil_point)
+template <int VEC, bool ADVF>
+__device__ __forceinline__ void stencil_kept(const Kept<VEC>& kp, const RowN<VEC>& um, const RowN<VEC>& uc,
+                                             const RowN<VEC>& up, double axc, double ayc, double (&Ax)[VEC]) {
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const double uC = uc.at(v), uW = uc.west(v), uE = uc.east(v);
+    const double uN = up.at(v), uS = um.at(v);
+    const double uNW = up.west(v), uNE = up.east(v);
+    const double uSW = um.west(v), uSE = um.east(v);
+    double a = kp.fE[v] * (uE - uC) - kp.fW[v] * (uC - uW);
+    a += kp.fN[v] * (uN - uC) - kp.fS[v] * (uC - uS);
+    a += kp.mE[v] * (uNE - uSE) - kp.mW[v] * (uNW - uSW);
+    a += kp.mN[v] * (uNE - uNW) - kp.mS[v] * (uSE - uSW);
+    if constexpr (ADVF) {
+      a += kp.aE[v] * uE - kp.aW[v] * uW + kp.aN[v] * uN - kp.aS[v] * uS;
+    } else {
+      a += axc * (uE - uW) + ayc * (uN - uS);
+    }
+    Ax[v] = a;
+  }
+}
+
+// Stage 1 of an output row j (wave-uniform): y_{k+1} at row j into the LDS
+// ring, keeping the face coefficients and p_k.  Returns false when the gate
+// is closed.
 template <typename TF, typename TY, int VEC, bool ADVF>
 __device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restrict__ yin, Stage1Ep<VEC>& ep,
                                            const Strip& g, int j, const double* __restrict__ pin, bool own,
@@ -401,21 +429,40 @@ __device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restr
   const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
   const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
   const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
-  RowN<VEC> u[3];
+  RowN<VEC> u[3], m[3], k, ac;
+  RowC<VEC> gg[3], ay[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
     row_n<TY, VEC, MODE_ZERO>(yin, j - 1 + t, F, g, u[t]);
-    row_c<TF, VEC, MODE_EDGE>(kyy, j - 1 + t, F, g, kp.gg[t]);
-    row_n<TF, VEC, MODE_ZERO>(kxy, j - 1 + t, F, g, kp.m[t]);
-    if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, j - 1 + t, F, g, kp.ay[t]);
+    row_c<TF, VEC, MODE_EDGE>(kyy, j - 1 + t, F, g, gg[t]);
+    row_n<TF, VEC, MODE_ZERO>(kxy, j - 1 + t, F, g, m[t]);
+    if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, j - 1 + t, F, g, ay[t]);
   }
-  row_n<TF, VEC, MODE_EDGE>(kxx, j, F, g, kp.k);
-  if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, j, F, g, kp.ac);
+  row_n<TF, VEC, MODE_EDGE>(kxx, j, F, g, k);
+  if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, j, F, g, ac);
   if (own) ldr<double, VEC>(pin + (long)j * F.nx, g.col0, kp.pk);
   if (!ep.go()) return false;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const double kC = k.at(v), kW = k.west(v), kE = k.east(v);
+    const double gC = gg[1].c[v], gN = gg[2].c[v], gS = gg[0].c[v];
+    kp.fE[v] = 0.5 * (kC + kE);
+    kp.fW[v] = 0.5 * (kC + kW);
+    kp.fN[v] = 0.5 * (gC + gN);
+    kp.fS[v] = 0.5 * (gC + gS);
+    kp.mE[v] = m[1].east(v);
+    kp.mW[v] = m[1].west(v);
+    kp.mN[v] = m[2].at(v);
+    kp.mS[v] = m[0].at(v);
+    if constexpr (ADVF) {
+      kp.aE[v] = ac.east(v);
+      kp.aW[v] = ac.west(v);
+      kp.aN[v] = ay[2].c[v];
+      kp.aS[v] = ay[0].c[v];
+    }
+  }
   double Ax[VEC];
-  stencil_point<VEC, ADVF>(u[0], u[1], u[2], kp.gg[0], kp.gg[1], kp.gg[2], kp.m[0], kp.m[1], kp.m[2], kp.k, kp.ac,
-                           kp.ay[0], kp.ay[2], F.axc, F.ayc, Ax);
+  stencil_kept<VEC, ADVF>(kp, u[0], u[1], u[2], F.axc, F.ayc, Ax);
   typename Stage1Ep<VEC>::Extra none;
   ep.finish(j, g, Ax, u[1].c, none);
   return true;
@@ -476,8 +523,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
 #pragma unroll
       for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(lds, (j - 1 + t - ep1.r0) & (kRing - 1), u[t]);
       double Ax[VEC];
-      stencil_point<VEC, ADVF>(u[0], u[1], u[2], kp.gg[0], kp.gg[1], kp.gg[2], kp.m[0], kp.m[1], kp.m[2], kp.k,
-                               kp.ac, kp.ay[0], kp.ay[2], F.axc, F.ayc, Ax);
+      stencil_kept<VEC, ADVF>(kp, u[0], u[1], u[2], F.axc, F.ayc, Ax);
       if (own) {
         const long ro = (long)j * F.nx;
         const double* y1row = lds + (long)((j - ep1.r0) & (kRing - 1)) * W + lane * VEC;
