@@ -148,6 +148,15 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
  * block partial sums of the norms are grouped differently).  ADL_EINVAL for
  * other values. */
 int adl_op_set_term_fusion(adl_op* op, int two_terms);
+
+/* Cache hints of the Newton-Leja launches: mode = 1 marks the vectors a
+ * launch reads or writes exactly once (p_k, y and p of its terms) as
+ * non-temporal, so that on grids far beyond the caches the rows re-read by
+ * neighbouring tiles stay in L2; mode = 0 uses ordinary loads and stores;
+ * mode = -1 (the default) chooses 1 when the sweep's working set (fields,
+ * the input vector, two y and four p buffers) exceeds 512 MiB.  Results are
+ * identical in every mode.  ADL_EINVAL for other values. */
+int adl_op_set_streaming(adl_op* op, int mode);
 int adl_op_get_tiling(const adl_op* op, int* cols_per_lane, int* rows, int* nblocks);
 
 /* y = A x (one stencil application).  x, y: device [ny][nx] FP64, not

@@ -73,6 +73,7 @@ _SIG = {
     "adl_op_profile": (_I, [_P, _I]),
     "adl_op_set_tiling": (_I, [_P, _I, _I]),
     "adl_op_set_term_fusion": (_I, [_P, _I]),
+    "adl_op_set_streaming": (_I, [_P, _I]),
     "adl_op_get_tiling": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "adl_op_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(_D)]),
@@ -225,6 +226,10 @@ class Op:
 
     def set_term_fusion(self, two_terms: bool = True):
         _check(lib().adl_op_set_term_fusion(self.handle, int(bool(two_terms))))
+
+    def set_streaming(self, mode: int = -1):
+        """Non-temporal hints on the Newton vectors: -1 auto, 0 off, 1 on."""
+        _check(lib().adl_op_set_streaming(self.handle, int(mode)))
 
     def get_tiling(self):
         v, r, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

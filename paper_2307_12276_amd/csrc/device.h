@@ -73,6 +73,53 @@ __device__ __forceinline__ void str(T* rowp, int col, const double (&c)[VEC]) {
   store_c<T, VEC>(at_col(rowp, col), 0, c);
 }
 
+// Forms for vectors that one launch reads or writes exactly once (p_k in,
+// y and p out), with the non-temporal hint when NT is set: on working sets
+// beyond the caches their lines then go first, so the rows that
+// neighbouring waves re-read stay in L2.  (A template parameter, not a
+// runtime flag: the compiler merges the two forms of a runtime branch and
+// drops the hint.)
+template <bool NT, typename T, int VEC>
+__device__ __forceinline__ void ldr_s(const T* rowp, int col, double (&c)[VEC]) {
+  const T* a = at_col(rowp, col);
+  if constexpr (!NT) {
+    load_c<T, VEC>(a, 0, c);
+  } else if constexpr (VEC == 1) {
+    c[0] = (double)__builtin_nontemporal_load(a);
+  } else if constexpr (sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(a));
+    c[0] = v.x;
+    c[1] = v.y;
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(a));
+    c[0] = (double)v.x;
+    c[1] = (double)v.y;
+  }
+}
+template <bool NT, typename T, int VEC>
+__device__ __forceinline__ void str_s(T* rowp, int col, const double (&c)[VEC]) {
+  T* a = at_col(rowp, col);
+  if constexpr (!NT) {
+    store_c<T, VEC>(a, 0, c);
+  } else if constexpr (VEC == 1) {
+    __builtin_nontemporal_store((T)c[0], a);
+  } else if constexpr (sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 v;
+    v.x = c[0];
+    v.y = c[1];
+    __builtin_nontemporal_store(v, reinterpret_cast<d2*>(a));
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 v;
+    v.x = (float)c[0];
+    v.y = (float)c[1];
+    __builtin_nontemporal_store(v, reinterpret_cast<f2*>(a));
+  }
+}
+
 // Row index after the boundary rule; zero = the whole row is a zero ghost row.
 __device__ __forceinline__ int map_row(int r, int ny, int bc, int mode, bool& zero) {
   zero = false;

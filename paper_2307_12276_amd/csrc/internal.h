@@ -110,6 +110,7 @@ struct LejaArgs {
   int first;         // k == 0: p = d0 y0 + d1 y1, zero-vector test
   int ystore_f32;    // y stored as float
   int yin_f32;       // y_k stored as float
+  int stream;        // non-temporal hints on p_k and the written vectors
   double* partials;  // two slots of 6 x (max blocks) values
   long slot_stride;
   int slot;          // slot written by this launch

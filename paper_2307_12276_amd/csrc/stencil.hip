@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kTileBlock) void apply_kernel(FieldView F, Tiling T
 
 // One Newton-Leja term (fused): y' = (A y + w2c w2 - shift y) invg,
 // p' = p + d_{k+1} y'  (p = d_0 y at k = 0); partial norms of d y' and p'.
-template <typename TYO, int VEC, bool FIRST>
+template <typename TYO, int VEC, bool FIRST, bool NT>
 struct LejaEp {
   struct Extra {
     double p[VEC];
@@ -181,7 +181,7 @@ struct LejaEp {
     if constexpr (FIRST) {
       if (w2) ldr<double, VEC>(w2 + ro, g.col0, e.w);
     } else {
-      ldr<double, VEC>(pin + ro, g.col0, e.p);
+      ldr_s<NT, double, VEC>(pin + ro, g.col0, e.p);
     }
   }
   __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&yc)[VEC],
@@ -207,8 +207,8 @@ struct LejaEp {
         if (w2) acc[2] = nanmax(acc[2], fabs(e.w[v]));
       }
     }
-    str<TYO, VEC>(yout + ro, g.col0, yn);
-    str<double, VEC>(p + ro, g.col0, pn);
+    str_s<NT, TYO, VEC>(yout + ro, g.col0, yn);
+    str_s<NT, double, VEC>(p + ro, g.col0, pn);
   }
 };
 
@@ -294,7 +294,7 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
 // The first term of a sweep (y_0 = v in FP64, the augmented column w2, the
 // zero-vector check) is a kernel of its own, so that the other terms'
 // register allocation does not carry its extra state.
-template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
+template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST, bool NT>
 __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
   if (A.decide_only || blockIdx.x == 0) {
     if (!FIRST) {
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T,
     return;
   }
   const int b = blockIdx.x - 1;
-  LejaEp<TYO, VEC, FIRST> ep;
+  LejaEp<TYO, VEC, FIRST, NT> ep;
   ep.nx = F.nx;
   ep.yout = reinterpret_cast<TYO*>(A.yout);
   ep.pin = FIRST ? nullptr : A.pin;
@@ -330,8 +330,8 @@ __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T,
 // wave strip that starts VEC columns to the left; lanes 0 and 63 are the
 // one-column frame) and marches down a run of row bands, one output row per
 // wave per step.  Stage 1 computes y_{k+1} on the step's rows over the
-// strip's 64*VEC columns into an LDS ring, each wave keeping the fields and
-// p_k of its own row in registers; the one-row frame above is already in the
+// strip's 64*VEC columns into an LDS ring, each wave keeping the face
+// coefficients and p_k of its own row in registers; the one-row frame above is already in the
 // ring and one wave adds the frame row below.  After a block barrier, stage 2
 // computes y_{k+2} from the ring (x-neighbours by the same DPP shifts) and
 // updates p twice: p_{k+1} = p_k + d_{k+1} y_{k+1} (written: it is the result
@@ -420,7 +420,7 @@ __device__ __forceinline__ void stencil_kept(const Kept<VEC>& kp, const RowN<VEC
 // Stage 1 of an output row j (wave-uniform): y_{k+1} at row j into the LDS
 // ring, keeping the face coefficients and p_k.  Returns false when the gate
 // is closed.
-template <typename TF, typename TY, int VEC, bool ADVF>
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 __device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restrict__ yin, Stage1Ep<VEC>& ep,
                                            const Strip& g, int j, const double* __restrict__ pin, bool own,
                                            Kept<VEC>& kp) {
@@ -440,7 +440,7 @@ __device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restr
   }
   row_n<TF, VEC, MODE_EDGE>(kxx, j, F, g, k);
   if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, j, F, g, ac);
-  if (own) ldr<double, VEC>(pin + (long)j * F.nx, g.col0, kp.pk);
+  if (own) ldr_s<NT, double, VEC>(pin + (long)j * F.nx, g.col0, kp.pk);
   if (!ep.go()) return false;
 #pragma unroll
   for (int v = 0; v < VEC; ++v) {
@@ -474,7 +474,7 @@ __device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restr
 // previous step's last own row, already in the ring (a prologue computes it
 // for the first step).  The frame row below is computed again as the next
 // step's first own row, from input rows this CU has just read.
-template <typename TF, typename TY, int VEC, bool ADVF>
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ double lds[];
   if (A.decide_only || blockIdx.x == 0) {
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
     const int below = min(j0 + kWavesY2, F.ny);
     if (live && wave == wfr) live = stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, below);
     Kept<VEC> kp;
-    if (live && has) live = stage1_own<TF, TY, VEC, ADVF>(F, yin, ep1, g, j, A.pin, own, kp);
+    if (live && has) live = stage1_own<TF, TY, VEC, ADVF, NT>(F, yin, ep1, g, j, A.pin, own, kp);
     __syncthreads();
     if (live && has) {
       RowN<VEC> u[3];
@@ -540,9 +540,9 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
           acc[2] += t2 * t2;
           acc[3] += p2[v] * p2[v];
         }
-        str<TY, VEC>(yout + ro, g.col0, y2);
-        str<double, VEC>(A.pmid + ro, g.col0, pm);
-        str<double, VEC>(A.p + ro, g.col0, p2);
+        str_s<NT, TY, VEC>(yout + ro, g.col0, y2);
+        str_s<NT, double, VEC>(A.pmid + ro, g.col0, pm);
+        str_s<NT, double, VEC>(A.p + ro, g.col0, p2);
       }
     }
     __syncthreads();
@@ -828,25 +828,28 @@ hipError_t launch_apply(const FieldView& f, const Tiling& t, const double* x, do
   return launch_apply2(f, t, x, y, s1, a1, s2, a2, nullptr, 0.0, st);
 }
 
-template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST>
+template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST, bool NT>
 static void leja_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
   const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock);
   if (a.ev_start)
-    hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF, FIRST>), grid, blk, 0, st, a.ev_start, a.ev_stop,
-                          0, f, t, a);
+    hipExtLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF, FIRST, NT>), grid, blk, 0, st, a.ev_start,
+                          a.ev_stop, 0, f, t, a);
   else
-    hipLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF, FIRST>), grid, blk, 0, st, f, t, a);
+    hipLaunchKernelGGL((leja_kernel<TF, TYI, TYO, VEC, ADVF, FIRST, NT>), grid, blk, 0, st, f, t, a);
 }
 
 template <typename TF, int VEC, bool ADVF>
 static void leja_dispatch_y(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  const bool nt = a.stream && !a.decide_only;
   if (a.first) {  // y_0 = v, FP64
-    if (a.ystore_f32) leja_launch<TF, double, float, VEC, ADVF, true>(f, t, a, st);
-    else leja_launch<TF, double, double, VEC, ADVF, true>(f, t, a, st);
+    if (a.ystore_f32) leja_launch<TF, double, float, VEC, ADVF, true, false>(f, t, a, st);
+    else leja_launch<TF, double, double, VEC, ADVF, true, false>(f, t, a, st);
   } else if (a.ystore_f32) {
-    leja_launch<TF, float, float, VEC, ADVF, false>(f, t, a, st);
+    if (nt) leja_launch<TF, float, float, VEC, ADVF, false, true>(f, t, a, st);
+    else leja_launch<TF, float, float, VEC, ADVF, false, false>(f, t, a, st);
   } else {
-    leja_launch<TF, double, double, VEC, ADVF, false>(f, t, a, st);
+    if (nt) leja_launch<TF, double, double, VEC, ADVF, false, true>(f, t, a, st);
+    else leja_launch<TF, double, double, VEC, ADVF, false, false>(f, t, a, st);
   }
 }
 
@@ -862,14 +865,15 @@ hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs&
   return hipGetLastError();
 }
 
-template <typename TF, typename TY, int VEC, bool ADVF>
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 static void leja2_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
   const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock2);
   const size_t lds = (size_t)kRing * kWave * VEC * sizeof(double);
   if (a.ev_start)
-    hipExtLaunchKernelGGL((leja2_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
+    hipExtLaunchKernelGGL((leja2_kernel<TF, TY, VEC, ADVF, NT>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t,
+                          a);
   else
-    hipLaunchKernelGGL((leja2_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, f, t, a);
+    hipLaunchKernelGGL((leja2_kernel<TF, TY, VEC, ADVF, NT>), grid, blk, lds, st, f, t, a);
 }
 
 hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
@@ -878,12 +882,22 @@ hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs
                          a.pin == a.pmid || a.p == a.pmid))
     return hipErrorInvalidValue;
   ADL_DISPATCH_TILE(t, f, {
-    if (f.f32) {
-      if (a.ystore_f32) leja2_launch<float, float, VEC, ADVF>(f, t, a, st);
-      else leja2_launch<float, double, VEC, ADVF>(f, t, a, st);
+    if (a.stream) {
+      if (f.f32) {
+        if (a.ystore_f32) leja2_launch<float, float, VEC, ADVF, true>(f, t, a, st);
+        else leja2_launch<float, double, VEC, ADVF, true>(f, t, a, st);
+      } else {
+        if (a.ystore_f32) leja2_launch<double, float, VEC, ADVF, true>(f, t, a, st);
+        else leja2_launch<double, double, VEC, ADVF, true>(f, t, a, st);
+      }
     } else {
-      if (a.ystore_f32) leja2_launch<double, float, VEC, ADVF>(f, t, a, st);
-      else leja2_launch<double, double, VEC, ADVF>(f, t, a, st);
+      if (f.f32) {
+        if (a.ystore_f32) leja2_launch<float, float, VEC, ADVF, false>(f, t, a, st);
+        else leja2_launch<float, double, VEC, ADVF, false>(f, t, a, st);
+      } else {
+        if (a.ystore_f32) leja2_launch<double, float, VEC, ADVF, false>(f, t, a, st);
+        else leja2_launch<double, double, VEC, ADVF, false>(f, t, a, st);
+      }
     }
   });
   return hipGetLastError();

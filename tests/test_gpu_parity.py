@@ -275,3 +275,28 @@ def test_two_term_launches_match_one_term_launches(nx, ny, bc, storage):
         degs.append(st["max_degree"])
     assert degs[0] == degs[1], degs
     assert rel(outs[1], outs[0]) < 1e-13
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (130, 70), (257, 33)])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
+@pytest.mark.parametrize("storage", [0, 2])
+def test_streaming_hints_do_not_change_results(nx, ny, bc, storage):
+    """Non-temporal hints on the Newton vectors change cache policy only:
+    bitwise the same result in every mode, one and two terms per launch."""
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=3 * nx + ny, field_advection=(storage == 0))
+    hx, hy = 1.0 / nx, 1.0 / ny
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, hx, hy, bc, storage)
+    gop.set_bound(bounds.gershgorin(oop))
+    v = to_dev(W.random_vector((ny, nx), 5))
+    dt = 200.0 / abs(bounds.gershgorin(oop))
+    for fuse in (False, True):
+        gop.set_term_fusion(fuse)
+        outs = []
+        for mode in (0, 1, -1):
+            gop.set_streaming(mode)
+            out = torch.empty_like(v)
+            gop.leja_phi(1, dt, v, out, 1e-10)
+            outs.append(to_np(out))
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    with pytest.raises(A.AdlError):
+        gop.set_streaming(2)
