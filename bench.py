@@ -145,6 +145,51 @@ def run_roofline_leg(w, storage, two_terms=True):
     return res
 
 
+def paper_cases_leg(n=256, tol=1e-10):
+    """The paper's test problems (Sec. 3, Cases I-IV; workloads.paper_case)
+    at n x n, FP64, each with its default step (I: one phi_0 step over the
+    whole interval; II: steps of 1e4 dt_CFL; III/IV: exponential Gauss
+    quadrature, steps of 100 dt_CFL, T = 0.1), the GPU's own Gershgorin
+    bound: GPU time to T with the source arrays already on the device.
+    Accuracy on these problems is checked in tests/test_gpu_paper_cases.py."""
+    import torch
+    import paper_2307_12276_amd as A
+    import workloads as W
+    res = []
+    for case in W.PAPER_CASES:
+        w = W.paper_case(case, n, tol=tol)
+        op = make_op(w, A.STORAGE_FP64)
+        op.spectral_bound(A.BOUND_GERSHGORIN)
+        u = dev_tensor(w.u0)
+        out = torch.empty_like(u)
+        S = [] if w.scheme == "exp" else [[None if a is None else dev_tensor(a) for a in w.stage_sources(k)]
+                                          for k in range(w.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mv = 0
+        for k in range(w.steps):
+            if w.scheme == "exp":
+                st = op.leja_phi(0, w.dt, u, out, tol)
+                u, out = out, u
+            elif w.scheme == "midpoint":
+                st = op.midpoint_step(u, S[k][0], w.dt, tol)
+            else:
+                st = op.quad2_step(u, S[k][0], S[k][1], w.c1, w.c2, w.dt, tol)
+            mv += st["matvecs"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res.append({"case": case, "n": n, "scheme": {"exp": "phi_0 (one step)", "midpoint": "exp. midpoint",
+                                                     "quad2": "exp. Gauss"}[w.scheme],
+                    "T": w.extra["T"], "steps": w.steps, "dt_over_dt_cfl": w.dt / w.extra["dt_cfl"],
+                    "tol": tol, "matvecs": mv, "seconds": el, "matvecs_per_s": mv / el,
+                    "us_per_matvec": 1e6 * el / max(mv, 1)})
+        log("paper case %s (%d^2, %s): %d steps, %d matvecs in %.3fs (%.2f us per matvec)" % (
+            case, n, res[-1]["scheme"], w.steps, mv, el, res[-1]["us_per_matvec"]))
+        del op, S
+        torch.cuda.empty_cache()
+    return res
+
+
 def chosen_vs_plain(steps=10, tol=1e-9):
     """Momentum-bin workload (256 bins, grids from {128,...,512}^2, k_par =
     p^0.5, shared circular field, midpoint, shared dt).
@@ -289,7 +334,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline and bins legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline, bins and paper-case legs")
     ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
     ap.add_argument("--one-term", action="store_true", help="with --profile-leja: one Newton term per launch")
@@ -405,6 +450,7 @@ def main():
                 legs[-1]["us_per_term"], legs[-1]["achieved_GBs"], 100 * legs[-1]["frac_of_8TBs"]))
         out["roofline_4096"] = legs
         out["chosen_vs_plain"] = chosen_vs_plain()
+        out["paper_cases"] = paper_cases_leg()
 
     print(json.dumps(out), flush=True)
 

@@ -194,7 +194,7 @@ class Workload:
     dt: float
     steps: int
     tol: float
-    scheme: str                   # "midpoint" | "quad2"
+    scheme: str                   # "midpoint" | "quad2" | "exp" (u <- phi_0(dt A) u, no source)
     c1: float = 0.5
     c2: float = 0.5
     source: Optional[Callable[[float], np.ndarray]] = None
@@ -281,6 +281,70 @@ def roofline_shape(n: int = 4096, seed: int = 0, steps: int = 1, tol: float = 1e
     on-chip caches, FP64, exponential midpoint with the pulsed source."""
     w = c3_stream_function(n=n, seed=seed, steps=steps, tol=tol, storage=0, scheme="midpoint")
     w.name = "roofline-stream-%d" % n
+    return w
+
+
+# --------------------------------------------------------------------------
+# the paper's own test problems (Sec. 3)
+# --------------------------------------------------------------------------
+PAPER_BOX = (-1.0, 1.0, -1.0, 1.0)
+PAPER_CASES = ("I", "II", "III", "IV")
+PAPER_END_TIMES = {"I": (0.75,), "II": (0.85,), "III": (0.10, 0.30), "IV": (0.10, 0.30)}
+
+
+def paper_case(case: str, n: int = 256, dt_mult: Optional[float] = None, T: Optional[float] = None,
+               scheme: Optional[str] = None, tol: float = 1e-10) -> Workload:
+    """Cases I-IV of Sec. 3 on an n x n grid.
+
+    I   ring tensor (eq. 6), no advection, no source: u(T) = exp(T A) u0,
+        taken as one step over the whole interval (scheme "exp", phi_0);
+    II  spiral 2 (eq. 7, s = 4), a = (1, 1), time-independent sources
+        (eq. 8): the exponential midpoint rule is exact in time here;
+    III spiral 1 (s = 1), a = (1, 1), time-dependent sources (eq. 9);
+    IV  spiral 2, a = (1, 2), time-dependent sources (eq. 9).
+    End times: I 0.75, II 0.85, III/IV 0.10 or 0.30.
+
+    The paper gives no domain, grid, boundary or initial data.  Readings:
+    [-1, 1]^2 (every source centre of eq. 8-9 lies inside it), zero
+    Dirichlet boundary on interior nodes, the tensors exactly as printed
+    (k_perp = 0), and one initial Gaussian of width 0.1 centred at
+    (0.5, 0) for every case.  The step is dt_mult * dt_CFL, shortened so
+    that a whole number of steps ends at T (default: one step for I,
+    10^4 dt_CFL for II, 100 dt_CFL for III/IV); scheme "quad2" uses the
+    Gauss nodes 1/2 -+ sqrt(3)/6 (eq. 5)."""
+    if case not in PAPER_CASES:
+        raise ValueError("case must be one of %s" % (PAPER_CASES,))
+    X, Y, hx, hy = grid_2d(n, n, DIRICHLET, box=PAPER_BOX)
+    if case == "I":
+        Dxx, Dxy, Dyy = ring_tensor(X, Y)
+        ax_c, ay_c, src = 0.0, 0.0, None
+    elif case == "II":
+        Dxx, Dxy, Dyy = spiral_tensor(X, Y, 2)
+        ax_c, ay_c = 1.0, 1.0
+        S = source_tis(X, Y)
+        src = lambda t, S=S: S
+    else:
+        Dxx, Dxy, Dyy = spiral_tensor(X, Y, 1 if case == "III" else 2)
+        ax_c, ay_c = (1.0, 1.0) if case == "III" else (1.0, 2.0)
+        src = lambda t, X=X, Y=Y: source_tds(X, Y, t)
+    if T is None:
+        T = PAPER_END_TIMES[case][0]
+    dcfl = cfl_dt(Dxx, Dyy, hx, hy)
+    if dt_mult is None:
+        steps = 1 if case == "I" else max(1, math.ceil(T / ((1e4 if case == "II" else 100.0) * dcfl)))
+    else:
+        steps = max(1, math.ceil(T / (dt_mult * dcfl)))
+    dt = T / steps
+    if scheme is None:
+        scheme = "exp" if case == "I" else ("midpoint" if case == "II" else "quad2")
+    if scheme == "quad2":
+        c1, c2 = 0.5 - math.sqrt(3.0) / 6.0, 0.5 + math.sqrt(3.0) / 6.0
+    else:
+        c1 = c2 = 0.5
+    u0 = gaussian(X, Y, 0.5, 0.0, 0.1)
+    w = Workload("paper-case-%s-%d" % (case, n), n, n, hx, hy, DIRICHLET, Dxx, Dxy, Dyy,
+                 None, None, ax_c, ay_c, u0, dt, steps, tol, scheme, c1, c2, src)
+    w.extra.update(T=T, dt_cfl=dcfl, case=case)
     return w
 
 
