@@ -141,13 +141,16 @@ int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, doub
  * output pointer may be NULL). */
 int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
 
-/* Newton terms per launch of a sweep (Sec. 2 recurrence): two_terms = 1 (the
+/* Newton terms per launch of a sweep (Sec. 2 recurrence): mode = 1 (the
  * default) computes terms k+1 and k+2 in one launch, keeping y_{k+1} on chip
- * (read y_k, the fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2});
- * two_terms = 0 launches one kernel per term.  Results agree to rounding (the
- * block partial sums of the norms are grouped differently).  ADL_EINVAL for
- * other values. */
-int adl_op_set_term_fusion(adl_op* op, int two_terms);
+ * (read y_k, the fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2}), with
+ * the input rows staged in LDS on grids whose working set exceeds the caches
+ * (the rule of adl_op_set_streaming) and one-row frames in registers
+ * otherwise; mode = 2 and mode = 3
+ * force the LDS-staged and the register-frame form; mode = 0 launches one
+ * kernel per term.  Results agree to rounding (the block partial sums of the
+ * norms are grouped differently).  ADL_EINVAL for other values. */
+int adl_op_set_term_fusion(adl_op* op, int mode);
 
 /* Cache hints of the Newton-Leja launches: mode = 1 marks the vectors a
  * launch reads or writes exactly once (p_k, y and p of its terms) as

@@ -224,8 +224,11 @@ class Op:
     def set_tiling(self, rows: int = 0, cols_per_lane: int = 0):
         _check(lib().adl_op_set_tiling(self.handle, int(rows), int(cols_per_lane)))
 
-    def set_term_fusion(self, two_terms: bool = True):
-        _check(lib().adl_op_set_term_fusion(self.handle, int(bool(two_terms))))
+    def set_term_fusion(self, mode=True):
+        """Newton terms per launch: True/1 two (kernel chosen by the tiling),
+        2 two with LDS-staged rows, 3 two with register frames, False/0 one."""
+        m = int(mode) if not isinstance(mode, bool) else int(mode)
+        _check(lib().adl_op_set_term_fusion(self.handle, m))
 
     def set_streaming(self, mode: int = -1):
         """Non-temporal hints on the Newton vectors: -1 auto, 0 off, 1 on."""

@@ -111,6 +111,7 @@ struct LejaArgs {
   int ystore_f32;    // y stored as float
   int yin_f32;       // y_k stored as float
   int stream;        // non-temporal hints on p_k and the written vectors
+  int staged;        // two-term launch: input rows staged in LDS (leja2s_kernel)
   double* partials;  // two slots of 6 x (max blocks) values
   long slot_stride;
   int slot;          // slot written by this launch

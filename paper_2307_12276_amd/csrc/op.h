@@ -47,7 +47,7 @@ struct adl_op {
   Tiling t1{};  // one column per lane: used when a caller's vector is not 16-byte aligned
   Tiling t2{};  // two-term Newton-Leja kernel (two columns per lane when nx is even)
   Tiling t21{}; // two-term kernel, one column per lane
-  int fuse_terms = 1;  // Newton terms two per launch
+  int fuse_terms = 1;  // 0 one Newton term per launch, 1 two (kernel by tiling), 2 two (LDS-staged), 3 two (frames)
   int streaming = -1;  // non-temporal hints on Newton vectors: -1 auto, 0 off, 1 on
   int nx = 0, ny = 0, bc = 0, storage = 0;
   double hx = 0, hy = 0;

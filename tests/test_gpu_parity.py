@@ -257,8 +257,9 @@ def test_deterministic_bitwise():
 @pytest.mark.parametrize("storage", [0, 1, 2])
 def test_two_term_launches_match_one_term_launches(nx, ny, bc, storage):
     """Two Newton terms per launch (y_{k+1} kept on chip, one-column frames
-    recomputed) give the one-term result: same degree, same polynomial up to
-    the grouping of the norm partial sums."""
+    recomputed), with the input rows staged in LDS or read into registers,
+    give the one-term result: same degree, same polynomial up to the
+    grouping of the norm partial sums."""
     Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=nx + 7 * ny, field_advection=(storage == 0))
     hx, hy = 1.0 / nx, 0.8 / ny
     oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, hx, hy, bc, storage)
@@ -267,14 +268,16 @@ def test_two_term_launches_match_one_term_launches(nx, ny, bc, storage):
     v = to_dev(W.random_vector((ny, nx), 11))
     dt = 300.0 / abs(alpha)
     outs, degs = [], []
-    for fuse in (False, True):
-        gop.set_term_fusion(fuse)
+    # one term per launch; two with LDS-staged rows; two with register frames
+    for mode in (0, 2, 3):
+        gop.set_term_fusion(mode)
         out = torch.empty_like(v)
         st = gop.leja_phi(1, dt, v, out, 1e-10)
         outs.append(to_np(out))
         degs.append(st["max_degree"])
-    assert degs[0] == degs[1], degs
+    assert degs[0] == degs[1] == degs[2], degs
     assert rel(outs[1], outs[0]) < 1e-13
+    assert rel(outs[2], outs[0]) < 1e-13
 
 
 @pytest.mark.parametrize("nx,ny", [(64, 64), (130, 70), (257, 33)])
