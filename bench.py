@@ -110,15 +110,22 @@ def kernel_roofline(op_ms, launches, nbytes):
     return avg_ms, per_launch, achieved
 
 
-def run_roofline_leg(w, storage, two_terms=True):
+LEG_KERNELS = {0: ("one-term", "leja_kernel"),
+               1: ("two-term", "leja2s_kernel (input rows staged in LDS) + leja_kernel (first term)"),
+               3: ("two-term, register frames", "leja2_kernel + leja_kernel (first term)")}
+
+
+def run_roofline_leg(w, storage, mode=1):
     """One midpoint step of the stream-function field at n x n: the
     Newton-Leja kernels' dispatch-timed bandwidth on a working set far beyond
-    the caches, with two terms per launch (leja2_kernel) or one."""
+    the caches, with one term per launch (mode 0), two with the kernel the
+    library picks at this size (mode 1: input rows staged in LDS) or two with
+    the register-frame kernel (mode 3)."""
     import torch
     import paper_2307_12276_amd as A
     n = w.nx
     op = make_op(w, storage)
-    op.set_term_fusion(two_terms)
+    op.set_term_fusion(mode)
     op.spectral_bound(A.BOUND_GERSHGORIN)
     u = dev_tensor(w.u0)
     srcs = device_sources(w)
@@ -134,8 +141,8 @@ def run_roofline_leg(w, storage, two_terms=True):
     avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)
     terms = st["matvecs"] - 1  # the stage vector's matrix application is not a Newton term
     res = {"workload": w.name, "storage": ["fp64", "fp32-fields", "fp32-fields+y"][storage],
-           "launches_of": "two-term" if two_terms else "one-term",
-           "nx": n, "ny": n, "kernel": "leja2_kernel + leja_kernel" if two_terms else "leja_kernel",
+           "launches_of": LEG_KERNELS[mode][0],
+           "nx": n, "ny": n, "kernel": LEG_KERNELS[mode][1],
            "launches": launches, "bytes_per_launch": per_launch, "avg_kernel_us": avg_ms * 1e3,
            "us_per_term": ms * 1e3 / max(terms + 1, 1),
            "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
@@ -273,14 +280,15 @@ def chosen_vs_plain(steps=10, tol=1e-9):
     return res
 
 
-def profile_leja(n, two_terms=True):
-    """One phi_1 sweep on the n x n stream-function field (profiler driver)."""
+def profile_leja(n, mode=1):
+    """One phi_1 sweep on the n x n stream-function field (profiler driver);
+    mode as for adl_op_set_term_fusion."""
     import torch
     import paper_2307_12276_amd as A
     import workloads as W
     w = W.roofline_shape(n=n)
     op = make_op(w, A.STORAGE_FP64)
-    op.set_term_fusion(two_terms)
+    op.set_term_fusion(mode)
     op.spectral_bound(A.BOUND_GERSHGORIN)
     v = dev_tensor(w.u0)
     out = torch.empty_like(v)
@@ -338,9 +346,11 @@ def main():
     ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
     ap.add_argument("--one-term", action="store_true", help="with --profile-leja: one Newton term per launch")
+    ap.add_argument("--frames", action="store_true",
+                    help="with --profile-leja: two terms per launch with the register-frame kernel")
     args = ap.parse_args()
     if args.profile_leja:
-        profile_leja(args.profile_leja, not args.one_term)
+        profile_leja(args.profile_leja, 0 if args.one_term else (3 if args.frames else 1))
         return
     if args.calibrate_copy:
         calibrate_copy()
@@ -443,8 +453,9 @@ def main():
         t0 = time.time()
         rw = W.roofline_shape(n=4096)
         log("roofline leg: 4096^2 fields built in %.1fs" % (time.time() - t0))
-        for storage, two in ((A.STORAGE_FP64, False), (A.STORAGE_FP64, True), (A.STORAGE_FP32_FIELDS, True)):
-            legs.append(run_roofline_leg(rw, storage, two))
+        for storage, mode in ((A.STORAGE_FP64, 0), (A.STORAGE_FP64, 1), (A.STORAGE_FP64, 3),
+                              (A.STORAGE_FP32_FIELDS, 1)):
+            legs.append(run_roofline_leg(rw, storage, mode))
             log("roofline leg %s %s: %.1f us/launch, %.1f us/term, %.0f GB/s (%.1f%% of 8 TB/s)" % (
                 legs[-1]["storage"], legs[-1]["launches_of"], legs[-1]["avg_kernel_us"],
                 legs[-1]["us_per_term"], legs[-1]["achieved_GBs"], 100 * legs[-1]["frac_of_8TBs"]))

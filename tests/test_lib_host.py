@@ -94,3 +94,20 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.lower(), f
+
+
+def test_xcd_block_order_is_a_bijection():
+    """The staged two-term kernel's dispatch-to-logical block map (each XCD
+    a contiguous range): a permutation of [0, n) that keeps block 0 (the
+    decision block) first, restated here from its definition."""
+    def f(bid, n):
+        q, rem = n // 8, n % 8
+        x, l = bid % 8, bid // 8
+        return x * (q + 1) + l if x < rem else rem * (q + 1) + (x - rem) * q + l
+    for n in (1, 2, 7, 8, 9, 15, 16, 17, 641, 3877, 4097):
+        got = [f(b, n) for b in range(n)]
+        assert sorted(got) == list(range(n)) and got[0] == 0
+        # blocks dealt to one XCD are consecutive logical blocks
+        for x in range(min(n, 8)):
+            seq = [got[b] for b in range(x, n, 8)]
+            assert seq == list(range(seq[0], seq[0] + len(seq)))
