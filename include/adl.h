@@ -231,6 +231,12 @@ int adl_batch_destroy(adl_batch* b);
 int adl_batch_set_tile_rows(adl_batch* b, int rows);
 int adl_batch_get_tile_rows(const adl_batch* b, int* rows);
 
+/* Newton terms per launch of the batched sweep: two_terms = 1 (the default)
+ * computes terms k+1 and k+2 of every running bin in one launch after the
+ * first term (one wave per tile marches down its rows with y_{k+1} in LDS);
+ * 0 launches one kernel per term.  ADL_EINVAL for other values. */
+int adl_batch_set_term_fusion(adl_batch* batch, int two_terms);
+
 /* Autotuner: times the launches of one step (stage and sweep; u is not
  * modified) for each of the ncand candidate tile heights (host array) and
  * installs the fastest; best_rows / best_ms (host, may be NULL) receive it. */

@@ -91,6 +91,7 @@ _SIG = {
     "adl_batch_destroy": (_I, [_P]),
     "adl_batch_set_tile_rows": (_I, [_P, _I]),
     "adl_batch_get_tile_rows": (_I, [_P, ctypes.POINTER(_I)]),
+    "adl_batch_set_term_fusion": (_I, [_P, _I]),
     "adl_batch_autotune": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, ctypes.POINTER(_I), _I,
                                 ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
     "adl_batch_midpoint_step": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, _I,
@@ -366,6 +367,10 @@ class Batch:
         r = ctypes.c_int()
         _check(lib().adl_batch_get_tile_rows(self.handle, ctypes.byref(r)))
         return r.value
+
+    def set_term_fusion(self, two_terms: bool = True):
+        """Newton terms per batched launch after the first: two (default) or one."""
+        _check(lib().adl_batch_set_term_fusion(self.handle, int(bool(two_terms))))
 
     def autotune(self, us, S_halfs, dt: float, tol: float, candidates=(8, 16, 32), stream=None):
         up, sp = self._ptr_arrays(us, S_halfs)

@@ -6,8 +6,10 @@
 // bin.  Every kernel of a step covers the tiles of all bins:
 //   stage      w_b = A_b u_b + S_b
 //   term k     y_{k+1} = ((A_b - c_b)/gamma_b - xi_k) y_k,
-//              p_{b,k+1} = p_{b,k} + d_{b,k+1} y_{k+1} into the bin's other p buffer,
-//              for every bin still running, with the bin's own plan
+//              p_{b,k+1} = p_{b,k} + d_{b,k+1} y_{k+1},
+//              for every bin still running, with the bin's own plan; after
+//              the first term two terms per launch by default (y_{k+1} kept
+//              in LDS, as for a single operator)
 //   finalize   the decision of the last term, one wave per bin
 //   update     u_b += dt p_b for converged bins
 // The stopping decision lags one launch behind the work, as for a single
@@ -43,20 +45,22 @@ struct BinDesc {
   const double* u;
   const double* S;
   double* w;
-  void* y0;
+  void* y0;             // y of launch L's last term in y0 (L odd) or y1 (L even)
   void* y1;
-  double* p0;           // p_m of degree m lives in p0 (m even) or p1 (m odd)
-  double* p1;
+  double* pb[4];        // p_m of degree m: pb[pbuf_index(m)]
   const double* d;      // d_0 .. d_{M-1} of the bin's plan
   const double* shift;  // c + gamma xi_k
   double invg;
   double tol2;
   double dt;
   int max_degree;
-  int ncb;        // strips of 64*VEC columns
+  int ncb;        // strips of 64*VEC columns (one-term tiles)
   int rows;       // band height
   int ntiles;
   int tile_base;  // first global tile of this bin
+  int ncb2;       // strips of 62*VEC output columns (two-term tiles)
+  int ntiles2;
+  int tile_base2;
   int active;     // 0: the bin is advanced by the single-op path instead
 };
 
@@ -70,12 +74,25 @@ struct BinCtl {
 
 struct BatchArgs {
   const BinDesc* bins;
-  const int* tile_bin;  // global tile -> bin
+  const int* tile_bin;   // global one-term tile -> bin
+  const int* tile_bin2;  // global two-term tile -> bin
   BinCtl* ctl;
-  double* partials;     // 2 parities x total_tiles x 3
+  double* partials;      // 2 launch parities x tiles x 6
   int total_tiles;
-  int k;                // term index (Leja launches)
+  int total_tiles2;
+  long part_stride;      // doubles per parity
+  int L;                 // launch index within the sweep
+  int k;                 // terms before this launch
+  int kprev, nprev;      // the previous launch: terms before it, its terms (1 or 2)
+  int two;               // p buffers in pairs per launch (two-term sweeps)
 };
+
+// buffer of p_m: two-term sweeps keep the terms of a launch in one pair, the
+// pairs alternating (a launch never overwrites the p its decision may pick);
+// one-term sweeps alternate by degree
+__device__ __forceinline__ int pbuf_index(int m, int two) {
+  return two ? 2 * ((m >> 1) & 1) + (m & 1) : (m & 1);
+}
 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_sum3(double (&v)[3]) {
@@ -89,29 +106,47 @@ __device__ __forceinline__ void wave_sum3(double (&v)[3]) {
   }
 }
 
-// Decision for term kprev+1 of bin b (whole wave; identical in every tile).
-__device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B, int b, int kprev, bool record) {
-  const double* part = A.partials + ((long)(kprev & 1) * A.total_tiles + B.tile_base) * 3;
-  double tot[3] = {0.0, 0.0, 0.0};
+// Decision for the terms of the previous launch of bin b (kprev+1, and
+// kprev+2 after a two-term launch, in order), from that launch's tile
+// partials (whole wave; fixed order).
+__device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B, int b, bool record) {
+  const bool two = A.nprev == 2;
+  const int base = two ? B.tile_base2 : B.tile_base;
+  const int nt = two ? B.ntiles2 : B.ntiles;
+  const double* part = A.partials + (long)((A.L - 1) & 1) * A.part_stride + (long)base * 6;
+  double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   bool any = false;
-  for (int t = threadIdx.x & 63; t < B.ntiles; t += 64) {
-    tot[0] += part[t * 3 + 0];
-    tot[1] += part[t * 3 + 1];
-    tot[2] = any ? nanmax(tot[2], part[t * 3 + 2]) : part[t * 3 + 2];
+  for (int t = threadIdx.x & 63; t < nt; t += 64) {
+    tot[0] += part[t * 6 + 0];
+    tot[1] += part[t * 6 + 1];
+    tot[2] = any ? nanmax(tot[2], part[t * 6 + 2]) : part[t * 6 + 2];
+    tot[3] += part[t * 6 + 3];
+    tot[4] += part[t * 6 + 4];
     any = true;
   }
-  wave_sum3(tot);
-  const double tn2 = tot[0], pn2 = tot[1];
-  const int deg = kprev + 1;
-  int stop = 0, status = 0, degree = deg;
-  if (!isfinite(tn2) || !isfinite(pn2)) {
-    stop = 1; status = 2;
-  } else if (kprev == 0 && tot[2] == 0.0) {
-    stop = 1; status = 1; degree = 0;
-  } else if (tn2 <= B.tol2 * pn2) {
-    stop = 1; status = 1;
-  } else if (deg >= B.max_degree) {
-    stop = 1; status = 3;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double t = __shfl_xor(tot[q], o);
+      tot[q] = q == 2 ? nanmax(tot[q], t) : tot[q] + t;
+    }
+  }
+  int stop = 0, status = 0, degree = 0;
+  double tn2 = 0.0, pn2 = 0.0;
+  for (int i = 0; i < (two ? 2 : 1) && !stop; ++i) {
+    tn2 = tot[3 * i];
+    pn2 = tot[3 * i + 1];
+    degree = A.kprev + 1 + i;
+    if (!isfinite(tn2) || !isfinite(pn2)) {
+      stop = 1; status = 2;
+    } else if (A.kprev == 0 && i == 0 && tot[2] == 0.0) {
+      stop = 1; status = 1; degree = 0;
+    } else if (tn2 <= B.tol2 * pn2) {
+      stop = 1; status = 1;
+    } else if (degree >= B.max_degree) {
+      stop = 1; status = 3;
+    }
   }
   if (record && (threadIdx.x & 63) == 0) {
     BinCtl* c = A.ctl + b;
@@ -202,6 +237,10 @@ __global__ __launch_bounds__(64) void batch_stage_kernel(BatchArgs A) {
   stencil_tile<TF, double, VEC, ADVF>(B.f, B.u, ep, cb, j0, j1);
 }
 
+__device__ __forceinline__ double* tile_partials(const BatchArgs& A, long tile) {
+  return A.partials + (long)(A.L & 1) * A.part_stride + tile * 6;
+}
+
 template <typename TF, int VEC, bool ADVF, bool FIRST>
 __device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B, int t) {
   const int rb = t / B.ncb, cb = t - rb * B.ncb;
@@ -209,29 +248,30 @@ __device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B,
   const int k = A.k;
   BatchLejaEp<VEC, FIRST> ep;
   ep.nx = B.f.nx;
-  ep.yout = reinterpret_cast<double*>(((k + 1) & 1) ? B.y1 : B.y0);
-  ep.pin = FIRST ? nullptr : ((k & 1) ? B.p1 : B.p0);
-  ep.p = ((k + 1) & 1) ? B.p1 : B.p0;
+  ep.yout = reinterpret_cast<double*>(((A.L + 1) & 1) ? B.y1 : B.y0);
+  ep.pin = FIRST ? nullptr : B.pb[pbuf_index(k, A.two)];
+  ep.p = B.pb[pbuf_index(k + 1, A.two)];
   ep.shift = B.shift[k];
   ep.invg = B.invg;
   ep.d0 = B.d[0];
   ep.dk1 = B.d[k + 1];
   ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
-  const double* yin = FIRST ? B.w : reinterpret_cast<const double*>((k & 1) ? B.y1 : B.y0);
+  const double* yin = FIRST ? B.w : reinterpret_cast<const double*>((A.L & 1) ? B.y1 : B.y0);
   stencil_tile<TF, double, VEC, ADVF>(B.f, yin, ep, cb, j0, j1);
   wave_sum3(ep.acc);
   if ((threadIdx.x & 63) == 0) {
-    double* part = A.partials + ((long)(k & 1) * A.total_tiles + B.tile_base + t) * 3;
+    double* part = tile_partials(A, B.tile_base + t);
     part[0] = ep.acc[0];
     part[1] = ep.acc[1];
     part[2] = ep.acc[2];
+    part[3] = part[4] = part[5] = 0.0;
   }
 }
 
-// Term launch k: blocks [0, nbins) decide term k-1 of their bin (from the
-// partials of launch k-1), blocks [nbins, nbins + total tiles) compute term
-// k+1 of their tile's bin unless the bin has stopped.  The first term (k = 0,
-// y_0 = w) is a kernel of its own.
+// Term launch L (terms k+1 .. k+nterms): blocks [0, nbins) decide the terms
+// of launch L-1 of their bin (from its partials), the tile blocks compute the
+// launch's terms of their bin unless the bin has stopped.  The first term
+// (k = 0, y_0 = w) is a kernel of its own.
 template <typename TF, int VEC, bool ADVF, bool FIRST>
 __global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A, int nbins) {
   if ((int)blockIdx.x < nbins) {
@@ -239,7 +279,7 @@ __global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A, int nbins) 
     const BinDesc& B = A.bins[b];
     if (FIRST || !B.active) return;
     if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    bin_decide(A, B, b, A.k - 1, true);
+    bin_decide(A, B, b, true);
     return;
   }
   const int gt = blockIdx.x - nbins;
@@ -251,14 +291,133 @@ __global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A, int nbins) 
   batch_term<TF, VEC, ADVF, FIRST>(A, B, gt - B.tile_base);
 }
 
-// decision of term k (the last launched) for every running bin: one wave per bin
+// Two terms per launch (k >= 1) on one wave per tile of 62*VEC output columns
+// x `rows` rows (lanes 0 and 63 are the one-column frame): the wave marches
+// down its rows, computing y_{k+1} of row r+1 into a four-row LDS ring of its
+// own and then y_{k+2} of row r from the ring rows r-1 .. r+1; p_{k+1} and
+// p_{k+2} as for a single operator.  Each lane reads back only the ring
+// elements it wrote (its x-neighbours come from DPP shifts), so the wave needs
+// no barrier.
+constexpr int kBRing = 4;
+
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B, int t) {
+  __shared__ double ring[kBRing * kWave * VEC];
+  const FieldView& F = B.f;
+  const int rb = t / B.ncb2, cb = t - rb * B.ncb2;
+  const int j0 = rb * B.rows, j1 = min(j0 + B.rows, F.ny);
+  const int k = A.k;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int M = B.max_degree;
+  const Strip g = strip_at<VEC>(F, cb * (kWave - 2) * VEC - VEC);
+  const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
+  const double* yin = reinterpret_cast<const double*>((A.L & 1) ? B.y1 : B.y0);
+  double* yout = reinterpret_cast<double*>(((A.L + 1) & 1) ? B.y1 : B.y0);
+  const double* pin = B.pb[pbuf_index(k, A.two)];
+  double* pmid = B.pb[pbuf_index(k + 1, A.two)];
+  double* pout = B.pb[pbuf_index(k + 2, A.two)];
+  // (a second term past the bin's degree cap is computed with the last plan
+  // entries and discarded by the decision at the cap)
+  const double shift2 = B.shift[min(k + 1, M)];
+  const double dk1 = B.d[k + 1], dk2 = B.d[min(k + 2, M)];
+  Stage1Ep<VEC, kBRing> ep1;
+  ep1.lds = ring;
+  ep1.r0 = j0 - 1;
+  ep1.ny = F.ny;
+  ep1.per = F.bc == BC_PERIODIC;
+  ep1.shift = B.shift[k];
+  ep1.invg = B.invg;
+  ep1.stopflag = 0;
+  stencil_group<TF, double, VEC, ADVF, 1>(F, yin, ep1, g, j0 - 1);
+  stencil_group<TF, double, VEC, ADVF, 1>(F, yin, ep1, g, j0);
+  const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
+  const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
+  const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
+  const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
+  const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int r = j0; r < j1; ++r) {
+    stencil_group<TF, double, VEC, ADVF, 1>(F, yin, ep1, g, r + 1);
+    RowN<VEC> u[3], m[3], kc, ac;
+    RowC<VEC> gg[3], ay[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lds_row_n<double, VEC>(ring, (unsigned)(r - 1 + q - ep1.r0) % kBRing, u[q]);
+      row_c<TF, VEC, MODE_EDGE>(kyy, r - 1 + q, F, g, gg[q]);
+      row_n<TF, VEC, MODE_ZERO>(kxy, r - 1 + q, F, g, m[q]);
+      if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, r - 1 + q, F, g, ay[q]);
+    }
+    row_n<TF, VEC, MODE_EDGE>(kxx, r, F, g, kc);
+    if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, r, F, g, ac);
+    double Ax[VEC];
+    stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], kc, ac, ay[0], ay[2], F.axc,
+                             F.ayc, Ax);
+    if (own) {
+      const long ro = (long)r * F.nx;
+      double pk[VEC], y2[VEC], pm[VEC], p2[VEC];
+      ldr<double, VEC>(pin + ro, g.col0, pk);
+      const double* y1row = ring + ((unsigned)(r - ep1.r0) % kBRing) * (kWave * VEC) + lane * VEC;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const double t1 = dk1 * y1row[v];
+        pm[v] = pk[v] + t1;
+        y2[v] = (Ax[v] - shift2 * u[1].c[v]) * B.invg;
+        const double t2 = dk2 * y2[v];
+        p2[v] = pm[v] + t2;
+        acc[0] += t1 * t1;
+        acc[1] += pm[v] * pm[v];
+        acc[2] += t2 * t2;
+        acc[3] += p2[v] * p2[v];
+      }
+      str<double, VEC>(yout + ro, g.col0, y2);
+      str<double, VEC>(pmid + ro, g.col0, pm);
+      str<double, VEC>(pout + ro, g.col0, p2);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
+  }
+  if (lane == 0) {
+    double* part = tile_partials(A, B.tile_base2 + t);
+    part[0] = acc[0];
+    part[1] = acc[1];
+    part[2] = 0.0;
+    part[3] = acc[2];
+    part[4] = acc[3];
+    part[5] = 0.0;
+  }
+}
+
+template <typename TF, int VEC, bool ADVF>
+__global__ __launch_bounds__(64) void batch_leja2_kernel(BatchArgs A, int nbins) {
+  if ((int)blockIdx.x < nbins) {
+    const int b = blockIdx.x;
+    const BinDesc& B = A.bins[b];
+    if (!B.active) return;
+    if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    bin_decide(A, B, b, true);
+    return;
+  }
+  const int gt = blockIdx.x - nbins;
+  const int b = A.tile_bin2[gt];
+  const BinDesc& B = A.bins[b];
+  if (!B.active) return;
+  if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (A.k >= B.max_degree) return;
+  batch_term2<TF, VEC, ADVF>(A, B, gt - B.tile_base2);
+}
+
+// decision of the last launch for every running bin: one wave per bin
 __global__ __launch_bounds__(64) void batch_finalize_kernel(BatchArgs A, int nbins) {
   const int b = blockIdx.x;
   if (b >= nbins) return;
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
   if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  if (A.k > 0) bin_decide(A, B, b, A.k - 1, true);
+  if (A.L > 0) bin_decide(A, B, b, true);
 }
 
 __global__ __launch_bounds__(256) void batch_reset_kernel(BinCtl* ctl, int nbins) {
@@ -276,7 +435,7 @@ __global__ __launch_bounds__(64) void batch_update_kernel(BatchArgs A, double* c
   const int b = A.tile_bin[gt];
   const BinDesc& B = A.bins[b];
   if (!B.active || A.ctl[b].status != 1 || A.ctl[b].degree == 0) return;  // degree 0: p = 0
-  const double* pb = (A.ctl[b].degree & 1) ? B.p1 : B.p0;
+  const double* pb = B.pb[pbuf_index(A.ctl[b].degree, A.two)];
   const int t = gt - B.tile_base;
   const int rb = t / B.ncb, cb = t - rb * B.ncb;
   const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
@@ -315,13 +474,21 @@ struct adl_batch {
   BinDesc* d_bins = nullptr;
   BinCtl* d_ctl = nullptr;
   int* d_tile_bin = nullptr;
+  int* d_tile_bin2 = nullptr;
   double* d_partials = nullptr;
   double* d_plans = nullptr;   // nbins x 2 x M
   double** d_uptrs = nullptr;  // nbins
   BinCtl* h_ctl = nullptr;     // pinned
   int total_tiles = 0;
+  int total_tiles2 = 0;
+  long part_stride = 0;  // doubles per launch parity of the partials
+  int two = 1;           // two Newton terms per launch after the first
   std::vector<BinDesc> bins;
-  std::vector<int> tile_bin;
+  std::vector<int> tile_bin, tile_bin2;
+  // launch state of the sweep being enqueued: launches so far, and the last
+  // launch's terms-before and term count (restored after a graph replay)
+  int sL = 0, skprev = 0, snprev = 0;
+  int gL = 0, gkprev = 0, gnprev = 0, gcovered = 0;
   // plan keys uploaded to d_plans
   std::vector<double> plan_alpha, plan_dt;
   // graph
@@ -347,14 +514,17 @@ int bfail(int code, const char* msg) {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int tiles_of(int nx, int ny, int vec, int rows) {
-  const int ncb = (nx + kWave * vec - 1) / (kWave * vec);
+// two-term tiles: strips of 62*vec output columns (at least as many as the
+// one-term tiles of 64*vec columns)
+int tiles2_of(int nx, int ny, int vec, int rows) {
+  const int w = (kWave - 2) * vec;
+  const int ncb = (nx + w - 1) / w;
   const int nrb = (ny + rows - 1) / rows;
   return ncb * nrb;
 }
 
 struct BLayout {
-  size_t bins, ctl, tile_bin, partials, plans, uptrs, total;
+  size_t bins, ctl, tile_bin, tile_bin2, partials, plans, uptrs, total;
 };
 
 BLayout blayout(int nbins, long max_tiles, int M) {
@@ -368,16 +538,18 @@ BLayout blayout(int nbins, long max_tiles, int M) {
   L.bins = take(sizeof(BinDesc) * nbins);
   L.ctl = take(sizeof(BinCtl) * nbins);
   L.tile_bin = take(sizeof(int) * max_tiles);
-  L.partials = take(sizeof(double) * 6 * max_tiles);
+  L.tile_bin2 = take(sizeof(int) * max_tiles);
+  L.partials = take(sizeof(double) * 2 * 6 * max_tiles);
   L.plans = take(sizeof(double) * 2 * (size_t)M * nbins);
   L.uptrs = take(sizeof(double*) * nbins);
   L.total = o;
   return L;
 }
 
+// the most tiles of either kind (one column per lane, one row per tile)
 long max_tiles_for(int nbins, adl_op* const* ops) {
   long t = 0;
-  for (int b = 0; b < nbins; ++b) t += tiles_of(ops[b]->nx, ops[b]->ny, 1, 1);
+  for (int b = 0; b < nbins; ++b) t += tiles2_of(ops[b]->nx, ops[b]->ny, 1, 1);
   return t;
 }
 
@@ -389,18 +561,32 @@ long max_tiles_for(int nbins, adl_op* const* ops) {
 
 void build_tiles(adl_batch* B) {
   B->tile_bin.clear();
-  int base = 0;
+  B->tile_bin2.clear();
+  int base = 0, base2 = 0;
   for (int b = 0; b < B->nbins; ++b) {
     adl_op* op = B->ops[b];
     BinDesc& d = B->bins[b];
+    const int nrb = (op->ny + B->rows - 1) / B->rows;
     d.ncb = (op->nx + kWave * B->vec - 1) / (kWave * B->vec);
     d.rows = B->rows;
-    d.ntiles = d.ncb * ((op->ny + B->rows - 1) / B->rows);
+    d.ntiles = d.ncb * nrb;
     d.tile_base = base;
+    d.ncb2 = (op->nx + (kWave - 2) * B->vec - 1) / ((kWave - 2) * B->vec);
+    d.ntiles2 = d.ncb2 * nrb;
+    d.tile_base2 = base2;
     for (int t = 0; t < d.ntiles; ++t) B->tile_bin.push_back(b);
+    for (int t = 0; t < d.ntiles2; ++t) B->tile_bin2.push_back(b);
     base += d.ntiles;
+    base2 += d.ntiles2;
   }
   B->total_tiles = base;
+  B->total_tiles2 = base2;
+}
+
+int upload_tiles(adl_batch* B) {
+  BCHK(hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(B->d_tile_bin2, B->tile_bin2.data(), sizeof(int) * B->total_tiles2, hipMemcpyHostToDevice));
+  return ADL_OK;
 }
 
 template <typename F>
@@ -420,33 +606,67 @@ void dispatch(const adl_batch* B, F&& f) {
   }
 }
 
-// enqueue reset, stage and n terms starting at k0 (+ finalize) on st
-int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t st) {
+BatchArgs base_args(const adl_batch* B) {
   BatchArgs a{};
   a.bins = B->d_bins;
   a.tile_bin = B->d_tile_bin;
+  a.tile_bin2 = B->d_tile_bin2;
   a.ctl = B->d_ctl;
   a.partials = B->d_partials;
   a.total_tiles = B->total_tiles;
+  a.total_tiles2 = B->total_tiles2;
+  a.part_stride = B->part_stride;
+  a.two = B->two;
+  return a;
+}
+
+// Enqueue launches covering terms k0+1 .. k0+nterms at least (reset and stage
+// first when with_stage), then the decision of the last launch.  The first
+// term is a launch of its own; later launches take two terms while the batch
+// fuses terms and the second stays within the degree cap.  `covered` returns
+// the number of terms enqueued (nterms, or one more).
+int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t st, int* covered = nullptr) {
+  BatchArgs a = base_args(B);
   if (with_stage) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((B->nbins + 255) / 256), dim3(256), 0, st, B->d_ctl, B->nbins);
     dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
       hipLaunchKernelGGL((batch_stage_kernel<TF, VEC, ADVF>), dim3(B->total_tiles), dim3(64), 0, st, a);
     });
+    B->sL = B->skprev = B->snprev = 0;
   }
-  for (int i = 0; i < nterms; ++i) {
-    a.k = k0 + i;
-    const dim3 grid(B->nbins + B->total_tiles);
-    dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
-      if (a.k == 0)
-        hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF, true>), grid, dim3(64), 0, st, a, B->nbins);
-      else
-        hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF, false>), grid, dim3(64), 0, st, a, B->nbins);
-    });
+  int k = k0;
+  while (k < k0 + nterms) {
+    const int n = (k == 0 || !B->two || k + 2 > B->max_degree) ? 1 : 2;
+    a.L = B->sL;
+    a.k = k;
+    a.kprev = B->skprev;
+    a.nprev = B->snprev;
+    if (n == 1) {
+      const dim3 grid(B->nbins + B->total_tiles);
+      dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
+        if (a.k == 0)
+          hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF, true>), grid, dim3(64), 0, st, a, B->nbins);
+        else
+          hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF, false>), grid, dim3(64), 0, st, a, B->nbins);
+      });
+    } else {
+      const dim3 grid(B->nbins + B->total_tiles2);
+      dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
+        hipLaunchKernelGGL((batch_leja2_kernel<TF, VEC, ADVF>), grid, dim3(64), 0, st, a, B->nbins);
+      });
+    }
+    B->skprev = k;
+    B->snprev = n;
+    ++B->sL;
+    k += n;
   }
-  a.k = k0 + nterms;
+  a.L = B->sL;
+  a.k = k;
+  a.kprev = B->skprev;
+  a.nprev = B->snprev;
   hipLaunchKernelGGL(batch_finalize_kernel, dim3(B->nbins), dim3(64), 0, st, a, B->nbins);
   BCHK(hipGetLastError());
+  if (covered) *covered = k - k0;
   return ADL_OK;
 }
 
@@ -469,8 +689,10 @@ int upload_bins(adl_batch* B, double* const* u, const double* const* S, double d
     d.w = op->w1;
     d.y0 = op->ybuf[0];
     d.y1 = op->ybuf[1];
-    d.p0 = op->p2;
-    d.p1 = op->p;
+    d.pb[0] = op->p2;
+    d.pb[1] = op->p;
+    d.pb[2] = op->p3;
+    d.pb[3] = op->p4;
     d.tol2 = tol * tol;
     d.dt = dt;
     d.max_degree = std::min(op->max_degree, B->max_degree);
@@ -562,6 +784,8 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
   B->d_bins = reinterpret_cast<BinDesc*>(B->ws + L.bins);
   B->d_ctl = reinterpret_cast<BinCtl*>(B->ws + L.ctl);
   B->d_tile_bin = reinterpret_cast<int*>(B->ws + L.tile_bin);
+  B->d_tile_bin2 = reinterpret_cast<int*>(B->ws + L.tile_bin2);
+  B->part_stride = 6 * mt;
   B->d_partials = reinterpret_cast<double*>(B->ws + L.partials);
   B->d_plans = reinterpret_cast<double*>(B->ws + L.plans);
   B->d_uptrs = reinterpret_cast<double**>(B->ws + L.uptrs);
@@ -570,6 +794,8 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
   B->plan_dt.assign(nbins, NAN);
   build_tiles(B);
   hipError_t e = hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(B->d_tile_bin2, B->tile_bin2.data(), sizeof(int) * B->total_tiles2, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&B->h_ctl), sizeof(BinCtl) * nbins, hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreate(&B->cap_stream);
   if (e != hipSuccess) {
@@ -596,8 +822,24 @@ int adl_batch_set_tile_rows(adl_batch* B, int rows) {
   if (rows == B->rows) return ADL_OK;
   B->rows = rows;
   build_tiles(B);
-  BCHK(hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice));
+  const int rc = upload_tiles(B);
+  if (rc != ADL_OK) return rc;
   BCHK(hipMemcpy(B->d_bins, B->bins.data(), sizeof(BinDesc) * B->nbins, hipMemcpyHostToDevice));
+  if (B->gexec) {
+    hipGraphExecDestroy(B->gexec);
+    B->gexec = nullptr;
+  }
+  if (B->graph) {
+    hipGraphDestroy(B->graph);
+    B->graph = nullptr;
+  }
+  return ADL_OK;
+}
+
+int adl_batch_set_term_fusion(adl_batch* B, int two_terms) {
+  if (!B || (two_terms != 0 && two_terms != 1)) return bfail(ADL_EINVAL, "two_terms must be 0 or 1");
+  if (two_terms == B->two) return ADL_OK;
+  B->two = two_terms;
   if (B->gexec) {
     hipGraphExecDestroy(B->gexec);
     B->gexec = nullptr;
@@ -687,7 +929,8 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
         B->gexec = nullptr;
         B->graph = nullptr;
         BCHK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_sweep(B, 0, nterms, true, B->cap_stream);
+        int cov = 0;
+        rc = enqueue_sweep(B, 0, nterms, true, B->cap_stream, &cov);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
         if (rc != ADL_OK) return rc;
@@ -696,7 +939,15 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
         BCHK(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
         B->g_launches = nterms;
         B->g_rows = B->rows;
+        B->gL = B->sL;
+        B->gkprev = B->skprev;
+        B->gnprev = B->snprev;
+        B->gcovered = cov;
       }
+      // the launch state the graph leaves behind
+      B->sL = B->gL;
+      B->skprev = B->gkprev;
+      B->snprev = B->gnprev;
       // order the graph after prior work on the caller's stream
       hipEvent_t ev;
       BCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -706,11 +957,14 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
       BCHK(hipEventRecord(ev, B->cap_stream));
       BCHK(hipStreamWaitEvent(st, ev, 0));
       BCHK(hipEventDestroy(ev));
+    }
+    int launched = 0;
+    if (use_graph) {
+      launched = B->gcovered;
     } else {
-      rc = enqueue_sweep(B, 0, nterms, true, st);
+      rc = enqueue_sweep(B, 0, nterms, true, st, &launched);
       if (rc != ADL_OK) return rc;
     }
-    int launched = use_graph ? B->g_launches : nterms;
     // continue bins that have not stopped yet
     while (true) {
       BCHK(hipMemcpyAsync(B->h_ctl, B->d_ctl, sizeof(BinCtl) * B->nbins, hipMemcpyDeviceToHost, st));
@@ -720,16 +974,12 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
         if (B->bins[b].active && !B->h_ctl[b].stop) running = true;
       if (!running || launched >= B->max_degree) break;
       const int more = std::min(B->max_degree - launched, std::max(8, launched / 4));
-      rc = enqueue_sweep(B, launched, more, false, st);
+      int cov = 0;
+      rc = enqueue_sweep(B, launched, more, false, st, &cov);
       if (rc != ADL_OK) return rc;
-      launched += more;
+      launched += cov;
     }
-    BatchArgs a{};
-    a.bins = B->d_bins;
-    a.tile_bin = B->d_tile_bin;
-    a.ctl = B->d_ctl;
-    a.partials = B->d_partials;
-    a.total_tiles = B->total_tiles;
+    BatchArgs a = base_args(B);
     if (B->vec == 2)
       hipLaunchKernelGGL((batch_update_kernel<2>), dim3(B->total_tiles), dim3(64), 0, st, a, B->d_uptrs);
     else

@@ -221,4 +221,48 @@ __device__ __forceinline__ bool stencil_tile(const FieldView& F, const TX* __res
   return true;
 }
 
+// ---- rows of y_{k+1} kept in LDS (two Newton terms per launch) -----------
+// Stage 1 writes y_{k+1} of a strip row into a ring of LDS rows; stage 2
+// reads a lane's VEC values back (rounded to the y storage type, as a
+// one-term launch would read them from memory) and takes x-neighbours from
+// the DPP shifts.  A lane only reads back what it wrote itself.
+template <typename TY>
+__device__ __forceinline__ double storage_round(double v) {
+  return (double)(TY)v;
+}
+
+// stage 1 epilogue: y_{k+1} of one strip row into the LDS ring (all lanes)
+constexpr int kRing = 8;  // slots of the LDS ring of y_{k+1} rows (a power of two)
+static_assert(kRing >= 2 * kWavesY2, "a step writes its rows and the frame below while the previous step's "
+                                     "rows are still read");
+template <int VEC, int NR = kRing>
+struct Stage1Ep {
+  struct Extra {};
+  double* lds;   // [NR][64*VEC]: row r in slot (r - r0) mod NR
+  int r0;        // grid row of slot 0 (the row above the block's first tile)
+  int ny;
+  bool per;
+  double shift, invg;
+  int stopflag;
+  __device__ __forceinline__ bool go() const { return __builtin_amdgcn_readfirstlane(stopflag) == 0; }
+  __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
+  __device__ __forceinline__ void finish(int r, const Strip& g, const double (&Ax)[VEC], const double (&xc)[VEC],
+                                         const Extra&) {
+    const bool ghost = !per && (!g.inside || r < 0 || r >= ny);
+    double* row = lds + (long)((unsigned)(r - r0) % NR) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) row[v] = ghost ? 0.0 : (Ax[v] - shift * xc[v]) * invg;
+  }
+};
+
+// y_{k+1} row q of LDS (rounded to the storage type) with its x-neighbours
+template <typename TY, int VEC>
+__device__ __forceinline__ void lds_row_n(const double* lds, int q, RowN<VEC>& o) {
+  const double* row = lds + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = storage_round<TY>(row[v]);
+  o.l = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
+  o.r = dpp_f64<kDppWaveShl1>(o.c[0]);
+}
+
 }  // namespace adl

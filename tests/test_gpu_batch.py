@@ -36,9 +36,11 @@ def oracle_steps(w, oop, nsteps):
 
 
 @pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_matches_oracle_per_bin(use_graph):
+@pytest.mark.parametrize("two_terms", [True, False])
+def test_batch_matches_oracle_per_bin(use_graph, two_terms):
     bins = W.c4_bins(nbins=10, sizes=(128, 130, 192, 256))
     pairs, b = make_batch(bins)
+    b.set_term_fusion(two_terms)
     us = [to_dev(w.u0) for w in bins]
     Ss = [to_dev(w.S(0)) for w in bins]
     for step in range(2):
@@ -49,10 +51,13 @@ def test_batch_matches_oracle_per_bin(use_graph):
         assert rel(to_np(u), ref) < 1e-10, w.name
 
 
-def test_batch_graph_replays_equal_eager():
+@pytest.mark.parametrize("two_terms", [True, False])
+def test_batch_graph_replays_equal_eager(two_terms):
     bins = W.c4_bins(nbins=6, sizes=(128, 256))
     _, b1 = make_batch(bins)
     _, b2 = make_batch(bins)
+    b1.set_term_fusion(two_terms)
+    b2.set_term_fusion(two_terms)
     ua = [to_dev(w.u0) for w in bins]
     ub = [to_dev(w.u0) for w in bins]
     S = [to_dev(w.S(0)) for w in bins]
