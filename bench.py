@@ -76,7 +76,7 @@ def device_sources(w):
     return srcs
 
 
-KERNEL_SOURCES = ("device.h", "internal.h", "stencil.hip", "tile.h")
+KERNEL_SOURCES = ("device.h", "internal.h", "stencil.hip", "tile.h", "staged.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_kernel_traffic.txt")
 
 

@@ -1,0 +1,288 @@
+// Two Newton-Leja terms per block pass with the input rows staged in LDS
+// (the pass of leja2s_kernel, stencil.hip): ring layout, row loads and puts,
+// the stencil from the rings, and one block's run over a strip.
+#pragma once
+
+#include "tile.h"
+
+namespace adl {
+
+// Two Newton-Leja terms per launch with the input rows staged in LDS (for
+// runs of several bands).  Same strips, bands and runs as leja2_kernel.  Per
+// band step (output rows j0 .. j0+3) every wave loads one new row of y_k,
+// kyy, kxy and kxx (and ax', ay') -- rows j0+2 .. j0+5 -- and puts it into
+// an LDS row ring, so each input row of a run leaves HBM once and is read by
+// the stencils of the rows around it from LDS.  Stage 1 computes y_{k+1} on
+// rows j0+1 .. j0+4, one row per wave (rows j0-1 and j0 come from the
+// previous step, or the run's prologue); stage 2 computes y_{k+2} on
+// j0 .. j0+3 and updates p as leja2_kernel does.  The next step's rows are
+// loaded into registers when a step starts and put into the rings after its
+// stage 2, so their latency hides behind the step's arithmetic.
+// A ring row holds [left halo, the strip's 64*VEC values, right halo]; a
+// reader takes its lane's VEC values and the elements on either side and
+// applies the Dirichlet ghost-column selects of row_n.
+//
+// Ring sizes of the staged kernel: a band step reads input rows j0-1 .. j0+5
+// (7 rows) and, after its last reads, replaces j0-1 .. j0+2 by j0+6 .. j0+9;
+// stage 2 reads y_{k+1} rows j0-1 .. j0+4 (6 rows), the next stage 1 writes
+// j0+5 .. j0+8 after a barrier.  With these sizes a block's LDS (35 KB in
+// FP64 with constant advection) lets four blocks share a CU.
+constexpr int kSRing = 2 * kWavesY2 - 1;
+constexpr int kSY1 = kWavesY2 + 2;
+
+__device__ __forceinline__ int map_row_any(int r, int ny, int bc, int mode, bool& zero) {
+  zero = false;
+  if (r >= 0 && r < ny) return r;
+  if (bc == BC_PERIODIC) {
+    const int m = r % ny;
+    return m < 0 ? m + ny : m;
+  }
+  if (mode == MODE_EDGE) return r < 0 ? 0 : ny - 1;
+  zero = true;
+  return 0;
+}
+
+// one lane's part of an input row, as loaded (boundary rule on the row index)
+template <int VEC>
+struct RawRow {
+  double c[VEC];
+  double h;
+  bool zero;
+};
+
+template <typename T, int VEC, int MODE>
+__device__ __forceinline__ void raw_load(const T* __restrict__ a, int r, const FieldView& F, const Strip& g,
+                                         RawRow<VEC>& o) {
+  const int row = map_row_any(r, F.ny, F.bc, MODE, o.zero);
+  const T* rp = a + (long)row * F.nx;
+  ldr<T, VEC>(rp, g.colc, o.c);
+  o.h = ld1<T>(rp, g.hcol);
+}
+
+template <int VEC>
+__device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<VEC>& x) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) row[1 + lane * VEC + v] = x.zero ? 0.0 : x.c[v];
+  if (g.lane0) row[0] = x.zero ? 0.0 : x.h;
+  if (g.lane63) row[kWave * VEC + 1] = x.zero ? 0.0 : x.h;
+}
+
+template <int VEC, int MODE>
+__device__ __forceinline__ void ring_rown(const double* row, const Strip& g, RowN<VEC>& o) {
+  const double* p = row + (threadIdx.x & (kWave - 1)) * VEC;
+  const double l = p[0];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = p[1 + v];
+  const double r = p[VEC + 1];
+  const double gl = MODE == MODE_EDGE ? o.c[0] : 0.0;
+  const double gr = MODE == MODE_EDGE ? o.c[VEC - 1] : 0.0;
+  o.l = g.ghostL ? gl : l;
+  o.r = g.ghostR ? gr : r;
+}
+
+template <int VEC>
+__device__ __forceinline__ void ring_rowc(const double* row, RowC<VEC>& o) {
+  const double* p = row + (threadIdx.x & (kWave - 1)) * VEC + 1;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = p[v];
+}
+
+// the input rings of a block: y_k, kyy, kxy, kxx (+ ax', ay'), kSRing rows each
+template <int VEC, bool ADVF>
+struct Rings {
+  static constexpr int kRow = kWave * VEC + 2;
+  static constexpr int kArrays = ADVF ? 6 : 4;
+  double* base;
+  int r0;  // grid row of slot 0
+  __device__ __forceinline__ double* row(int a, int r) const {
+    return base + ((long)a * kSRing + (unsigned)(r - r0) % kSRing) * kRow;
+  }
+};
+
+// the loads of one grid row for every input ring
+template <int VEC, bool ADVF>
+struct RowSet {
+  RawRow<VEC> y, gy, m, k, ax, ay;
+};
+
+template <typename TF, typename TY, int VEC, bool ADVF>
+__device__ __forceinline__ void rowset_load(const FieldView& F, const TY* __restrict__ yin, const Strip& g, int r,
+                                            RowSet<VEC, ADVF>& s) {
+  raw_load<TY, VEC, MODE_ZERO>(yin, r, F, g, s.y);
+  raw_load<TF, VEC, MODE_EDGE>(reinterpret_cast<const TF*>(F.kyy), r, F, g, s.gy);
+  raw_load<TF, VEC, MODE_ZERO>(reinterpret_cast<const TF*>(F.kxy), r, F, g, s.m);
+  raw_load<TF, VEC, MODE_EDGE>(reinterpret_cast<const TF*>(F.kxx), r, F, g, s.k);
+  if constexpr (ADVF) {
+    raw_load<TF, VEC, MODE_ZERO>(reinterpret_cast<const TF*>(F.ax), r, F, g, s.ax);
+    raw_load<TF, VEC, MODE_ZERO>(reinterpret_cast<const TF*>(F.ay), r, F, g, s.ay);
+  }
+}
+
+template <int VEC, bool ADVF>
+__device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF>& R, const Strip& g, int r,
+                                           const RowSet<VEC, ADVF>& s) {
+  ring_put<VEC>(R.row(0, r), g, s.y);
+  ring_put<VEC>(R.row(1, r), g, s.gy);
+  ring_put<VEC>(R.row(2, r), g, s.m);
+  ring_put<VEC>(R.row(3, r), g, s.k);
+  if constexpr (ADVF) {
+    ring_put<VEC>(R.row(4, r), g, s.ax);
+    ring_put<VEC>(R.row(5, r), g, s.ay);
+  }
+}
+
+// (A x) at row r from the rings, x = y_k (ring 0) or the rows u[] given
+template <int VEC, bool ADVF>
+__device__ __forceinline__ void ring_stencil(const Rings<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
+                                             const RowN<VEC>& um, const RowN<VEC>& uc, const RowN<VEC>& up,
+                                             double (&Ax)[VEC]) {
+  RowN<VEC> m[3], k, ac;
+  RowC<VEC> gg[3], ay[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    ring_rowc<VEC>(R.row(1, r - 1 + t), gg[t]);
+    ring_rown<VEC, MODE_ZERO>(R.row(2, r - 1 + t), g, m[t]);
+    if constexpr (ADVF) ring_rowc<VEC>(R.row(5, r - 1 + t), ay[t]);
+  }
+  ring_rown<VEC, MODE_EDGE>(R.row(3, r), g, k);
+  if constexpr (ADVF) ring_rown<VEC, MODE_ZERO>(R.row(4, r), g, ac);
+  stencil_point<VEC, ADVF>(um, uc, up, gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc, F.ayc,
+                           Ax);
+}
+
+// stage 1 of row r: y_{k+1} into the y_{k+1} ring (ghost rule of Stage1Ep)
+template <int VEC, bool ADVF>
+__device__ __forceinline__ void ring_stage1(const Rings<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
+                                            Stage1Ep<VEC, kSY1>& ep) {
+  RowN<VEC> u[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) ring_rown<VEC, MODE_ZERO>(R.row(0, r - 1 + t), g, u[t]);
+  double Ax[VEC];
+  ring_stencil<VEC, ADVF>(R, g, r, F, u[0], u[1], u[2], Ax);
+  typename Stage1Ep<VEC, kSY1>::Extra none;
+  ep.finish(r, g, Ax, u[1].c, none);
+}
+
+
+// What a block's run reads and writes (one operator's buffers and plan
+// scalars for the launch's terms k+1, k+2).
+template <typename TY>
+struct StagedIO {
+  const TY* yin;
+  TY* yout;
+  const double* pin;
+  double* pmid;
+  double* p;
+  double shift, shift2, invg, dk1, dk2;
+};
+
+// One block (kWavesY2 waves) over bands rb0 .. rb1-1 of the strip whose
+// first loaded column is i0: the run's prologue, then per band step the next
+// rows' loads, stage 1, stage 2 and the stores; acc gets the lane's norm sums
+// (term k+1: ||d y||^2, ||p||^2; term k+2: the same).  `stopflag` gates the
+// work after the first loads; every wave executes every barrier.
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
+__device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY>& io, double* lds, int i0, int rb0,
+                                           int rb1, int stopflag, double (&acc)[4]) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int W = kWave * VEC;
+  const Strip g = strip_at<VEC>(F, i0);
+  const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
+  const int J0 = rb0 * kWavesY2;
+  Stage1Ep<VEC, kSY1> ep1;
+  ep1.lds = lds;
+  ep1.r0 = J0 - 1;
+  ep1.ny = F.ny;
+  ep1.per = F.bc == BC_PERIODIC;
+  ep1.shift = io.shift;
+  ep1.invg = io.invg;
+  ep1.stopflag = stopflag;
+  Rings<VEC, ADVF> R;
+  R.base = lds + kSY1 * W;
+  R.r0 = J0 - 2;
+  const TY* __restrict__ yin = io.yin;
+  // prologue: input rows J0-2 .. J0+1, y_{k+1} on J0-1 and J0, then input
+  // rows J0+2 .. J0+5 (the last of them takes the slot of J0-2)
+  RowSet<VEC, ADVF> cur, nxt;
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 - 2 + wave, cur);
+  const bool live = ep1.go();
+  if (live) {
+    rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 2 + wave, nxt);
+    rowset_put<VEC, ADVF>(R, g, J0 - 2 + wave, cur);
+  }
+  __syncthreads();
+  if (live && wave < 2) ring_stage1<VEC, ADVF>(R, g, J0 - 1 + wave, F, ep1);
+  __syncthreads();
+  if (live) rowset_put<VEC, ADVF>(R, g, J0 + 2 + wave, nxt);
+  __syncthreads();
+#pragma unroll 1
+  for (int rb = rb0; rb < rb1; ++rb) {
+    const int j0 = rb * kWavesY2;
+    const int j = j0 + wave;
+    const bool has = j < F.ny;
+    const bool more = rb + 1 < rb1;
+    // the next step's input rows and this step's p_k, in flight during the step
+    double pk[VEC];
+    if (live) {
+      if (more) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 6 + wave, nxt);
+      if (own && has) ldr_s<NT, double, VEC>(io.pin + (long)j * F.nx, g.col0, pk);
+      // stage 1: y_{k+1} on row j0+1+wave
+      ring_stage1<VEC, ADVF>(R, g, j0 + 1 + wave, F, ep1);
+    }
+    __syncthreads();
+    if (live && has) {
+      // stage 2: y_{k+2} on row j
+      RowN<VEC> u[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(lds, (unsigned)(j - 1 + t - ep1.r0) % kSY1, u[t]);
+      double Ax[VEC];
+      ring_stencil<VEC, ADVF>(R, g, j, F, u[0], u[1], u[2], Ax);
+      if (own) {
+        const long ro = (long)j * F.nx;
+        const double* y1row = lds + (long)((unsigned)(j - ep1.r0) % kSY1) * W + lane * VEC;
+        double y2[VEC], pm[VEC], p2[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double t1 = io.dk1 * y1row[v];
+          pm[v] = pk[v] + t1;
+          y2[v] = (Ax[v] - io.shift2 * u[1].c[v]) * io.invg;
+          const double t2 = io.dk2 * y2[v];
+          p2[v] = pm[v] + t2;
+          acc[0] += t1 * t1;
+          acc[1] += pm[v] * pm[v];
+          acc[2] += t2 * t2;
+          acc[3] += p2[v] * p2[v];
+        }
+        str_s<NT, TY, VEC>(io.yout + ro, g.col0, y2);
+        str_s<NT, double, VEC>(io.pmid + ro, g.col0, pm);
+        str_s<NT, double, VEC>(io.p + ro, g.col0, p2);
+      }
+    }
+    __syncthreads();
+    // the next step's rows replace rows j0-1 .. j0+2, read for the last time above
+    if (live && more) rowset_put<VEC, ADVF>(R, g, j0 + 6 + wave, nxt);
+    __syncthreads();
+  }
+}
+
+// dynamic LDS of a staged block
+template <int VEC, bool ADVF>
+constexpr size_t staged_lds_bytes() {
+  return ((size_t)kSY1 * kWave * VEC + (size_t)Rings<VEC, ADVF>::kArrays * kSRing * Rings<VEC, ADVF>::kRow) *
+         sizeof(double);
+}
+
+// Dispatch index -> logical block, such that each XCD (the dispatcher deals
+// blocks to the 8 XCDs round-robin) runs a contiguous range of logical blocks:
+// neighbouring strips then share the 128-byte lines at their common edge in
+// one L2 (at 4096^2: 13 % fewer HBM reads).  A bijection on [0, n) that keeps
+// 0 at 0.
+__device__ __forceinline__ int xcd_contiguous(int bid, int n) {
+  const int q = n / 8, rem = n % 8;
+  const int x = bid % 8, l = bid / 8;
+  return x < rem ? x * (q + 1) + l : rem * (q + 1) + (x - rem) * q + l;
+}
+
+}  // namespace adl
