@@ -309,6 +309,42 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes": a.numel() * 8}), flush=True)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read nbytes, write nbytes), timed with
+    HIP events on the current stream: the practical HBM rate next to the 8 TB/s
+    peak.  Returns GB/s of moved bytes (2 * nbytes per copy), best of reps."""
+    import torch
+    a = torch.zeros(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 0.0
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2.0 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
+def host_cpu():
+    """Model name of the host CPU and the number of logical CPUs."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle, single-threaded, on the first steps of the same
     workload until budget_s seconds of CPU work have been spent."""
@@ -413,7 +449,7 @@ def main():
                                "a=(0.2,0), time-independent Gaussian source, two-stage exp. quadrature "
                                "c=(1/3,2/3), dt=200 dt_CFL, tol=1e-10",
                    "nx": 512, "ny": 512, "dt": w.dt, "tol": w.tol, "alpha": alpha,
-                   "matvecs_per_step": mv / args.steps, "setup_s": setup_s},
+                   "matvecs_per_step": mv / args.steps, "matvecs_per_s": mv / el, "setup_s": setup_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "leja2_kernel (two Newton terms per launch; the first term of a sweep "
@@ -439,9 +475,11 @@ def main():
             gpu_step(op2, cw, ug, n, s2)
         torch.cuda.synchronize()
         err = float(np.linalg.norm(ug.cpu().numpy() - u_cpu) / np.linalg.norm(u_cpu))
+        model, ncpu = host_cpu()
         out["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": 1, "kind": "oracle",
                                "sample": "first %d steps of the same 512^2 workload (%.1fs), NumPy FP64, "
-                                         "single-threaded" % (nst, el_cpu)}
+                                         "single-threaded" % (nst, el_cpu),
+                               "host_cpu": model, "host_logical_cpus": ncpu}
         out["parity"] = {"steps": nst, "rel_l2_vs_oracle": err}
         log("cpu oracle: %.3f steps/s over %d steps; GPU rel err on those steps %.2e" % (rate, nst, err))
         del op2
@@ -459,7 +497,12 @@ def main():
             log("roofline leg %s %s: %.1f us/launch, %.1f us/term, %.0f GB/s (%.1f%% of 8 TB/s)" % (
                 legs[-1]["storage"], legs[-1]["launches_of"], legs[-1]["avg_kernel_us"],
                 legs[-1]["us_per_term"], legs[-1]["achieved_GBs"], 100 * legs[-1]["frac_of_8TBs"]))
+        copy_gbs = copy_bandwidth()
+        log("device copy of 1 GiB: %.0f GB/s (read + write)" % copy_gbs)
+        for leg in legs:
+            leg["frac_of_copy"] = leg["achieved_GBs"] / copy_gbs
         out["roofline_4096"] = legs
+        out["copy_GBs"] = copy_gbs
         out["chosen_vs_plain"] = chosen_vs_plain()
         out["paper_cases"] = paper_cases_leg()
 

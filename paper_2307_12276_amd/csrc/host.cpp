@@ -5,9 +5,11 @@
 // approximated by Newton interpolation of phi_l((c + gamma xi) dt) at Leja
 // points xi in [-2, 2], c = alpha/2, gamma = -alpha/4, applied term by term:
 //   y_{k+1} = ((A - c I)/gamma - xi_k I) y_k,   p_{k+1} = p_k + d_{k+1} y_{k+1}.
-// One GPU launch per term (fused stencil + axpy + norms); the last block of
-// each launch sets a device stop flag so that launches enqueued after
-// convergence are no-ops, and the host reads the flag once per chunk.
+// Two terms per GPU launch after the first (fused stencils + axpys + norms);
+// one block of each launch takes the stopping decision of the previous
+// launch's terms and sets a device stop flag, so that launches enqueued after
+// convergence do no work, and the host reads the control block once per chunk
+// of launches.
 #include "op.h"
 
 #include <algorithm>

@@ -13,16 +13,19 @@
 // Layout and mapping.  Arrays are [ny][nx], x contiguous.  A tile is one strip
 // of 64 * VEC columns by 4 * rows rows; the four waves of a block take the
 // four row bands of a tile (stacked in y, so the rows they share are L1 hits),
-// each wave computing its rows in load groups of two (tile.h).  Blocks walk
-// the tiles in row-major order with a grid stride; with 32 strips per row
-// band (4096 columns) the tile below a tile runs on the same XCD, whose L2
-// serves the shared rows.
+// each wave computing one row per load group (tile.h).  Block b takes strip
+// b mod ncb and a run of consecutive row bands, so the rows shared between
+// consecutive bands are re-read from cache soon after their first load.
+// Newton-Leja sweeps run one term (leja_kernel) or two terms per launch: the
+// register-frame kernel (leja2_kernel) on cache-resident grids, the kernel
+// with input rows staged in LDS (leja2s_kernel, staged.h) beyond the caches.
 //
 // Reductions (norms for the Leja stopping test, power iteration) are fixed
 // order: shuffle tree per wave, waves in order, block partials written to
-// memory.  The next launch's blocks each sum the partials in the same fixed
-// order before doing any work (no agent-scope fence; a kernel boundary makes
-// the partials visible).  Results are bitwise reproducible for a given tiling.
+// memory.  One block of the next launch (or a one-block launch closing a
+// chunk) sums them in index order and records the decision; worker waves only
+// read the stop flag (no agent-scope fence; a kernel boundary makes the
+// partials visible).  Results are bitwise reproducible for a given tiling.
 #include "staged.h"
 
 #include <hip/hip_ext.h>
