@@ -136,3 +136,31 @@ def test_learned_interval_4096_fp32_storage():
     assert el <= 1e-5 and ep <= 1e-5
     assert tl < tp
     assert max(dl, dp, d_ref) < 1e-10
+
+
+def test_two_term_kernels_at_4096_match_one_term_launches():
+    """The 4096^2 stream-function field of the bench's roofline legs (FP64,
+    a working set beyond the caches, so the library picks the LDS-staged
+    two-term kernel with non-temporal hints): one phi_1 sweep with one term
+    per launch, with the staged kernel and with the register-frame kernel.
+    Same degree, and the same polynomial up to the grouping of the norm
+    partial sums (the one-term path equals the oracle at smaller sizes)."""
+    w = W.roofline_shape(n=4096)
+    op = make_op(w, A.STORAGE_FP64)
+    op.spectral_bound(A.BOUND_GERSHGORIN)
+    v = to_dev(w.u0)
+    outs, degs = {}, {}
+    for mode in (0, 1, 3):
+        op.set_term_fusion(mode)
+        out = torch.empty_like(v)
+        st = op.leja_phi(1, w.dt, v, out, w.tol)
+        outs[mode] = out
+        degs[mode] = st["max_degree"]
+    r1 = float((outs[1] - outs[0]).norm() / outs[0].norm())
+    r3 = float((outs[3] - outs[0]).norm() / outs[0].norm())
+    print("4096^2 phi_1 sweep: degrees %s, staged vs one-term %.2e, frames vs one-term %.2e, staged vs frames %s"
+          % (degs, r1, r3, "bitwise" if torch.equal(outs[1], outs[3]) else "differ"))
+    assert degs[0] == degs[1] == degs[3]
+    assert r1 < 1e-13 and r3 < 1e-13
+    del op
+    torch.cuda.empty_cache()
