@@ -160,6 +160,19 @@ int adl_op_set_term_fusion(adl_op* op, int mode);
  * the input vector, two y and four p buffers) exceeds 512 MiB.  Results are
  * identical in every mode.  ADL_EINVAL for other values. */
 int adl_op_set_streaming(adl_op* op, int mode);
+
+/* How the host learns where a sweep stopped (the stopping rule of Sec. 2 is
+ * evaluated on the GPU once per chunk of launches).  mode = 1 (the default):
+ * the chunk's decision launch writes the outcome into a cache line of
+ * coherent pinned host memory that the op holds, and the host spins on it;
+ * mode = 0: the control block is copied back and the stream synchronised
+ * (many microseconds more per chunk).  Without such memory, and while
+ * adl_op_profile is on, mode 0 is used.  Results are identical in both modes;
+ * a launch error ends the spin with ADL_EHIP.  adl_op_host_wait reports the
+ * mode in effect (1 only if the op holds the memory).  ADL_EINVAL for other
+ * values or a NULL mode. */
+int adl_op_set_host_wait(adl_op* op, int mode);
+int adl_op_host_wait(const adl_op* op, int* mode);
 int adl_op_get_tiling(const adl_op* op, int* cols_per_lane, int* rows, int* nblocks);
 
 /* y = A x (one stencil application).  x, y: device [ny][nx] FP64, not

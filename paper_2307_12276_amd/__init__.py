@@ -74,6 +74,8 @@ _SIG = {
     "adl_op_set_tiling": (_I, [_P, _I, _I]),
     "adl_op_set_term_fusion": (_I, [_P, _I]),
     "adl_op_set_streaming": (_I, [_P, _I]),
+    "adl_op_set_host_wait": (_I, [_P, _I]),
+    "adl_op_host_wait": (_I, [_P, ctypes.POINTER(_I)]),
     "adl_op_get_tiling": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "adl_op_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(_D)]),
@@ -234,6 +236,16 @@ class Op:
     def set_streaming(self, mode: int = -1):
         """Non-temporal hints on the Newton vectors: -1 auto, 0 off, 1 on."""
         _check(lib().adl_op_set_streaming(self.handle, int(mode)))
+
+    def set_host_wait(self, spin: bool = True):
+        """How the host awaits a sweep's outcome: spin on a pinned host mirror
+        (True, the default) or copy the control block back and synchronise."""
+        _check(lib().adl_op_set_host_wait(self.handle, int(bool(spin))))
+
+    def host_wait(self) -> bool:
+        m = ctypes.c_int()
+        _check(lib().adl_op_host_wait(self.handle, ctypes.byref(m)))
+        return bool(m.value)
 
     def get_tiling(self):
         v, r, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -8,11 +8,15 @@
 // Two terms per GPU launch after the first (fused stencils + axpys + norms);
 // one block of each launch takes the stopping decision of the previous
 // launch's terms and sets a device stop flag, so that launches enqueued after
-// convergence do no work, and the host reads the control block once per chunk
-// of launches.
+// convergence do no work, and the host learns the outcome once per chunk of
+// launches (by spinning on a pinned host mirror that the chunk's decision
+// launch writes, or by copying the control block back).
 #include "op.h"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -20,6 +24,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 namespace adl {
@@ -258,6 +263,101 @@ static int read_ctl(adl_op* op, hipStream_t st) {
   return ADL_OK;
 }
 
+// --------------------------------------------------------------------------
+// sweep outcome mirrors (HostCtl): coherent pinned host memory in pages of
+// kMirrorSlots cache lines per device, allocated on first use and kept until
+// the process ends; ops take a slot at creation and give it back when
+// destroyed.  Sequence numbers come from one process-wide counter, so a
+// number never repeats in a slot, whichever op held it before.
+// --------------------------------------------------------------------------
+constexpr int kMirrorSlots = 64;
+constexpr int kMirrorQueryUs = 50;  // stream query interval while spinning
+
+struct MirrorPool {
+  std::mutex m;
+  std::unordered_map<int, std::vector<std::pair<HostCtl*, HostCtl*>>> free;  // device -> (host, device address)
+};
+static MirrorPool& mirror_pool() {
+  static MirrorPool* p = new MirrorPool;  // never destroyed: slots may outlive static destructors
+  return *p;
+}
+static std::atomic<int> g_hseq{0};
+
+static int next_hseq() {
+  int v = g_hseq.fetch_add(1, std::memory_order_relaxed) + 1;
+  if (v <= 0) {  // wrapped: restart above zero (a slot starts at 0)
+    g_hseq.store(1, std::memory_order_relaxed);
+    v = 1;
+  }
+  return v;
+}
+
+static void mirror_take(adl_op* op) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  MirrorPool& P = mirror_pool();
+  std::lock_guard<std::mutex> g(P.m);
+  auto& fl = P.free[dev];
+  if (fl.empty()) {
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, kMirrorSlots * sizeof(HostCtl),
+                      hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable) != hipSuccess) {
+      (void)hipGetLastError();
+      return;  // the op copies the control block back instead
+    }
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      hipHostFree(h);  // no kernel has seen it yet
+      return;
+    }
+    std::memset(h, 0, kMirrorSlots * sizeof(HostCtl));
+    for (int i = kMirrorSlots - 1; i >= 0; --i)
+      fl.emplace_back(reinterpret_cast<HostCtl*>(h) + i, reinterpret_cast<HostCtl*>(d) + i);
+  }
+  op->hctl = fl.back().first;
+  op->hctl_dev = fl.back().second;
+  op->mirror_dev = dev;
+  fl.pop_back();
+}
+
+static void mirror_give(adl_op* op) {
+  if (!op->hctl) return;
+  MirrorPool& P = mirror_pool();
+  std::lock_guard<std::mutex> g(P.m);
+  P.free[op->mirror_dev].emplace_back(op->hctl, op->hctl_dev);
+  op->hctl = op->hctl_dev = nullptr;
+}
+
+// Waits until the chunk's decision launch has published sequence number
+// op->hseq, then copies the outcome into op->host_ctl.  The stream is queried
+// every kMirrorQueryUs while waiting, so that a failed launch ends the wait
+// with its error.
+static int await_outcome(adl_op* op, hipStream_t st) {
+  const HostCtl* h = op->hctl;
+  const int want = op->hseq;
+  auto seen = [&] { return __atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) == want; };
+  auto next = std::chrono::steady_clock::now() + std::chrono::microseconds(kMirrorQueryUs);
+  while (!seen()) {
+    __builtin_ia32_pause();
+    const auto now = std::chrono::steady_clock::now();
+    if (now < next) continue;
+    next = now + std::chrono::microseconds(kMirrorQueryUs);
+    const hipError_t q = hipStreamQuery(st);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail(ADL_EHIP, "Leja sweep failed: %s", hipGetErrorString(q));
+    if (seen()) break;
+    return fail(ADL_EHIP, "Leja sweep ended without publishing its outcome");
+  }
+  op->host_ctl->stop = __atomic_load_n(&h->stop, __ATOMIC_RELAXED);
+  op->host_ctl->status = __atomic_load_n(&h->status, __ATOMIC_RELAXED);
+  op->host_ctl->degree = __atomic_load_n(&h->degree, __ATOMIC_RELAXED);
+  return ADL_OK;
+}
+
 Plan& adl::get_plan(adl_op* op, int l, double alpha, double h) {
   for (Plan& P : op->plans)
     if (P.l == l && P.alpha == alpha && P.h == h && P.M == op->max_degree + 1) return P;
@@ -441,8 +541,15 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     a.nterms_prev = prev_n;
     a.slot_prev = prev_slot;
     a.decide_only = 1;
+    // outcome: published to the host mirror and awaited by spinning, or (when
+    // timing launches with events, which need the stream synchronised, or
+    // without a mirror) copied back
+    const bool spin = op->hctl && op->host_wait && !op->prof;
+    a.hctl = spin ? op->hctl_dev : nullptr;
+    a.hseq = spin ? (op->hseq = next_hseq()) : 0;
     HIPCHK(launch_leja_step(op->f, T, a, st));
-    RETCHK(read_ctl(op, st));
+    a.hctl = nullptr;
+    RETCHK(spin ? await_outcome(op, st) : read_ctl(op, st));
     if (op->prof) {
       // launches after the one that ran beside the final decision skipped
       // their work: time the others
@@ -700,6 +807,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
     delete op;
     return fail(ADL_EHIP, "hipHostMalloc failed: %s", hipGetErrorString(e));
   }
+  mirror_take(op);
   hipStream_t st = S(stream);
   const long n = op->n;
   int rc = ADL_OK;
@@ -718,6 +826,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   }
   if (rc != ADL_OK) {
     hipHostFree(op->host_ctl);
+    mirror_give(op);
     delete op;
     return rc;
   }
@@ -730,6 +839,7 @@ int adl_op_destroy(adl_op* op) {
   if (!op) return ADL_OK;
   for (hipEvent_t e : op->evs) hipEventDestroy(e);
   if (op->host_ctl) hipHostFree(op->host_ctl);
+  mirror_give(op);
   delete op;
   return ADL_OK;
 }
@@ -781,6 +891,20 @@ int adl_op_set_term_fusion(adl_op* op, int mode) {
   RETCHK(check_op(op));
   if (mode < 0 || mode > 3) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2 or 3");
   op->fuse_terms = mode;
+  return ADL_OK;
+}
+
+int adl_op_set_host_wait(adl_op* op, int mode) {
+  RETCHK(check_op(op));
+  if (mode != 0 && mode != 1) return fail(ADL_EINVAL, "host wait mode must be 0 or 1");
+  op->host_wait = mode;
+  return ADL_OK;
+}
+
+int adl_op_host_wait(const adl_op* op, int* mode) {
+  RETCHK(check_op(op));
+  if (!mode) return fail(ADL_EINVAL, "null mode");
+  *mode = op->hctl && op->host_wait ? 1 : 0;
   return ADL_OK;
 }
 

@@ -48,6 +48,19 @@ struct Ctl {
 };
 static_assert(sizeof(Ctl) <= 128, "ctl size");
 
+// The outcome of a sweep as the host reads it: a copy of the control block's
+// fields, written by the chunk's one-block decision launch into coherent
+// (fine-grained) pinned host memory, fields first and the sequence number
+// last with a system-scope release.  The host spins on the number instead of
+// copying the control block back and synchronising the stream, which wakes
+// the host many microseconds later.  One cache line per op.
+struct HostCtl {
+  int seq;
+  int stop, status, degree;
+  int pad[12];
+};
+static_assert(sizeof(HostCtl) == 64, "one cache line");
+
 // The stored operator.  Coefficients are pre-scaled:
 //   kxx = Dxx / hx^2, kyy = Dyy / hy^2, kxy = Dxy / (4 hx hy),
 //   ax' = ax / (2 hx), ay' = ay / (2 hy)
@@ -121,6 +134,8 @@ struct LejaArgs {
   int slot_prev;
   int decide_only;   // only take the decision of the previous launch (1-block launch)
   Ctl* ctl;
+  HostCtl* hctl;     // decision launch: publish the outcome here (device address), or null
+  int hseq;          // ... with this sequence number
   hipEvent_t ev_start;  // optional: dispatch-attached timing events
   hipEvent_t ev_stop;
 };

@@ -80,6 +80,11 @@ struct adl_op {
   double* partials = nullptr;
   Ctl* ctl = nullptr;
   Ctl* host_ctl = nullptr;  // pinned
+  adl::HostCtl* hctl = nullptr;  // sweep outcome mirror (coherent pinned host memory; null: copy back instead)
+  adl::HostCtl* hctl_dev = nullptr;  // its device address
+  int hseq = 0;             // sequence number of the pending publication
+  int mirror_dev = 0;       // device whose pool holds the slot
+  int host_wait = 1;        // 1: spin on the mirror when there is one; 0: copy back + synchronise
   std::vector<Plan> plans;  // small cache
   int plan_next = 0;
   // kernel profiling of the Newton-Leja iteration kernel

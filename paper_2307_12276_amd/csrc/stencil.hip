@@ -269,6 +269,19 @@ __device__ __forceinline__ void leja_decide(const LejaArgs& A) {
   }
 }
 
+// The sweep's outcome for the host (thread 0 of the decision launch, after
+// leja_decide): the control block's fields (written by this thread, or by an
+// earlier launch), then the sequence number with a system-scope release, so
+// that a host that sees the number sees the fields too.
+__device__ __forceinline__ void publish_outcome(const LejaArgs& A) {
+  HostCtl* h = A.hctl;
+  const Ctl* c = A.ctl;
+  h->stop = __hip_atomic_load(&c->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  h->status = c->status;
+  h->degree = c->degree;
+  __hip_atomic_store(&h->seq, A.hseq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // The sweep's stop flag, read once per block (thread 0) and broadcast, so that
 // a concurrent update of the flag cannot split a block.
 __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
@@ -302,6 +315,7 @@ __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T,
   if (A.decide_only || blockIdx.x == 0) {
     if (!FIRST) {
       leja_decide(A);
+      if (A.decide_only && A.hctl && threadIdx.x == 0) publish_outcome(A);
     } else if (threadIdx.x == 0) {
       // a new sweep: clear the control block (no block of this launch reads it)
       Ctl c{};

@@ -303,3 +303,78 @@ def test_streaming_hints_do_not_change_results(nx, ny, bc, storage):
         assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
     with pytest.raises(A.AdlError):
         gop.set_streaming(2)
+
+
+def _wait_case(spin, v, dt, alpha, fields):
+    """A fresh op (so that its first sweep guesses the chunk length), one
+    phi_1 sweep and one quad2 step with the given host wait mode."""
+    oop, gop = make_pair(*fields)
+    gop.set_bound(alpha)
+    gop.set_host_wait(spin)
+    assert gop.host_wait() == spin
+    out = torch.empty_like(v)
+    s1 = gop.leja_phi(1, dt, v, out, 1e-10)
+    u = v.clone()
+    S = torch.full_like(v, 0.5)
+    s2 = gop.quad2_step(u, S, 2.0 * S, 1.0 / 3.0, 2.0 / 3.0, dt, 1e-10)
+    return to_np(out), s1, to_np(u), s2
+
+
+def test_host_wait_modes_agree():
+    """The sweep outcome awaited by spinning on the op's pinned host mirror
+    (the default) or by copying the control block back: bitwise the same
+    phi_1 result and quad2 step and the same statistics, over sweeps of
+    several chunks (dt = 2000 / |alpha|: two substeps of degree 138 and 123,
+    the first sweep of the plan guesses 114 terms and needs a second chunk);
+    the phi_1 result matches the oracle."""
+    nx, ny = 130, 70
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=11)
+    fields = (Dxx, Dxy, Dyy, ax, ay, 1.0 / nx, 1.0 / ny, O.DIRICHLET)
+    oop = O.make_operator(*fields)
+    alpha = bounds.gershgorin(oop)
+    v0 = W.random_vector((ny, nx), 5)
+    v = to_dev(v0)
+    dt = 2000.0 / abs(alpha)
+    spin = _wait_case(True, v, dt, alpha, fields)
+    copy = _wait_case(False, v, dt, alpha, fields)
+    assert np.array_equal(spin[0], copy[0]) and np.array_equal(spin[2], copy[2])
+    assert spin[1] == copy[1] and spin[3] == copy[3]
+    st = {}
+    ref = leja.phi_apply(lambda x: O.apply(oop, x), 1, dt, v0, alpha, 1e-10, stats=st)
+    assert spin[1]["matvecs"] == st["matvecs"] and spin[1]["matvecs"] > 40
+    assert rel(spin[0], ref) < 1e-10
+    _, gop = make_pair(*fields)
+    assert gop.host_wait()  # the default where pinned memory is available
+    with pytest.raises(A.AdlError):
+        A._check(A.lib().adl_op_set_host_wait(gop.handle, 2))
+
+
+def test_host_mirror_slots_are_recycled():
+    """More ops alive at once than one page of mirror slots (64), then all
+    destroyed and as many created again (slots reused): every op's sweep
+    gives the same result as the first op's, spinning on its mirror
+    (76 terms in two chunks)."""
+    n = 24
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(n, n, seed=5)
+    fields = (Dxx, Dxy, Dyy, ax, ay, 1.0 / n, 1.0 / n, O.PERIODIC)
+    alpha = bounds.gershgorin(O.make_operator(*fields))
+    v = to_dev(W.random_vector((n, n), 2))
+    dt = 300.0 / abs(alpha)
+
+    def run(op):
+        op.set_bound(alpha)
+        out = torch.empty_like(v)
+        st = op.leja_phi(1, dt, v, out, 1e-10)
+        return to_np(out), st
+
+    first = None
+    for _ in range(2):
+        ops = [make_pair(*fields)[1] for _ in range(80)]
+        for op in ops:
+            assert op.host_wait()
+            out, st = run(op)
+            if first is None:
+                first = (out, st)
+            assert np.array_equal(out, first[0]) and st == first[1]
+        for op in ops:
+            op.close()
