@@ -23,6 +23,7 @@
 // replayed: one graph launch per step.  Kernel boundaries give cross-XCD
 // visibility of y_k, so no wave ever waits on another and no agent-scope fence
 // is needed.
+#include "staged.h"
 #include "tile.h"
 #include "op.h"
 
@@ -36,6 +37,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace adl {
@@ -224,7 +226,7 @@ struct BatchLejaEp {
 template <typename TF, int VEC, bool ADVF>
 __global__ __launch_bounds__(64) void batch_stage_kernel(BatchArgs A) {
   const int gt = blockIdx.x;
-  const int b = A.tile_bin[gt];
+  const int b = __builtin_amdgcn_readfirstlane(A.tile_bin[gt]);
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
   const int t = gt - B.tile_base;
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A, int nbins) 
     return;
   }
   const int gt = blockIdx.x - nbins;
-  const int b = A.tile_bin[gt];
+  const int b = __builtin_amdgcn_readfirstlane(A.tile_bin[gt]);
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
   if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
@@ -293,87 +295,346 @@ __global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A, int nbins) 
 
 // Two terms per launch (k >= 1) on one wave per tile of 62*VEC output columns
 // x `rows` rows (lanes 0 and 63 are the one-column frame): the wave marches
-// down its rows, computing y_{k+1} of row r+1 into a four-row LDS ring of its
-// own and then y_{k+2} of row r from the ring rows r-1 .. r+1; p_{k+1} and
-// p_{k+2} as for a single operator.  Each lane reads back only the ring
-// elements it wrote (its x-neighbours come from DPP shifts), so the wave needs
-// no barrier.
-constexpr int kBRing = 4;
+// down its rows with every vertical window in registers -- input rows r ..
+// r+2 of y_k, rows r-1 .. r+2 of kyy and kxy (ay'), rows r .. r+1 of kxx
+// (ax'), y_{k+1} on rows r-1 .. r+1 -- computing y_{k+1} of row r+1 and then
+// y_{k+2} of row r; p_{k+1} and p_{k+2} as for a single operator.  Each step
+// first issues the loads of the next step's new input row (and of its p_k
+// row), so that their latency hides behind the step's arithmetic, and every
+// input element of the tile is loaded once.  The x-neighbours of y_{k+1} come
+// from DPP shifts within the wave (the frame lanes compute y_{k+1} too), so
+// the wave needs neither LDS nor a barrier.
+
+// Global-memory pointers.  A bin's array addresses come from its descriptor
+// in memory, so the compiler sees them as generic pointers and would access
+// them with FLAT instructions (64-bit per-lane addresses, and counted by the
+// LDS/scalar counter too, so that every use of a loaded value waits for all
+// loads in flight, the prefetched rows included).  The two-term tile converts
+// them to address space 1 once and keeps them there down to each load and
+// store (a cast back to a generic pointer would be folded away with the
+// first one).
+template <typename T>
+using GP = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ GP<const T> gp(const void* p) {
+  return (GP<const T>)p;
+}
+template <typename T>
+__device__ __forceinline__ GP<T> gpw(void* p) {
+  return (GP<T>)p;
+}
+// element `col` of the row starting at rowp (wave-uniform row start, 32-bit lane offset)
+template <typename T>
+__device__ __forceinline__ GP<const T> gcol(GP<const T> rowp, int col) {
+  return (GP<const T>)((GP<const char>)rowp + (unsigned)(col * (int)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ GP<T> gcolw(GP<T> rowp, int col) {
+  return (GP<T>)((GP<char>)rowp + (unsigned)(col * (int)sizeof(T)));
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void gload(GP<const T> p, T (&c)[VEC]) {
+  if constexpr (VEC == 2) {
+    typedef T t2 __attribute__((ext_vector_type(2)));
+    const t2 v = *(GP<const t2>)p;
+    c[0] = v.x;
+    c[1] = v.y;
+  } else {
+    c[0] = *p;
+  }
+}
+template <int VEC>
+__device__ __forceinline__ void gstore(GP<double> p, const double (&c)[VEC]) {
+  if constexpr (VEC == 2) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 v;
+    v.x = c[0];
+    v.y = c[1];
+    *(GP<d2>)p = v;
+  } else {
+    *p = c[0];
+  }
+}
+
+// Wave-uniform copies (scalar registers) of values a tile reads from its
+// bin's descriptor: loaded by vector loads, they would otherwise stay in
+// vector registers, and so would every address computed from them.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uni64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double uni(double v) {
+  return __longlong_as_double((long long)uni64((unsigned long long)__double_as_longlong(v)));
+}
+template <typename T>
+__device__ __forceinline__ GP<T> uni(GP<T> p) {
+  return (GP<T>)uni64((unsigned long long)p);
+}
+
+// one lane's part of a row as stored (type T): its VEC values, the halo
+// element (lane 0: left, lane 63: right) and the zero-ghost-row flag
+template <typename T, int VEC>
+struct TRow {
+  T c[VEC];
+  T h;
+  bool zero;
+};
+template <typename T, int VEC>
+struct TRowC {
+  T c[VEC];
+  bool zero;
+};
+
+template <typename T, int VEC, int MODE>
+__device__ __forceinline__ void trow_load(GP<const T> a, int r, const FieldView& F, const Strip& g,
+                                          TRow<T, VEC>& o) {
+  const int row = uni(map_row_any(r, F.ny, F.bc, MODE, o.zero));
+  const GP<const T> rp = a + (long)row * F.nx;
+  gload<T, VEC>(gcol<T>(rp, g.colc), o.c);
+  o.h = *gcol<T>(rp, g.hcol);
+}
+
+template <typename T, int VEC, int MODE>
+__device__ __forceinline__ void trowc_load(GP<const T> a, int r, const FieldView& F, const Strip& g,
+                                           TRowC<T, VEC>& o) {
+  const int row = uni(map_row_any(r, F.ny, F.bc, MODE, o.zero));
+  gload<T, VEC>(gcol<T>(a + (long)row * F.nx, g.colc), o.c);
+}
+
+template <typename T, int CTRL>
+__device__ __forceinline__ double dpp_t(T v) {
+  if constexpr (sizeof(T) == 8) {
+    return dpp_f64<CTRL>(v);
+  } else {
+    return (double)__int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  }
+}
+
+// a stored row with its x-neighbours (DPP shifts, halo element, Dirichlet
+// ghost selects), in FP64, as row_n builds it
+template <typename T, int VEC, int MODE>
+__device__ __forceinline__ RowN<VEC> rown_of(const TRow<T, VEC>& x, const Strip& g) {
+  RowN<VEC> o;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = x.zero ? 0.0 : (double)x.c[v];
+  const double l = x.zero ? 0.0 : dpp_t<T, kDppWaveShr1>(x.c[VEC - 1]);
+  const double rr = x.zero ? 0.0 : dpp_t<T, kDppWaveShl1>(x.c[0]);
+  const double hz = x.zero ? 0.0 : (double)x.h;
+  const double gl = MODE == MODE_EDGE ? o.c[0] : 0.0;
+  const double gr = MODE == MODE_EDGE ? o.c[VEC - 1] : 0.0;
+  o.l = g.ghostL ? gl : (g.useL ? hz : l);
+  o.r = g.ghostR ? gr : (g.useR ? hz : rr);
+  return o;
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ RowC<VEC> rowc_of(const TRowC<T, VEC>& x) {
+  RowC<VEC> o;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = x.zero ? 0.0 : (double)x.c[v];
+  return o;
+}
+
+// y_{k+1} values of a row (zero at ghost positions) with their x-neighbours
+template <int VEC>
+__device__ __forceinline__ RowN<VEC> rown_y1(const double (&c)[VEC]) {
+  RowN<VEC> o;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = c[v];
+  o.l = dpp_f64<kDppWaveShr1>(c[VEC - 1]);
+  o.r = dpp_f64<kDppWaveShl1>(c[0]);
+  return o;
+}
+
+// the new rows of one marching step, as stored: input row q of y_k, kyy,
+// kxy (ay'), row q-1 of kxx (ax'), and p_k of the step's output row
+template <typename TF, int VEC>
+struct StepRows {
+  TRow<double, VEC> y;
+  TRow<TF, VEC> m, k, ax;
+  TRowC<TF, VEC> g, ay;
+  double p[VEC];
+};
+
+// the arrays a two-term tile reads, as global pointers
+template <typename TF>
+struct TileIn {
+  GP<const double> y, p;
+  GP<const TF> kxx, kxy, kyy, ax, ay;
+};
+
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void load_step_rows(const FieldView& F, const TileIn<TF>& in, const Strip& g, bool own,
+                                               int q, bool with_k, int pr, StepRows<TF, VEC>& s) {
+  trow_load<double, VEC, MODE_ZERO>(in.y, q, F, g, s.y);
+  trowc_load<TF, VEC, MODE_EDGE>(in.kyy, q, F, g, s.g);
+  trow_load<TF, VEC, MODE_ZERO>(in.kxy, q, F, g, s.m);
+  if constexpr (ADVF) trowc_load<TF, VEC, MODE_ZERO>(in.ay, q, F, g, s.ay);
+  if (with_k) {
+    trow_load<TF, VEC, MODE_EDGE>(in.kxx, q - 1, F, g, s.k);
+    if constexpr (ADVF) trow_load<TF, VEC, MODE_ZERO>(in.ax, q - 1, F, g, s.ax);
+  }
+  if (own) gload<double, VEC>(gcol<double>(in.p + (long)pr * F.nx, g.col0), s.p);
+}
 
 template <typename TF, int VEC, bool ADVF>
 __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B, int t) {
-  __shared__ double ring[kBRing * kWave * VEC];
-  const FieldView& F = B.f;
-  const int rb = t / B.ncb2, cb = t - rb * B.ncb2;
-  const int j0 = rb * B.rows, j1 = min(j0 + B.rows, F.ny);
+  // the descriptor's values, read once: a reference would be re-read after
+  // every store of the tile (the compiler cannot rule out that the stores
+  // overwrite the descriptor), each time waiting for the loads in flight
+  FieldView F = B.f;
+  F.nx = uni(F.nx);
+  F.ny = uni(F.ny);
+  F.bc = uni(F.bc);
+  F.axc = uni(F.axc);
+  F.ayc = uni(F.ayc);
+  const int ncb2 = uni(B.ncb2), rows = uni(B.rows);
+  const int rb = t / ncb2, cb = t - rb * ncb2;
+  const int j0 = rb * rows, j1 = min(j0 + rows, F.ny);
   const int k = A.k;
   const int lane = threadIdx.x & (kWave - 1);
-  const int M = B.max_degree;
+  const int M = uni(B.max_degree);
   const Strip g = strip_at<VEC>(F, cb * (kWave - 2) * VEC - VEC);
   const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
-  const double* yin = reinterpret_cast<const double*>((A.L & 1) ? B.y1 : B.y0);
-  double* yout = reinterpret_cast<double*>(((A.L + 1) & 1) ? B.y1 : B.y0);
-  const double* pin = B.pb[pbuf_index(k, A.two)];
-  double* pmid = B.pb[pbuf_index(k + 1, A.two)];
-  double* pout = B.pb[pbuf_index(k + 2, A.two)];
+  const bool per = F.bc == BC_PERIODIC;
+  TileIn<TF> in;
+  in.y = uni(gp<double>((A.L & 1) ? B.y1 : B.y0));
+  in.p = uni(gp<double>(B.pb[pbuf_index(k, A.two)]));
+  in.kxx = uni(gp<TF>(F.kxx));
+  in.kxy = uni(gp<TF>(F.kxy));
+  in.kyy = uni(gp<TF>(F.kyy));
+  in.ax = uni(gp<TF>(F.ax));
+  in.ay = uni(gp<TF>(F.ay));
+  const GP<double> yout = uni(gpw<double>(((A.L + 1) & 1) ? B.y1 : B.y0));
+  const GP<double> pmid = uni(gpw<double>(B.pb[pbuf_index(k + 1, A.two)]));
+  const GP<double> pout = uni(gpw<double>(B.pb[pbuf_index(k + 2, A.two)]));
   // (a second term past the bin's degree cap is computed with the last plan
   // entries and discarded by the decision at the cap)
-  const double shift2 = B.shift[min(k + 1, M)];
-  const double dk1 = B.d[k + 1], dk2 = B.d[min(k + 2, M)];
-  Stage1Ep<VEC, kBRing> ep1;
-  ep1.lds = ring;
-  ep1.r0 = j0 - 1;
-  ep1.ny = F.ny;
-  ep1.per = F.bc == BC_PERIODIC;
-  ep1.shift = B.shift[k];
-  ep1.invg = B.invg;
-  ep1.stopflag = 0;
-  stencil_group<TF, double, VEC, ADVF, 1>(F, yin, ep1, g, j0 - 1);
-  stencil_group<TF, double, VEC, ADVF, 1>(F, yin, ep1, g, j0);
-  const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
-  const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
-  const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
-  const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
-  const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (int r = j0; r < j1; ++r) {
-    stencil_group<TF, double, VEC, ADVF, 1>(F, yin, ep1, g, r + 1);
-    RowN<VEC> u[3], m[3], kc, ac;
-    RowC<VEC> gg[3], ay[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      lds_row_n<double, VEC>(ring, (unsigned)(r - 1 + q - ep1.r0) % kBRing, u[q]);
-      row_c<TF, VEC, MODE_EDGE>(kyy, r - 1 + q, F, g, gg[q]);
-      row_n<TF, VEC, MODE_ZERO>(kxy, r - 1 + q, F, g, m[q]);
-      if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, r - 1 + q, F, g, ay[q]);
+  const double shift1 = uni(B.shift[k]), shift2 = uni(B.shift[min(k + 1, M)]);
+  const double dk1 = uni(B.d[k + 1]), dk2 = uni(B.d[min(k + 2, M)]);
+  const double invg = uni(B.invg);
+  using RY = TRow<double, VEC>;
+  using RF = TRow<TF, VEC>;
+  using RC = TRowC<TF, VEC>;
+  // (A y_k) on row s from the stored rows s-1 .. s+1, then y_{k+1} (zero at ghost positions)
+  auto stage1 = [&](int s, const RY& y0, const RY& y1, const RY& y2, const RC& g0, const RC& g1, const RC& g2,
+                    const RF& m0, const RF& m1, const RF& m2, const RF& kc, const RF& xc, const RC& a0,
+                    const RC& a2, double (&o)[VEC]) {
+    const RowN<VEC> u1 = rown_of<double, VEC, MODE_ZERO>(y1, g);
+    RowN<VEC> xn{};
+    RowC<VEC> an0{}, an2{};
+    if constexpr (ADVF) {
+      xn = rown_of<TF, VEC, MODE_ZERO>(xc, g);
+      an0 = rowc_of<TF, VEC>(a0);
+      an2 = rowc_of<TF, VEC>(a2);
     }
-    row_n<TF, VEC, MODE_EDGE>(kxx, r, F, g, kc);
-    if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, r, F, g, ac);
     double Ax[VEC];
-    stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], kc, ac, ay[0], ay[2], F.axc,
-                             F.ayc, Ax);
-    if (own) {
-      const long ro = (long)r * F.nx;
-      double pk[VEC], y2[VEC], pm[VEC], p2[VEC];
-      ldr<double, VEC>(pin + ro, g.col0, pk);
-      const double* y1row = ring + ((unsigned)(r - ep1.r0) % kBRing) * (kWave * VEC) + lane * VEC;
+    stencil_point<VEC, ADVF>(rown_of<double, VEC, MODE_ZERO>(y0, g), u1, rown_of<double, VEC, MODE_ZERO>(y2, g),
+                             rowc_of<TF, VEC>(g0), rowc_of<TF, VEC>(g1), rowc_of<TF, VEC>(g2),
+                             rown_of<TF, VEC, MODE_ZERO>(m0, g), rown_of<TF, VEC, MODE_ZERO>(m1, g),
+                             rown_of<TF, VEC, MODE_ZERO>(m2, g), rown_of<TF, VEC, MODE_EDGE>(kc, g), xn, an0, an2,
+                             F.axc, F.ayc, Ax);
+    const bool ghost = !per && (!g.inside || s < 0 || s >= F.ny);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        const double t1 = dk1 * y1row[v];
-        pm[v] = pk[v] + t1;
-        y2[v] = (Ax[v] - shift2 * u[1].c[v]) * B.invg;
-        const double t2 = dk2 * y2[v];
-        p2[v] = pm[v] + t2;
-        acc[0] += t1 * t1;
-        acc[1] += pm[v] * pm[v];
-        acc[2] += t2 * t2;
-        acc[3] += p2[v] * p2[v];
+    for (int v = 0; v < VEC; ++v) o[v] = ghost ? 0.0 : (Ax[v] - shift1 * u1.c[v]) * invg;
+  };
+  // the march starts two rows above the tile: steps r = j0-2 and j0-1 only
+  // compute y_{k+1} on rows j0-1 and j0.  Windows at step r, as stored: y_k
+  // rows r, r+1; kyy, kxy, ay' rows r-1 .. r+1; kxx, ax' row r; y_{k+1} rows
+  // r-1, r (za, zb); the step's new rows (input row r+2, kxx row r+1, p_k row
+  // r) were loaded during the previous step.
+  StepRows<TF, VEC> s0, s1, na, nb;
+  load_step_rows<TF, VEC, ADVF>(F, in, g, false, j0 - 2, false, j0, s0);
+  load_step_rows<TF, VEC, ADVF>(F, in, g, false, j0 - 1, false, j0, s1);
+  load_step_rows<TF, VEC, ADVF>(F, in, g, false, j0, true, j0, na);
+  RY wy0 = s0.y, wy1 = s1.y;
+  RC wg0 = s0.g, wg1 = s0.g, wg2 = s1.g;  // (row r-1 is first read at step j0)
+  RF wm0 = s0.m, wm1 = s0.m, wm2 = s1.m;
+  RF wk = na.k, wx = na.ax;                // (first read at step j0)
+  RC wa0 = s0.ay, wa1 = s0.ay, wa2 = s1.ay;
+  double za[VEC] = {}, zb[VEC] = {};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // one marching step: `cur` holds the rows loaded during the previous step,
+  // the next step's rows go into `nxt` (two buffers taking turns, so that no
+  // register holding a load in flight is ever copied: a copy would wait for
+  // it).  The loads are issued unconditionally (past the tile's last rows
+  // they repeat its last row), so that every step has the same count of
+  // loads in flight.  Steps j0-2 and j0-1 compute only stage 1 (s2 false);
+  // lp: the step loads p_k of the next step's output row.
+  auto step = [&](auto s2, auto lp, int r, const StepRows<TF, VEC>& cur, StepRows<TF, VEC>& nxt) {
+    load_step_rows<TF, VEC, ADVF>(F, in, g, own && decltype(lp)::value, min(r + 3, j1 + 1), true,
+                                  min(r + 1, j1 - 1), nxt);
+    // stage 1: y_{k+1} on row r+1
+    double zc[VEC];
+    stage1(r + 1, wy0, wy1, cur.y, wg1, wg2, cur.g, wm1, wm2, cur.m, cur.k, cur.ax, wa1, cur.ay, zc);
+    // stage 2: y_{k+2} on row r
+    if constexpr (decltype(s2)::value) {
+      RowN<VEC> xn{};
+      RowC<VEC> an0{}, an2{};
+      if constexpr (ADVF) {
+        xn = rown_of<TF, VEC, MODE_ZERO>(wx, g);
+        an0 = rowc_of<TF, VEC>(wa0);
+        an2 = rowc_of<TF, VEC>(wa2);
       }
-      str<double, VEC>(yout + ro, g.col0, y2);
-      str<double, VEC>(pmid + ro, g.col0, pm);
-      str<double, VEC>(pout + ro, g.col0, p2);
+      double Ax[VEC];
+      stencil_point<VEC, ADVF>(rown_y1<VEC>(za), rown_y1<VEC>(zb), rown_y1<VEC>(zc), rowc_of<TF, VEC>(wg0),
+                               rowc_of<TF, VEC>(wg1), rowc_of<TF, VEC>(wg2), rown_of<TF, VEC, MODE_ZERO>(wm0, g),
+                               rown_of<TF, VEC, MODE_ZERO>(wm1, g), rown_of<TF, VEC, MODE_ZERO>(wm2, g),
+                               rown_of<TF, VEC, MODE_EDGE>(wk, g), xn, an0, an2, F.axc, F.ayc, Ax);
+      if (own) {
+        const long ro = (long)r * F.nx;
+        double y2[VEC], pm[VEC], p2[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double t1 = dk1 * zb[v];
+          pm[v] = cur.p[v] + t1;
+          y2[v] = (Ax[v] - shift2 * zb[v]) * invg;
+          const double t2 = dk2 * y2[v];
+          p2[v] = pm[v] + t2;
+          acc[0] += t1 * t1;
+          acc[1] += pm[v] * pm[v];
+          acc[2] += t2 * t2;
+          acc[3] += p2[v] * p2[v];
+        }
+        gstore<VEC>(gcolw<double>(yout + ro, g.col0), y2);
+        gstore<VEC>(gcolw<double>(pmid + ro, g.col0), pm);
+        gstore<VEC>(gcolw<double>(pout + ro, g.col0), p2);
+      }
     }
+    // slide the windows down one row
+    wy0 = wy1;
+    wy1 = cur.y;
+    wg0 = wg1;
+    wg1 = wg2;
+    wg2 = cur.g;
+    wm0 = wm1;
+    wm1 = wm2;
+    wm2 = cur.m;
+    wk = cur.k;
+    if constexpr (ADVF) {
+      wx = cur.ax;
+      wa0 = wa1;
+      wa1 = wa2;
+      wa2 = cur.ay;
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      za[v] = zb[v];
+      zb[v] = zc[v];
+    }
+  };
+  using No = std::false_type;
+  using Yes = std::true_type;
+  step(No{}, No{}, j0 - 2, na, nb);
+  step(No{}, Yes{}, j0 - 1, nb, na);
+#pragma unroll 1
+  for (int r = j0; r < j1; r += 2) {
+    step(Yes{}, Yes{}, r, na, nb);
+    if (r + 1 >= j1) break;
+    step(Yes{}, Yes{}, r + 1, nb, na);
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -402,7 +663,7 @@ __global__ __launch_bounds__(64) void batch_leja2_kernel(BatchArgs A, int nbins)
     return;
   }
   const int gt = blockIdx.x - nbins;
-  const int b = A.tile_bin2[gt];
+  const int b = __builtin_amdgcn_readfirstlane(A.tile_bin2[gt]);
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
   if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
@@ -432,7 +693,7 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BinCtl* ctl, int nbins
 template <int VEC>
 __global__ __launch_bounds__(64) void batch_update_kernel(BatchArgs A, double* const* u) {
   const int gt = blockIdx.x;
-  const int b = A.tile_bin[gt];
+  const int b = __builtin_amdgcn_readfirstlane(A.tile_bin[gt]);
   const BinDesc& B = A.bins[b];
   if (!B.active || A.ctl[b].status != 1 || A.ctl[b].degree == 0) return;  // degree 0: p = 0
   const double* pb = B.pb[pbuf_index(A.ctl[b].degree, A.two)];
