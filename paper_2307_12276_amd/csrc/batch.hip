@@ -305,55 +305,58 @@ __global__ __launch_bounds__(64) void batch_leja_kernel(BatchArgs A, int nbins) 
 // from DPP shifts within the wave (the frame lanes compute y_{k+1} too), so
 // the wave needs neither LDS nor a barrier.
 
-// Global-memory pointers.  A bin's array addresses come from its descriptor
-// in memory, so the compiler sees them as generic pointers and would access
-// them with FLAT instructions (64-bit per-lane addresses, and counted by the
-// LDS/scalar counter too, so that every use of a loaded value waits for all
-// loads in flight, the prefetched rows included).  The two-term tile converts
-// them to address space 1 once and keeps them there down to each load and
-// store (a cast back to a generic pointer would be folded away with the
-// first one).
-template <typename T>
-using GP = __attribute__((address_space(1))) T*;
+// Memory access of the two-term tile: buffer loads and stores through one
+// buffer resource per array (base address in scalar registers), the row's
+// byte offset as the scalar offset and the lane's column as a 32-bit vector
+// offset.  (A bin's array addresses come from its descriptor in memory; used
+// as plain pointers they are generic to the compiler, which then accesses
+// them with FLAT instructions -- counted by the LDS/scalar counter too, so
+// that every use of a loaded value waits for all loads in flight -- and keeps
+// a 64-bit address per lane and load.)  Arrays are limited to 2 GiB (checked
+// when a batch is created).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (CDNA)
 
-template <typename T>
-__device__ __forceinline__ GP<const T> gp(const void* p) {
-  return (GP<const T>)p;
+__device__ __forceinline__ Rsrc rsrc_of(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, 0x7fffffff, kRsrcWord3);
 }
-template <typename T>
-__device__ __forceinline__ GP<T> gpw(void* p) {
-  return (GP<T>)p;
-}
-// element `col` of the row starting at rowp (wave-uniform row start, 32-bit lane offset)
-template <typename T>
-__device__ __forceinline__ GP<const T> gcol(GP<const T> rowp, int col) {
-  return (GP<const T>)((GP<const char>)rowp + (unsigned)(col * (int)sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ GP<T> gcolw(GP<T> rowp, int col) {
-  return (GP<T>)((GP<char>)rowp + (unsigned)(col * (int)sizeof(T)));
-}
+
 template <typename T, int VEC>
-__device__ __forceinline__ void gload(GP<const T> p, T (&c)[VEC]) {
-  if constexpr (VEC == 2) {
-    typedef T t2 __attribute__((ext_vector_type(2)));
-    const t2 v = *(GP<const t2>)p;
+__device__ __forceinline__ void bload(Rsrc r, int voff, int soff, T (&c)[VEC]) {
+  if constexpr (sizeof(T) == 8 && VEC == 2) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    c[0] = v.x;
+    c[1] = v.y;
+  } else if constexpr (sizeof(T) == 8) {
+    c[0] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else if constexpr (VEC == 2) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
     c[0] = v.x;
     c[1] = v.y;
   } else {
-    c[0] = *p;
+    c[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
 }
+template <typename T>
+__device__ __forceinline__ T bload1(Rsrc r, int voff, int soff) {
+  T c[1];
+  bload<T, 1>(r, voff, soff, c);
+  return c[0];
+}
 template <int VEC>
-__device__ __forceinline__ void gstore(GP<double> p, const double (&c)[VEC]) {
+__device__ __forceinline__ void bstore(Rsrc r, int voff, int soff, const double (&c)[VEC]) {
   if constexpr (VEC == 2) {
     typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
     d2 v;
     v.x = c[0];
     v.y = c[1];
-    *(GP<d2>)p = v;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, soff, 0);
   } else {
-    *p = c[0];
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, c[0]), r, voff, soff, 0);
   }
 }
 
@@ -370,8 +373,8 @@ __device__ __forceinline__ double uni(double v) {
   return __longlong_as_double((long long)uni64((unsigned long long)__double_as_longlong(v)));
 }
 template <typename T>
-__device__ __forceinline__ GP<T> uni(GP<T> p) {
-  return (GP<T>)uni64((unsigned long long)p);
+__device__ __forceinline__ T* uni(T* p) {
+  return (T*)uni64((unsigned long long)p);
 }
 
 // one lane's part of a row as stored (type T): its VEC values, the halo
@@ -388,20 +391,25 @@ struct TRowC {
   bool zero;
 };
 
+// a lane's byte offsets in a row: its own columns and its halo column, for
+// 8- and 4-byte elements, and its output columns (8-byte)
+struct LaneOff {
+  int c8, h8, c4, h4, o8;
+};
+
 template <typename T, int VEC, int MODE>
-__device__ __forceinline__ void trow_load(GP<const T> a, int r, const FieldView& F, const Strip& g,
-                                          TRow<T, VEC>& o) {
+__device__ __forceinline__ void trow_load(Rsrc a, int r, const FieldView& F, const LaneOff& lo, TRow<T, VEC>& o) {
   const int row = uni(map_row_any(r, F.ny, F.bc, MODE, o.zero));
-  const GP<const T> rp = a + (long)row * F.nx;
-  gload<T, VEC>(gcol<T>(rp, g.colc), o.c);
-  o.h = *gcol<T>(rp, g.hcol);
+  const int soff = row * F.nx * (int)sizeof(T);
+  bload<T, VEC>(a, sizeof(T) == 8 ? lo.c8 : lo.c4, soff, o.c);
+  o.h = bload1<T>(a, sizeof(T) == 8 ? lo.h8 : lo.h4, soff);
 }
 
 template <typename T, int VEC, int MODE>
-__device__ __forceinline__ void trowc_load(GP<const T> a, int r, const FieldView& F, const Strip& g,
+__device__ __forceinline__ void trowc_load(Rsrc a, int r, const FieldView& F, const LaneOff& lo,
                                            TRowC<T, VEC>& o) {
   const int row = uni(map_row_any(r, F.ny, F.bc, MODE, o.zero));
-  gload<T, VEC>(gcol<T>(a + (long)row * F.nx, g.colc), o.c);
+  bload<T, VEC>(a, sizeof(T) == 8 ? lo.c8 : lo.c4, row * F.nx * (int)sizeof(T), o.c);
 }
 
 template <typename T, int CTRL>
@@ -459,25 +467,57 @@ struct StepRows {
   double p[VEC];
 };
 
-// the arrays a two-term tile reads, as global pointers
-template <typename TF>
+// A copy into fresh registers that the compiler cannot merge with its
+// source: a step copies the rows it was handed before using them, so that
+// their load registers are free again for the loads of the next step,
+// and the loop carries each buffer of loads in flight in the same registers
+// (otherwise the register allocator may copy a register whose load is still
+// in flight at the loop's back edge, and such a copy waits for the load).
+__device__ __forceinline__ float vcopy(float v) {
+  float o;
+  asm("v_mov_b32 %0, %1" : "=v"(o) : "v"(v));
+  return o;
+}
+__device__ __forceinline__ double vcopy(double v) {
+  double o;
+  asm("v_mov_b64 %0, %1" : "=v"(o) : "v"(v));
+  return o;
+}
+template <typename T, int VEC>
+__device__ __forceinline__ TRow<T, VEC> vcopy(const TRow<T, VEC>& x) {
+  TRow<T, VEC> o;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = vcopy(x.c[v]);
+  o.h = vcopy(x.h);
+  o.zero = x.zero;
+  return o;
+}
+template <typename T, int VEC>
+__device__ __forceinline__ TRowC<T, VEC> vcopy(const TRowC<T, VEC>& x) {
+  TRowC<T, VEC> o;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = vcopy(x.c[v]);
+  o.zero = x.zero;
+  return o;
+}
+
+// the arrays a two-term tile reads, as buffer resources
 struct TileIn {
-  GP<const double> y, p;
-  GP<const TF> kxx, kxy, kyy, ax, ay;
+  Rsrc y, p, kxx, kxy, kyy, ax, ay;
 };
 
 template <typename TF, int VEC, bool ADVF>
-__device__ __forceinline__ void load_step_rows(const FieldView& F, const TileIn<TF>& in, const Strip& g, bool own,
+__device__ __forceinline__ void load_step_rows(const FieldView& F, const TileIn& in, const LaneOff& lo, bool own,
                                                int q, bool with_k, int pr, StepRows<TF, VEC>& s) {
-  trow_load<double, VEC, MODE_ZERO>(in.y, q, F, g, s.y);
-  trowc_load<TF, VEC, MODE_EDGE>(in.kyy, q, F, g, s.g);
-  trow_load<TF, VEC, MODE_ZERO>(in.kxy, q, F, g, s.m);
-  if constexpr (ADVF) trowc_load<TF, VEC, MODE_ZERO>(in.ay, q, F, g, s.ay);
+  trow_load<double, VEC, MODE_ZERO>(in.y, q, F, lo, s.y);
+  trowc_load<TF, VEC, MODE_EDGE>(in.kyy, q, F, lo, s.g);
+  trow_load<TF, VEC, MODE_ZERO>(in.kxy, q, F, lo, s.m);
+  if constexpr (ADVF) trowc_load<TF, VEC, MODE_ZERO>(in.ay, q, F, lo, s.ay);
   if (with_k) {
-    trow_load<TF, VEC, MODE_EDGE>(in.kxx, q - 1, F, g, s.k);
-    if constexpr (ADVF) trow_load<TF, VEC, MODE_ZERO>(in.ax, q - 1, F, g, s.ax);
+    trow_load<TF, VEC, MODE_EDGE>(in.kxx, q - 1, F, lo, s.k);
+    if constexpr (ADVF) trow_load<TF, VEC, MODE_ZERO>(in.ax, q - 1, F, lo, s.ax);
   }
-  if (own) gload<double, VEC>(gcol<double>(in.p + (long)pr * F.nx, g.col0), s.p);
+  if (own) bload<double, VEC>(in.p, lo.o8, pr * F.nx * 8, s.p);
 }
 
 template <typename TF, int VEC, bool ADVF>
@@ -500,17 +540,20 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
   const Strip g = strip_at<VEC>(F, cb * (kWave - 2) * VEC - VEC);
   const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
   const bool per = F.bc == BC_PERIODIC;
-  TileIn<TF> in;
-  in.y = uni(gp<double>((A.L & 1) ? B.y1 : B.y0));
-  in.p = uni(gp<double>(B.pb[pbuf_index(k, A.two)]));
-  in.kxx = uni(gp<TF>(F.kxx));
-  in.kxy = uni(gp<TF>(F.kxy));
-  in.kyy = uni(gp<TF>(F.kyy));
-  in.ax = uni(gp<TF>(F.ax));
-  in.ay = uni(gp<TF>(F.ay));
-  const GP<double> yout = uni(gpw<double>(((A.L + 1) & 1) ? B.y1 : B.y0));
-  const GP<double> pmid = uni(gpw<double>(B.pb[pbuf_index(k + 1, A.two)]));
-  const GP<double> pout = uni(gpw<double>(B.pb[pbuf_index(k + 2, A.two)]));
+  const LaneOff lo{g.colc * 8, g.hcol * 8, g.colc * 4, g.hcol * 4, g.col0 * 8};
+  TileIn in;
+  in.y = rsrc_of(uni((A.L & 1) ? B.y1 : B.y0));
+  in.p = rsrc_of(uni(B.pb[pbuf_index(k, A.two)]));
+  in.kxx = rsrc_of(uni(F.kxx));
+  in.kxy = rsrc_of(uni(F.kxy));
+  in.kyy = rsrc_of(uni(F.kyy));
+  if constexpr (ADVF) {
+    in.ax = rsrc_of(uni(F.ax));
+    in.ay = rsrc_of(uni(F.ay));
+  }
+  const Rsrc yout = rsrc_of(uni(((A.L + 1) & 1) ? B.y1 : B.y0));
+  const Rsrc pmid = rsrc_of(uni(B.pb[pbuf_index(k + 1, A.two)]));
+  const Rsrc pout = rsrc_of(uni(B.pb[pbuf_index(k + 2, A.two)]));
   // (a second term past the bin's degree cap is computed with the last plan
   // entries and discarded by the decision at the cap)
   const double shift1 = uni(B.shift[k]), shift2 = uni(B.shift[min(k + 1, M)]);
@@ -547,9 +590,9 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
   // r-1, r (za, zb); the step's new rows (input row r+2, kxx row r+1, p_k row
   // r) were loaded during the previous step.
   StepRows<TF, VEC> s0, s1, na, nb;
-  load_step_rows<TF, VEC, ADVF>(F, in, g, false, j0 - 2, false, j0, s0);
-  load_step_rows<TF, VEC, ADVF>(F, in, g, false, j0 - 1, false, j0, s1);
-  load_step_rows<TF, VEC, ADVF>(F, in, g, false, j0, true, j0, na);
+  load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0 - 2, false, j0, s0);
+  load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0 - 1, false, j0, s1);
+  load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0, true, j0, na);
   RY wy0 = s0.y, wy1 = s1.y;
   RC wg0 = s0.g, wg1 = s0.g, wg2 = s1.g;  // (row r-1 is first read at step j0)
   RF wm0 = s0.m, wm1 = s0.m, wm2 = s1.m;
@@ -564,9 +607,23 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
   // they repeat its last row), so that every step has the same count of
   // loads in flight.  Steps j0-2 and j0-1 compute only stage 1 (s2 false);
   // lp: the step loads p_k of the next step's output row.
-  auto step = [&](auto s2, auto lp, int r, const StepRows<TF, VEC>& cur, StepRows<TF, VEC>& nxt) {
-    load_step_rows<TF, VEC, ADVF>(F, in, g, own && decltype(lp)::value, min(r + 3, j1 + 1), true,
+  auto step = [&](auto s2, auto lp, int r, const StepRows<TF, VEC>& held, StepRows<TF, VEC>& nxt) {
+    // (nxt was copied out by the step before: its registers are free)
+    load_step_rows<TF, VEC, ADVF>(F, in, lo, own && decltype(lp)::value, min(r + 3, j1 + 1), true,
                                   min(r + 1, j1 - 1), nxt);
+    StepRows<TF, VEC> cur;
+    cur.y = vcopy(held.y);
+    cur.g = vcopy(held.g);
+    cur.m = vcopy(held.m);
+    cur.k = vcopy(held.k);
+    if constexpr (ADVF) {
+      cur.ax = vcopy(held.ax);
+      cur.ay = vcopy(held.ay);
+    }
+    if constexpr (decltype(s2)::value) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) cur.p[v] = own ? vcopy(held.p[v]) : 0.0;
+    }
     // stage 1: y_{k+1} on row r+1
     double zc[VEC];
     stage1(r + 1, wy0, wy1, cur.y, wg1, wg2, cur.g, wm1, wm2, cur.m, cur.k, cur.ax, wa1, cur.ay, zc);
@@ -585,7 +642,6 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
                                rown_of<TF, VEC, MODE_ZERO>(wm1, g), rown_of<TF, VEC, MODE_ZERO>(wm2, g),
                                rown_of<TF, VEC, MODE_EDGE>(wk, g), xn, an0, an2, F.axc, F.ayc, Ax);
       if (own) {
-        const long ro = (long)r * F.nx;
         double y2[VEC], pm[VEC], p2[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
@@ -599,9 +655,10 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
           acc[2] += t2 * t2;
           acc[3] += p2[v] * p2[v];
         }
-        gstore<VEC>(gcolw<double>(yout + ro, g.col0), y2);
-        gstore<VEC>(gcolw<double>(pmid + ro, g.col0), pm);
-        gstore<VEC>(gcolw<double>(pout + ro, g.col0), p2);
+        const int so = r * F.nx * 8;
+        bstore<VEC>(yout, lo.o8, so, y2);
+        bstore<VEC>(pmid, lo.o8, so, pm);
+        bstore<VEC>(pout, lo.o8, so, p2);
       }
     }
     // slide the windows down one row
@@ -630,12 +687,13 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
   using Yes = std::true_type;
   step(No{}, No{}, j0 - 2, na, nb);
   step(No{}, Yes{}, j0 - 1, nb, na);
+  int r = j0;
 #pragma unroll 1
-  for (int r = j0; r < j1; r += 2) {
+  for (; r + 1 < j1; r += 2) {
     step(Yes{}, Yes{}, r, na, nb);
-    if (r + 1 >= j1) break;
     step(Yes{}, Yes{}, r + 1, nb, na);
   }
+  if (r < j1) step(Yes{}, Yes{}, r, na, nb);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
 #pragma unroll
@@ -1025,6 +1083,8 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
       return bfail(ADL_EINVAL, "all bins must share storage mode and advection kind");
     if (op->storage == ADL_STORAGE_FP32_FIELDS_Y) return bfail(ADL_EINVAL, "batch supports FP64 Newton vectors only");
     if (op->nx % 2 != 0 || op->nx < 2 * kWave) all_even = false;
+    // (the two-term kernel addresses a vector with 32-bit byte offsets)
+    if ((long)op->nx * op->ny * 8 > 0x7fffffffL) return bfail(ADL_EINVAL, "batch bins are limited to 2^28 points");
   }
   if (tile_rows < 0) return bfail(ADL_EINVAL, "tile_rows must be >= 0");
   const int M = kMaxDegreeDefault + 1;
