@@ -520,6 +520,64 @@ __device__ __forceinline__ void load_step_rows(const FieldView& F, const TileIn&
   if (own) bload<double, VEC>(in.p, lo.o8, pr * F.nx * 8, s.p);
 }
 
+// The stencil coefficients of a row's VEC points (Sec. 2, eq. 3 discretised
+// as in stencil_point: face averages of kxx and kyy, kxy at the four
+// neighbours, the advection values with field advection), computed once by
+// stage 1 and applied again by stage 2 to y_{k+1} on the same row.
+template <int VEC, bool ADVF>
+struct Coef {
+  double kE[VEC], kW[VEC], gN[VEC], gS[VEC], mE[VEC], mW[VEC], mN[VEC], mS[VEC];
+  double aE[ADVF ? VEC : 1], aW[ADVF ? VEC : 1], yN[ADVF ? VEC : 1], yS[ADVF ? VEC : 1];
+};
+
+template <int VEC, bool ADVF>
+__device__ __forceinline__ void coef_of(const RowC<VEC>& gm, const RowC<VEC>& gc, const RowC<VEC>& gp,
+                                        const RowN<VEC>& mm, const RowN<VEC>& mc, const RowN<VEC>& mp,
+                                        const RowN<VEC>& kc, const RowN<VEC>& ac, const RowC<VEC>& ym,
+                                        const RowC<VEC>& yp, Coef<VEC, ADVF>& o) {
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    o.kE[v] = 0.5 * (kc.at(v) + kc.east(v));
+    o.kW[v] = 0.5 * (kc.at(v) + kc.west(v));
+    o.gN[v] = 0.5 * (gc.c[v] + gp.c[v]);
+    o.gS[v] = 0.5 * (gc.c[v] + gm.c[v]);
+    o.mE[v] = mc.east(v);
+    o.mW[v] = mc.west(v);
+    o.mN[v] = mp.at(v);
+    o.mS[v] = mm.at(v);
+    if constexpr (ADVF) {
+      o.aE[v] = ac.east(v);
+      o.aW[v] = ac.west(v);
+      o.yN[v] = yp.c[v];
+      o.yS[v] = ym.c[v];
+    }
+  }
+}
+
+// (A u) at a row's VEC points from its coefficients and rows j-1 (um), j
+// (uc), j+1 (up) of u; the same operations in the same order as stencil_point
+template <int VEC, bool ADVF>
+__device__ __forceinline__ void coef_apply(const Coef<VEC, ADVF>& c, const RowN<VEC>& um, const RowN<VEC>& uc,
+                                           const RowN<VEC>& up, double axc, double ayc, double (&Ax)[VEC]) {
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const double uC = uc.at(v), uW = uc.west(v), uE = uc.east(v);
+    const double uN = up.at(v), uS = um.at(v);
+    const double uNW = up.west(v), uNE = up.east(v);
+    const double uSW = um.west(v), uSE = um.east(v);
+    double a = c.kE[v] * (uE - uC) - c.kW[v] * (uC - uW);
+    a += c.gN[v] * (uN - uC) - c.gS[v] * (uC - uS);
+    a += c.mE[v] * (uNE - uSE) - c.mW[v] * (uNW - uSW);
+    a += c.mN[v] * (uNE - uNW) - c.mS[v] * (uSE - uSW);
+    if constexpr (ADVF) {
+      a += c.aE[v] * uE - c.aW[v] * uW + c.yN[v] * uN - c.yS[v] * uS;
+    } else {
+      a += axc * (uE - uW) + ayc * (uN - uS);
+    }
+    Ax[v] = a;
+  }
+}
+
 template <typename TF, int VEC, bool ADVF>
 __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B, int t) {
   // the descriptor's values, read once: a reference would be re-read after
@@ -562,11 +620,13 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
   using RY = TRow<double, VEC>;
   using RF = TRow<TF, VEC>;
   using RC = TRowC<TF, VEC>;
-  // (A y_k) on row s from the stored rows s-1 .. s+1, then y_{k+1} (zero at ghost positions)
+  using CF = Coef<VEC, ADVF>;
+  // stage 1 on row s: its coefficients from the stored field rows s-1 .. s+1
+  // (kept in o_c for stage 2 on the same row one step later), (A y_k)(s) from
+  // the stored rows of y_k, then y_{k+1} (zero at ghost positions)
   auto stage1 = [&](int s, const RY& y0, const RY& y1, const RY& y2, const RC& g0, const RC& g1, const RC& g2,
                     const RF& m0, const RF& m1, const RF& m2, const RF& kc, const RF& xc, const RC& a0,
-                    const RC& a2, double (&o)[VEC]) {
-    const RowN<VEC> u1 = rown_of<double, VEC, MODE_ZERO>(y1, g);
+                    const RC& a2, CF& o_c, double (&o)[VEC]) {
     RowN<VEC> xn{};
     RowC<VEC> an0{}, an2{};
     if constexpr (ADVF) {
@@ -574,40 +634,44 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
       an0 = rowc_of<TF, VEC>(a0);
       an2 = rowc_of<TF, VEC>(a2);
     }
+    coef_of<VEC, ADVF>(rowc_of<TF, VEC>(g0), rowc_of<TF, VEC>(g1), rowc_of<TF, VEC>(g2),
+                       rown_of<TF, VEC, MODE_ZERO>(m0, g), rown_of<TF, VEC, MODE_ZERO>(m1, g),
+                       rown_of<TF, VEC, MODE_ZERO>(m2, g), rown_of<TF, VEC, MODE_EDGE>(kc, g), xn, an0, an2, o_c);
+    const RowN<VEC> u1 = rown_of<double, VEC, MODE_ZERO>(y1, g);
     double Ax[VEC];
-    stencil_point<VEC, ADVF>(rown_of<double, VEC, MODE_ZERO>(y0, g), u1, rown_of<double, VEC, MODE_ZERO>(y2, g),
-                             rowc_of<TF, VEC>(g0), rowc_of<TF, VEC>(g1), rowc_of<TF, VEC>(g2),
-                             rown_of<TF, VEC, MODE_ZERO>(m0, g), rown_of<TF, VEC, MODE_ZERO>(m1, g),
-                             rown_of<TF, VEC, MODE_ZERO>(m2, g), rown_of<TF, VEC, MODE_EDGE>(kc, g), xn, an0, an2,
-                             F.axc, F.ayc, Ax);
+    coef_apply<VEC, ADVF>(o_c, rown_of<double, VEC, MODE_ZERO>(y0, g), u1, rown_of<double, VEC, MODE_ZERO>(y2, g),
+                          F.axc, F.ayc, Ax);
     const bool ghost = !per && (!g.inside || s < 0 || s >= F.ny);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) o[v] = ghost ? 0.0 : (Ax[v] - shift1 * u1.c[v]) * invg;
   };
   // the march starts two rows above the tile: steps r = j0-2 and j0-1 only
-  // compute y_{k+1} on rows j0-1 and j0.  Windows at step r, as stored: y_k
-  // rows r, r+1; kyy, kxy, ay' rows r-1 .. r+1; kxx, ax' row r; y_{k+1} rows
-  // r-1, r (za, zb); the step's new rows (input row r+2, kxx row r+1, p_k row
-  // r) were loaded during the previous step.
+  // compute y_{k+1} (and the coefficients) on rows j0-1 and j0.  Windows at
+  // step r, as stored: y_k rows r, r+1; kyy, kxy, ay' rows r, r+1; y_{k+1}
+  // rows r-1, r (za, zb); the coefficients of row r.  The step's new rows
+  // (input row r+2, kxx and ax' row r+1, p_k row r) were loaded during the
+  // previous step.
   StepRows<TF, VEC> s0, s1, na, nb;
   load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0 - 2, false, j0, s0);
   load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0 - 1, false, j0, s1);
   load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0, true, j0, na);
   RY wy0 = s0.y, wy1 = s1.y;
-  RC wg0 = s0.g, wg1 = s0.g, wg2 = s1.g;  // (row r-1 is first read at step j0)
-  RF wm0 = s0.m, wm1 = s0.m, wm2 = s1.m;
-  RF wk = na.k, wx = na.ax;                // (first read at step j0)
-  RC wa0 = s0.ay, wa1 = s0.ay, wa2 = s1.ay;
+  RC wgA = s0.g, wgB = s1.g;
+  RF wmA = s0.m, wmB = s1.m;
+  RC waA = s0.ay, waB = s1.ay;
   double za[VEC] = {}, zb[VEC] = {};
+  CF c0, c1;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  // one marching step: `cur` holds the rows loaded during the previous step,
+  // one marching step: `held` holds the rows loaded during the previous step,
   // the next step's rows go into `nxt` (two buffers taking turns, so that no
   // register holding a load in flight is ever copied: a copy would wait for
-  // it).  The loads are issued unconditionally (past the tile's last rows
-  // they repeat its last row), so that every step has the same count of
-  // loads in flight.  Steps j0-2 and j0-1 compute only stage 1 (s2 false);
-  // lp: the step loads p_k of the next step's output row.
-  auto step = [&](auto s2, auto lp, int r, const StepRows<TF, VEC>& held, StepRows<TF, VEC>& nxt) {
+  // it; the coefficient buffers take turns likewise).  The loads are issued
+  // unconditionally (past the tile's last rows they repeat its last row), so
+  // that every step has the same count of loads in flight.  s2: the step
+  // computes stage 2 (not at j0-2, j0-1); lp: it loads p_k of the next step's
+  // output row.
+  auto step = [&](auto s2, auto lp, int r, const StepRows<TF, VEC>& held, StepRows<TF, VEC>& nxt, const CF& c_r,
+                  CF& c_next) {
     // (nxt was copied out by the step before: its registers are free)
     load_step_rows<TF, VEC, ADVF>(F, in, lo, own && decltype(lp)::value, min(r + 3, j1 + 1), true,
                                   min(r + 1, j1 - 1), nxt);
@@ -624,23 +688,13 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
 #pragma unroll
       for (int v = 0; v < VEC; ++v) cur.p[v] = own ? vcopy(held.p[v]) : 0.0;
     }
-    // stage 1: y_{k+1} on row r+1
+    // stage 1: y_{k+1} and the coefficients on row r+1
     double zc[VEC];
-    stage1(r + 1, wy0, wy1, cur.y, wg1, wg2, cur.g, wm1, wm2, cur.m, cur.k, cur.ax, wa1, cur.ay, zc);
-    // stage 2: y_{k+2} on row r
+    stage1(r + 1, wy0, wy1, cur.y, wgA, wgB, cur.g, wmA, wmB, cur.m, cur.k, cur.ax, waA, cur.ay, c_next, zc);
+    // stage 2: y_{k+2} on row r, with row r's coefficients from the step before
     if constexpr (decltype(s2)::value) {
-      RowN<VEC> xn{};
-      RowC<VEC> an0{}, an2{};
-      if constexpr (ADVF) {
-        xn = rown_of<TF, VEC, MODE_ZERO>(wx, g);
-        an0 = rowc_of<TF, VEC>(wa0);
-        an2 = rowc_of<TF, VEC>(wa2);
-      }
       double Ax[VEC];
-      stencil_point<VEC, ADVF>(rown_y1<VEC>(za), rown_y1<VEC>(zb), rown_y1<VEC>(zc), rowc_of<TF, VEC>(wg0),
-                               rowc_of<TF, VEC>(wg1), rowc_of<TF, VEC>(wg2), rown_of<TF, VEC, MODE_ZERO>(wm0, g),
-                               rown_of<TF, VEC, MODE_ZERO>(wm1, g), rown_of<TF, VEC, MODE_ZERO>(wm2, g),
-                               rown_of<TF, VEC, MODE_EDGE>(wk, g), xn, an0, an2, F.axc, F.ayc, Ax);
+      coef_apply<VEC, ADVF>(c_r, rown_y1<VEC>(za), rown_y1<VEC>(zb), rown_y1<VEC>(zc), F.axc, F.ayc, Ax);
       if (own) {
         double y2[VEC], pm[VEC], p2[VEC];
 #pragma unroll
@@ -664,18 +718,13 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
     // slide the windows down one row
     wy0 = wy1;
     wy1 = cur.y;
-    wg0 = wg1;
-    wg1 = wg2;
-    wg2 = cur.g;
-    wm0 = wm1;
-    wm1 = wm2;
-    wm2 = cur.m;
-    wk = cur.k;
+    wgA = wgB;
+    wgB = cur.g;
+    wmA = wmB;
+    wmB = cur.m;
     if constexpr (ADVF) {
-      wx = cur.ax;
-      wa0 = wa1;
-      wa1 = wa2;
-      wa2 = cur.ay;
+      waA = waB;
+      waB = cur.ay;
     }
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -685,15 +734,15 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
   };
   using No = std::false_type;
   using Yes = std::true_type;
-  step(No{}, No{}, j0 - 2, na, nb);
-  step(No{}, Yes{}, j0 - 1, nb, na);
+  step(No{}, No{}, j0 - 2, na, nb, c1, c0);
+  step(No{}, Yes{}, j0 - 1, nb, na, c0, c1);
   int r = j0;
 #pragma unroll 1
   for (; r + 1 < j1; r += 2) {
-    step(Yes{}, Yes{}, r, na, nb);
-    step(Yes{}, Yes{}, r + 1, nb, na);
+    step(Yes{}, Yes{}, r, na, nb, c1, c0);
+    step(Yes{}, Yes{}, r + 1, nb, na, c0, c1);
   }
-  if (r < j1) step(Yes{}, Yes{}, r, na, nb);
+  if (r < j1) step(Yes{}, Yes{}, r, na, nb, c1, c0);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
 #pragma unroll
