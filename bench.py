@@ -251,13 +251,14 @@ def chosen_vs_plain(steps=10, tol=1e-9):
     t_bound_c = time.perf_counter() - t0
     batch = A.Batch(ops_c)
     uc = [dev_tensor(b.u0) for b in bins]
-    best_rows, _ = batch.autotune(uc, S, dt, tol, candidates=(2, 4, 8, 16))
+    best_rows, _ = batch.autotune(uc, S, dt, tol, candidates=(8, 16, 32, 64))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mv_c = 0
     fb = 0
+    batch.bind(uc, S)
     for n in range(steps):
-        st = batch.midpoint_step(uc, S, dt, tol, use_graph=True)
+        st = batch.midpoint_step(None, None, dt, tol, use_graph=True)
         mv_c += sum(x["matvecs"] for x in st)
         fb += sum(x["fallback"] for x in st)
     torch.cuda.synchronize()
@@ -295,6 +296,32 @@ def profile_leja(n, mode=1):
     st = op.leja_phi(1, w.dt, v, out, w.tol)
     torch.cuda.synchronize()
     print(json.dumps({"profile_leja": n, "terms": st["matvecs"]}), flush=True)
+
+
+def profile_bins(steps=4, tile_rows=16, tol=1e-9):
+    """The chosen form of the 256-bin momentum workload alone (FP32 fields,
+    learned interval, one hipGraph per batched midpoint step) for a few
+    steps, for rocprofv3."""
+    import torch
+    import paper_2307_12276_amd as A
+    from paper_2307_12276_amd import learned
+    import workloads as W
+    bins = W.c4_bins(steps=steps)
+    dt = bins[0].dt
+    S = [dev_tensor(b.S(0)) for b in bins]
+    ops = [make_op(b, A.STORAGE_FP32_FIELDS) for b in bins]
+    Wd = torch.from_numpy(learned.load()).cuda()
+    scratch = torch.empty(64, dtype=torch.float32, device="cuda")
+    for op in ops:
+        op.learned_bound(dt, Wd, scratch)
+    batch = A.Batch(ops, tile_rows=tile_rows)
+    u = [dev_tensor(b.u0) for b in bins]
+    batch.bind(u, S)
+    mv = 0
+    for _ in range(steps):
+        mv += sum(x["matvecs"] for x in batch.midpoint_step(None, None, dt, tol))
+    torch.cuda.synchronize()
+    log("bins: %d steps, %d matvecs, tile rows %d" % (steps, mv, tile_rows))
 
 
 def calibrate_copy():
@@ -381,6 +408,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline, bins and paper-case legs")
     ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
+    ap.add_argument("--profile-bins", action="store_true",
+                    help="run the chosen 256-bin batched form for a few steps and exit")
     ap.add_argument("--one-term", action="store_true", help="with --profile-leja: one Newton term per launch")
     ap.add_argument("--frames", action="store_true",
                     help="with --profile-leja: two terms per launch with the register-frame kernel")
@@ -390,6 +419,9 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.profile_bins:
+        profile_bins()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -393,10 +393,27 @@ class Batch:
                                         ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
         return best.value, ms.value
 
+    def bind(self, us, S_halfs):
+        """Validate the bins' state vectors (and sources) once for many steps:
+        midpoint_step(None, None, ...) then advances these tensors without
+        checking them again (they are kept alive here; they must keep their
+        storage, dtype and shape).  bind(None, None) drops them."""
+        if us is None:
+            self._bound = None
+            return
+        self._bound = (self._ptr_arrays(us, S_halfs), list(us), None if S_halfs is None else list(S_halfs))
+
     def midpoint_step(self, us, S_halfs, dt: float, tol: float, use_graph: bool = True,
                       stream=None):
+        """One exponential midpoint step of every bin; us=None advances the
+        tensors given to bind()."""
         n = len(self.ops)
-        up, sp = self._ptr_arrays(us, S_halfs)
+        if us is None:
+            if getattr(self, "_bound", None) is None:
+                raise ValueError("no bound state: pass us and S_halfs, or call bind() first")
+            up, sp = self._bound[0]
+        else:
+            up, sp = self._ptr_arrays(us, S_halfs)
         stats = (Stats * n)()
         _check(lib().adl_batch_midpoint_step(self.handle, up, sp, float(dt), float(tol), int(bool(use_graph)),
                                              stats, _stream(stream)))

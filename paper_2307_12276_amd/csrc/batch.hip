@@ -161,31 +161,6 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
   return stop != 0;
 }
 
-template <int VEC>
-struct StageEp {
-  struct Extra {};
-  int nx;
-  double* __restrict__ out;
-  const double* __restrict__ s;
-  __device__ __forceinline__ bool go() const { return true; }
-  __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
-  __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&)[VEC],
-                                         const Extra&) {
-    if (!g.inside) return;
-    const long ro = (long)j * nx;
-    double r[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) r[v] = Ax[v];
-    if (s) {
-      double q[VEC];
-      ldr<double, VEC>(s + ro, g.col0, q);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) r[v] += q[v];
-    }
-    str<double, VEC>(out + ro, g.col0, r);
-  }
-};
-
 template <int VEC, bool FIRST>
 struct BatchLejaEp {
   struct Extra {
@@ -223,20 +198,20 @@ struct BatchLejaEp {
   }
 };
 
+// marching one-term tiles of the stage launch and of the first Newton term
+// (defined with the marching machinery below)
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void batch_stage_tile(const BatchArgs& A, const BinDesc& B, int t);
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void batch_first_tile(const BatchArgs& A, const BinDesc& B, int t);
+
 template <typename TF, int VEC, bool ADVF>
 __global__ __launch_bounds__(64) void batch_stage_kernel(BatchArgs A) {
   const int gt = blockIdx.x;
   const int b = __builtin_amdgcn_readfirstlane(A.tile_bin[gt]);
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
-  const int t = gt - B.tile_base;
-  const int rb = t / B.ncb, cb = t - rb * B.ncb;
-  const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
-  StageEp<VEC> ep;
-  ep.nx = B.f.nx;
-  ep.out = B.w;
-  ep.s = B.S;
-  stencil_tile<TF, double, VEC, ADVF>(B.f, B.u, ep, cb, j0, j1);
+  batch_stage_tile<TF, VEC, ADVF>(A, B, gt - B.tile_base);
 }
 
 __device__ __forceinline__ double* tile_partials(const BatchArgs& A, long tile) {
@@ -245,6 +220,10 @@ __device__ __forceinline__ double* tile_partials(const BatchArgs& A, long tile) 
 
 template <typename TF, int VEC, bool ADVF, bool FIRST>
 __device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B, int t) {
+  if constexpr (FIRST) {
+    batch_first_tile<TF, VEC, ADVF>(A, B, t);
+    return;
+  }
   const int rb = t / B.ncb, cb = t - rb * B.ncb;
   const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
   const int k = A.k;
@@ -518,6 +497,178 @@ __device__ __forceinline__ void load_step_rows(const FieldView& F, const TileIn&
     if constexpr (ADVF) trow_load<TF, VEC, MODE_ZERO>(in.ax, q - 1, F, lo, s.ax);
   }
   if (own) bload<double, VEC>(in.p, lo.o8, pr * F.nx * 8, s.p);
+}
+
+// One stencil application per row on the one-term tiling (a wave per strip
+// of 64*VEC columns x `rows` rows, halo elements at the strip edges), with
+// the two-term tile's marching: windows of stored rows (y rows r-1, r; kyy,
+// kxy, ay' rows r-1, r), each step's new rows (input row r+1, kxx and ax' row
+// r, the epilogue's extra input row r) loaded during the step before, two
+// buffers taking turns.  fin(r, Ax, y_r, extra_r) consumes each row; `extra`
+// (wave-uniform) says whether in.p holds an extra input to load.
+template <typename TF, int VEC, bool ADVF, class Fin>
+__device__ __forceinline__ void march1(const FieldView& F, const TileIn& in, const LaneOff& lo, const Strip& g,
+                                       bool extra, int j0, int j1, Fin&& fin) {
+  using RY = TRow<double, VEC>;
+  using RF = TRow<TF, VEC>;
+  using RC = TRowC<TF, VEC>;
+  const bool ld = g.inside && extra;
+  StepRows<TF, VEC> s0, s1, na, nb;
+  load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0 - 1, false, j0, s0);
+  load_step_rows<TF, VEC, ADVF>(F, in, lo, false, j0, false, j0, s1);
+  load_step_rows<TF, VEC, ADVF>(F, in, lo, ld, j0 + 1, true, j0, na);
+  RY wy0 = s0.y, wy1 = s1.y;
+  RC wgA = s0.g, wgB = s1.g;
+  RF wmA = s0.m, wmB = s1.m;
+  RC waA = s0.ay, waB = s1.ay;
+  auto step = [&](int r, const StepRows<TF, VEC>& held, StepRows<TF, VEC>& nxt) {
+    // (nxt was copied out by the step before: its registers are free)
+    load_step_rows<TF, VEC, ADVF>(F, in, lo, ld, min(r + 2, j1), true, min(r + 1, j1 - 1), nxt);
+    StepRows<TF, VEC> cur;
+    cur.y = vcopy(held.y);
+    cur.g = vcopy(held.g);
+    cur.m = vcopy(held.m);
+    cur.k = vcopy(held.k);
+    if constexpr (ADVF) {
+      cur.ax = vcopy(held.ax);
+      cur.ay = vcopy(held.ay);
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) cur.p[v] = ld ? vcopy(held.p[v]) : 0.0;
+    RowN<VEC> xn{};
+    RowC<VEC> an0{}, an2{};
+    if constexpr (ADVF) {
+      xn = rown_of<TF, VEC, MODE_ZERO>(cur.ax, g);
+      an0 = rowc_of<TF, VEC>(waA);
+      an2 = rowc_of<TF, VEC>(cur.ay);
+    }
+    const RowN<VEC> uc = rown_of<double, VEC, MODE_ZERO>(wy1, g);
+    double Ax[VEC];
+    stencil_point<VEC, ADVF>(rown_of<double, VEC, MODE_ZERO>(wy0, g), uc, rown_of<double, VEC, MODE_ZERO>(cur.y, g),
+                             rowc_of<TF, VEC>(wgA), rowc_of<TF, VEC>(wgB), rowc_of<TF, VEC>(cur.g),
+                             rown_of<TF, VEC, MODE_ZERO>(wmA, g), rown_of<TF, VEC, MODE_ZERO>(wmB, g),
+                             rown_of<TF, VEC, MODE_ZERO>(cur.m, g), rown_of<TF, VEC, MODE_EDGE>(cur.k, g), xn, an0,
+                             an2, F.axc, F.ayc, Ax);
+    fin(r, Ax, uc.c, cur.p);
+    wy0 = wy1;
+    wy1 = cur.y;
+    wgA = wgB;
+    wgB = cur.g;
+    wmA = wmB;
+    wmB = cur.m;
+    if constexpr (ADVF) {
+      waA = waB;
+      waB = cur.ay;
+    }
+  };
+  int r = j0;
+#pragma unroll 1
+  for (; r + 1 < j1; r += 2) {
+    step(r, na, nb);
+    step(r + 1, nb, na);
+  }
+  if (r < j1) step(r, na, nb);
+}
+
+// the descriptor's values for a one-term tile, read once into scalar registers
+struct TileSetup {
+  FieldView F;
+  int j0, j1;
+  Strip g;
+  LaneOff lo;
+};
+template <int VEC>
+__device__ __forceinline__ TileSetup tile_setup(const BinDesc& B, int t) {
+  TileSetup s;
+  s.F = B.f;
+  s.F.nx = uni(s.F.nx);
+  s.F.ny = uni(s.F.ny);
+  s.F.bc = uni(s.F.bc);
+  s.F.axc = uni(s.F.axc);
+  s.F.ayc = uni(s.F.ayc);
+  const int ncb = uni(B.ncb), rows = uni(B.rows);
+  const int rb = t / ncb, cb = t - rb * ncb;
+  s.j0 = rb * rows;
+  s.j1 = min(s.j0 + rows, s.F.ny);
+  s.g = make_strip<VEC>(s.F, cb);
+  s.lo = LaneOff{s.g.colc * 8, s.g.hcol * 8, s.g.colc * 4, s.g.hcol * 4, s.g.col0 * 8};
+  return s;
+}
+template <typename TF, bool ADVF>
+__device__ __forceinline__ void fields_in(const FieldView& F, TileIn& in) {
+  in.kxx = rsrc_of(uni(F.kxx));
+  in.kxy = rsrc_of(uni(F.kxy));
+  in.kyy = rsrc_of(uni(F.kyy));
+  if constexpr (ADVF) {
+    in.ax = rsrc_of(uni(F.ax));
+    in.ay = rsrc_of(uni(F.ay));
+  }
+}
+
+// w = A u + S on a one-term tile (S may be absent)
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void batch_stage_tile(const BatchArgs& A, const BinDesc& B, int t) {
+  (void)A;
+  const TileSetup ts = tile_setup<VEC>(B, t);
+  const bool has_s = uni((int)(B.S != nullptr)) != 0;
+  TileIn in;
+  in.y = rsrc_of(uni(B.u));
+  in.p = rsrc_of(uni(has_s ? B.S : B.u));  // (loaded only with a source)
+  fields_in<TF, ADVF>(ts.F, in);
+  const Rsrc out = rsrc_of(uni(B.w));
+  march1<TF, VEC, ADVF>(ts.F, in, ts.lo, ts.g, has_s, ts.j0, ts.j1,
+                        [&](int r, const double (&Ax)[VEC], const double (&)[VEC], const double (&sv)[VEC]) {
+                          if (!ts.g.inside) return;
+                          double o[VEC];
+#pragma unroll
+                          for (int v = 0; v < VEC; ++v) {
+                            o[v] = Ax[v];
+                            if (has_s) o[v] += sv[v];
+                          }
+                          bstore<VEC>(out, ts.lo.o8, r * ts.F.nx * 8, o);
+                        });
+}
+
+// the first Newton term of every bin's sweep on a one-term tile: y_1 from
+// y_0 = w, p_1 = d_0 y_0 + d_1 y_1, the tile's partial norms and max |y_0|
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void batch_first_tile(const BatchArgs& A, const BinDesc& B, int t) {
+  const TileSetup ts = tile_setup<VEC>(B, t);
+  TileIn in;
+  in.y = rsrc_of(uni(B.w));
+  in.p = in.y;  // (no extra input)
+  fields_in<TF, ADVF>(ts.F, in);
+  const Rsrc yout = rsrc_of(uni(((A.L + 1) & 1) ? B.y1 : B.y0));
+  const Rsrc pout = rsrc_of(uni(B.pb[pbuf_index(1, A.two)]));
+  const double shift = uni(B.shift[0]), invg = uni(B.invg), d0 = uni(B.d[0]), dk1 = uni(B.d[1]);
+  double acc[3] = {0.0, 0.0, 0.0};
+  march1<TF, VEC, ADVF>(ts.F, in, ts.lo, ts.g, false, ts.j0, ts.j1,
+                        [&](int r, const double (&Ax)[VEC], const double (&yc)[VEC], const double (&)[VEC]) {
+                          if (!ts.g.inside) return;
+                          double yn[VEC], pn[VEC];
+#pragma unroll
+                          for (int v = 0; v < VEC; ++v) {
+                            const double y1 = (Ax[v] - shift * yc[v]) * invg;
+                            const double tt = dk1 * y1;
+                            const double pv = d0 * yc[v] + tt;
+                            yn[v] = y1;
+                            pn[v] = pv;
+                            acc[0] += tt * tt;
+                            acc[1] += pv * pv;
+                            acc[2] = nanmax(acc[2], fabs(yc[v]));
+                          }
+                          const int so = r * ts.F.nx * 8;
+                          bstore<VEC>(yout, ts.lo.o8, so, yn);
+                          bstore<VEC>(pout, ts.lo.o8, so, pn);
+                        });
+  wave_sum3(acc);
+  if ((threadIdx.x & 63) == 0) {
+    double* part = tile_partials(A, B.tile_base + t);
+    part[0] = acc[0];
+    part[1] = acc[1];
+    part[2] = acc[2];
+    part[3] = part[4] = part[5] = 0.0;
+  }
 }
 
 // The stencil coefficients of a row's VEC points (Sec. 2, eq. 3 discretised

@@ -70,6 +70,30 @@ def test_batch_graph_replays_equal_eager(two_terms):
             assert torch.equal(x, y)
 
 
+def test_batch_bound_state_steps_like_passed_state():
+    """bind() once and step with us=None: the same results as passing the
+    tensors every step; stepping without bound state is refused."""
+    bins = W.c4_bins(nbins=5, sizes=(128, 192))
+    _, b1 = make_batch(bins)
+    _, b2 = make_batch(bins)
+    ua = [to_dev(w.u0) for w in bins]
+    ub = [to_dev(w.u0) for w in bins]
+    S = [to_dev(w.S(0)) for w in bins]
+    with pytest.raises(ValueError):
+        b1.midpoint_step(None, None, bins[0].dt, bins[0].tol)
+    b1.bind(ua, S)
+    for _ in range(3):
+        s1 = b1.midpoint_step(None, None, bins[0].dt, bins[0].tol)
+        s2 = b2.midpoint_step(ub, S, bins[0].dt, bins[0].tol)
+        assert [x["matvecs"] for x in s1] == [x["matvecs"] for x in s2]
+    torch.cuda.synchronize()
+    for x, y in zip(ua, ub):
+        assert torch.equal(x, y)
+    b1.bind(None, None)
+    with pytest.raises(ValueError):
+        b1.midpoint_step(None, None, bins[0].dt, bins[0].tol)
+
+
 def test_batch_fallback_bins_and_autotune():
     """A bin whose step needs substeps, a source-free bin and a zero operator
     are advanced by the single-op path inside the same call."""
