@@ -94,6 +94,65 @@ def test_batch_bound_state_steps_like_passed_state():
         b1.midpoint_step(None, None, bins[0].dt, bins[0].tol)
 
 
+def varied_bins(shapes, bcs, field_adv, seed):
+    """Bins with smooth random coefficient fields, random u0 and source, the
+    given shapes and boundary conditions, field or constant advection, and a
+    shared dt = 50 min dt_CFL."""
+    bins = []
+    for i, ((nx, ny), bc) in enumerate(zip(shapes, bcs)):
+        Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed + i, field_advection=field_adv)
+        _, _, hx, hy = W.grid_2d(nx, ny, bc)
+        u0 = W.random_vector((ny, nx), seed + 100 + i)
+        S = 0.1 * W.random_vector((ny, nx), seed + 200 + i)
+        bins.append(W.Workload("varied%d-%dx%d" % (i, nx, ny), nx, ny, hx, hy, bc, Dxx, Dxy, Dyy,
+                               ax if field_adv else None, ay if field_adv else None,
+                               0.0 if field_adv else ax, 0.0 if field_adv else ay, u0, 0.0, 2, 1e-10,
+                               "midpoint", 0.5, 0.5, lambda t, S=S: S))
+    dt = 50.0 * min(W.cfl_dt(w.Dxx, w.Dyy, w.hx, w.hy) for w in bins)
+    for w in bins:
+        w.dt = dt
+    return bins
+
+
+# (shapes, boundary conditions, field advection, storage, tile rows): odd
+# widths take one column per lane; odd tile heights and ragged last tiles
+# take the marching tiles' single-row tail step
+VARIED = {
+    "periodic-field-adv-fp64-vec1": ([(97, 64), (64, 33), (33, 20)], [O.PERIODIC] * 3, True, 0, 5),
+    "dirichlet-field-adv-fp32-vec2": ([(128, 45), (130, 70), (256, 19)], [O.DIRICHLET] * 3, True, 1, 7),
+    "mixed-bc-const-adv-fp32-vec2": ([(128, 37), (256, 20), (192, 9)], [O.PERIODIC, O.DIRICHLET, O.PERIODIC],
+                                     False, 1, 3),
+}
+
+
+@pytest.mark.parametrize("two_terms", [True, False])
+@pytest.mark.parametrize("case", sorted(VARIED))
+def test_batch_varied_bins_match_oracle(case, two_terms):
+    """Batched bins beyond the C4 layout (periodic and mixed boundaries,
+    field advection, FP32 fields, odd widths, odd tile heights) against the
+    oracle bin by bin over two midpoint steps: same matvec count, 1e-10."""
+    shapes, bcs, field_adv, storage, rows = VARIED[case]
+    bins = varied_bins(shapes, bcs, field_adv, seed=len(case))
+    pairs = [workload_pair(w, storage) for w in bins]
+    alphas = [bounds.gershgorin(oop) for oop, _ in pairs]
+    for (oop, gop), a in zip(pairs, alphas):
+        gop.set_bound(a)
+    b = A.Batch([g for _, g in pairs], tile_rows=rows)
+    b.set_term_fusion(two_terms)
+    us = [to_dev(w.u0) for w in bins]
+    Ss = [to_dev(w.S(0)) for w in bins]
+    for _ in range(2):
+        stats = b.midpoint_step(us, Ss, bins[0].dt, bins[0].tol)
+    for w, (oop, _), a, u, st in zip(bins, pairs, alphas, us, stats):
+        ref = w.u0.copy()
+        for _ in range(2):
+            ost = {}
+            ref = integrators.exp_midpoint_step(lambda x: O.apply(oop, x), ref, w.S(0), w.dt, a, w.tol, stats=ost)
+        assert st["substeps"] == 1, (w.name, st)  # advanced by the batched kernels
+        assert st["fallback"] == 0 and st["matvecs"] == ost["matvecs"], (w.name, st, ost)
+        assert rel(to_np(u), ref) < 1e-10, (w.name, rel(to_np(u), ref))
+
+
 def test_batch_fallback_bins_and_autotune():
     """A bin whose step needs substeps, a source-free bin and a zero operator
     are advanced by the single-op path inside the same call."""
