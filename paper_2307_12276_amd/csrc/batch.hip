@@ -3,13 +3,15 @@
 // step (Sec. 2, eq. 4) together.
 //
 // Work unit: a tile = one wave64 strip of 64*VEC columns x `rows` rows of one
-// bin.  Every kernel of a step covers the tiles of all bins:
+// bin, which the wave marches down row by row (the windows of rows it needs
+// in registers, the next row's loads in flight).  Every kernel of a step
+// covers the tiles of all bins:
 //   stage      w_b = A_b u_b + S_b
 //   term k     y_{k+1} = ((A_b - c_b)/gamma_b - xi_k) y_k,
 //              p_{b,k+1} = p_{b,k} + d_{b,k+1} y_{k+1},
 //              for every bin still running, with the bin's own plan; after
 //              the first term two terms per launch by default (y_{k+1} kept
-//              in LDS, as for a single operator)
+//              in registers)
 //   finalize   the decision of the last term, one wave per bin
 //   update     u_b += dt p_b for converged bins
 // The stopping decision lags one launch behind the work, as for a single
@@ -161,49 +163,14 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
   return stop != 0;
 }
 
-template <int VEC, bool FIRST>
-struct BatchLejaEp {
-  struct Extra {
-    double p[VEC];
-  };
-  int nx;
-  double* __restrict__ yout;
-  const double* __restrict__ pin;  // p_k (not on the first term)
-  double* __restrict__ p;          // p_{k+1}
-  double shift, invg, d0, dk1;
-  double acc[3];
-  __device__ __forceinline__ bool go() const { return true; }
-  __device__ __forceinline__ void load(int j, const Strip& g, Extra& e) {
-    if (!g.inside) return;
-    if constexpr (!FIRST) ldr<double, VEC>(pin + (long)j * nx, g.col0, e.p);
-  }
-  __device__ __forceinline__ void finish(int j, const Strip& g, const double (&Ax)[VEC], const double (&yc)[VEC],
-                                         const Extra& e) {
-    if (!g.inside) return;
-    const long ro = (long)j * nx;
-    double yn[VEC], pn[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      const double y1 = (Ax[v] - shift * yc[v]) * invg;
-      const double t = dk1 * y1;
-      const double pv = (FIRST ? d0 * yc[v] : e.p[v]) + t;
-      yn[v] = y1;
-      pn[v] = pv;
-      acc[0] += t * t;
-      acc[1] += pv * pv;
-      if constexpr (FIRST) acc[2] = nanmax(acc[2], fabs(yc[v]));
-    }
-    str<double, VEC>(yout + ro, g.col0, yn);
-    str<double, VEC>(p + ro, g.col0, pn);
-  }
-};
-
-// marching one-term tiles of the stage launch and of the first Newton term
-// (defined with the marching machinery below)
+// marching one-term tiles of the stage launch and of the Newton terms of
+// one-term launches (defined with the marching machinery below)
 template <typename TF, int VEC, bool ADVF>
 __device__ __forceinline__ void batch_stage_tile(const BatchArgs& A, const BinDesc& B, int t);
 template <typename TF, int VEC, bool ADVF>
 __device__ __forceinline__ void batch_first_tile(const BatchArgs& A, const BinDesc& B, int t);
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void batch_next_tile(const BatchArgs& A, const BinDesc& B, int t);
 
 template <typename TF, int VEC, bool ADVF>
 __global__ __launch_bounds__(64) void batch_stage_kernel(BatchArgs A) {
@@ -220,33 +187,8 @@ __device__ __forceinline__ double* tile_partials(const BatchArgs& A, long tile) 
 
 template <typename TF, int VEC, bool ADVF, bool FIRST>
 __device__ __forceinline__ void batch_term(const BatchArgs& A, const BinDesc& B, int t) {
-  if constexpr (FIRST) {
-    batch_first_tile<TF, VEC, ADVF>(A, B, t);
-    return;
-  }
-  const int rb = t / B.ncb, cb = t - rb * B.ncb;
-  const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
-  const int k = A.k;
-  BatchLejaEp<VEC, FIRST> ep;
-  ep.nx = B.f.nx;
-  ep.yout = reinterpret_cast<double*>(((A.L + 1) & 1) ? B.y1 : B.y0);
-  ep.pin = FIRST ? nullptr : B.pb[pbuf_index(k, A.two)];
-  ep.p = B.pb[pbuf_index(k + 1, A.two)];
-  ep.shift = B.shift[k];
-  ep.invg = B.invg;
-  ep.d0 = B.d[0];
-  ep.dk1 = B.d[k + 1];
-  ep.acc[0] = ep.acc[1] = ep.acc[2] = 0.0;
-  const double* yin = FIRST ? B.w : reinterpret_cast<const double*>((A.L & 1) ? B.y1 : B.y0);
-  stencil_tile<TF, double, VEC, ADVF>(B.f, yin, ep, cb, j0, j1);
-  wave_sum3(ep.acc);
-  if ((threadIdx.x & 63) == 0) {
-    double* part = tile_partials(A, B.tile_base + t);
-    part[0] = ep.acc[0];
-    part[1] = ep.acc[1];
-    part[2] = ep.acc[2];
-    part[3] = part[4] = part[5] = 0.0;
-  }
+  if constexpr (FIRST) batch_first_tile<TF, VEC, ADVF>(A, B, t);
+  else batch_next_tile<TF, VEC, ADVF>(A, B, t);
 }
 
 // Term launch L (terms k+1 .. k+nterms): blocks [0, nbins) decide the terms
@@ -656,6 +598,49 @@ __device__ __forceinline__ void batch_first_tile(const BatchArgs& A, const BinDe
                             acc[0] += tt * tt;
                             acc[1] += pv * pv;
                             acc[2] = nanmax(acc[2], fabs(yc[v]));
+                          }
+                          const int so = r * ts.F.nx * 8;
+                          bstore<VEC>(yout, ts.lo.o8, so, yn);
+                          bstore<VEC>(pout, ts.lo.o8, so, pn);
+                        });
+  wave_sum3(acc);
+  if ((threadIdx.x & 63) == 0) {
+    double* part = tile_partials(A, B.tile_base + t);
+    part[0] = acc[0];
+    part[1] = acc[1];
+    part[2] = acc[2];
+    part[3] = part[4] = part[5] = 0.0;
+  }
+}
+
+// a later Newton term (k >= 1) of one-term launches: y_{k+1} from y_k,
+// p_{k+1} = p_k + d_{k+1} y_{k+1} (p_k the march's extra input row), the
+// tile's partial norms
+template <typename TF, int VEC, bool ADVF>
+__device__ __forceinline__ void batch_next_tile(const BatchArgs& A, const BinDesc& B, int t) {
+  const TileSetup ts = tile_setup<VEC>(B, t);
+  const int k = A.k;
+  TileIn in;
+  in.y = rsrc_of(uni((A.L & 1) ? B.y1 : B.y0));
+  in.p = rsrc_of(uni(B.pb[pbuf_index(k, A.two)]));
+  fields_in<TF, ADVF>(ts.F, in);
+  const Rsrc yout = rsrc_of(uni(((A.L + 1) & 1) ? B.y1 : B.y0));
+  const Rsrc pout = rsrc_of(uni(B.pb[pbuf_index(k + 1, A.two)]));
+  const double shift = uni(B.shift[k]), invg = uni(B.invg), dk1 = uni(B.d[k + 1]);
+  double acc[3] = {0.0, 0.0, 0.0};
+  march1<TF, VEC, ADVF>(ts.F, in, ts.lo, ts.g, true, ts.j0, ts.j1,
+                        [&](int r, const double (&Ax)[VEC], const double (&yc)[VEC], const double (&pk)[VEC]) {
+                          if (!ts.g.inside) return;
+                          double yn[VEC], pn[VEC];
+#pragma unroll
+                          for (int v = 0; v < VEC; ++v) {
+                            const double y1 = (Ax[v] - shift * yc[v]) * invg;
+                            const double tt = dk1 * y1;
+                            const double pv = pk[v] + tt;
+                            yn[v] = y1;
+                            pn[v] = pv;
+                            acc[0] += tt * tt;
+                            acc[1] += pv * pv;
                           }
                           const int so = r * ts.F.nx * 8;
                           bstore<VEC>(yout, ts.lo.o8, so, yn);
