@@ -281,14 +281,14 @@ def chosen_vs_plain(steps=10, tol=1e-9):
     return res
 
 
-def profile_leja(n, mode=1):
+def profile_leja(n, mode=1, fp32=False):
     """One phi_1 sweep on the n x n stream-function field (profiler driver);
-    mode as for adl_op_set_term_fusion."""
+    mode as for adl_op_set_term_fusion; fp32: fields stored in FP32."""
     import torch
     import paper_2307_12276_amd as A
     import workloads as W
     w = W.roofline_shape(n=n)
-    op = make_op(w, A.STORAGE_FP64)
+    op = make_op(w, A.STORAGE_FP32_FIELDS if fp32 else A.STORAGE_FP64)
     op.set_term_fusion(mode)
     op.spectral_bound(A.BOUND_GERSHGORIN)
     v = dev_tensor(w.u0)
@@ -408,6 +408,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline, bins and paper-case legs")
     ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
+    ap.add_argument("--fp32", action="store_true", help="with --profile-leja: fields stored in FP32")
     ap.add_argument("--profile-bins", action="store_true",
                     help="run the chosen 256-bin batched form for a few steps and exit")
     ap.add_argument("--one-term", action="store_true", help="with --profile-leja: one Newton term per launch")
@@ -415,7 +416,7 @@ def main():
                     help="with --profile-leja: two terms per launch with the register-frame kernel")
     args = ap.parse_args()
     if args.profile_leja:
-        profile_leja(args.profile_leja, 0 if args.one_term else (3 if args.frames else 1))
+        profile_leja(args.profile_leja, 0 if args.one_term else (3 if args.frames else 1), args.fp32)
         return
     if args.calibrate_copy:
         calibrate_copy()

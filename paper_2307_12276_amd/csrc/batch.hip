@@ -349,8 +349,11 @@ __device__ __forceinline__ RowN<VEC> rown_of(const TRow<T, VEC>& x, const Strip&
   RowN<VEC> o;
 #pragma unroll
   for (int v = 0; v < VEC; ++v) o.c[v] = x.zero ? 0.0 : (double)x.c[v];
-  const double l = x.zero ? 0.0 : dpp_t<T, kDppWaveShr1>(x.c[VEC - 1]);
-  const double rr = x.zero ? 0.0 : dpp_t<T, kDppWaveShl1>(x.c[0]);
+  // (shifts taken on every lane, then selected: see ring_rown)
+  const double sl = dpp_t<T, kDppWaveShr1>(x.c[VEC - 1]);
+  const double sr = dpp_t<T, kDppWaveShl1>(x.c[0]);
+  const double l = x.zero ? 0.0 : sl;
+  const double rr = x.zero ? 0.0 : sr;
   const double hz = x.zero ? 0.0 : (double)x.h;
   const double gl = MODE == MODE_EDGE ? o.c[0] : 0.0;
   const double gr = MODE == MODE_EDGE ? o.c[VEC - 1] : 0.0;

@@ -18,9 +18,10 @@ namespace adl {
 // j0 .. j0+3 and updates p as leja2_kernel does.  The next step's rows are
 // loaded into registers when a step starts and put into the rings after its
 // stage 2, so their latency hides behind the step's arithmetic.
-// A ring row holds [left halo, the strip's 64*VEC values, right halo]; a
-// reader takes its lane's VEC values and the elements on either side and
-// applies the Dirichlet ghost-column selects of row_n.
+// A ring row holds a left halo element, the strip's 64*VEC values and a right
+// halo element (RingRow); a reader takes its lane's VEC values, the
+// neighbours from the adjacent lanes, and applies the Dirichlet ghost-column
+// selects of row_n.
 //
 // Ring sizes of the staged kernel: a band step reads input rows j0-1 .. j0+5
 // (7 rows) and, after its last reads, replaces j0-1 .. j0+2 by j0+6 .. j0+9;
@@ -59,22 +60,72 @@ __device__ __forceinline__ void raw_load(const T* __restrict__ a, int r, const F
   o.h = ld1<T>(rp, g.hcol);
 }
 
+// Layout of a ring row: [left halo, pad, the strip's 64*VEC values, right
+// halo, pad].  A lane's VEC values start on a 16-byte boundary, so the lane
+// writes and reads them with one aligned access (a layout with the values
+// one element off that boundary made every access two 8-byte ones at a
+// 16-byte lane stride, which collide in the LDS banks: measured at 4096^2,
+// bank-conflict cycles twice the LDS instruction cycles); the x-neighbours
+// come from the adjacent lanes by DPP, and lanes 0 and 63 read the halo
+// elements.
 template <int VEC>
-__device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<VEC>& x) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int v = 0; v < VEC; ++v) row[1 + lane * VEC + v] = x.zero ? 0.0 : x.c[v];
-  if (g.lane0) row[0] = x.zero ? 0.0 : x.h;
-  if (g.lane63) row[kWave * VEC + 1] = x.zero ? 0.0 : x.h;
+struct RingRow {
+  static constexpr int kLeft = 0;
+  static constexpr int kOwn = 2;
+  static constexpr int kRight = kOwn + kWave * VEC;
+  static constexpr int kLen = kRight + 2;
+};
+
+template <int VEC>
+__device__ __forceinline__ void lds_get(const double* p, double (&c)[VEC]) {
+  if constexpr (VEC == 2) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = *reinterpret_cast<const d2*>(p);
+    c[0] = v.x;
+    c[1] = v.y;
+  } else {
+    c[0] = p[0];
+  }
 }
 
+template <int VEC>
+__device__ __forceinline__ void lds_set(double* p, const double (&c)[VEC]) {
+  if constexpr (VEC == 2) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 v;
+    v.x = c[0];
+    v.y = c[1];
+    *reinterpret_cast<d2*>(p) = v;
+  } else {
+    p[0] = c[0];
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<VEC>& x) {
+  using L = RingRow<VEC>;
+  const int lane = threadIdx.x & (kWave - 1);
+  double c[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) c[v] = x.zero ? 0.0 : x.c[v];
+  lds_set<VEC>(row + L::kOwn + lane * VEC, c);
+  if (g.lane0) row[L::kLeft] = x.zero ? 0.0 : x.h;
+  if (g.lane63) row[L::kRight] = x.zero ? 0.0 : x.h;
+}
+
+// Every lane of the wave must execute it: the DPP shifts read the adjacent
+// lanes, and a lane that is switched off hands over zero.  The shifts are
+// therefore taken unconditionally and selected afterwards (a conditional
+// expression around them would run them only on the lanes it selects).
 template <int VEC, int MODE>
 __device__ __forceinline__ void ring_rown(const double* row, const Strip& g, RowN<VEC>& o) {
-  const double* p = row + (threadIdx.x & (kWave - 1)) * VEC;
-  const double l = p[0];
-#pragma unroll
-  for (int v = 0; v < VEC; ++v) o.c[v] = p[1 + v];
-  const double r = p[VEC + 1];
+  using L = RingRow<VEC>;
+  lds_get<VEC>(row + L::kOwn + (threadIdx.x & (kWave - 1)) * VEC, o.c);
+  const double h = row[g.lane0 ? L::kLeft : L::kRight];  // (used by lanes 0 and 63)
+  const double sl = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
+  const double sr = dpp_f64<kDppWaveShl1>(o.c[0]);
+  const double l = g.lane0 ? h : sl;
+  const double r = g.lane63 ? h : sr;
   const double gl = MODE == MODE_EDGE ? o.c[0] : 0.0;
   const double gr = MODE == MODE_EDGE ? o.c[VEC - 1] : 0.0;
   o.l = g.ghostL ? gl : l;
@@ -83,15 +134,13 @@ __device__ __forceinline__ void ring_rown(const double* row, const Strip& g, Row
 
 template <int VEC>
 __device__ __forceinline__ void ring_rowc(const double* row, RowC<VEC>& o) {
-  const double* p = row + (threadIdx.x & (kWave - 1)) * VEC + 1;
-#pragma unroll
-  for (int v = 0; v < VEC; ++v) o.c[v] = p[v];
+  lds_get<VEC>(row + RingRow<VEC>::kOwn + (threadIdx.x & (kWave - 1)) * VEC, o.c);
 }
 
 // the input rings of a block: y_k, kyy, kxy, kxx (+ ax', ay'), kSRing rows each
 template <int VEC, bool ADVF>
 struct Rings {
-  static constexpr int kRow = kWave * VEC + 2;
+  static constexpr int kRow = RingRow<VEC>::kLen;
   static constexpr int kArrays = ADVF ? 6 : 4;
   double* base;
   int r0;  // grid row of slot 0
