@@ -144,9 +144,8 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
 /* Newton terms per launch of a sweep (Sec. 2 recurrence): mode = 1 (the
  * default) computes terms k+1 and k+2 in one launch, keeping y_{k+1} on chip
  * (read y_k, the fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2}), with
- * the input rows staged in LDS on grids whose working set exceeds the caches
- * (the rule of adl_op_set_streaming) and one-row frames in registers
- * otherwise; mode = 2 and mode = 3
+ * the input rows staged in LDS on grids of at least 2^20 points and one-row
+ * frames in registers on smaller ones; mode = 2 and mode = 3
  * force the LDS-staged and the register-frame form; mode = 0 launches one
  * kernel per term.  Results agree to rounding (the block partial sums of the
  * norms are grouped differently).  ADL_EINVAL for other values. */

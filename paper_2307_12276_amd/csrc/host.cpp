@@ -391,6 +391,7 @@ static double leja_bytes(const adl_op* op, int k, int n, bool with_w2) {
 // launches at 512^2 and at 2048^2, 335 MB; 4-10 % faster at 2896^2 and
 // 4096^2).
 constexpr double kStreamMinBytes = 512.0 * 1024 * 1024;
+constexpr long kStagedMinPoints = 1L << 20;  // two-term launches stage their rows in LDS from here up
 static int streaming_on(const adl_op* op) {
   if (op->streaming >= 0) return op->streaming;
   const double fs = op->f.f32 ? 4.0 : 8.0;
@@ -468,13 +469,13 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   a.max_degree = maxdeg;
   a.ystore_f32 = ys32;
   a.stream = streaming_on(op);
-  // two-term kernel: input rows staged in LDS when the working set exceeds
-  // the caches and blocks march over runs of several bands (each input row
-  // then leaves HBM once per run: 4096^2 FP64 280 -> 243 us per launch); the
-  // register-frame kernel otherwise (cache-resident grids re-read rows from
-  // L2 cheaply and save the staged kernel's prologue and extra barrier:
-  // 512^2-2048^2 5-15 % faster)
-  a.staged = op->fuse_terms == 2 || (op->fuse_terms == 1 && T2.bands >= 2 && streaming_on(op));
+  // two-term kernel: input rows staged in LDS from kStagedMinPoints up (each
+  // input row then leaves memory once per run of bands: 4096^2 FP64 286 ->
+  // 225-234 us per launch); the register-frame kernel on smaller grids,
+  // where the staged kernel's prologue and extra barrier do not pay (measured
+  // per launch, staged / frames: 512^2 1.14, 768^2 0.93-1.05, 1024^2
+  // 0.87-0.92, 1536^2 0.78-0.86, 2048^2 0.84-0.89)
+  a.staged = op->fuse_terms == 2 || (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints);
   a.partials = op->partials;
   a.slot_stride = op->slot_stride;
   a.ctl = op->ctl;
