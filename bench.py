@@ -242,14 +242,13 @@ def chosen_vs_plain(steps=10, tol=1e-9):
     # chosen
     ops_c = [make_op(b, A.STORAGE_FP32_FIELDS) for b in bins]
     Wd = torch.from_numpy(learned.load()).cuda()
-    scratch = torch.empty(64, dtype=torch.float32, device="cuda")
+    batch = A.Batch(ops_c)
+    scratch = torch.empty(72 * len(ops_c), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for op in ops_c:
-        op.learned_bound(dt, Wd, scratch)
+    batch.learned_bound(dt, Wd, scratch)
     torch.cuda.synchronize()
     t_bound_c = time.perf_counter() - t0
-    batch = A.Batch(ops_c)
     uc = [dev_tensor(b.u0) for b in bins]
     best_rows, _ = batch.autotune(uc, S, dt, tol, candidates=(8, 16, 32, 64))
     torch.cuda.synchronize()
@@ -311,10 +310,8 @@ def profile_bins(steps=4, tile_rows=16, tol=1e-9):
     S = [dev_tensor(b.S(0)) for b in bins]
     ops = [make_op(b, A.STORAGE_FP32_FIELDS) for b in bins]
     Wd = torch.from_numpy(learned.load()).cuda()
-    scratch = torch.empty(64, dtype=torch.float32, device="cuda")
-    for op in ops:
-        op.learned_bound(dt, Wd, scratch)
     batch = A.Batch(ops, tile_rows=tile_rows)
+    batch.learned_bound(dt, Wd, torch.empty(72 * len(ops), dtype=torch.float32, device="cuda"))
     u = [dev_tensor(b.u0) for b in bins]
     batch.bind(u, S)
     mv = 0

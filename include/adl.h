@@ -341,13 +341,27 @@ typedef struct adl_learned_info {
 /* Predict and install the op's interval for step size dt with the trained
  * network W (device, ADL_MLP_PARAMS floats): field statistics, the network's
  * forward pass and the Gershgorin cap run on the GPU.  scratch: device, >= 32
- * floats.  Power iteration stays the fallback and the judge: while the learned
+ * floats.  Power iteration stays the fallback and the arbiter: while the learned
  * interval is installed, a sweep needing more than 1.5 degree_hat + 10 terms,
  * or producing a non-finite value, makes adl_exp_midpoint_step /
  * adl_exp_quad2_step replace the interval by power iteration's and redo the
  * step (adl_stats.fallback = 1).  info (host) may be NULL. */
 int adl_learned_bound(adl_op* op, double dt, const float* W, float* scratch, adl_learned_info* info,
                       void* stream);
+
+/* adl_learned_bound for n ops (momentum bins) at once, with the same result
+ * per op, bit for bit: one launch reduces every op's field statistics and
+ * missing Gershgorin bound (each op's blocks as its own launch would run them),
+ * one readback, and one forward pass of the network over the n feature rows,
+ * so the host waits twice in all instead of two or three times per op.
+ * The ops' first-step Newton coefficients are built on up to 16 host threads.
+ * ops: host array of n >= 1 distinct ops (EINVAL if one appears twice), all on
+ * the device of stream.  scratch:
+ * device, >= 72 n floats, 16-byte aligned.  infos: host array of n, or NULL.
+ * On an error the ops before the failing one keep their new interval and the
+ * rest their old one. */
+int adl_learned_bound_many(int n, adl_op* const* ops, double dt, const float* W, float* scratch,
+                           adl_learned_info* infos, void* stream);
 
 /* Thread-local message of the last error (never NULL). */
 const char* adl_last_error(void);

@@ -108,6 +108,7 @@ _SIG = {
     "adl_learned_decode": (_I, [ctypes.POINTER(_F), _D, ctypes.POINTER(_F), ctypes.POINTER(_D), ctypes.POINTER(_I),
                                 ctypes.POINTER(_I)]),
     "adl_learned_bound": (_I, [_P, _D, _P, _P, ctypes.POINTER(LearnedInfo), _P]),
+    "adl_learned_bound_many": (_I, [_I, _P, _D, _P, _P, ctypes.POINTER(LearnedInfo), _P]),
     "adl_leja_points": (_I, [_I, ctypes.POINTER(_D)]),
     "adl_newton_coefficients": (_I, [_I, _D, _D, _I, ctypes.POINTER(_D)]),
 }
@@ -329,6 +330,23 @@ class Op:
         return feats
 
 
+def learned_bound_many(ops: Sequence[Op], dt: float, W, scratch, stream=None):
+    """Op.learned_bound for every op at once (one readback, one forward pass
+    of the network); scratch holds >= 72 floats per op.  Returns the per-op
+    info dicts."""
+    import torch
+    n = len(ops)
+    if n < 1:
+        raise AdlError(EINVAL, "no ops")
+    if scratch is None or scratch.numel() < 72 * n:
+        raise AdlError(EINVAL, f"scratch needs {72 * n} floats")
+    arr = (ctypes.c_void_p * n)(*[o.handle.value for o in ops])
+    infos = (LearnedInfo * n)()
+    _check(lib().adl_learned_bound_many(n, arr, float(dt), _ptr(W, torch.float32, (MLP_PARAMS,), "W"),
+                                        _ptr(scratch, torch.float32, None, "scratch"), infos, _stream(stream)))
+    return [i.as_dict() for i in infos]
+
+
 class Batch:
     """Many ops advanced together by one persistent launch per step."""
 
@@ -359,6 +377,10 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def learned_bound(self, dt: float, W, scratch, stream=None):
+        """learned_bound_many over the batch's ops."""
+        return learned_bound_many(self.ops, dt, W, scratch, stream)
 
     def _ptr_arrays(self, us, S_halfs):
         import torch

@@ -150,9 +150,11 @@ __device__ __forceinline__ double nanmax(double a, double b) {
 }
 
 // Block partials -> last block sums them in fixed order -> fin(totals).
-// Sums for the first NS values, NaN-propagating max for the rest.
+// Sums for the first NS values, NaN-propagating max for the rest.  nb blocks
+// take part (block b writes partial b), counted on ctl->ticket; a launch may
+// hold several such reductions, each with its own partials and ticket.
 template <int NA, int NS, class Fin>
-__device__ __forceinline__ void grid_reduce(double (&acc)[NA], double* partials, Ctl* ctl, Fin fin) {
+__device__ __forceinline__ void grid_reduce(double (&acc)[NA], double* partials, Ctl* ctl, int nb, int b, Fin fin) {
   __shared__ double sh[NA * 16];
   __shared__ int last;
   // block reduce: sums for k < NS, max for k >= NS
@@ -171,13 +173,12 @@ __device__ __forceinline__ void grid_reduce(double (&acc)[NA], double* partials,
     for (int k = 0; k < NA; ++k) sh[wave * NA + k] = acc[k];
   }
   __syncthreads();
-  const int nb = gridDim.x;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
       double s = sh[k];
       for (int w = 1; w < nw; ++w) s = (k < NS) ? s + sh[w * NA + k] : nanmax(s, sh[w * NA + k]);
-      partials[(long)k * nb + blockIdx.x] = s;
+      partials[(long)k * nb + b] = s;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned int t = atomicAdd(&ctl->ticket, 1u);
@@ -223,6 +224,12 @@ __device__ __forceinline__ void grid_reduce(double (&acc)[NA], double* partials,
     fin(tot);
     ctl->ticket = 0u;
   }
+}
+
+// the same over the whole grid
+template <int NA, int NS, class Fin>
+__device__ __forceinline__ void grid_reduce(double (&acc)[NA], double* partials, Ctl* ctl, Fin fin) {
+  grid_reduce<NA, NS>(acc, partials, ctl, (int)gridDim.x, (int)blockIdx.x, fin);
 }
 
 

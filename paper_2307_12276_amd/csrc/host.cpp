@@ -22,6 +22,8 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <system_error>
+#include <thread>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -1340,6 +1342,68 @@ int adl_learned_decode(const float* f, double g, const float* y, double* rho, in
   return ADL_OK;
 }
 
+// Installs the learned interval of op from its field statistics f, Gershgorin
+// bound ag, network input x and output y (shared by the one-op and many-op
+// entry points); *m receives the predicted Leja degree.
+static int install_learned(adl_op* op, const float (&f)[9], double ag, const float (&x)[9], const float (&y)[3],
+                           adl_learned_info* info, int* m_out) {
+  double rho;
+  int m, K;
+  RETCHK(adl_learned_decode(f, -ag, y, &rho, &m, &K));
+  const double alpha = -std::min(kLearnedSafety * rho, std::fabs(ag));
+  if (!(alpha < 0.0) || !std::isfinite(alpha)) return fail(ADL_EBOUND, "learned bound unusable");
+  op->alpha = alpha;
+  op->has_bound = true;
+  op->learned = true;
+  op->budget = std::min(op->max_degree, (int)std::ceil(1.5 * m) + 10);
+  op->substeps_hint = K;
+  *m_out = m;
+  if (info) {
+    info->rho_hat = rho;
+    info->alpha = alpha;
+    info->gershgorin = ag;
+    info->degree_hat = m;
+    info->substeps_hat = K;
+    for (int i = 0; i < 9; ++i) {
+      info->feats[i] = f[i];
+      info->x[i] = x[i];
+    }
+    for (int i = 0; i < 3; ++i) info->y[i] = y[i];
+  }
+  return ADL_OK;
+}
+
+// Builds the plan (Newton coefficients) of op's first step of size dt on the
+// installed learned interval and seeds its predicted degree m, so that the
+// first chunk of the sweep is sized right.
+static void seed_plan(adl_op* op, double dt, int m) {
+  const int Kp = std::max(op->substeps_hint, substeps_for(op->alpha, dt, op->rho_max));
+  Plan& P = get_plan(op, 1, op->alpha, dt / Kp);
+  if (P.last_degree <= 0) P.last_degree = m;
+}
+
+// seed_plan for n distinct ops on up to 16 host threads (a plan is O(M^2)
+// divided differences on the host, ~0.1 ms at M = 501; each thread builds the
+// plans of its own ops, so the coefficients are those of the serial build)
+static void seed_plans(int n, adl_op* const* ops, double dt, const int* m) {
+  const long hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = (int)std::min({hw, 16L, (long)(n + 7) / 8});
+  std::vector<std::thread> th;
+  if (nt > 1) {
+    try {
+      for (int t = 0; t < nt; ++t)
+        th.emplace_back([=] {
+          for (int i = t; i < n; i += nt) seed_plan(ops[i], dt, m[i]);
+        });
+    } catch (const std::system_error&) {
+      // fewer threads than asked: the serial pass below completes the rest
+    }
+  }
+  for (std::thread& x : th) x.join();
+  if ((int)th.size() < nt || nt <= 1)
+    for (int i = 0; i < n; ++i) seed_plan(ops[i], dt, m[i]);  // plans already built are found, not rebuilt
+}
+
 int adl_learned_bound(adl_op* op, double dt, const float* W, float* scratch, adl_learned_info* info, void* stream) {
   RETCHK(check_op(op));
   if (!W || !scratch) return fail(ADL_EINVAL, "null W or scratch");
@@ -1360,32 +1424,91 @@ int adl_learned_bound(adl_op* op, double dt, const float* W, float* scratch, adl
   HIPCHK(launch_mlp_forward(W, d_x, d_y, nullptr, 1, st));
   HIPCHK(hipMemcpyAsync(y, d_y, sizeof y, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  double rho;
-  int m, K;
-  RETCHK(adl_learned_decode(f, -ag, y, &rho, &m, &K));
-  const double alpha = -std::min(kLearnedSafety * rho, std::fabs(ag));
-  if (!(alpha < 0.0) || !std::isfinite(alpha)) return fail(ADL_EBOUND, "learned bound unusable");
-  op->alpha = alpha;
-  op->has_bound = true;
-  op->learned = true;
-  op->budget = std::min(op->max_degree, (int)std::ceil(1.5 * m) + 10);
-  op->substeps_hint = K;
-  // seed the plan's predicted degree so the first chunk is sized right
-  const int Kp = std::max(K, substeps_for(alpha, dt, op->rho_max));
-  Plan& P = get_plan(op, 1, alpha, dt / Kp);
-  if (P.last_degree <= 0) P.last_degree = m;
-  if (info) {
-    info->rho_hat = rho;
-    info->alpha = alpha;
-    info->gershgorin = ag;
-    info->degree_hat = m;
-    info->substeps_hat = K;
-    for (int i = 0; i < 9; ++i) {
-      info->feats[i] = f[i];
-      info->x[i] = x[i];
-    }
-    for (int i = 0; i < 3; ++i) info->y[i] = y[i];
+  int m = 0;
+  RETCHK(install_learned(op, f, ag, x, y, info, &m));
+  seed_plan(op, dt, m);
+  return ADL_OK;
+}
+
+int adl_learned_bound_many(int n, adl_op* const* ops, double dt, const float* W, float* scratch,
+                           adl_learned_info* infos, void* stream) {
+  if (n < 1 || !ops) return fail(ADL_EINVAL, "need n >= 1 ops");
+  for (int i = 0; i < n; ++i) RETCHK(check_op(ops[i]));
+  {
+    std::vector<adl_op*> sorted(ops, ops + n);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return fail(ADL_EINVAL, "an op appears twice");
   }
+  if (!W || !scratch) return fail(ADL_EINVAL, "null W or scratch");
+  if (reinterpret_cast<uintptr_t>(scratch) % 16) return fail(ADL_EINVAL, "scratch must be 16-byte aligned");
+  RETCHK(check_dt(dt));
+  hipStream_t st = S(stream);
+  // scratch (72 n floats): statistics [0, 9n), network input [12n, 21n) and
+  // output [24n, 27n) as floats; Gershgorin bounds as doubles from float 28n;
+  // the jobs from byte 128n (128 B each), then their first blocks (n + 1 ints)
+  unsigned char* base = reinterpret_cast<unsigned char*>(scratch);
+  float* d_feat = scratch;
+  float* d_x = scratch + 12L * n;
+  float* d_y = scratch + 24L * n;
+  double* d_gmin = reinterpret_cast<double*>(scratch + 28L * n);
+  BoundJob* d_jobs = reinterpret_cast<BoundJob*>(base + 128L * n);
+  int* d_blk0 = reinterpret_cast<int*>(base + 256L * n);
+  // every op's statistics and missing Gershgorin bound in one launch
+  std::vector<unsigned char> up(128L * n + 4L * (n + 1));
+  BoundJob* jobs = reinterpret_cast<BoundJob*>(up.data());
+  int* blk0 = reinterpret_cast<int*>(up.data() + 128L * n);
+  long total = 0;
+  for (int i = 0; i < n; ++i) {
+    const adl_op* op = ops[i];
+    const int nb = stats_blocks((long)op->nx * op->ny);
+    BoundJob& J = jobs[i];
+    J = BoundJob{};
+    J.f = op->f;
+    J.hx = op->hx;
+    J.hy = op->hy;
+    J.partials = op->partials;
+    J.ctl = op->ctl;
+    J.blk0 = (int)total;
+    J.nb_s = nb;
+    J.nb_g = std::isnan(op->gersh) ? nb : 0;
+    blk0[i] = (int)total;
+    total += J.nb_s + J.nb_g;
+    if (total > INT_MAX) return fail(ADL_EINVAL, "too many ops for one statistics launch");
+  }
+  blk0[n] = (int)total;
+  HIPCHK(hipMemcpyAsync(d_jobs, up.data(), up.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_bound_stats_many(d_jobs, d_blk0, n, (int)total, dt, d_feat, d_gmin, st));
+  std::vector<unsigned char> down(120L * n);
+  HIPCHK(hipMemcpyAsync(down.data(), scratch, down.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const float* f = reinterpret_cast<const float*>(down.data());
+  const double* gmin = reinterpret_cast<const double*>(down.data() + 112L * n);
+  std::vector<float> x(9L * n), y(3L * n);
+  std::vector<double> ag(n);
+  for (int i = 0; i < n; ++i) {
+    if (jobs[i].nb_g) ops[i]->gersh = gmin[i];
+    ag[i] = ops[i]->gersh;
+    if (!(ag[i] < 0.0)) return fail(ADL_EBOUND, "op %d: zero operator, no learned interval", i);
+    RETCHK(adl_learned_features(&f[9L * i], -ag[i], &x[9L * i]));
+  }
+  // one forward pass of the network over all ops
+  HIPCHK(hipMemcpyAsync(d_x, x.data(), sizeof(float) * 9 * n, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_mlp_forward(W, d_x, d_y, nullptr, n, st));
+  HIPCHK(hipMemcpyAsync(y.data(), d_y, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int> m(n);
+  for (int i = 0; i < n; ++i) {
+    float fi[9], xi[9], yi[3];
+    std::copy(&f[9L * i], &f[9L * i] + 9, fi);
+    std::copy(&x[9L * i], &x[9L * i] + 9, xi);
+    std::copy(&y[3L * i], &y[3L * i] + 3, yi);
+    const int rc = install_learned(ops[i], fi, ag[i], xi, yi, infos ? &infos[i] : nullptr, &m[i]);
+    if (rc != ADL_OK) {
+      seed_plans(i, ops, dt, m.data());
+      return rc;
+    }
+  }
+  seed_plans(n, ops, dt, m.data());
   return ADL_OK;
 }
 

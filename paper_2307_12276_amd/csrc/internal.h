@@ -175,6 +175,34 @@ hipError_t launch_prepare_field(long n, const double* in, double scale, void* ou
                                 hipStream_t st);
 
 // ---- learned bound (mlp.hip) -----------------------------------------------
+// blocks of a one-pass reduction over n nodes (field statistics, Gershgorin):
+// eight nodes per thread, so that the per-block release fence and ticket
+// (the cost of such a launch on cache-resident grids) are paid once per 2048
+// nodes; at most 1024 blocks
+inline int stats_blocks(long n) {
+  const long nb = (n + 8L * kBlock - 1) / (8L * kBlock);
+  return (int)(nb < 1 ? 1 : (nb > 1024 ? 1024 : nb));
+}
+// Gershgorin partials of a batched statistics launch, after the statistics'
+constexpr long kGershPartials = 6 * 1024;
+
+// One op's share of the batched statistics launch (read by the kernel from
+// device memory): blocks [blk0, blk0 + nb_s) reduce its field statistics with
+// ctl[0]'s ticket, the next nb_g (0: Gershgorin bound already known) its
+// Gershgorin bound with ctl[1]'s, each exactly as the op's own launch would.
+struct BoundJob {
+  FieldView f;
+  double hx, hy;
+  double* partials;
+  Ctl* ctl;
+  int blk0, nb_s, nb_g, pad;
+};
+static_assert(sizeof(BoundJob) <= 128, "job size");
+// jobs[n] and blk0[n + 1] (prefix of nb_s + nb_g, blk0[n] = all blocks) in
+// device memory; feats[9 i ..] and gmin[i] receive job i's results.  Resets
+// the jobs' ctl[0] and ctl[1] first.
+hipError_t launch_bound_stats_many(const BoundJob* jobs, const int* blk0, int n, int nblocks, double dt,
+                                   float* feats, double* gmin, hipStream_t st);
 hipError_t launch_field_stats(const FieldView& f, double hx, double hy, double dt, float* feats,
                               double* partials, Ctl* ctl, hipStream_t st);
 hipError_t launch_mlp_forward(const float* W, const float* X, float* Y, float* cache, int B,

@@ -9,7 +9,7 @@
 // in LDS); the backward kernel runs in a single block and walks the batch in
 // chunks so that every parameter gradient is a fixed-order sum over samples
 // (bitwise reproducible, no atomics).
-#include "device.h"
+#include "bounds.h"
 
 namespace adl {
 
@@ -203,53 +203,12 @@ template <typename TF, bool ADVF>
 __global__ __launch_bounds__(kBlock) void field_stats_kernel(FieldView F, double hx, double hy, double dt,
                                                              float* __restrict__ feats, double* partials,
                                                              Ctl* ctl) {
-  const TF* kxx = reinterpret_cast<const TF*>(F.kxx);
-  const TF* kxy = reinterpret_cast<const TF*>(F.kxy);
-  const TF* kyy = reinterpret_cast<const TF*>(F.kyy);
-  const TF* fax = reinterpret_cast<const TF*>(F.ax);
-  const TF* fay = reinterpret_cast<const TF*>(F.ay);
-  const double sxx = hx * hx, syy = hy * hy, sxy = 4.0 * hx * hy, sax = 2.0 * hx, say = 2.0 * hy;
-  const long n = (long)F.nx * F.ny;
-  // sums: kpar, kperp', |a|; maxima: kpar, kperp', |a|
-  double acc[6] = {0.0, 0.0, 0.0, -INFINITY, -INFINITY, -INFINITY};
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double dxx = (double)kxx[i] * sxx, dyy = (double)kyy[i] * syy, dxy = (double)kxy[i] * sxy;
-    const double m = 0.5 * (dxx + dyy);
-    const double r = sqrt(0.25 * (dxx - dyy) * (dxx - dyy) + dxy * dxy);
-    const double kp = m + r;
-    const double kq = fmax(m - r, 0.0) + 1e-30;
-    double ax = F.axc * sax, ay = F.ayc * say;
-    if constexpr (ADVF) {
-      ax = (double)fax[i] * sax;
-      ay = (double)fay[i] * say;
-    }
-    const double am = sqrt(ax * ax + ay * ay);
-    acc[0] += kp;
-    acc[1] += kq;
-    acc[2] += am;
-    acc[3] = nanmax(acc[3], kp);
-    acc[4] = nanmax(acc[4], kq);
-    acc[5] = nanmax(acc[5], am);
-  }
-  const double nn = (double)n;
-  grid_reduce<6, 3>(acc, partials, ctl, [=](const double (&tot)[6]) {
-    feats[0] = (float)log10(fmax(tot[3], 1e-30));
-    feats[1] = (float)log10(fmax(tot[0] / nn, 1e-30));
-    feats[2] = (float)log10(tot[4]);
-    feats[3] = (float)log10(tot[1] / nn);
-    feats[4] = (float)tot[5];
-    feats[5] = (float)(tot[2] / nn);
-    feats[6] = (float)log10(hx);
-    feats[7] = (float)log10(hy);
-    feats[8] = (float)log10(dt);
-  });
+  field_stats_blocks<TF, ADVF>(F, hx, hy, dt, feats, partials, ctl, (int)gridDim.x, (int)blockIdx.x);
 }
 
 hipError_t launch_field_stats(const FieldView& f, double hx, double hy, double dt, float* feats, double* partials,
                               Ctl* ctl, hipStream_t st) {
-  const long n = (long)f.nx * f.ny;
-  long nb = (n + kBlock - 1) / kBlock;
-  if (nb > 1024) nb = 1024;
+  const int nb = stats_blocks((long)f.nx * f.ny);
   const bool advf = f.ax != nullptr;
   if (f.f32) {
     if (advf)
@@ -262,6 +221,62 @@ hipError_t launch_field_stats(const FieldView& f, double hx, double hy, double d
     else
       hipLaunchKernelGGL((field_stats_kernel<double, false>), dim3(nb), dim3(kBlock), 0, st, f, hx, hy, dt, feats, partials, ctl);
   }
+  return hipGetLastError();
+}
+
+// Batched statistics: every job's ctl[0] and ctl[1] cleared, one thread per job.
+__global__ __launch_bounds__(kBlock) void bound_jobs_reset_kernel(const BoundJob* __restrict__ jobs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    Ctl* c = jobs[i].ctl;
+    const Ctl z{};
+    c[0] = z;
+    c[1] = z;
+  }
+}
+
+// Block b finds its job (the one i with blk0[i] <= b < blk0[i + 1]; blk0 is
+// strictly increasing from 0 and the grid has blk0[n] blocks, so exactly one
+// thread finds it) and runs that job's statistics or Gershgorin block.
+__global__ __launch_bounds__(kBlock) void bound_stats_many_kernel(const BoundJob* __restrict__ jobs,
+                                                                  const int* __restrict__ blk0, int n, double dt,
+                                                                  float* __restrict__ feats, double* gmin) {
+  __shared__ int s_job;
+  const int b = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (blk0[i] <= b && b < blk0[i + 1]) s_job = i;
+  __syncthreads();
+  const int i = s_job;
+  const BoundJob J = jobs[i];
+  const int lb = b - J.blk0;
+  const bool advf = J.f.ax != nullptr;
+  if (lb < J.nb_s) {
+    float* fo = feats + 9L * i;
+    if (J.f.f32) {
+      if (advf) field_stats_blocks<float, true>(J.f, J.hx, J.hy, dt, fo, J.partials, J.ctl, J.nb_s, lb);
+      else field_stats_blocks<float, false>(J.f, J.hx, J.hy, dt, fo, J.partials, J.ctl, J.nb_s, lb);
+    } else {
+      if (advf) field_stats_blocks<double, true>(J.f, J.hx, J.hy, dt, fo, J.partials, J.ctl, J.nb_s, lb);
+      else field_stats_blocks<double, false>(J.f, J.hx, J.hy, dt, fo, J.partials, J.ctl, J.nb_s, lb);
+    }
+  } else {
+    double* pg = J.partials + kGershPartials;
+    const int gb = lb - J.nb_s;
+    if (J.f.f32) {
+      if (advf) gershgorin_blocks<float, true>(J.f, pg, J.ctl + 1, J.nb_g, gb, gmin + i);
+      else gershgorin_blocks<float, false>(J.f, pg, J.ctl + 1, J.nb_g, gb, gmin + i);
+    } else {
+      if (advf) gershgorin_blocks<double, true>(J.f, pg, J.ctl + 1, J.nb_g, gb, gmin + i);
+      else gershgorin_blocks<double, false>(J.f, pg, J.ctl + 1, J.nb_g, gb, gmin + i);
+    }
+  }
+}
+
+hipError_t launch_bound_stats_many(const BoundJob* jobs, const int* blk0, int n, int nblocks, double dt,
+                                   float* feats, double* gmin, hipStream_t st) {
+  if (n < 1 || nblocks < n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bound_jobs_reset_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, jobs, n);
+  hipLaunchKernelGGL(bound_stats_many_kernel, dim3(nblocks), dim3(kBlock), 0, st, jobs, blk0, n, dt, feats, gmin);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@
 // chunk) sums them in index order and records the decision; worker waves only
 // read the stop flag (no agent-scope fence; a kernel boundary makes the
 // partials visible).  Results are bitwise reproducible for a given tiling.
+#include "bounds.h"
 #include "staged.h"
 
 #include <hip/hip_ext.h>
@@ -678,52 +679,7 @@ __global__ __launch_bounds__(kBlock) void power_init_kernel(long n, uint64_t see
 // Gershgorin: min over rows of A_ii - sum_{j != i} |A_ij| (one thread per node).
 template <typename TF, bool ADVF>
 __global__ __launch_bounds__(kBlock) void gershgorin_kernel(FieldView F, double* partials, Ctl* ctl) {
-  const int nx = F.nx, ny = F.ny;
-  const bool per = F.bc == BC_PERIODIC;
-  const TF* kxx = reinterpret_cast<const TF*>(F.kxx);
-  const TF* kxy = reinterpret_cast<const TF*>(F.kxy);
-  const TF* kyy = reinterpret_cast<const TF*>(F.kyy);
-  const TF* fax = reinterpret_cast<const TF*>(F.ax);
-  const TF* fay = reinterpret_cast<const TF*>(F.ay);
-  double acc[1] = {INFINITY};
-  const long n = (long)nx * ny;
-  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
-    const int j = (int)(idx / nx), i = (int)(idx - (long)j * nx);
-    const bool hasE = per || i + 1 < nx, hasW = per || i > 0;
-    const bool hasN = per || j + 1 < ny, hasS = per || j > 0;
-    const int iE = i + 1 < nx ? i + 1 : (per ? 0 : i);
-    const int iW = i > 0 ? i - 1 : (per ? nx - 1 : i);
-    const int jN = j + 1 < ny ? j + 1 : (per ? 0 : j);
-    const int jS = j > 0 ? j - 1 : (per ? ny - 1 : j);
-    auto at = [&](const TF* a, int jj, int ii) { return (double)a[(long)jj * nx + ii]; };
-    const double kC = at(kxx, j, i), kE = at(kxx, j, iE), kW = at(kxx, j, iW);
-    const double gC = at(kyy, j, i), gN = at(kyy, jN, i), gS = at(kyy, jS, i);
-    const double mE = hasE ? at(kxy, j, iE) : 0.0, mW = hasW ? at(kxy, j, iW) : 0.0;
-    const double mN = hasN ? at(kxy, jN, i) : 0.0, mS = hasS ? at(kxy, jS, i) : 0.0;
-    double aE = F.axc, aW = F.axc, aN = F.ayc, aS = F.ayc;
-    if constexpr (ADVF) {
-      aE = hasE ? at(fax, j, iE) : 0.0;
-      aW = hasW ? at(fax, j, iW) : 0.0;
-      aN = hasN ? at(fay, jN, i) : 0.0;
-      aS = hasS ? at(fay, jS, i) : 0.0;
-    }
-    const double fe = 0.5 * (kC + kE), fw = 0.5 * (kC + kW), fn = 0.5 * (gC + gN), fs = 0.5 * (gC + gS);
-    const double cen = -(fe + fw + fn + fs);
-    double rad = 0.0;
-    if (hasE) rad += fabs(fe + aE);
-    if (hasW) rad += fabs(fw - aW);
-    if (hasN) rad += fabs(fn + aN);
-    if (hasS) rad += fabs(fs - aS);
-    if (hasE && hasN) rad += fabs(mE + mN);
-    if (hasW && hasN) rad += fabs(mW + mN);
-    if (hasE && hasS) rad += fabs(mE + mS);
-    if (hasW && hasS) rad += fabs(mW + mS);
-    const double v = cen - rad;
-    acc[0] = -nanmax(-acc[0], -v);
-  }
-  // reduce as a NaN-propagating max of -value
-  acc[0] = -acc[0];
-  grid_reduce<1, 0>(acc, partials, ctl, [=](const double (&tot)[1]) { ctl->gmin = -tot[0]; });
+  gershgorin_blocks<TF, ADVF>(F, partials, ctl, (int)gridDim.x, (int)blockIdx.x, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -955,8 +911,7 @@ hipError_t launch_power_step(const FieldView& f, const Tiling& t, const PowerArg
 }
 
 hipError_t launch_gershgorin(const FieldView& f, double* partials, Ctl* ctl, hipStream_t st) {
-  const long n = (long)f.nx * f.ny;
-  const int nb = ew_blocks(n) < 1024 ? ew_blocks(n) : 1024;
+  const int nb = stats_blocks((long)f.nx * f.ny);
   const bool advf = f.ax != nullptr;
   if (f.f32) {
     if (advf) hipLaunchKernelGGL((gershgorin_kernel<float, true>), dim3(nb), dim3(kBlock), 0, st, f, partials, ctl);

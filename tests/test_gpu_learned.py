@@ -136,3 +136,45 @@ def test_learned_bound_gain_and_accuracy():
     print("learned bound %.2f ms vs power iteration %.2f ms (%d matvecs); step matvecs %d vs %d; "
           "errors %.2e vs %.2e; fallback %d"
           % (1e3 * t_learned, 1e3 * t_power, its, sL["matvecs"], sP["matvecs"], eL, eP, sL["fallback"]))
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+@pytest.mark.parametrize("through_batch", [False, True])
+def test_learned_bound_many_matches_one_at_a_time(through_batch):
+    """The many-op bound (one readback, one forward pass over every op's
+    features) installs exactly what the one-op call installs, op by op: the
+    same statistics, network output, interval and Leja budget, hence
+    identical steps.  A second call (Gershgorin bound then cached) repeats it;
+    too small a scratch and an op listed twice are refused.  Without a batch the ops mix FP64 and
+    FP32 field storage; a batch holds one storage mode."""
+    from paper_2307_12276_amd import learned
+    Wd = f32(learned.load())
+    samples = [W.learned_sample(90_000 + i, sizes=(64, 96, 128)) for i in range(7)]
+    dt = float(np.median([d["dt"] for d in samples]))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    storage = lambda i: A.STORAGE_FP32_FIELDS if through_batch or i % 2 else A.STORAGE_FP64
+    mk = lambda d, i: A.Op(t(d["Dxx"]), t(d["Dxy"]), t(d["Dyy"]), d["hx"], d["hy"], d["bc"], storage(i),
+                           ax_c=d["ax_c"], ay_c=d["ay_c"])
+    ones = [mk(d, i) for i, d in enumerate(samples)]
+    many = [mk(d, i) for i, d in enumerate(samples)]
+    scratch1 = torch.empty(32, dtype=torch.float32, device=DEV)
+    info1 = [op.learned_bound(dt, Wd, scratch1) for op in ones]
+    batch = A.Batch(many) if through_batch else None
+    call = batch.learned_bound if through_batch else (lambda *a: A.learned_bound_many(many, *a))
+    with pytest.raises(A.AdlError):
+        call(dt, Wd, torch.empty(72 * len(many) - 1, dtype=torch.float32, device=DEV))
+    scratch = torch.empty(72 * len(many), dtype=torch.float32, device=DEV)
+    with pytest.raises(A.AdlError, match="twice"):
+        A.learned_bound_many([many[0], many[1], many[0]], dt, Wd, scratch)
+    for _ in range(2):
+        infoN = call(dt, Wd, scratch)
+        assert infoN == info1
+    for i, (d, a, b) in enumerate(zip(samples, ones, many)):
+        u0 = W.random_vector((d["ny"], d["nx"]), 7 + i)
+        ua, ub = t(u0), t(u0)
+        sa = a.midpoint_step(ua, None, dt, 1e-9)
+        sb = b.midpoint_step(ub, None, dt, 1e-9)
+        assert sa == sb, (i, sa, sb)
+        assert torch.equal(ua, ub), i
+    if batch is not None:
+        batch.close()
