@@ -145,10 +145,14 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
  * default) computes terms k+1 and k+2 in one launch, keeping y_{k+1} on chip
  * (read y_k, the fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2}), with
  * the input rows staged in LDS on grids of at least 2^20 points and one-row
- * frames in registers on smaller ones; mode = 2 and mode = 3
- * force the LDS-staged and the register-frame form; mode = 0 launches one
- * kernel per term.  Results agree to rounding (the block partial sums of the
- * norms are grouped differently).  ADL_EINVAL for other values. */
+ * frames in registers on smaller ones, and four terms per launch (mode 4's
+ * form) on grids of 3 * 2^17 points up to 2^20; mode = 2 and mode = 3
+ * force the LDS-staged and the register-frame form; mode = 4 computes four
+ * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames; p_{k+1}
+ * .. p_{k+4} written), on grids below 2^20 points without non-temporal hints
+ * (ADL_EINVAL otherwise); mode = 0 launches one kernel per term.  Results
+ * agree to rounding (the block partial sums of the norms are grouped
+ * differently).  ADL_EINVAL for other values. */
 int adl_op_set_term_fusion(adl_op* op, int mode);
 
 /* Cache hints of the Newton-Leja launches: mode = 1 marks the vectors a

@@ -195,7 +195,16 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
   size_t kxx, kxy, kyy, ax, ay, y0, y1, p, p2, p3, p4, w1, w2, yacc, tmp, tmp2, partials, ctl, total;
+  size_t p58;  // p5 .. p8 (four-term launches), or kNone
 };
+constexpr size_t kNone = ~(size_t)0;
+// four Newton terms per launch on grids below this many points (each launch
+// then needs eight p buffers; the grid's vectors stay in the caches) ...
+constexpr long kFourTermMaxPoints = 1L << 20;
+// ... and by default from this many up: measured on MI355X (FP64, steps/s of
+// the two-stage quadrature, two terms per launch -> four): 512^2 and 576^2
+// -9 %, 640^2 +22 %, 704^2 +19 %, 768^2 +27 %, 896^2 +29 %, 1000^2 +7 %
+constexpr long kFourTermMinPoints = 3L << 17;
 
 static size_t max_partial_blocks(int nx, int ny) {
   // stencil launches: at most max(kMaxGrid, number of strips) blocks (one
@@ -235,6 +244,7 @@ static WsLayout ws_layout(int nx, int ny, int storage) {
   L.p2 = take(n * 8);
   L.p3 = take(n * 8);
   L.p4 = take(n * 8);
+  L.p58 = (long)n < kFourTermMaxPoints ? take(4 * align_up(n * 8)) : kNone;
   L.partials = take(2 * 6 * max_partial_blocks(nx, ny) * 8);
   L.ctl = take(4 * 128);
   L.total = o;
@@ -402,6 +412,14 @@ static int streaming_on(const adl_op* op) {
   return per_pt * (double)op->n > kStreamMinBytes ? 1 : 0;
 }
 
+// Whether the op can run four Newton terms per launch: its workspace has the
+// eight p buffers, a launch's 12 partial rows fit a partials slot, and the
+// sweep runs without non-temporal hints (the four-term kernel has none).
+static bool four_terms_ok(const adl_op* op) {
+  const long nb = std::max(op->t4.nblocks, op->t41.nblocks);
+  return op->p5 && 12L * nb <= op->slot_stride && !streaming_on(op);
+}
+
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
 //
@@ -422,7 +440,12 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
   const Tiling& T = tiling_for(op, v, p_out);
   const Tiling& T2 = T.vec == op->t2.vec ? op->t2 : op->t21;
+  const Tiling& T4 = T.vec == op->t4.vec ? op->t4 : op->t41;
   const bool fuse = op->fuse_terms != 0;
+  const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n >= kFourTermMinPoints &&
+                                               op->n < kFourTermMaxPoints)) &&
+                    four_terms_ok(op);
+  const int S = four ? 4 : 2;  // p buffers per launch (two sets)
   // first chunk: the last degree of this plan plus one (the degree moves by
   // about one from step to step; one launch too many costs its work, one too
   // few a second chunk and host round trip); the first sweep of a plan
@@ -437,25 +460,33 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   std::vector<int> lk, ln;
   auto plan_terms = [&](int kcov) {
     if (kcov == 0) return 1;
-    const bool two = fuse && kcov + 2 <= maxdeg && !(w2 && (P.s[kcov] != 0.0 || P.s[kcov + 1] != 0.0));
+    auto aug = [&](int n) {  // the augmented column enters one of terms kcov+1 .. kcov+n
+      if (!w2) return false;
+      for (int i = 0; i < n; ++i)
+        if (P.s[kcov + i] != 0.0) return true;
+      return false;
+    };
+    if (four && kcov + 4 <= maxdeg && !aug(4)) return 4;
+    const bool two = fuse && kcov + 2 <= maxdeg && !aug(2);
     return two ? 2 : 1;
   };
-  // slot of term j in the four p buffers: pair L mod 2, last term in the second buffer
+  // slot of term j among the 2S p buffers: set L mod 2 of launch L, its last
+  // term in the set's last buffer and the earlier ones just before it
   auto slot_of_term = [&](int j) -> int {
     int kcov = 0, L = 0;
     while (true) {
       const int n = plan_terms(kcov);
-      if (j <= kcov + n) return 2 * (L & 1) + (j == kcov + n ? 1 : 0);
+      if (j <= kcov + n) return S * (L & 1) + (S - 1) - (kcov + n - j);
       kcov += n;
       ++L;
     }
   };
-  double* pbuf[4];
+  double* pbuf[8];
   {
     const int want = slot_of_term(std::max(mexp, 1));
-    double* ws[4] = {op->p, op->p2, op->p3, op->p4};
+    double* ws[8] = {op->p, op->p2, op->p3, op->p4, op->p5, op->p6, op->p7, op->p8};
     int wi = 0;
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < 2 * S; ++s) {
       if (s == want) {
         pbuf[s] = p_out;
       } else {
@@ -506,26 +537,33 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.yin = kcov == 0 ? (const void*)v : op->ybuf[L & 1];
       a.yout = op->ybuf[(L + 1) & 1];
       a.yin_f32 = (kcov > 0) && ys32;
-      a.pin = kcov == 0 ? nullptr : pbuf[2 * ((L + 1) & 1) + 1];
-      a.p = pbuf[2 * (L & 1) + 1];
-      a.pmid = n == 2 ? pbuf[2 * (L & 1)] : nullptr;
+      a.pin = kcov == 0 ? nullptr : pbuf[S * ((L + 1) & 1) + S - 1];
+      a.p = pbuf[S * (L & 1) + S - 1];
+      a.pmid = n >= 2 ? pbuf[S * (L & 1) + S - n] : nullptr;
+      a.pmid2 = n == 4 ? pbuf[S * (L & 1) + S - 3] : nullptr;
+      a.pmid3 = n == 4 ? pbuf[S * (L & 1) + S - 2] : nullptr;
       a.w2 = (kcov == 0 && w2 && P.s[0] != 0.0) ? w2 : nullptr;
       a.w2c = P.s[kcov] * w2scale;
       a.shift = P.shift[kcov];
-      a.shift2 = n == 2 ? P.shift[kcov + 1] : 0.0;
+      a.shift2 = n >= 2 ? P.shift[kcov + 1] : 0.0;
+      a.shift3 = n == 4 ? P.shift[kcov + 2] : 0.0;
+      a.shift4 = n == 4 ? P.shift[kcov + 3] : 0.0;
       a.dk1 = P.d[kcov + 1];
-      a.dk2 = n == 2 ? P.d[kcov + 2] : 0.0;
+      a.dk2 = n >= 2 ? P.d[kcov + 2] : 0.0;
+      a.dk3 = n == 4 ? P.d[kcov + 3] : 0.0;
+      a.dk4 = n == 4 ? P.d[kcov + 4] : 0.0;
       a.slot = L & 1;
       a.nb_prev = prev_nb;
       a.k_prev = prev_k;
       a.nterms_prev = prev_n;
       a.slot_prev = prev_slot;
       a.decide_only = 0;
-      if (n == 2) HIPCHK(launch_leja2_step(op->f, T2, a, st));
+      if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
+      else if (n == 2) HIPCHK(launch_leja2_step(op->f, T2, a, st));
       else HIPCHK(launch_leja_step(op->f, T, a, st));
       lk.push_back(kcov);
       ln.push_back(n);
-      prev_nb = n == 2 ? T2.nblocks : T.nblocks;
+      prev_nb = n == 4 ? T4.nblocks : (n == 2 ? T2.nblocks : T.nblocks);
       prev_k = kcov;
       prev_n = n;
       prev_slot = L & 1;
@@ -791,6 +829,8 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->t1 = make_tiling(nx, ny, 0, 1);
   op->t2 = make_tiling2(nx, ny, 0);
   op->t21 = make_tiling2(nx, ny, 0, 1);
+  op->t4 = make_tiling4(nx, ny);
+  op->t41 = make_tiling4(nx, ny, 1);
   op->ybuf[0] = base + L.y0;
   op->ybuf[1] = base + L.y1;
   op->p = reinterpret_cast<double*>(base + L.p);
@@ -802,6 +842,13 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->p2 = reinterpret_cast<double*>(base + L.p2);
   op->p3 = reinterpret_cast<double*>(base + L.p3);
   op->p4 = reinterpret_cast<double*>(base + L.p4);
+  if (L.p58 != kNone) {
+    const size_t st = align_up((size_t)nx * ny * 8);
+    op->p5 = reinterpret_cast<double*>(base + L.p58);
+    op->p6 = reinterpret_cast<double*>(base + L.p58 + st);
+    op->p7 = reinterpret_cast<double*>(base + L.p58 + 2 * st);
+    op->p8 = reinterpret_cast<double*>(base + L.p58 + 3 * st);
+  }
   op->slot_stride = 6 * (long)max_partial_blocks(nx, ny);
   op->partials = reinterpret_cast<double*>(base + L.partials);
   op->ctl = reinterpret_cast<Ctl*>(base + L.ctl);
@@ -887,12 +934,16 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
   op->t1 = make_tiling(op->nx, op->ny, rows, 1);
   op->t2 = make_tiling2(op->nx, op->ny, rows, cols_per_lane);
   op->t21 = make_tiling2(op->nx, op->ny, rows, 1);
+  op->t4 = make_tiling4(op->nx, op->ny, cols_per_lane);
+  op->t41 = make_tiling4(op->nx, op->ny, 1);
   return ADL_OK;
 }
 
 int adl_op_set_term_fusion(adl_op* op, int mode) {
   RETCHK(check_op(op));
-  if (mode < 0 || mode > 3) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2 or 3");
+  if (mode < 0 || mode > 4) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2, 3 or 4");
+  if (mode == 4 && !four_terms_ok(op))
+    return fail(ADL_EINVAL, "four terms per launch need a grid below 2^20 points and no non-temporal hints");
   op->fuse_terms = mode;
   return ADL_OK;
 }

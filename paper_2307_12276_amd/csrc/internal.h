@@ -109,7 +109,7 @@ struct LejaArgs {
   void* yout;        // y of the launch's last term
   const double* pin; // p_k (k >= 1; FP64)
   double* p;         // p of the launch's last term (a different buffer from pin)
-  double* pmid;      // two-term launch: p_{k+1}
+  double* pmid;      // two-term launch: p_{k+1}; four-term launch: p_{k+1}
   const double* w2;  // augmented column (first term only), or null
   double w2c;        // s_0 / h
   double shift;      // c + gamma xi_k   (term k+1)
@@ -138,12 +138,24 @@ struct LejaArgs {
   int hseq;          // ... with this sequence number
   hipEvent_t ev_start;  // optional: dispatch-attached timing events
   hipEvent_t ev_stop;
+  // four-term launch: terms k+3 and k+4, and p_{k+2}, p_{k+3} (at the end:
+  // fields inserted further up move the arguments the other kernels read,
+  // which cost the two-term register-frame launch 10 % at 2048^2)
+  double shift3, shift4;
+  double dk3, dk4;
+  double* pmid2;
+  double* pmid3;
 };
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // two-term launch (terms k+1, k+2; k >= 1) on the two-term tiling
 hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // tiling of the two-term kernel: strips of 62*vec output columns, bands of kWavesY*rows rows
 Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint = 0);
+// four-term launch (terms k+1 .. k+4; k >= 1) on the four-term tiling; the
+// launch's block partials take 12 x nblocks values of its slot
+hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
+// tiling of the four-term kernel: strips of 56*vec output columns, 8 output rows per block
+Tiling make_tiling4(int nx, int ny, int vec_hint = 0);
 
 // power iteration launch k: w = A(x) / ||x||, stopping test of iteration k
 struct PowerArgs {

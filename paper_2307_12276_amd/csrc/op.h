@@ -47,7 +47,10 @@ struct adl_op {
   Tiling t1{};  // one column per lane: used when a caller's vector is not 16-byte aligned
   Tiling t2{};  // two-term Newton-Leja kernel (two columns per lane when nx is even)
   Tiling t21{}; // two-term kernel, one column per lane
-  int fuse_terms = 1;  // 0 one Newton term per launch, 1 two (kernel by tiling), 2 two (LDS-staged), 3 two (frames)
+  Tiling t4{};  // four-term Newton-Leja kernel (two columns per lane when nx is even)
+  Tiling t41{}; // four-term kernel, one column per lane
+  int fuse_terms = 1;  // 0 one Newton term per launch, 1 two (kernel by tiling), 2 two (LDS-staged), 3 two (frames),
+                       // 4 four (grids below 2^20 points)
   int streaming = -1;  // non-temporal hints on Newton vectors: -1 auto, 0 off, 1 on
   int nx = 0, ny = 0, bc = 0, storage = 0;
   double hx = 0, hy = 0;
@@ -76,6 +79,10 @@ struct adl_op {
   double* p2 = nullptr;     // Newton polynomial buffers of a sweep (with the caller's p_out)
   double* p3 = nullptr;
   double* p4 = nullptr;
+  double* p5 = nullptr;     // four-term launches (grids below 2^20 points only): four more
+  double* p6 = nullptr;
+  double* p7 = nullptr;
+  double* p8 = nullptr;
   long slot_stride = 0;     // doubles per partials slot
   double* partials = nullptr;
   Ctl* ctl = nullptr;

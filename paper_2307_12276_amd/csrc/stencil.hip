@@ -225,34 +225,43 @@ __device__ __forceinline__ void leja_decide(const LejaArgs& A) {
   // load and the partial loads are in flight together
   const double* part = A.partials + (long)A.slot_prev * A.slot_stride;
   const int nb = A.nb_prev;
-  const bool two = A.nterms_prev == 2;
-  // tn2 / pn2 of the first and second term (sums), max(|y0|, |w2|), flag (max)
-  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int nt = A.nterms_prev;
+  // tn2 / pn2 of terms 1 .. 4 of the decided launch (sums; term t's partials
+  // at rows 3t, 3t + 1), max(|y0|, |w2|) (row 2), flag (max)
+  double v[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (threadIdx.x == 0)
-    v[5] = (double)__hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v[9] = (double)__hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   bool any = false;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
     v[0] += part[i];
     v[1] += part[(long)nb + i];
     const double m = part[2L * nb + i];
-    v[4] = any ? nanmax(v[4], m) : m;
-    if (two) {
+    v[8] = any ? nanmax(v[8], m) : m;
+    if (nt >= 2) {
       v[2] += part[3L * nb + i];
       v[3] += part[4L * nb + i];
     }
+    if (nt >= 3) {
+      v[4] += part[6L * nb + i];
+      v[5] += part[7L * nb + i];
+    }
+    if (nt >= 4) {
+      v[6] += part[9L * nb + i];
+      v[7] += part[10L * nb + i];
+    }
     any = true;
   }
-  block_allreduce<6, 4>(v);
-  if (v[5] != 0.0) return;  // decided by an earlier launch
+  block_allreduce<10, 8>(v);
+  if (v[9] != 0.0) return;  // decided by an earlier launch
   int stop = 0, status = 0, degree = A.k_prev + A.nterms_prev;
   double tn2 = 0.0, pn2 = 0.0;
-  for (int t = 0; t < A.nterms_prev && !stop; ++t) {
-    tn2 = t ? v[2] : v[0];
-    pn2 = t ? v[3] : v[1];
+  for (int t = 0; t < nt && !stop; ++t) {
+    tn2 = v[2 * t];
+    pn2 = v[2 * t + 1];
     const int deg = A.k_prev + t + 1;
     if (!isfinite(tn2) || !isfinite(pn2)) {
       stop = 1; status = 2; degree = deg;
-    } else if (deg == 1 && v[4] == 0.0) {
+    } else if (deg == 1 && v[8] == 0.0) {
       stop = 1; status = 1; degree = 0;
     } else if (tn2 <= A.tol2 * pn2) {
       stop = 1; status = 1; degree = deg;
@@ -541,6 +550,182 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Four Newton-Leja terms per launch (k >= 1), for grids of up to 2^20 points:
+// there a two-term launch is mostly fixed cost (measured on MI355X, FP64:
+// 5.8 us at 256^2, 8.5 us at 512^2, 16 us at 768^2), which four terms share
+// out twice as far.  A block owns kR4 output rows of a strip of 56*VEC
+// output columns (lanes 4..59 of a wave strip that starts 4*VEC columns to
+// the left).  Stage 1 computes y_{k+1} on the kQ4 = kR4 + 6 rows around them
+// from memory into an LDS ring; stage t = 2, 3 computes y_{k+t} on two rows
+// fewer from the other ring (x-neighbours by the DPP shifts, so each stage
+// leaves one more lane per side invalid: the four frame lanes); stage 4
+// computes y_{k+4} on the output rows.  The field rows are read again at each
+// stage (cache hits on these grids).  Each wave keeps p of its two output
+// rows in registers and updates it after every stage:
+// p_{k+t} = p_{k+t-1} + d_{k+t} y_{k+t}, written for t = 1, 2, 3 (one of them
+// is the result if the sweep stops there) and 4, with y_{k+4}.  Rows and
+// columns outside a Dirichlet grid hold zero at every stage; periodic ones are
+// computed from wrapped field rows.  Stages read y from LDS rounded to the y
+// storage type, as a one-term launch reads it back from memory; p and the
+// norms use it unrounded.
+// ---------------------------------------------------------------------------
+#ifndef ADL_WAVES4
+#define ADL_WAVES4 4
+#endif
+constexpr int kT4 = 4;                    // terms per launch
+constexpr int kR4 = 8;                    // output rows per block
+constexpr int kQ4 = kR4 + 2 * (kT4 - 1);  // stage-1 rows per block
+constexpr int kRing4 = 16;                // rows of each LDS ring
+constexpr int kW4 = ADL_WAVES4;           // waves per block
+constexpr int kOW4 = (kR4 + kW4 - 1) / kW4;  // output rows per wave
+static_assert(kQ4 <= kRing4, "ring rows");
+
+// y_{k+t} (t >= 2) at grid row r (ring row q) from ring `in` holding y_{k+t-1}
+// (rows q-1, q, q+1), written to ring `out`: (A y - shift y) / gamma, or zero
+// outside a Dirichlet grid; returns y_{k+t} (unrounded) in yt
+template <typename TF, typename TY, int VEC, bool ADVF>
+__device__ __forceinline__ void stage_from_ring(const FieldView& F, const Strip& g, const double* in, double* out,
+                                                int q, int r, double shift, double invg, double (&yt)[VEC]) {
+  const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
+  const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
+  const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
+  const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
+  const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
+  RowN<VEC> u[3], m[3], k, ac;
+  RowC<VEC> gg[3], ay[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    row_c<TF, VEC, MODE_EDGE>(kyy, r - 1 + t, F, g, gg[t]);
+    row_n<TF, VEC, MODE_ZERO>(kxy, r - 1 + t, F, g, m[t]);
+    if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, r - 1 + t, F, g, ay[t]);
+  }
+  row_n<TF, VEC, MODE_EDGE>(kxx, r, F, g, k);
+  if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, r, F, g, ac);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(in, q - 1 + t, u[t]);
+  double Ax[VEC];
+  stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc,
+                           F.ayc, Ax);
+  const bool ghost = F.bc != BC_PERIODIC && (!g.inside || r < 0 || r >= F.ny);
+  double* row = out ? out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC : nullptr;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    yt[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
+    if (out) row[v] = yt[v];
+  }
+}
+
+template <typename TF, typename TY, int VEC, bool ADVF>
+__global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling T, LejaArgs A) {
+  extern __shared__ double lds[];
+  if (A.decide_only || blockIdx.x == 0) {
+    leja_decide(A);
+    return;
+  }
+  if (block_stopped(A.ctl)) return;  // uniform over the block
+  const int b = blockIdx.x - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int W = kWave * VEC;
+  double* ringA = lds;
+  double* ringB = lds + kRing4 * W;
+  const TY* __restrict__ yin = reinterpret_cast<const TY*>(A.yin);
+  TY* __restrict__ yout = reinterpret_cast<TY*>(A.yout);
+  const int cb = b % T.ncb;
+  const int J0 = (b / T.ncb) * kR4;      // first output row
+  const int r0 = J0 - (kT4 - 1);          // grid row of ring row 0
+  const Strip g = strip_at<VEC>(F, cb * (kWave - 2 * kT4) * VEC - kT4 * VEC);
+  const bool own = lane >= kT4 && lane < kWave - kT4 && g.inside;
+  // the wave's output rows o = wave + h kW4 < kR4 (ring rows o + 3)
+  int jo[kOW4];
+  bool ho[kOW4];
+  double pk[kOW4][VEC];
+#pragma unroll
+  for (int h = 0; h < kOW4; ++h) {
+    jo[h] = J0 + wave + h * kW4;
+    ho[h] = own && wave + h * kW4 < kR4 && jo[h] < F.ny;
+    if (ho[h]) ldr_s<false, double, VEC>(A.pin + (long)jo[h] * F.nx, g.col0, pk[h]);
+  }
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // p_{k+t} of the output rows from y_{k+t} in ring `rg`, stored to dst;
+  // tn / pn accumulate the term's ||d y||^2 and ||p||^2
+  auto update_p = [&](const double* rg, double d, double& tn, double& pn, double* dst) {
+#pragma unroll
+    for (int h = 0; h < kOW4; ++h) {
+      if (ho[h]) {
+        const double* yr = rg + (long)(jo[h] - r0) * W + lane * VEC;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double tv = d * yr[v];
+          pk[h][v] += tv;
+          tn += tv * tv;
+          pn += pk[h][v] * pk[h][v];
+        }
+        str_s<false, double, VEC>(dst + (long)jo[h] * F.nx, g.col0, pk[h]);
+      }
+    }
+  };
+  // stage 1: y_{k+1} on ring rows 0 .. kQ4-1 from memory
+  Stage1Ep<VEC, kRing4> ep1;
+  ep1.lds = ringA;
+  ep1.r0 = r0;
+  ep1.ny = F.ny;
+  ep1.per = F.bc == BC_PERIODIC;
+  ep1.shift = A.shift;
+  ep1.invg = A.invg;
+  ep1.stopflag = 0;
+#pragma unroll 1
+  for (int q = wave; q < kQ4; q += kW4) stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, r0 + q);
+  __syncthreads();
+  update_p(ringA, A.dk1, acc[0], acc[1], A.pmid);
+  // stage 2: ring rows 1 .. kQ4-2, A -> B
+  double yt[VEC];
+#pragma unroll 1
+  for (int q = 1 + wave; q < kQ4 - 1; q += kW4)
+    stage_from_ring<TF, TY, VEC, ADVF>(F, g, ringA, ringB, q, r0 + q, A.shift2, A.invg, yt);
+  __syncthreads();
+  update_p(ringB, A.dk2, acc[2], acc[3], A.pmid2);
+  // stage 3: ring rows 2 .. kQ4-3, B -> A (stage 2 and the p update have
+  // finished reading A at the barrier above)
+#pragma unroll 1
+  for (int q = 2 + wave; q < kQ4 - 2; q += kW4)
+    stage_from_ring<TF, TY, VEC, ADVF>(F, g, ringB, ringA, q, r0 + q, A.shift3, A.invg, yt);
+  __syncthreads();
+  update_p(ringA, A.dk3, acc[4], acc[5], A.pmid3);
+  // stage 4: the wave's own output rows from A, in registers
+#pragma unroll
+  for (int h = 0; h < kOW4; ++h) {
+    if (wave + h * kW4 >= kR4) continue;  // wave-uniform
+    const int q = jo[h] - r0;
+    stage_from_ring<TF, TY, VEC, ADVF>(F, g, ringA, nullptr, q, jo[h], A.shift4, A.invg, yt);
+    if (ho[h]) {
+      const long ro = (long)jo[h] * F.nx;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const double tv = A.dk4 * yt[v];
+        pk[h][v] += tv;
+        acc[6] += tv * tv;
+        acc[7] += pk[h][v] * pk[h][v];
+      }
+      str_s<false, TY, VEC>(yout + ro, g.col0, yt);
+      str_s<false, double, VEC>(A.p + ro, g.col0, pk[h]);
+    }
+  }
+  // block partials: term t at rows 3t (||d y||^2), 3t + 1 (||p||^2), 3t + 2 (0)
+  block_allreduce<8, 8>(acc);
+  if (threadIdx.x == 0) {
+    double* part = A.partials + (long)A.slot * A.slot_stride;
+    const int nb = T.nblocks;
+#pragma unroll
+    for (int t = 0; t < kT4; ++t) {
+      part[(3L * t) * nb + b] = acc[2 * t];
+      part[(3L * t + 1) * nb + b] = acc[2 * t + 1];
+      part[(3L * t + 2) * nb + b] = 0.0;
+    }
+  }
+}
+
 template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 __global__ __launch_bounds__(kTileBlock2) void leja2s_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ double lds[];
@@ -757,6 +942,19 @@ Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint) {
   return t;
 }
 
+Tiling make_tiling4(int nx, int ny, int vec_hint) {
+  Tiling t;
+  const bool two = nx % 2 == 0 && nx >= 2 * kWave;
+  t.vec = (vec_hint == 1 || !two) ? 1 : 2;
+  const int wo = (kWave - 2 * kT4) * t.vec;  // output columns of a strip
+  t.ncb = (nx + wo - 1) / wo;
+  t.rows = kR4;
+  t.nrb = (ny + kR4 - 1) / kR4;
+  t.bands = 1;
+  t.nblocks = t.ncb * t.nrb;
+  return t;
+}
+
 static inline int ew_blocks(long n) {
   long b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
@@ -867,6 +1065,41 @@ template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 static void leja2_any(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
   if (a.staged) leja2s_launch<TF, TY, VEC, ADVF, NT>(f, t, a, st);
   else leja2_launch<TF, TY, VEC, ADVF, NT>(f, t, a, st);
+}
+
+template <typename TF, typename TY, int VEC, bool ADVF>
+static void leja4_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kWave * kW4);
+  const size_t lds = 2 * (size_t)kRing4 * kWave * VEC * sizeof(double);
+  if (a.ev_start)
+    hipExtLaunchKernelGGL((leja4_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
+  else
+    hipLaunchKernelGGL((leja4_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, f, t, a);
+}
+
+hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if (a.first || a.k < 1 || a.nterms != kT4 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || a.stream)
+    return hipErrorInvalidValue;
+  if (t.rows != kR4 || t.bands != 1 || t.nblocks != t.ncb * t.nrb) return hipErrorInvalidValue;
+  if (!a.decide_only) {
+    // p_k is read while the four p outputs are written: all distinct
+    const double* o[5] = {a.pin, a.pmid, a.pmid2, a.pmid3, a.p};
+    for (int i = 0; i < 5; ++i) {
+      if (o[i] == nullptr) return hipErrorInvalidValue;
+      for (int j = 0; j < i; ++j)
+        if (o[i] == o[j]) return hipErrorInvalidValue;
+    }
+  }
+  ADL_DISPATCH_TILE(t, f, {
+    if (f.f32) {
+      if (a.ystore_f32) leja4_launch<float, float, VEC, ADVF>(f, t, a, st);
+      else leja4_launch<float, double, VEC, ADVF>(f, t, a, st);
+    } else {
+      if (a.ystore_f32) leja4_launch<double, float, VEC, ADVF>(f, t, a, st);
+      else leja4_launch<double, double, VEC, ADVF>(f, t, a, st);
+    }
+  });
+  return hipGetLastError();
 }
 
 hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {

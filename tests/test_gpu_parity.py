@@ -280,6 +280,89 @@ def test_two_term_launches_match_one_term_launches(nx, ny, bc, storage):
     assert rel(outs[2], outs[0]) < 1e-13
 
 
+@pytest.mark.parametrize("nx,ny", [(33, 45), (64, 64), (130, 70), (257, 33), (300, 129), (250, 7), (70, 200)])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_four_term_launches_match_one_term_launches(nx, ny, bc, storage):
+    """Four Newton terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row
+    and three-lane frames recomputed) give the one-term result: same degree
+    wherever the sweep stops inside a launch, same polynomial up to the
+    grouping of the norm partial sums; the phi_1 + phi_2 sweep of the
+    augmented form (the first term alone, then four per launch) too."""
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=5 * nx + ny, field_advection=(storage == 0))
+    hx, hy = 1.0 / nx, 0.8 / ny
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, hx, hy, bc, storage)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    v = to_dev(W.random_vector((ny, nx), 13))
+    outs, degs, quads = [], [], []
+    for mode in (0, 4):
+        gop.set_term_fusion(mode)
+        o, d = [], []
+        for mult in (40.0, 300.0, 2000.0):
+            out = torch.empty_like(v)
+            st = gop.leja_phi(1, mult / abs(alpha), v, out, 1e-10)
+            o.append(to_np(out))
+            d.append(st["max_degree"])
+        outs.append(o)
+        degs.append(d)
+        u = v.clone()
+        S = torch.full_like(v, 0.5)
+        qs = gop.quad2_step(u, S, 2.0 * S, 1.0 / 3.0, 2.0 / 3.0, 300.0 / abs(alpha), 1e-10)
+        quads.append((to_np(u), qs["matvecs"]))
+    assert degs[0] == degs[1], degs
+    # each kernel rounds (and fuses) the m terms' updates on its own: the
+    # difference grows with the degree, ~m ulp of the largest partial sum
+    errs = [rel(b, a) for a, b in zip(outs[0], outs[1])]
+    print("degrees %s, four-term vs one-term %s" % (degs[0], ["%.1e" % e for e in errs]))
+    for e, m in zip(errs, degs[0]):
+        assert e < max(1e-13, 4e-15 * m), (e, m)
+    # the quadrature step, with the same rounding bound over its matvecs; a
+    # stage sweep whose stopping estimate lands within rounding of the
+    # tolerance may stop one term apart in the two modes, a difference of the
+    # order of tol |p|
+    eq = rel(quads[1][0], quads[0][0])
+    mq = quads[0][1]
+    print("quad2 step: matvecs %d / %d, four-term vs one-term %.1e" % (mq, quads[1][1], eq))
+    assert eq < (max(1e-13, 4e-15 * mq) if mq == quads[1][1] else 1e-10), eq
+
+
+def test_default_mode_runs_four_terms_on_mid_grids():
+    """From 3 * 2^17 points up to 2^20 the default mode launches four terms
+    at a time (a quarter of the launches of a one-term sweep, give or take
+    the first term and the tail), with the one-term result to rounding."""
+    nx, ny = 704, 600
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=17, field_advection=False)
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, 1.0 / nx, 1.0 / ny, O.DIRICHLET, 0)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    v = to_dev(W.random_vector((ny, nx), 3))
+    res = {}
+    for mode in (0, 1):
+        gop.set_term_fusion(mode)
+        gop.profile(True)
+        out = torch.empty_like(v)
+        st = gop.leja_phi(1, 500.0 / abs(alpha), v, out, 1e-10)
+        _, launches, _ = gop.profile_read()
+        gop.profile(False)
+        res[mode] = (to_np(out), st["max_degree"], launches)
+    m = res[0][1]
+    assert res[1][1] == m
+    assert res[0][2] >= m and res[1][2] <= (m + 2) // 4 + 3, (res[0][2], res[1][2], m)
+    assert rel(res[1][0], res[0][0]) < max(1e-13, 4e-15 * m)
+
+
+def test_four_term_mode_needs_a_small_grid():
+    """Mode 4 is refused where the workspace has no room for its eight p
+    buffers (2^20 points and more)."""
+    nx = ny = 1024
+    z = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    op = A.Op(z + 1.0, z, z + 1.0, 1.0 / nx, 1.0 / ny, A.BC_PERIODIC, A.STORAGE_FP64)
+    with pytest.raises(A.AdlError, match="2\\^20"):
+        op.set_term_fusion(4)
+    op.set_term_fusion(1)
+
+
 @pytest.mark.parametrize("nx,ny", [(64, 64), (130, 70), (257, 33)])
 @pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
 @pytest.mark.parametrize("storage", [0, 2])
