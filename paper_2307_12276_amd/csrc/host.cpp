@@ -201,10 +201,12 @@ constexpr size_t kNone = ~(size_t)0;
 // four Newton terms per launch on grids below this many points (each launch
 // then needs eight p buffers; the grid's vectors stay in the caches) ...
 constexpr long kFourTermMaxPoints = 1L << 20;
-// ... and by default from this many up: measured on MI355X (FP64, steps/s of
-// the two-stage quadrature, two terms per launch -> four): 512^2 and 576^2
-// -9 %, 640^2 +22 %, 704^2 +19 %, 768^2 +27 %, 896^2 +29 %, 1000^2 +7 %
+// ... and by default on grids of kFourTermMinPoints up to kFourTermAutoMax:
+// measured on MI355X (FP64, steps/s of the two-stage quadrature, two terms
+// per launch -> four): 512^2 -1 %, 576^2 -2 %, 640^2 +31 %, 704^2 +11 %,
+// 768^2 +18 %, 896^2 +19 %, 1000^2 -1 %
 constexpr long kFourTermMinPoints = 3L << 17;
+constexpr long kFourTermAutoMax = 7L << 17;
 
 static size_t max_partial_blocks(int nx, int ny) {
   // stencil launches: at most max(kMaxGrid, number of strips) blocks (one
@@ -443,9 +445,15 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const Tiling& T4 = T.vec == op->t4.vec ? op->t4 : op->t41;
   const bool fuse = op->fuse_terms != 0;
   const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n >= kFourTermMinPoints &&
-                                               op->n < kFourTermMaxPoints)) &&
+                                               op->n < kFourTermAutoMax)) &&
                     four_terms_ok(op);
   const int S = four ? 4 : 2;  // p buffers per launch (two sets)
+  if (four && op->cus <= 0) {
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    op->cus = cus > 0 ? cus : 1;
+  }
   // first chunk: the last degree of this plan plus one (the degree moves by
   // about one from step to step; one launch too many costs its work, one too
   // few a second chunk and host round trip); the first sweep of a plan
@@ -552,6 +560,9 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.dk2 = n >= 2 ? P.d[kcov + 2] : 0.0;
       a.dk3 = n == 4 ? P.d[kcov + 3] : 0.0;
       a.dk4 = n == 4 ? P.d[kcov + 4] : 0.0;
+      // four-term launch: field rows kept in LDS when its blocks fit the chip
+      // at once at two per CU (the LDS they take)
+      a.lds_fields = n == 4 && T4.nblocks <= 2 * op->cus;
       a.slot = L & 1;
       a.nb_prev = prev_nb;
       a.k_prev = prev_k;

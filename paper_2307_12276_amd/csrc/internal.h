@@ -145,6 +145,7 @@ struct LejaArgs {
   double dk3, dk4;
   double* pmid2;
   double* pmid3;
+  int lds_fields;    // four-term launch: stage 1 keeps the field rows in LDS for stages 2-4
 };
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // two-term launch (terms k+1, k+2; k >= 1) on the two-term tiling

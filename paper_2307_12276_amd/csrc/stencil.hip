@@ -560,9 +560,13 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
 // from memory into an LDS ring; stage t = 2, 3 computes y_{k+t} on two rows
 // fewer from the other ring (x-neighbours by the DPP shifts, so each stage
 // leaves one more lane per side invalid: the four frame lanes); stage 4
-// computes y_{k+4} on the output rows.  The field rows are read again at each
-// stage (cache hits on these grids).  Each wave keeps p of its two output
-// rows in registers and updates it after every stage:
+// computes y_{k+4} on the output rows.  Stage 1 also keeps the centre field
+// row of each row it computes in LDS, so that stages 2-4 read no memory
+// (LF; 75 KB of LDS per block in FP64, two blocks per CU), or, when the
+// launch has more blocks than the chip holds at two per CU, the later stages
+// read the field rows again from memory (cache hits on these grids; 32 KB
+// per block).  Each wave keeps p of its output rows in registers and updates
+// it after every stage:
 // p_{k+t} = p_{k+t-1} + d_{k+t} y_{k+t}, written for t = 1, 2, 3 (one of them
 // is the result if the sweep stops there) and 4, with y_{k+4}.  Rows and
 // columns outside a Dirichlet grid hold zero at every stage; periodic ones are
@@ -581,12 +585,121 @@ constexpr int kW4 = ADL_WAVES4;           // waves per block
 constexpr int kOW4 = (kR4 + kW4 - 1) / kW4;  // output rows per wave
 static_assert(kQ4 <= kRing4, "ring rows");
 
+// Field rows kept in LDS for stages 2-4: stage 1 stores the centre row of
+// each field it loads (after the row rule: edge rows for kxx and kyy, zero
+// rows for kxy and the advection fields), kQ4 rows per field; a later stage
+// takes the x-neighbours by DPP and applies the Dirichlet ghost-column
+// selects of the register path (lanes 0 and 63, whose halo element is not
+// kept, are frame lanes by then)
+template <bool ADVF>
+constexpr int kNF4 = ADVF ? 5 : 3;  // kxx, kxy, kyy (, ax', ay')
+template <int VEC>
+__device__ __forceinline__ double* fld_row(double* flds, int f, int q) {
+  return flds + ((long)f * kQ4 + q) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+}
+template <int VEC, int MODE>
+__device__ __forceinline__ void lds_field_n(double* flds, int f, int q, const Strip& g, RowN<VEC>& o) {
+  const double* row = fld_row<VEC>(flds, f, q);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = row[v];
+  const double l = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
+  const double rr = dpp_f64<kDppWaveShl1>(o.c[0]);
+  const double gl = MODE == MODE_EDGE ? o.c[0] : 0.0;
+  const double gr = MODE == MODE_EDGE ? o.c[VEC - 1] : 0.0;
+  o.l = g.ghostL ? gl : l;
+  o.r = g.ghostR ? gr : rr;
+}
+template <int VEC>
+__device__ __forceinline__ void lds_field_c(double* flds, int f, int q, RowC<VEC>& o) {
+  const double* row = fld_row<VEC>(flds, f, q);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = row[v];
+}
+
+// Stage 1 at grid row r (ring row q): y_{k+1} from memory into `out`, as
+// the one-term kernel computes it, and the centre field rows into flds
+template <typename TF, typename TY, int VEC, bool ADVF>
+__device__ __forceinline__ void stage1_row4(const FieldView& F, const TY* __restrict__ yin, const Strip& g,
+                                            double* out, double* flds, int q, int r, double shift, double invg) {
+  const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
+  const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
+  const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
+  const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
+  const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
+  RowN<VEC> u[3], m[3], k, ac;
+  RowC<VEC> gg[3], ay[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    row_n<TY, VEC, MODE_ZERO>(yin, r - 1 + t, F, g, u[t]);
+    row_c<TF, VEC, MODE_EDGE>(kyy, r - 1 + t, F, g, gg[t]);
+    row_n<TF, VEC, MODE_ZERO>(kxy, r - 1 + t, F, g, m[t]);
+    if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, r - 1 + t, F, g, ay[t]);
+  }
+  row_n<TF, VEC, MODE_EDGE>(kxx, r, F, g, k);
+  if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, r, F, g, ac);
+  double Ax[VEC];
+  stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc,
+                           F.ayc, Ax);
+  const bool ghost = F.bc != BC_PERIODIC && (!g.inside || r < 0 || r >= F.ny);
+  double* row = out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+  double* f0 = fld_row<VEC>(flds, 0, q);
+  double* f1 = fld_row<VEC>(flds, 1, q);
+  double* f2 = fld_row<VEC>(flds, 2, q);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    row[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
+    f0[v] = k.c[v];
+    f1[v] = m[1].c[v];
+    f2[v] = gg[1].c[v];
+  }
+  if constexpr (ADVF) {
+    double* f3 = fld_row<VEC>(flds, 3, q);
+    double* f4 = fld_row<VEC>(flds, 4, q);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      f3[v] = ac.c[v];
+      f4[v] = ay[1].c[v];
+    }
+  }
+}
+
 // y_{k+t} (t >= 2) at grid row r (ring row q) from ring `in` holding y_{k+t-1}
-// (rows q-1, q, q+1), written to ring `out`: (A y - shift y) / gamma, or zero
-// outside a Dirichlet grid; returns y_{k+t} (unrounded) in yt
+// (rows q-1, q, q+1) and the field rows in LDS, written to ring `out` (if
+// given): (A y - shift y) / gamma, or zero outside a Dirichlet grid; returns
+// y_{k+t} (unrounded) in yt
 template <typename TF, typename TY, int VEC, bool ADVF>
 __device__ __forceinline__ void stage_from_ring(const FieldView& F, const Strip& g, const double* in, double* out,
-                                                int q, int r, double shift, double invg, double (&yt)[VEC]) {
+                                                double* flds, int q, int r, double shift, double invg,
+                                                double (&yt)[VEC]) {
+  RowN<VEC> u[3], m[3], k, ac;
+  RowC<VEC> gg[3], ay[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    lds_field_c<VEC>(flds, 2, q - 1 + t, gg[t]);
+    lds_field_n<VEC, MODE_ZERO>(flds, 1, q - 1 + t, g, m[t]);
+    if constexpr (ADVF) lds_field_c<VEC>(flds, 4, q - 1 + t, ay[t]);
+    lds_row_n<TY, VEC>(in, q - 1 + t, u[t]);
+  }
+  lds_field_n<VEC, MODE_EDGE>(flds, 0, q, g, k);
+  if constexpr (ADVF) lds_field_n<VEC, MODE_ZERO>(flds, 3, q, g, ac);
+  double Ax[VEC];
+  stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc,
+                           F.ayc, Ax);
+  const bool ghost = F.bc != BC_PERIODIC && (!g.inside || r < 0 || r >= F.ny);
+  double* row = out ? out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC : nullptr;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    yt[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
+    if (out) row[v] = yt[v];
+  }
+}
+
+// The same with the field rows read again from memory (cache hits), for
+// launches whose blocks would not all fit the chip at once with the LDS field
+// rows (two blocks per CU)
+template <typename TF, typename TY, int VEC, bool ADVF>
+__device__ __forceinline__ void stage_from_ring_g(const FieldView& F, const Strip& g, const double* in, double* out,
+                                                  int q, int r, double shift, double invg, double (&yt)[VEC]) {
   const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
   const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
   const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
@@ -616,7 +729,15 @@ __device__ __forceinline__ void stage_from_ring(const FieldView& F, const Strip&
   }
 }
 
-template <typename TF, typename TY, int VEC, bool ADVF>
+// stage t >= 2 from the LDS field rows (LF) or from memory
+template <bool LF, typename TF, typename TY, int VEC, bool ADVF>
+__device__ __forceinline__ void stage_t(const FieldView& F, const Strip& g, const double* in, double* out,
+                                        double* flds, int q, int r, double shift, double invg, double (&yt)[VEC]) {
+  if constexpr (LF) stage_from_ring<TF, TY, VEC, ADVF>(F, g, in, out, flds, q, r, shift, invg, yt);
+  else stage_from_ring_g<TF, TY, VEC, ADVF>(F, g, in, out, q, r, shift, invg, yt);
+}
+
+template <bool LF, typename TF, typename TY, int VEC, bool ADVF>
 __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ double lds[];
   if (A.decide_only || blockIdx.x == 0) {
@@ -630,6 +751,7 @@ __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling 
   const int W = kWave * VEC;
   double* ringA = lds;
   double* ringB = lds + kRing4 * W;
+  double* flds = lds + 2 * kRing4 * W;  // kNF4<ADVF> fields x kQ4 rows
   const TY* __restrict__ yin = reinterpret_cast<const TY*>(A.yin);
   TY* __restrict__ yout = reinterpret_cast<TY*>(A.yout);
   const int cb = b % T.ncb;
@@ -666,31 +788,38 @@ __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling 
       }
     }
   };
-  // stage 1: y_{k+1} on ring rows 0 .. kQ4-1 from memory
-  Stage1Ep<VEC, kRing4> ep1;
-  ep1.lds = ringA;
-  ep1.r0 = r0;
-  ep1.ny = F.ny;
-  ep1.per = F.bc == BC_PERIODIC;
-  ep1.shift = A.shift;
-  ep1.invg = A.invg;
-  ep1.stopflag = 0;
+  // stage 1: y_{k+1} on ring rows 0 .. kQ4-1 from memory (and the field rows
+  // into LDS)
+  if constexpr (LF) {
 #pragma unroll 1
-  for (int q = wave; q < kQ4; q += kW4) stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, r0 + q);
+    for (int q = wave; q < kQ4; q += kW4)
+      stage1_row4<TF, TY, VEC, ADVF>(F, yin, g, ringA, flds, q, r0 + q, A.shift, A.invg);
+  } else {
+    Stage1Ep<VEC, kRing4> ep1;
+    ep1.lds = ringA;
+    ep1.r0 = r0;
+    ep1.ny = F.ny;
+    ep1.per = F.bc == BC_PERIODIC;
+    ep1.shift = A.shift;
+    ep1.invg = A.invg;
+    ep1.stopflag = 0;
+#pragma unroll 1
+    for (int q = wave; q < kQ4; q += kW4) stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, ep1, g, r0 + q);
+  }
   __syncthreads();
   update_p(ringA, A.dk1, acc[0], acc[1], A.pmid);
   // stage 2: ring rows 1 .. kQ4-2, A -> B
   double yt[VEC];
 #pragma unroll 1
   for (int q = 1 + wave; q < kQ4 - 1; q += kW4)
-    stage_from_ring<TF, TY, VEC, ADVF>(F, g, ringA, ringB, q, r0 + q, A.shift2, A.invg, yt);
+    stage_t<LF, TF, TY, VEC, ADVF>(F, g, ringA, ringB, flds, q, r0 + q, A.shift2, A.invg, yt);
   __syncthreads();
   update_p(ringB, A.dk2, acc[2], acc[3], A.pmid2);
   // stage 3: ring rows 2 .. kQ4-3, B -> A (stage 2 and the p update have
   // finished reading A at the barrier above)
 #pragma unroll 1
   for (int q = 2 + wave; q < kQ4 - 2; q += kW4)
-    stage_from_ring<TF, TY, VEC, ADVF>(F, g, ringB, ringA, q, r0 + q, A.shift3, A.invg, yt);
+    stage_t<LF, TF, TY, VEC, ADVF>(F, g, ringB, ringA, flds, q, r0 + q, A.shift3, A.invg, yt);
   __syncthreads();
   update_p(ringA, A.dk3, acc[4], acc[5], A.pmid3);
   // stage 4: the wave's own output rows from A, in registers
@@ -698,7 +827,7 @@ __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling 
   for (int h = 0; h < kOW4; ++h) {
     if (wave + h * kW4 >= kR4) continue;  // wave-uniform
     const int q = jo[h] - r0;
-    stage_from_ring<TF, TY, VEC, ADVF>(F, g, ringA, nullptr, q, jo[h], A.shift4, A.invg, yt);
+    stage_t<LF, TF, TY, VEC, ADVF>(F, g, ringA, nullptr, flds, q, jo[h], A.shift4, A.invg, yt);
     if (ho[h]) {
       const long ro = (long)jo[h] * F.nx;
 #pragma unroll
@@ -1067,14 +1196,20 @@ static void leja2_any(const FieldView& f, const Tiling& t, const LejaArgs& a, hi
   else leja2_launch<TF, TY, VEC, ADVF, NT>(f, t, a, st);
 }
 
+template <bool LF, typename TF, typename TY, int VEC, bool ADVF>
+static void leja4_launch_lf(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kWave * kW4);
+  const size_t lds = (2 * (size_t)kRing4 + (LF ? (size_t)kNF4<ADVF> * kQ4 : 0)) * kWave * VEC * sizeof(double);
+  if (a.ev_start)
+    hipExtLaunchKernelGGL((leja4_kernel<LF, TF, TY, VEC, ADVF>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t,
+                          a);
+  else
+    hipLaunchKernelGGL((leja4_kernel<LF, TF, TY, VEC, ADVF>), grid, blk, lds, st, f, t, a);
+}
 template <typename TF, typename TY, int VEC, bool ADVF>
 static void leja4_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kWave * kW4);
-  const size_t lds = 2 * (size_t)kRing4 * kWave * VEC * sizeof(double);
-  if (a.ev_start)
-    hipExtLaunchKernelGGL((leja4_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
-  else
-    hipLaunchKernelGGL((leja4_kernel<TF, TY, VEC, ADVF>), grid, blk, lds, st, f, t, a);
+  if (a.lds_fields) leja4_launch_lf<true, TF, TY, VEC, ADVF>(f, t, a, st);
+  else leja4_launch_lf<false, TF, TY, VEC, ADVF>(f, t, a, st);
 }
 
 hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
