@@ -152,6 +152,49 @@ def run_roofline_leg(w, storage, mode=1):
     return res
 
 
+def four_term_leg(n=640, steps=30):
+    """The C2-type two-stage quadrature on an n x n Dirichlet circular-field
+    grid (within the four-term default range), with two Newton terms per
+    launch (register frames) and with four: steps/s and the average
+    Newton-Leja launch from HIP events on a second, event-timed pass."""
+    import torch
+    import paper_2307_12276_amd as A
+    import workloads as W
+    w = W.c2_dirichlet_circular(n=n, steps=steps + 3)
+    res = {"workload": "dirichlet-circular-%d: the 512^2 workload's recipe on a %dx%d grid" % (n, n, n),
+           "steps": steps}
+    for mode, key in ((3, "two_terms"), (4, "four_terms")):
+        op = make_op(w, A.STORAGE_FP64)
+        op.spectral_bound(A.BOUND_GERSHGORIN)
+        op.set_term_fusion(mode)
+        srcs = device_sources(w)
+        u = dev_tensor(w.u0)
+        for k in range(3):
+            gpu_step(op, w, u, k, srcs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mv = 0
+        for k in range(3, 3 + steps):
+            mv += gpu_step(op, w, u, k, srcs)["matvecs"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        u = dev_tensor(w.u0)
+        op.profile(True)
+        for k in range(3, 3 + steps):
+            gpu_step(op, w, u, k, srcs)
+        torch.cuda.synchronize()
+        ms, nl, _ = op.profile_read()
+        op.profile(False)
+        res[key] = {"steps_per_s": steps / el, "matvecs_per_step": mv / steps, "avg_launch_us": 1e3 * ms / nl,
+                    "launches": nl}
+        del op
+    res["speedup_four_vs_two"] = res["four_terms"]["steps_per_s"] / res["two_terms"]["steps_per_s"]
+    log("four-term leg %d^2: two terms %.0f steps/s (%.1f us/launch), four terms %.0f steps/s (%.1f us/launch), "
+        "%.2fx" % (n, res["two_terms"]["steps_per_s"], res["two_terms"]["avg_launch_us"],
+                   res["four_terms"]["steps_per_s"], res["four_terms"]["avg_launch_us"], res["speedup_four_vs_two"]))
+    return res
+
+
 def paper_cases_leg(n=256, tol=1e-10):
     """The paper's test problems (Sec. 3, Cases I-IV; workloads.paper_case)
     at n x n, FP64, each with its default step (I: one phi_0 step over the
@@ -533,6 +576,7 @@ def main():
             leg["frac_of_copy"] = leg["achieved_GBs"] / copy_gbs
         out["roofline_4096"] = legs
         out["copy_GBs"] = copy_gbs
+        out["four_term_640"] = four_term_leg()
         out["chosen_vs_plain"] = chosen_vs_plain()
         out["paper_cases"] = paper_cases_leg()
 
