@@ -425,16 +425,18 @@ static bool four_terms_ok(const adl_op* op) {
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
 //
-// Launches: the first term (y_0 = v) alone, then two terms per launch while
-// the op fuses terms (one otherwise, or when one term is left before the
-// degree cap).  Each launch's block 0 takes the stopping decision of the
-// previous launch's terms from its block partials; a one-block launch at the
-// end of every chunk decides the chunk's last launch, and the host reads the
-// control block once per chunk.  p of the terms of launch L goes to the
-// buffer pair L mod 2 (the last term always to the pair's second buffer), so
-// a launch never overwrites a p that the decision it runs beside may pick.
-// The buffers are p_out and three workspace buffers, arranged so that the
-// predicted degree ends in p_out; otherwise the result is copied there.
+// Launches: the first term (y_0 = v) alone, then four terms per launch where
+// the op runs the four-term kernel, else two while the op fuses terms (fewer
+// when the degree cap is near; one per launch without fusion).  Each
+// launch's block 0 takes the stopping decision of the previous launch's terms
+// from its block partials; a one-block launch at the end of every chunk
+// decides the chunk's last launch, and the host reads the outcome once per
+// chunk.  p of the terms of launch L goes to the set L mod 2 of S buffers
+// (S = 4 with four-term launches, else 2; the last term always to the set's
+// last buffer), so a launch never overwrites a p that the decision it runs
+// beside may pick.  The buffers are p_out and 2S - 1 workspace buffers,
+// arranged so that the predicted degree ends in p_out; otherwise the result
+// is copied there.
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
                  double tol, int maxdeg, hipStream_t st, SweepOut& out) {
   if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;

@@ -16,9 +16,10 @@
 // each wave computing one row per load group (tile.h).  Block b takes strip
 // b mod ncb and a run of consecutive row bands, so the rows shared between
 // consecutive bands are re-read from cache soon after their first load.
-// Newton-Leja sweeps run one term (leja_kernel) or two terms per launch: the
-// register-frame kernel (leja2_kernel) on cache-resident grids, the kernel
-// with input rows staged in LDS (leja2s_kernel, staged.h) beyond the caches.
+// Newton-Leja sweeps run one term (leja_kernel), two terms per launch (the
+// register-frame kernel leja2_kernel on cache-resident grids, the kernel with
+// input rows staged in LDS, leja2s_kernel in staged.h, beyond the caches) or
+// four (leja4_kernel, on mid-size grids).
 //
 // Reductions (norms for the Leja stopping test, power iteration) are fixed
 // order: shuffle tree per wave, waves in order, block partials written to
