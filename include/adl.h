@@ -146,7 +146,7 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
  * (read y_k, the fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2}), with
  * the input rows staged in LDS on grids of at least 2^20 points and one-row
  * frames in registers on smaller ones, and four terms per launch (mode 4's
- * form) on grids of 3 * 2^17 up to 7 * 2^17 points; mode = 2 and mode = 3
+ * form) on grids of 5 * 2^16 up to 7 * 2^17 points; mode = 2 and mode = 3
  * force the LDS-staged and the register-frame form; mode = 4 computes four
  * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames; p_{k+1}
  * .. p_{k+4} written), on grids below 2^20 points without non-temporal hints

@@ -203,9 +203,10 @@ constexpr size_t kNone = ~(size_t)0;
 constexpr long kFourTermMaxPoints = 1L << 20;
 // ... and by default on grids of kFourTermMinPoints up to kFourTermAutoMax:
 // measured on MI355X (FP64, steps/s of the two-stage quadrature, two terms
-// per launch -> four): 512^2 -1 %, 576^2 -2 %, 640^2 +31 %, 704^2 +11 %,
-// 768^2 +18 %, 896^2 +19 %, 1000^2 -1 %
-constexpr long kFourTermMinPoints = 3L << 17;
+// per launch -> four, chunks ending on their targets): 512^2 +0.2 to +1 %
+// (left on two terms), 576^2 +4 %, 640^2 +33 %, 768^2 +21 %; before the
+// chunks ended on their targets, 704^2 +11 %, 896^2 +19 %, 1000^2 -1 %
+constexpr long kFourTermMinPoints = 5L << 16;
 constexpr long kFourTermAutoMax = 7L << 17;
 
 static size_t max_partial_blocks(int nx, int ny) {
@@ -468,7 +469,11 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const int mexp = P.last_degree > 0 ? P.last_degree : predicted;
   // launch plan: launch L covers terms kL+1 .. kL+nL
   std::vector<int> lk, ln;
-  auto plan_terms = [&](int kcov) {
+  // terms of the launch after kcov terms in a chunk that ends at `target`:
+  // four-term launches end the chunk on its target (a two- or one-term
+  // launch for the remainder), so that a sweep stopping at the predicted
+  // degree computes no terms past it
+  auto plan_terms = [&](int kcov, int target) {
     if (kcov == 0) return 1;
     auto aug = [&](int n) {  // the augmented column enters one of terms kcov+1 .. kcov+n
       if (!w2) return false;
@@ -476,16 +481,24 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         if (P.s[kcov + i] != 0.0) return true;
       return false;
     };
-    if (four && kcov + 4 <= maxdeg && !aug(4)) return 4;
-    const bool two = fuse && kcov + 2 <= maxdeg && !aug(2);
+    const int lim = four ? std::min(target, maxdeg) : maxdeg;
+    if (four && kcov + 4 <= lim && !aug(4)) return 4;
+    const bool two = fuse && kcov + 2 <= lim && !aug(2);
     return two ? 2 : 1;
+  };
+  // the chunk targets: the first chunk ends at the predicted degree, each
+  // later one max(8, kcov / 4) terms on, capped at the degree limit
+  auto next_target = [&](int kcov) {
+    const int t = kcov == 0 ? predicted : kcov + std::max(8, kcov / 4);
+    return t > maxdeg ? maxdeg : t;
   };
   // slot of term j among the 2S p buffers: set L mod 2 of launch L, its last
   // term in the set's last buffer and the earlier ones just before it
   auto slot_of_term = [&](int j) -> int {
-    int kcov = 0, L = 0;
+    int kcov = 0, L = 0, target = next_target(0);
     while (true) {
-      const int n = plan_terms(kcov);
+      if (kcov >= target) target = next_target(kcov);
+      const int n = plan_terms(kcov, target);
       if (j <= kcov + n) return S * (L & 1) + (S - 1) - (kcov + n - j);
       kcov += n;
       ++L;
@@ -525,11 +538,10 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   int kcov = 0, L = 0;
   int prev_nb = 0, prev_k = 0, prev_n = 0, prev_slot = 0;
   while (true) {
-    int target = kcov == 0 ? predicted : kcov + std::max(8, kcov / 4);
-    if (target > maxdeg) target = maxdeg;
+    const int target = next_target(kcov);
     const int L0 = L;
     while (kcov < target) {
-      const int n = plan_terms(kcov);
+      const int n = plan_terms(kcov, target);
       if (op->prof) {
         while ((int)op->evs.size() < 2 * (L - L0 + 1)) {
           hipEvent_t e;

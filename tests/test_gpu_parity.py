@@ -328,7 +328,7 @@ def test_four_term_launches_match_one_term_launches(nx, ny, bc, storage):
 
 
 def test_default_mode_runs_four_terms_on_mid_grids():
-    """From 3 * 2^17 up to 7 * 2^17 points the default mode launches four terms
+    """From 5 * 2^16 up to 7 * 2^17 points the default mode launches four terms
     at a time (a quarter of the launches of a one-term sweep, give or take
     the first term and the tail), with the one-term result to rounding."""
     nx, ny = 704, 600
