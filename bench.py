@@ -525,14 +525,15 @@ def main():
                    "matvecs_per_step": mv / args.steps, "matvecs_per_s": mv / el, "setup_s": setup_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "leja2_kernel (two Newton terms per launch; the first term of a sweep "
-                               "runs in leja_kernel)", "bytes_per_launch": per_launch,
+                     "kernel": "leja4_kernel (four Newton terms per launch, field rows kept in LDS; the "
+                               "first term of a sweep runs in leja_kernel, a chunk's remainder in "
+                               "leja2_kernel or leja_kernel)", "bytes_per_launch": per_launch,
                      "avg_kernel_us": avg_ms * 1e3, "launches": launches,
                      "timing": "HIP events on each Newton-Leja dispatch, second pass of %d steps "
                                "(%.3fs)" % (args.steps, el_prof),
                      "traffic_source": "profiles/leja_kernel_traffic.txt (rocprofv3 FETCH_SIZE x2.0 + "
                                        "WRITE_SIZE x1.0, calibrated on a 1 GiB copy), bytes per launch",
-                     "note": "512^2 FP64 working set (~15 MB/iteration) stays in L2/MALL"},
+                     "note": "512^2 FP64 working set (~21 MB per four-term launch) stays in L2/MALL"},
     }
 
     if not args.no_cpu:

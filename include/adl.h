@@ -142,11 +142,12 @@ int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, doub
 int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
 
 /* Newton terms per launch of a sweep (Sec. 2 recurrence): mode = 1 (the
- * default) computes terms k+1 and k+2 in one launch, keeping y_{k+1} on chip
- * (read y_k, the fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2}), with
- * the input rows staged in LDS on grids of at least 2^20 points and one-row
- * frames in registers on smaller ones, and four terms per launch (mode 4's
- * form) on grids of 5 * 2^16 up to 7 * 2^17 points; mode = 2 and mode = 3
+ * default) computes four terms per launch on grids below 2^20 points
+ * (mode 4's form, y_{k+1} .. y_{k+3} kept on chip) and, on larger grids,
+ * terms k+1 and k+2 in one launch, keeping y_{k+1} on chip (read y_k, the
+ * fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2}) with the input rows
+ * staged in LDS (without non-temporal hints, also below 2^20 points: one-row
+ * frames in registers); mode = 2 and mode = 3
  * force the LDS-staged and the register-frame form; mode = 4 computes four
  * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames; p_{k+1}
  * .. p_{k+4} written), on grids below 2^20 points without non-temporal hints

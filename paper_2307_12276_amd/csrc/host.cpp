@@ -201,13 +201,10 @@ constexpr size_t kNone = ~(size_t)0;
 // four Newton terms per launch on grids below this many points (each launch
 // then needs eight p buffers; the grid's vectors stay in the caches) ...
 constexpr long kFourTermMaxPoints = 1L << 20;
-// ... and by default on grids of kFourTermMinPoints up to kFourTermAutoMax:
-// measured on MI355X (FP64, steps/s of the two-stage quadrature, two terms
-// per launch -> four, chunks ending on their targets): 512^2 +0.2 to +1 %
-// (left on two terms), 576^2 +4 %, 640^2 +33 %, 768^2 +21 %; before the
-// chunks ended on their targets, 704^2 +11 %, 896^2 +19 %, 1000^2 -1 %
-constexpr long kFourTermMinPoints = 5L << 16;
-constexpr long kFourTermAutoMax = 7L << 17;
+// ... which is also the default there: measured on MI355X (FP64, steps/s of
+// the two-stage quadrature, two terms per launch -> four, LDS rows accessed
+// 16 bytes per lane, chunks ending on their targets): 256^2 +7 %, 384^2
+// +15 %, 512^2 +14 %, 640^2 +44 %, 896^2 +31 %, 1000^2 +11 %
 
 static size_t max_partial_blocks(int nx, int ny) {
   // stencil launches: at most max(kMaxGrid, number of strips) blocks (one
@@ -447,8 +444,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const Tiling& T2 = T.vec == op->t2.vec ? op->t2 : op->t21;
   const Tiling& T4 = T.vec == op->t4.vec ? op->t4 : op->t41;
   const bool fuse = op->fuse_terms != 0;
-  const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n >= kFourTermMinPoints &&
-                                               op->n < kFourTermAutoMax)) &&
+  const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n < kFourTermMaxPoints)) &&
                     four_terms_ok(op);
   const int S = four ? 4 : 2;  // p buffers per launch (two sets)
   if (four && op->cus <= 0) {

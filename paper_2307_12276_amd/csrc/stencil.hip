@@ -598,11 +598,22 @@ template <int VEC>
 __device__ __forceinline__ double* fld_row(double* flds, int f, int q) {
   return flds + ((long)f * kQ4 + q) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
 }
+// (all LDS rows of the four-term kernel are accessed with one aligned
+// 16-byte access per lane at two columns per lane: two 8-byte accesses at a
+// 16-byte lane stride made bank-conflict cycles 1.8x the active LDS cycles)
+// y row q of a ring (rounded to the storage type) with its x-neighbours
+template <typename TY, int VEC>
+__device__ __forceinline__ void ring4_row_n(const double* ring, int q, RowN<VEC>& o) {
+  double c[VEC];
+  lds_get<VEC>(ring + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC, c);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o.c[v] = storage_round<TY>(c[v]);
+  o.l = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
+  o.r = dpp_f64<kDppWaveShl1>(o.c[0]);
+}
 template <int VEC, int MODE>
 __device__ __forceinline__ void lds_field_n(double* flds, int f, int q, const Strip& g, RowN<VEC>& o) {
-  const double* row = fld_row<VEC>(flds, f, q);
-#pragma unroll
-  for (int v = 0; v < VEC; ++v) o.c[v] = row[v];
+  lds_get<VEC>(fld_row<VEC>(flds, f, q), o.c);
   const double l = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
   const double rr = dpp_f64<kDppWaveShl1>(o.c[0]);
   const double gl = MODE == MODE_EDGE ? o.c[0] : 0.0;
@@ -612,9 +623,7 @@ __device__ __forceinline__ void lds_field_n(double* flds, int f, int q, const St
 }
 template <int VEC>
 __device__ __forceinline__ void lds_field_c(double* flds, int f, int q, RowC<VEC>& o) {
-  const double* row = fld_row<VEC>(flds, f, q);
-#pragma unroll
-  for (int v = 0; v < VEC; ++v) o.c[v] = row[v];
+  lds_get<VEC>(fld_row<VEC>(flds, f, q), o.c);
 }
 
 // Stage 1 at grid row r (ring row q): y_{k+1} from memory into `out`, as
@@ -642,25 +651,16 @@ __device__ __forceinline__ void stage1_row4(const FieldView& F, const TY* __rest
   stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc,
                            F.ayc, Ax);
   const bool ghost = F.bc != BC_PERIODIC && (!g.inside || r < 0 || r >= F.ny);
-  double* row = out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
-  double* f0 = fld_row<VEC>(flds, 0, q);
-  double* f1 = fld_row<VEC>(flds, 1, q);
-  double* f2 = fld_row<VEC>(flds, 2, q);
+  double y1[VEC];
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) {
-    row[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
-    f0[v] = k.c[v];
-    f1[v] = m[1].c[v];
-    f2[v] = gg[1].c[v];
-  }
+  for (int v = 0; v < VEC; ++v) y1[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
+  lds_set<VEC>(out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC, y1);
+  lds_set<VEC>(fld_row<VEC>(flds, 0, q), k.c);
+  lds_set<VEC>(fld_row<VEC>(flds, 1, q), m[1].c);
+  lds_set<VEC>(fld_row<VEC>(flds, 2, q), gg[1].c);
   if constexpr (ADVF) {
-    double* f3 = fld_row<VEC>(flds, 3, q);
-    double* f4 = fld_row<VEC>(flds, 4, q);
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      f3[v] = ac.c[v];
-      f4[v] = ay[1].c[v];
-    }
+    lds_set<VEC>(fld_row<VEC>(flds, 3, q), ac.c);
+    lds_set<VEC>(fld_row<VEC>(flds, 4, q), ay[1].c);
   }
 }
 
@@ -679,7 +679,7 @@ __device__ __forceinline__ void stage_from_ring(const FieldView& F, const Strip&
     lds_field_c<VEC>(flds, 2, q - 1 + t, gg[t]);
     lds_field_n<VEC, MODE_ZERO>(flds, 1, q - 1 + t, g, m[t]);
     if constexpr (ADVF) lds_field_c<VEC>(flds, 4, q - 1 + t, ay[t]);
-    lds_row_n<TY, VEC>(in, q - 1 + t, u[t]);
+    ring4_row_n<TY, VEC>(in, q - 1 + t, u[t]);
   }
   lds_field_n<VEC, MODE_EDGE>(flds, 0, q, g, k);
   if constexpr (ADVF) lds_field_n<VEC, MODE_ZERO>(flds, 3, q, g, ac);
@@ -687,12 +687,9 @@ __device__ __forceinline__ void stage_from_ring(const FieldView& F, const Strip&
   stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc,
                            F.ayc, Ax);
   const bool ghost = F.bc != BC_PERIODIC && (!g.inside || r < 0 || r >= F.ny);
-  double* row = out ? out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC : nullptr;
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) {
-    yt[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
-    if (out) row[v] = yt[v];
-  }
+  for (int v = 0; v < VEC; ++v) yt[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
+  if (out) lds_set<VEC>(out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC, yt);
 }
 
 // The same with the field rows read again from memory (cache hits), for
@@ -717,17 +714,14 @@ __device__ __forceinline__ void stage_from_ring_g(const FieldView& F, const Stri
   row_n<TF, VEC, MODE_EDGE>(kxx, r, F, g, k);
   if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, r, F, g, ac);
 #pragma unroll
-  for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(in, q - 1 + t, u[t]);
+  for (int t = 0; t < 3; ++t) ring4_row_n<TY, VEC>(in, q - 1 + t, u[t]);
   double Ax[VEC];
   stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc,
                            F.ayc, Ax);
   const bool ghost = F.bc != BC_PERIODIC && (!g.inside || r < 0 || r >= F.ny);
-  double* row = out ? out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC : nullptr;
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) {
-    yt[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
-    if (out) row[v] = yt[v];
-  }
+  for (int v = 0; v < VEC; ++v) yt[v] = ghost ? 0.0 : (Ax[v] - shift * u[1].c[v]) * invg;
+  if (out) lds_set<VEC>(out + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC, yt);
 }
 
 // stage t >= 2 from the LDS field rows (LF) or from memory
@@ -740,7 +734,7 @@ __device__ __forceinline__ void stage_t(const FieldView& F, const Strip& g, cons
 
 template <bool LF, typename TF, typename TY, int VEC, bool ADVF>
 __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling T, LejaArgs A) {
-  extern __shared__ double lds[];
+  extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
   if (A.decide_only || blockIdx.x == 0) {
     leja_decide(A);
     return;
@@ -777,7 +771,8 @@ __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling 
 #pragma unroll
     for (int h = 0; h < kOW4; ++h) {
       if (ho[h]) {
-        const double* yr = rg + (long)(jo[h] - r0) * W + lane * VEC;
+        double yr[VEC];
+        lds_get<VEC>(rg + (long)(jo[h] - r0) * W + lane * VEC, yr);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
           const double tv = d * yr[v];
