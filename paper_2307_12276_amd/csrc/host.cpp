@@ -447,12 +447,6 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n < kFourTermMaxPoints)) &&
                     four_terms_ok(op);
   const int S = four ? 4 : 2;  // p buffers per launch (two sets)
-  if (four && op->cus <= 0) {
-    int dev = 0, cus = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    op->cus = cus > 0 ? cus : 1;
-  }
   // first chunk: the last degree of this plan plus one (the degree moves by
   // about one from step to step; one launch too many costs its work, one too
   // few a second chunk and host round trip); the first sweep of a plan
@@ -570,9 +564,10 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.dk2 = n >= 2 ? P.d[kcov + 2] : 0.0;
       a.dk3 = n == 4 ? P.d[kcov + 3] : 0.0;
       a.dk4 = n == 4 ? P.d[kcov + 4] : 0.0;
-      // four-term launch: field rows kept in LDS when its blocks fit the chip
-      // at once at two per CU (the LDS they take)
-      a.lds_fields = n == 4 && T4.nblocks <= 2 * op->cus;
+      // four-term launch: field rows kept in LDS (faster than reading them
+      // again on every grid measured, 256^2 to 1000^2, once the LDS rows were
+      // accessed 16 bytes per lane, also where the blocks take two rounds)
+      a.lds_fields = n == 4;
       a.slot = L & 1;
       a.nb_prev = prev_nb;
       a.k_prev = prev_k;

@@ -52,7 +52,6 @@ struct adl_op {
   int fuse_terms = 1;  // 0 one Newton term per launch, 1 two (kernel by tiling), 2 two (LDS-staged), 3 two (frames),
                        // 4 four (grids below 2^20 points)
   int streaming = -1;  // non-temporal hints on Newton vectors: -1 auto, 0 off, 1 on
-  int cus = 0;         // compute units of the op's device (0: not yet asked)
   int nx = 0, ny = 0, bc = 0, storage = 0;
   double hx = 0, hy = 0;
   long n = 0;

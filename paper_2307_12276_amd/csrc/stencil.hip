@@ -563,11 +563,11 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
 // leaves one more lane per side invalid: the four frame lanes); stage 4
 // computes y_{k+4} on the output rows.  Stage 1 also keeps the centre field
 // row of each row it computes in LDS, so that stages 2-4 read no memory
-// (LF; 75 KB of LDS per block in FP64, two blocks per CU), or, when the
-// launch has more blocks than the chip holds at two per CU, the later stages
-// read the field rows again from memory (cache hits on these grids; 32 KB
-// per block).  Each wave keeps p of its output rows in registers and updates
-// it after every stage:
+// (LF; 75 KB of LDS per block in FP64, two blocks per CU); the other form
+// (LF false: the later stages read the field rows again from memory, 32 KB
+// per block) measured slower on every grid once the LDS rows were accessed
+// 16 bytes per lane, and the host no longer picks it.  Each wave keeps p of
+// its output rows in registers and updates it after every stage:
 // p_{k+t} = p_{k+t-1} + d_{k+t} y_{k+t}, written for t = 1, 2, 3 (one of them
 // is the result if the sweep stops there) and 4, with y_{k+4}.  Rows and
 // columns outside a Dirichlet grid hold zero at every stage; periodic ones are
