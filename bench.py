@@ -1,19 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the Leja exponential integrator on one MI355X.
 
-Workload (one "step" = one pass of the hot path: stage vectors, the Newton-
-Leja sweep with its fused norm reductions, and the update): 512 x 512
-Dirichlet grid, circular field about the centre, k_par = 1, k_par/k_perp =
-1e3, a = (0.2, 0), centred time-independent Gaussian source, two-stage
-exponential quadrature c = (1/3, 2/3), dt = 200 dt_CFL, tol 1e-10, FP64.
-Operator setup and the Gershgorin bound happen once, before timing.
+Headline workload (one "step" = one pass of the hot path: the stage vector
+w = A u + S, the Newton-Leja sweep of phi_1 with its fused norm reductions
+and stopping decisions, and the update u += dt p): the 4096 x 4096 periodic
+stream-function field (32 seeded Fourier modes, wavenumber <= 8), k_par = 1,
+k_par/k_perp = 1e4, a = (0.2, 0), pulsed Gaussian source
+S = (1 + sin(2 pi t / T_s)) G, exponential midpoint rule, dt = 100 dt_CFL,
+tol 1e-10, FP64 -- the grid whose working set (~1 GB per Newton term) is far
+beyond L2 and the 256 MB Infinity Cache.  Operator setup, the Gershgorin
+bound and the source arrays of every step are on the device before timing.
 
 Prints one JSON line.  `value` = time steps per second on one GPU.
-`roofline` = the Newton-Leja launches (the dominant kernel: two terms per
-launch, the first term of a sweep alone): algorithmic bytes per launch /
-average dispatch-timed duration, against 8 TB/s.  `cpu_baseline` = the FP64 NumPy oracle, single-threaded, on a
-bounded sample of the same workload.  Extra legs: the same kernel on a
-4096 x 4096 grid (working set far beyond the caches).
+`roofline` = the dominant kernel, the two-term Newton-Leja launch
+(leja2s_kernel: input rows staged in LDS): 56 B per point and Newton term
+(read y, three tensor fields and p, write y and p, FP64) times the terms of
+a launch, over the launch's average duration from HIP events on its own
+dispatches, against 8 TB/s; `traffic` = the HBM bytes per launch measured by
+rocprofv3 counters (profiles/).  `cpu_baseline` = the FP64 NumPy oracle,
+single-threaded, on a bounded sample of the same workload.  Extra legs: the
+512^2 two-stage quadrature workload, one- and two-term kernels at 4096^2, four
+terms per launch at 640^2, the 256-bin momentum workload (chosen vs plain),
+the paper's Cases I-IV.
 """
 import os
 
@@ -77,14 +85,22 @@ def device_sources(w):
 
 
 KERNEL_SOURCES = ("device.h", "internal.h", "stencil.hip", "tile.h", "staged.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_kernel_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja2s_kernel_stream4096_traffic.txt")
+TRAFFIC_KEY = "traffic_bytes_per_launch_stream4096"
+BYTES_PER_TERM_FP64 = 56.0  # read y, Dxx, Dxy, Dyy, p; write y, p (FP64, constant advection)
 
 
-def measured_traffic():
-    """HBM bytes per Newton-Leja launch of the 512^2 workload from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the
-    kernel sources have changed since those counters were taken."""
+def sources_sha256():
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2307_12276_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record():
+    """key: value lines of the committed counter summary, or None."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as fh:
@@ -92,13 +108,20 @@ def measured_traffic():
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        h = hashlib.sha256()
-        for f in KERNEL_SOURCES:
-            with open(os.path.join(ROOT, "paper_2307_12276_amd", "csrc", f), "rb") as fh:
-                h.update(fh.read())
-        if h.hexdigest() != kv.get("kernel_sources_sha256"):
+        return kv
+    except OSError:
+        return None
+
+
+def measured_traffic():
+    """HBM bytes per two-term Newton-Leja launch of the 4096^2 workload from
+    the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the
+    kernel sources have changed since those counters were taken."""
+    kv = traffic_record()
+    try:
+        if kv is None or sources_sha256() != kv.get("kernel_sources_sha256"):
             return None
-        return float(kv["traffic_bytes_per_launch_dirichlet512"])
+        return float(kv[TRAFFIC_KEY])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -412,8 +435,8 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle, single-threaded, on the first steps of the same
+def cpu_baseline_c2(w, budget_s):
+    """The FP64 oracle, single-threaded, on the first steps of the 512^2
     workload until budget_s seconds of CPU work have been spent."""
     from threadpoolctl import threadpool_limits
     from oracle import bounds, integrators
@@ -427,10 +450,7 @@ def cpu_baseline(w, budget_s):
     with threadpool_limits(1):
         while True:
             S1, S2 = w.stage_sources(steps)
-            if w.scheme == "midpoint":
-                u = integrators.exp_midpoint_step(A_, u, S1, w.dt, alpha, w.tol)
-            else:
-                u = integrators.exp_quad2_step(A_, u, S1, S2, w.c1, w.c2, w.dt, alpha, w.tol)
+            u = integrators.exp_quad2_step(A_, u, S1, S2, w.c1, w.c2, w.dt, alpha, w.tol)
             steps += 1
             if time.perf_counter() - t0 >= budget_s:
                 break
@@ -438,14 +458,225 @@ def cpu_baseline(w, budget_s):
     return steps / el, steps, el, u
 
 
+def cpu_baseline_sample(w, budget_s, matvecs_per_step):
+    """The FP64 oracle, single-threaded, on a bounded sample of the headline
+    workload: the stage vector w = A u0 + S of step 1 (one matvec, with the
+    step's Newton coefficients) and then as many Newton terms of its phi_1
+    sweep as fit the budget.  The oracle's steps/s is 1 / (seconds per matvec
+    x the matvecs of a step)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bounds, leja
+    from oracle import operator as O
+    oop = O.make_operator(w.Dxx, w.Dxy, w.Dyy, w.ax_c, w.ay_c, w.hx, w.hy, w.bc)
+    A_ = lambda x: O.apply(oop, x)
+    alpha = bounds.gershgorin(oop)  # once per operator (setup), as on the GPU
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        S1 = w.stage_sources(0)[0]
+        v = A_(w.u0) + S1
+        d = leja.newton_coefficients(1, alpha, w.dt)
+        t_stage = time.perf_counter() - t0
+        n = max(2, min(matvecs_per_step, int(budget_s / max(t_stage, 1e-3)) - 1))
+        t1 = time.perf_counter()
+        leja.newton_sweep(A_, v, alpha, w.dt, d, w.tol, max_degree=n)
+        t_sweep = time.perf_counter() - t1
+    s_per_mv = (t_stage + t_sweep) / (1 + n)
+    return 1.0 / (s_per_mv * matvecs_per_step), n, t_stage + t_sweep, s_per_mv
+
+
+def c2_leg(steps=50, warmup=2, cpu_budget=0.0):
+    """The 512^2 Dirichlet two-stage quadrature workload (working set in
+    L2/MALL, four Newton terms per launch): steps/s, the Newton-Leja launches
+    from HIP events on a second pass, and the GPU's error against the
+    oracle on the first steps (with the oracle's steps/s) when cpu_budget > 0."""
+    import numpy as np
+    import torch
+    import paper_2307_12276_amd as A
+    import workloads as W
+    w = W.c2_dirichlet_circular(n=512, steps=warmup + 2 * steps)
+    op = make_op(w, A.STORAGE_FP64)
+    alpha, _ = op.spectral_bound(A.BOUND_GERSHGORIN)
+    u = dev_tensor(w.u0)
+    srcs = device_sources(w)
+    for n in range(warmup):
+        gpu_step(op, w, u, n, srcs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mv = 0
+    for n in range(warmup, warmup + steps):
+        mv += gpu_step(op, w, u, n, srcs)["matvecs"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    op.profile(True)
+    for n in range(warmup + steps, warmup + 2 * steps):
+        gpu_step(op, w, u, n, srcs)
+    torch.cuda.synchronize()
+    ms4, n4, b4, t4 = op.profile_read_kind(A.LAUNCH_FOUR)
+    ms, launches, nbytes = op.profile_read()
+    op.profile(False)
+    res = {"workload": "dirichlet-circular-512: Dirichlet 512x512, circular b, k_par/k_perp=1e3, a=(0.2,0), "
+                       "time-independent Gaussian source, two-stage exp. quadrature c=(1/3,2/3), "
+                       "dt=200 dt_CFL, tol=1e-10, FP64",
+           "steps": steps, "steps_per_s": steps / el, "matvecs_per_step": mv / steps,
+           "leja_launches": launches, "avg_leja_launch_us": 1e3 * ms / max(launches, 1),
+           "four_term_launches": n4, "avg_four_term_launch_us": 1e3 * ms4 / max(n4, 1),
+           "four_term_GBs_8d": (BYTES_PER_TERM_FP64 * w.nx * w.ny * t4 / max(n4, 1))
+           / (ms4 / max(n4, 1) * 1e-3) / 1e9 if n4 else None,
+           "note": "~15 MB per Newton term: L2/MALL-resident, launch-latency bound"}
+    log("512^2 leg: %.1f steps/s, %.1f matvecs/step, four-term launches %.2f us avg"
+        % (res["steps_per_s"], res["matvecs_per_step"], res["avg_four_term_launch_us"]))
+    if cpu_budget > 0:
+        cw = W.c2_dirichlet_circular(n=512, steps=steps)
+        rate, nst, el_cpu, u_cpu = cpu_baseline_c2(cw, cpu_budget)
+        op2 = make_op(cw, A.STORAGE_FP64)
+        op2.set_bound(alpha)
+        ug = dev_tensor(cw.u0)
+        s2 = device_sources(cw)
+        for n in range(nst):
+            gpu_step(op2, cw, ug, n, s2)
+        torch.cuda.synchronize()
+        err = float(np.linalg.norm(ug.cpu().numpy() - u_cpu) / np.linalg.norm(u_cpu))
+        res["oracle_steps_per_s"] = rate
+        res["parity"] = {"steps": nst, "rel_l2_vs_oracle": err, "oracle_seconds": el_cpu}
+        log("512^2 leg: oracle %.3f steps/s over %d steps; GPU rel err on those steps %.2e" % (rate, nst, err))
+        del op2
+    del op
+    torch.cuda.empty_cache()
+    return res
+
+
+def _c4_worker_init():
+    global _C4_BINS
+    import workloads as W
+    _C4_BINS = W.c4_bins(steps=1)
+
+
+def _c4_worker_step(b, tol):
+    """One oracle midpoint step of bin b (single-threaded, Gershgorin bound)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bounds, integrators
+    from oracle import operator as O
+    w = _C4_BINS[b]
+    with threadpool_limits(1):
+        oop = O.make_operator(w.Dxx, w.Dxy, w.Dyy, w.ax_c, w.ay_c, w.hx, w.hy, w.bc)
+        alpha = bounds.gershgorin(oop)
+        t0 = time.perf_counter()
+        st = {}
+        integrators.exp_midpoint_step(lambda x: O.apply(oop, x), w.u0, w.S(0.0), w.dt, alpha, tol, stats=st)
+        return time.perf_counter() - t0, st["matvecs"]
+
+
+def oracle_c4_all_cores(tol=1e-9, workers=None):
+    """The oracle on every host core: one midpoint step of all 256 momentum
+    bins, each bin in a single-threaded worker process (a process pool of one
+    worker per logical CPU, at most 16), with each bin's Gershgorin interval.
+    Returns steps/s of the whole 256-bin system (1 / wall time of the step)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    n = workers or min(16, os.cpu_count() or 1)
+    ctx = mp.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=n, mp_context=ctx, initializer=_c4_worker_init) as ex:
+        list(ex.map(_c4_worker_step, [0] * n, [tol] * n))  # start the workers, build the bins
+        t0 = time.perf_counter()
+        res = list(ex.map(_c4_worker_step, range(256), [tol] * 256))
+        wall = time.perf_counter() - t0
+    cpu = sum(r[0] for r in res)
+    return {"steps_per_s": 1.0 / wall, "wall_s": wall, "cpu_s": cpu, "workers": n,
+            "matvecs": sum(r[1] for r in res),
+            "sample": "one exponential midpoint step of all 256 bins (tol %g, Gershgorin interval per bin), "
+                      "one single-threaded NumPy process per logical CPU" % tol}
+
+
+def headline(args):
+    """The 4096^2 FP64 stream-function workload (module docstring)."""
+    import torch
+    import paper_2307_12276_amd as A
+    import workloads as W
+    total = args.warmup + 2 * args.steps
+    t0 = time.perf_counter()
+    w = W.roofline_shape(n=4096, steps=total)
+    log("headline: 4096^2 fields built in %.1fs" % (time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    op = make_op(w, A.STORAGE_FP64)
+    alpha, _ = op.spectral_bound(A.BOUND_GERSHGORIN)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    # the pulsed source at each step's midpoint, resident in HBM before timing
+    S = [dev_tensor(w.stage_sources(n)[0]) for n in range(total)]
+    u = dev_tensor(w.u0)
+    for n in range(args.warmup):
+        op.midpoint_step(u, S[n], w.dt, w.tol)
+    torch.cuda.synchronize()
+    # timed region: K steps, no per-launch instrumentation
+    t0 = time.perf_counter()
+    mv = 0
+    for n in range(args.warmup, args.warmup + args.steps):
+        mv += op.midpoint_step(u, S[n], w.dt, w.tol)["matvecs"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # kernel timing pass: the next K steps again, every Newton-Leja launch timed
+    # by HIP events attached to its dispatch on the op's stream (per-launch
+    # events slow the host loop, so they stay out of the timed region)
+    op.profile(True)
+    t1 = time.perf_counter()
+    for n in range(args.warmup + args.steps, total):
+        op.midpoint_step(u, S[n], w.dt, w.tol)
+    torch.cuda.synchronize()
+    el_prof = time.perf_counter() - t1
+    kinds = {k: op.profile_read_kind(getattr(A, "LAUNCH_" + k.upper())) for k in ("first", "one", "two", "four")}
+    op.profile_read()
+    op.profile(False)
+    ms2, n2, fused2, terms2 = kinds["two"]
+    N = w.nx * w.ny
+    avg_s = ms2 / max(n2, 1) * 1e-3
+    alg = BYTES_PER_TERM_FP64 * N * terms2 / max(n2, 1)
+    achieved = alg / avg_s / 1e9 if n2 else 0.0
+    traffic = measured_traffic()
+    value = args.steps / el
+    log("headline: %d steps in %.3fs: %.2f steps/s, %.1f matvecs/step; two-term launches %.1f us avg over %d "
+        "(%.2f terms each): %.0f GB/s by 56 B/pt/term (%.1f%% of 8 TB/s)"
+        % (args.steps, el, value, mv / args.steps, avg_s * 1e6, n2, terms2 / max(n2, 1), achieved,
+           100 * achieved / HBM_PEAK_GBS))
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded analytic fields)",
+        "config": {"workload": "periodic-stream-4096: periodic 4096x4096, b from a seeded 32-mode stream "
+                               "function, k_par=1, k_par/k_perp=1e4, a=(0.2,0), pulsed Gaussian source, "
+                               "exp. midpoint, dt=100 dt_CFL, tol=1e-10, FP64",
+                   "nx": w.nx, "ny": w.ny, "dt": w.dt, "tol": w.tol, "alpha": alpha,
+                   "matvecs_per_step": mv / args.steps, "matvecs_per_s": mv / el, "setup_s": setup_s},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "leja2s_kernel (two Newton terms per launch, input rows staged in LDS, "
+                               "non-temporal hints on the vectors read or written once)",
+                     "bytes_per_launch": alg, "bytes_rule": "56 B per point and Newton term (FP64) x %d points "
+                                                           "x %.2f terms per launch" % (N, terms2 / max(n2, 1)),
+                     "avg_kernel_us": avg_s * 1e6, "launches": n2,
+                     "fused_bytes_per_launch": fused2 / max(n2, 1),
+                     "timing": "HIP events on each two-term dispatch, second pass of %d steps (%.3fs)"
+                               % (args.steps, el_prof),
+                     "traffic_source": "profiles/leja2s_kernel_stream4096_traffic.txt (rocprofv3 FETCH_SIZE and "
+                                       "WRITE_SIZE per dispatch, scaled by a 1 GiB copy), bytes per launch"},
+        "launch_kinds": {k: {"launches": v[1], "avg_us": 1e3 * v[0] / v[1] if v[1] else None, "terms": v[3]}
+                         for k, v in kinds.items()},
+    }
+    if traffic:
+        out["roofline"]["traffic_GBs"] = traffic / avg_s / 1e9
+    del op, S, u
+    torch.cuda.empty_cache()
+    return out, w
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 roofline, bins and paper-case legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 512^2, roofline, bins and paper-case legs")
     ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
     ap.add_argument("--fp32", action="store_true", help="with --profile-leja: fields stored in FP32")
@@ -470,97 +701,29 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import paper_2307_12276_amd as A
     import workloads as W
 
     torch.cuda.init()
-    w = W.c2_dirichlet_circular(n=512, steps=args.warmup + 2 * args.steps)
-    t0 = time.perf_counter()
-    op = make_op(w, A.STORAGE_FP64)
-    alpha, _ = op.spectral_bound(A.BOUND_GERSHGORIN)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    u = dev_tensor(w.u0)
-    srcs = device_sources(w)
-    for n in range(args.warmup):
-        gpu_step(op, w, u, n, srcs)
-    torch.cuda.synchronize()
-
-    # timed region: K steps, no per-launch instrumentation
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mv = 0
-    for n in range(args.warmup, args.warmup + args.steps):
-        st = gpu_step(op, w, u, n, srcs)
-        mv += st["matvecs"]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    value = args.steps / el
-    # kernel timing pass: the next K steps again, every Newton-Leja launch
-    # timed by HIP events attached to its dispatch on the op's stream
-    # (per-launch events slow the host loop, so they stay out of the timed region)
-    op.profile(True)
-    t1 = time.perf_counter()
-    for n in range(args.warmup + args.steps, args.warmup + 2 * args.steps):
-        gpu_step(op, w, u, n, srcs)
-    torch.cuda.synchronize()
-    el_prof = time.perf_counter() - t1
-    ms, launches, nbytes = op.profile_read()
-    op.profile(False)
-    avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)
-    log("timed %d steps in %.3fs: %.1f steps/s, %.1f matvecs/step; kernel pass: Newton-Leja launches %.2f us avg "
-        "over %d launches, %.0f GB/s" % (args.steps, el, value, mv / args.steps, avg_ms * 1e3, launches, achieved))
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (seeded analytic fields)",
-        "config": {"workload": "dirichlet-circular-512: Dirichlet 512x512, circular b, k_par/k_perp=1e3, "
-                               "a=(0.2,0), time-independent Gaussian source, two-stage exp. quadrature "
-                               "c=(1/3,2/3), dt=200 dt_CFL, tol=1e-10",
-                   "nx": 512, "ny": 512, "dt": w.dt, "tol": w.tol, "alpha": alpha,
-                   "matvecs_per_step": mv / args.steps, "matvecs_per_s": mv / el, "setup_s": setup_s},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "leja4_kernel (four Newton terms per launch, field rows kept in LDS; the "
-                               "first term of a sweep runs in leja_kernel, a chunk's remainder in "
-                               "leja2_kernel or leja_kernel)", "bytes_per_launch": per_launch,
-                     "avg_kernel_us": avg_ms * 1e3, "launches": launches,
-                     "timing": "HIP events on each Newton-Leja dispatch, second pass of %d steps "
-                               "(%.3fs)" % (args.steps, el_prof),
-                     "traffic_source": "profiles/leja_kernel_traffic.txt (rocprofv3 FETCH_SIZE x2.0 + "
-                                       "WRITE_SIZE x1.0, calibrated on a 1 GiB copy), bytes per launch",
-                     "note": "512^2 FP64 working set (~21 MB per four-term launch) stays in L2/MALL"},
-    }
+    out, w = headline(args)
 
     if not args.no_cpu:
-        # same workload, first steps, oracle single-threaded
-        cw = W.c2_dirichlet_circular(n=512, steps=args.steps)
-        rate, nst, el_cpu, u_cpu = cpu_baseline(cw, args.cpu_budget)
-        # parity of the GPU on exactly those steps
-        op2 = make_op(cw, A.STORAGE_FP64)
-        op2.set_bound(alpha)
-        ug = dev_tensor(cw.u0)
-        s2 = device_sources(cw)
-        for n in range(nst):
-            gpu_step(op2, cw, ug, n, s2)
-        torch.cuda.synchronize()
-        err = float(np.linalg.norm(ug.cpu().numpy() - u_cpu) / np.linalg.norm(u_cpu))
+        mvs = out["config"]["matvecs_per_step"]
+        rate, nterms, el_cpu, s_mv = cpu_baseline_sample(w, args.cpu_budget, int(round(mvs)))
         model, ncpu = host_cpu()
         out["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": 1, "kind": "oracle",
-                               "sample": "first %d steps of the same 512^2 workload (%.1fs), NumPy FP64, "
-                                         "single-threaded" % (nst, el_cpu),
+                               "sample": "step 1 of the same 4096^2 workload: the stage vector and the first %d "
+                                         "Newton terms of its phi_1 sweep (%d matvecs, %.1fs, %.2fs per matvec); "
+                                         "steps/s = 1 / (s per matvec x %.1f matvecs per step), NumPy FP64, "
+                                         "single-threaded" % (nterms, nterms + 1, el_cpu, s_mv, mvs),
                                "host_cpu": model, "host_logical_cpus": ncpu}
-        out["parity"] = {"steps": nst, "rel_l2_vs_oracle": err}
-        log("cpu oracle: %.3f steps/s over %d steps; GPU rel err on those steps %.2e" % (rate, nst, err))
-        del op2
+        log("cpu oracle: %.2f s per matvec at 4096^2 -> %.4f steps/s" % (s_mv, rate))
+    del w
 
     if not args.no_extra:
-        del op
         torch.cuda.empty_cache()
+        out["c2_512"] = c2_leg(cpu_budget=0.0 if args.no_cpu else 5.0)
         legs = []
         t0 = time.time()
         rw = W.roofline_shape(n=4096)
@@ -579,6 +742,11 @@ def main():
         out["copy_GBs"] = copy_gbs
         out["four_term_640"] = four_term_leg()
         out["chosen_vs_plain"] = chosen_vs_plain()
+        if not args.no_cpu:
+            c4 = oracle_c4_all_cores()
+            out["chosen_vs_plain"]["oracle_all_cores"] = c4
+            log("oracle, all cores (%d workers): one step of 256 bins in %.1fs (%.1f s of CPU)"
+                % (c4["workers"], c4["wall_s"], c4["cpu_s"]))
         out["paper_cases"] = paper_cases_leg()
 
     print(json.dumps(out), flush=True)

@@ -133,6 +133,15 @@ int adl_op_set_quad2_mode(adl_op* op, int mode);
 int adl_op_profile(adl_op* op, int enable);
 int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, double* bytes);
 
+/* The same counters split by launch kind (read before adl_op_profile_read,
+ * which resets them): ADL_LAUNCH_FIRST = the first term of a sweep (y_0 = v,
+ * the augmented column), ADL_LAUNCH_ONE / _TWO / _FOUR = launches of one, two
+ * or four later terms.  terms (may be NULL) = Newton terms those launches
+ * computed.  ADL_EINVAL for another kind. */
+enum { ADL_LAUNCH_FIRST = 0, ADL_LAUNCH_ONE = 1, ADL_LAUNCH_TWO = 2, ADL_LAUNCH_FOUR = 3 };
+int adl_op_profile_read_kind(const adl_op* op, int kind, double* kernel_ms, long long* launches,
+                             double* bytes, long long* terms);
+
 /* Tiling of the stencil kernels (the autotuner's knobs): rows = rows each
  * wave computes per tile (a block of four waves covers 4 * rows rows of one
  * strip; default 1), cols_per_lane = columns per lane (1, or 2 for even
@@ -151,7 +160,9 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
  * force the LDS-staged and the register-frame form; mode = 4 computes four
  * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames; p_{k+1}
  * .. p_{k+4} written), on grids below 2^20 points without non-temporal hints
- * (ADL_EINVAL otherwise); mode = 0 launches one kernel per term.  Results
+ * and, on a periodic grid, ny >= 4 other than 5 and 9 (a block's rows wrap
+ * once; ADL_EINVAL otherwise; mode 1 then runs two terms per launch);
+ * mode = 0 launches one kernel per term.  Results
  * agree to rounding (the block partial sums of the norms are grouped
  * differently).  ADL_EINVAL for other values. */
 int adl_op_set_term_fusion(adl_op* op, int mode);

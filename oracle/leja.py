@@ -14,9 +14,20 @@ The paper's recipe (Sec. 2, "Leja method" paragraph):
 Readings of what the paper leaves open (all listed in the design notes):
   * Leja points: xi_0 = 2, then xi_k maximises prod_{j<k} |xi - xi_j| over
     [-2, 2]; ties (the first is at k = 3, +-2/sqrt 3) go to the smaller xi.
-  * Stopping: the sweep stops at the first k+1 >= 1 with
-        || d_{k+1} y_{k+1} ||_2 <= tol * || p_{k+1} ||_2
-    (FP64 Euclidean norms over the grid).  v = 0 gives 0 with degree 0.
+  * Stopping (tol is the desired accuracy of the result, Sec. 3): the error
+    of the degree-m interpolant is estimated by the norms of the last
+    STOP_WINDOW Newton terms, and the sweep stops at the first m >= STOP_WINDOW
+    with
+        sum_{j = m - STOP_WINDOW + 1}^{m} || d_j y_j ||_2 <= tol * || p_m ||_2
+    (FP64 Euclidean norms over the grid, summed oldest first).  The terms of
+    a sweep over a wide interval rise and fall by orders of magnitude from one
+    Leja point to the next, so a single small term says little about the
+    truncation error; over a window of five the estimate bounds it on the
+    paper's test problems.  v = 0 gives 0 with degree 0.
+  * phi_0 over K > 1 substeps is the K-fold product of sweeps whose relative
+    errors add up, so each of those sweeps uses tol / K.  (The phi_1 / phi_2
+    substep recursion sums h p_j, whose errors are already relative to that
+    sum, and keeps tol.)
   * Substepping: a sweep covers at most rho*h <= RHO_MAX (rho = |alpha|);
     a step dt is split into K = ceil(rho dt / RHO_MAX) equal substeps, and K
     is doubled if a sweep reaches the degree cap without converging.
@@ -35,6 +46,7 @@ import numpy as np
 from .phi import phi
 
 MAX_DEGREE = 500          # most Newton terms in one sweep
+STOP_WINDOW = 5           # Newton terms in the stopping estimate
 RHO_MAX = 1600.0          # largest rho*h covered by one sweep
 MAX_SUBSTEP_DOUBLINGS = 6
 TIE_TOL = 1e-12
@@ -147,7 +159,8 @@ def newton_sweep(A, v, alpha, h, d, tol, max_degree=MAX_DEGREE, w2=None):
     p approximates g(A) v where g was interpolated with coefficients d (Sec. 2
     recurrence).  With w2 given, the matrix is the augmented
     [[A, w2/h], [0, 0]] acting on [v; 1] and p is the top block.
-    m = number of applications of A (the polynomial degree)."""
+    m = number of applications of A (the polynomial degree); the sweep stops
+    when the norms of the last STOP_WINDOW terms sum to at most tol ||p||."""
     xi = leja_points(max(len(d), max_degree + 1))
     s = augmented_scalars(max(len(d), max_degree + 1)) if w2 is not None else None
     c, gamma = interval_map(alpha)
@@ -155,6 +168,7 @@ def newton_sweep(A, v, alpha, h, d, tol, max_degree=MAX_DEGREE, w2=None):
     p = d[0] * y
     if not np.any(y) and (w2 is None or not np.any(w2)):
         return np.zeros_like(y), 0, True
+    recent = []  # norms of the last STOP_WINDOW terms, oldest first
     for k in range(max_degree):
         Ay = A(y)
         if s is not None and s[k] != 0.0:
@@ -166,8 +180,15 @@ def newton_sweep(A, v, alpha, h, d, tol, max_degree=MAX_DEGREE, w2=None):
         pn = np.linalg.norm(p)
         if not (np.isfinite(tn) and np.isfinite(pn)):
             return p, k + 1, False
-        if tn <= tol * pn:
-            return p, k + 1, True
+        recent.append(tn)
+        if len(recent) > STOP_WINDOW:
+            recent.pop(0)
+        if len(recent) == STOP_WINDOW:
+            est = 0.0
+            for t in recent:
+                est += t
+            if est <= tol * pn:
+                return p, k + 1, True
     return p, max_degree, False
 
 
@@ -228,9 +249,10 @@ def phi_apply(A, l, dt, v, alpha, tol, max_degree=MAX_DEGREE, rho_max=RHO_MAX, s
     """phi_l(A dt) v for l in {0, 1, 2} (Sec. 2).
 
     One substep: the Newton interpolant of phi_l((c + gamma xi) dt).
-    K > 1 substeps: phi_0 is applied K times with h = dt/K; phi_1 and phi_2
-    come from the exact substep recursion of phi_combo, divided by dt
-    (phi_1: w1 = v;  phi_2: w1 = 0, w2 = v)."""
+    K > 1 substeps: phi_0 is applied K times with h = dt/K, each sweep with
+    tol / K (their relative errors add); phi_1 and phi_2 come from the exact
+    substep recursion of phi_combo, divided by dt (phi_1: w1 = v;  phi_2:
+    w1 = 0, w2 = v)."""
     st = stats if stats is not None else {}
     st.setdefault("matvecs", 0)
     st.setdefault("degrees", [])
@@ -254,7 +276,7 @@ def phi_apply(A, l, dt, v, alpha, tol, max_degree=MAX_DEGREE, rho_max=RHO_MAX, s
             y = v.copy()
             conv = True
             for _j in range(K):
-                y, m, conv = newton_sweep(A, y, alpha, h, d, tol, max_degree)
+                y, m, conv = newton_sweep(A, y, alpha, h, d, tol / K, max_degree)
                 st["matvecs"] += m
                 st["degrees"].append(m)
                 if not conv:

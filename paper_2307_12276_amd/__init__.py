@@ -20,6 +20,7 @@ BC_PERIODIC, BC_DIRICHLET = 0, 1
 STORAGE_FP64, STORAGE_FP32_FIELDS, STORAGE_FP32_FIELDS_Y = 0, 1, 2
 BOUND_GERSHGORIN, BOUND_POWER = 0, 1
 QUAD2_AUGMENTED, QUAD2_TWO_SWEEP = 0, 1
+LAUNCH_FIRST, LAUNCH_ONE, LAUNCH_TWO, LAUNCH_FOUR = 0, 1, 2, 3
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_CACHE_PER_ROW = 9155, 9, 3, 201
 
 _ERRNAMES = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EBOUND: "EBOUND", ENAN: "ENAN",
@@ -79,6 +80,8 @@ _SIG = {
     "adl_op_get_tiling": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "adl_op_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.POINTER(_D)]),
+    "adl_op_profile_read_kind": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "adl_apply": (_I, [_P, _P, _P, _P]),
     "adl_spectral_bound": (_I, [_P, _I, _I, _D, ctypes.c_uint64, ctypes.POINTER(_D),
                                 ctypes.POINTER(_I), _P]),
@@ -255,6 +258,18 @@ class Op:
 
     def profile(self, enable: bool = True):
         _check(lib().adl_op_profile(self.handle, int(bool(enable))))
+
+    def profile_read_kind(self, kind: int):
+        """(kernel ms, launches, algorithmic bytes, Newton terms) of the timed
+        Leja launches of one kind (LAUNCH_FIRST / _ONE / _TWO / _FOUR); call
+        before profile_read, which resets the counters."""
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        b = ctypes.c_double()
+        t = ctypes.c_longlong()
+        _check(lib().adl_op_profile_read_kind(self.handle, int(kind), ctypes.byref(ms), ctypes.byref(n),
+                                              ctypes.byref(b), ctypes.byref(t)))
+        return ms.value, n.value, b.value, t.value
 
     def profile_read(self):
         """(kernel ms, launches, algorithmic bytes) of the timed Leja launches."""

@@ -55,7 +55,7 @@ struct BinDesc {
   const double* d;      // d_0 .. d_{M-1} of the bin's plan
   const double* shift;  // c + gamma xi_k
   double invg;
-  double tol2;
+  double tol;
   double dt;
   int max_degree;
   int ncb;        // strips of 64*VEC columns (one-term tiles)
@@ -74,6 +74,7 @@ struct BinCtl {
   int degree;
   int pad;
   double tn2, pn2;
+  double hist[kStopHist];  // term norms of the stopping window (as in Ctl)
 };
 
 struct BatchArgs {
@@ -148,9 +149,19 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
       tot[q] = q == 2 ? nanmax(tot[q], t) : tot[q] + t;
     }
   }
+  BinCtl* c = A.ctl + b;
+  // terms up to `done` were decided already (the finalize launch of an
+  // earlier enqueue decided the launch this one is handed again): each term
+  // enters the stopping window once
+  const int done = c->degree;
+  if (A.kprev + (two ? 2 : 1) <= done) return false;
+  double hist[kStopHist];
+#pragma unroll
+  for (int i = 0; i < kStopHist; ++i) hist[i] = c->hist[i];
   int stop = 0, status = 0, degree = 0;
   double tn2 = 0.0, pn2 = 0.0;
   for (int i = 0; i < (two ? 2 : 1) && !stop; ++i) {
+    if (A.kprev + 1 + i <= done) continue;
     tn2 = tot[3 * i];
     pn2 = tot[3 * i + 1];
     degree = A.kprev + 1 + i;
@@ -158,16 +169,17 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
       stop = 1; status = 2;
     } else if (A.kprev == 0 && i == 0 && tot[2] == 0.0) {
       stop = 1; status = 1; degree = 0;
-    } else if (tn2 <= B.tol2 * pn2) {
+    } else if (window_stop(hist, degree, sqrt(tn2), pn2, B.tol)) {
       stop = 1; status = 1;
     } else if (degree >= B.max_degree) {
       stop = 1; status = 3;
     }
   }
   if (record && (threadIdx.x & 63) == 0) {
-    BinCtl* c = A.ctl + b;
     c->tn2 = tn2;
     c->pn2 = pn2;
+#pragma unroll
+    for (int i = 0; i < kStopHist; ++i) c->hist[i] = hist[i];
     c->degree = degree;
     c->status = status;
     __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1027,15 +1039,11 @@ struct adl_batch {
   int predicted = 0;
 };
 
-static thread_local std::string b_err;
-
 namespace {
 
-int bfail(int code, const char* msg) {
-  b_err = msg;
-  fprintf(stderr, "adl batch: %s\n", msg);
-  return code;
-}
+// errors of the batch entry points go to the library's thread-local message
+// (adl_last_error), like every other entry point's
+int bfail(int code, const char* msg) { return adl::set_error(code, "batch: %s", msg); }
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1208,7 +1216,7 @@ int upload_bins(adl_batch* B, double* const* u, const double* const* S, double d
     const double* Sb = S ? S[b] : nullptr;
     const int K = substeps_for(op->alpha, dt, op->rho_max);
     const bool active = op->has_bound && op->alpha < 0.0 && K == 1;
-    if (d.u != u[b] || d.S != Sb || d.dt != dt || d.tol2 != tol * tol || d.active != (int)active) changed = true;
+    if (d.u != u[b] || d.S != Sb || d.dt != dt || d.tol != tol || d.active != (int)active) changed = true;
     d.f = op->f;
     d.u = u[b];
     d.S = Sb;
@@ -1219,7 +1227,7 @@ int upload_bins(adl_batch* B, double* const* u, const double* const* S, double d
     d.pb[1] = op->p;
     d.pb[2] = op->p3;
     d.pb[3] = op->p4;
-    d.tol2 = tol * tol;
+    d.tol = tol;
     d.dt = dt;
     d.max_degree = std::min(op->max_degree, B->max_degree);
     d.active = active;

@@ -49,6 +49,16 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
 #define HIPCHK(expr)                                                                  \
   do {                                                                                \
     hipError_t e_ = (expr);                                                           \
@@ -413,10 +423,12 @@ static int streaming_on(const adl_op* op) {
 }
 
 // Whether the op can run four Newton terms per launch: its workspace has the
-// eight p buffers, a launch's 12 partial rows fit a partials slot, and the
-// sweep runs without non-temporal hints (the four-term kernel has none).
+// eight p buffers, a launch's 12 partial rows fit a partials slot, the sweep
+// runs without non-temporal hints (the four-term kernel has none), and a
+// periodic grid has enough rows for the kernel's one-wrap row rule.
 static bool four_terms_ok(const adl_op* op) {
   const long nb = std::max(op->t4.nblocks, op->t41.nblocks);
+  if (!four_term_rows_fit(op->ny, op->bc)) return false;
   return op->p5 && 12L * nb <= op->slot_stride && !streaming_on(op);
 }
 
@@ -511,7 +523,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   LejaArgs a{};
   a.invg = P.invg;
   a.d0 = P.d[0];
-  a.tol2 = tol * tol;
+  a.tol = tol;
   a.max_degree = maxdeg;
   a.ystore_f32 = ys32;
   a.stream = streaming_on(op);
@@ -617,9 +629,16 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         if (stopped && past) break;
         float ms = 0.0f;
         HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * (l - L0)], op->evs[2 * (l - L0) + 1]));
+        const double b = leja_bytes(op, lk[l], ln[l], lk[l] == 0 && w2 != nullptr && P.s[0] != 0.0);
         op->prof_ms += ms;
         op->prof_launches += 1;
-        op->prof_bytes += leja_bytes(op, lk[l], ln[l], lk[l] == 0 && w2 != nullptr && P.s[0] != 0.0);
+        op->prof_bytes += b;
+        const int kind = lk[l] == 0 ? ADL_LAUNCH_FIRST : (ln[l] == 4 ? ADL_LAUNCH_FOUR
+                                                          : (ln[l] == 2 ? ADL_LAUNCH_TWO : ADL_LAUNCH_ONE));
+        op->kind_ms[kind] += ms;
+        op->kind_launches[kind] += 1;
+        op->kind_bytes[kind] += b;
+        op->kind_terms[kind] += ln[l];
         if (lk[l] >= m) past = true;  // this launch ran beside (or after) the final decision
       }
     }
@@ -920,12 +939,20 @@ int adl_op_set_limits(adl_op* op, int max_degree, double rho_max) {
   return ADL_OK;
 }
 
-int adl_op_profile(adl_op* op, int enable) {
-  RETCHK(check_op(op));
-  op->prof = enable != 0;
+static void profile_reset(adl_op* op) {
   op->prof_ms = 0.0;
   op->prof_bytes = 0.0;
   op->prof_launches = 0;
+  for (int k = 0; k < 4; ++k) {
+    op->kind_ms[k] = op->kind_bytes[k] = 0.0;
+    op->kind_launches[k] = op->kind_terms[k] = 0;
+  }
+}
+
+int adl_op_profile(adl_op* op, int enable) {
+  RETCHK(check_op(op));
+  op->prof = enable != 0;
+  profile_reset(op);
   return ADL_OK;
 }
 
@@ -934,9 +961,18 @@ int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, doub
   if (kernel_ms) *kernel_ms = op->prof_ms;
   if (launches) *launches = op->prof_launches;
   if (bytes) *bytes = op->prof_bytes;
-  op->prof_ms = 0.0;
-  op->prof_bytes = 0.0;
-  op->prof_launches = 0;
+  profile_reset(op);
+  return ADL_OK;
+}
+
+int adl_op_profile_read_kind(const adl_op* op, int kind, double* kernel_ms, long long* launches, double* bytes,
+                             long long* terms) {
+  RETCHK(check_op(op));
+  if (kind < ADL_LAUNCH_FIRST || kind > ADL_LAUNCH_FOUR) return fail(ADL_EINVAL, "bad launch kind %d", kind);
+  if (kernel_ms) *kernel_ms = op->kind_ms[kind];
+  if (launches) *launches = op->kind_launches[kind];
+  if (bytes) *bytes = op->kind_bytes[kind];
+  if (terms) *terms = op->kind_terms[kind];
   return ADL_OK;
 }
 
@@ -959,7 +995,8 @@ int adl_op_set_term_fusion(adl_op* op, int mode) {
   RETCHK(check_op(op));
   if (mode < 0 || mode > 4) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2, 3 or 4");
   if (mode == 4 && !four_terms_ok(op))
-    return fail(ADL_EINVAL, "four terms per launch need a grid below 2^20 points and no non-temporal hints");
+    return fail(ADL_EINVAL, "four terms per launch need a grid below 2^20 points, no non-temporal hints and, "
+                            "on a periodic grid, ny >= 4 other than 5 and 9");
   op->fuse_terms = mode;
   return ADL_OK;
 }
@@ -1139,8 +1176,9 @@ int adl_leja_phi(adl_op* op, int l, double dt, const double* v, double* out, dou
         bool ok = true;
         for (int j = 0; j < K; ++j) {
           double* dst = (j == K - 1) ? out : bufs[j & 1];
+          // the K chained sweeps' relative errors add up: each gets tol / K
           SweepOut so;
-          RETCHK(sweep(op, P, src, nullptr, 0.0, dst, tol, op->max_degree, st, so));
+          RETCHK(sweep(op, P, src, nullptr, 0.0, dst, tol / K, op->max_degree, st, so));
           account(acc, so);
           if (so.status == 2) return status_to_code(2);
           if (so.status != 1) {

@@ -32,6 +32,34 @@ constexpr int kMaxGrid2 = ADL_MAX_GRID2;
 
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
 
+// Stopping rule of a Newton-Leja sweep (the paper leaves it open; tol is the
+// desired accuracy of the result, Sec. 3): the truncation error of the
+// degree-m interpolant is estimated by the norms of its last kStopWindow
+// terms, and the sweep stops at the first m >= kStopWindow with
+//   ||d_{m-4} y_{m-4}|| + ... + ||d_m y_m|| <= tol ||p_m||
+// (summed oldest first).  Single terms rise and fall by orders of magnitude
+// from one Leja point to the next on wide intervals, so one small term is no
+// estimate of the error.  The norms of the kStopWindow - 1 terms before a
+// decided launch are kept in the control block, slot m mod (kStopWindow - 1).
+constexpr int kStopWindow = 5;
+constexpr int kStopHist = kStopWindow - 1;
+
+// The stopping test of term m (norm tn of its term d_m y_m, squared norm pn2
+// of p_m) against the ring `hist` of the norms of terms m - 4 .. m - 1,
+// which it then updates with tn.
+__device__ __forceinline__ bool window_stop(double (&hist)[kStopHist], int m, double tn, double pn2, double tol) {
+  bool stop = false;
+  if (m >= kStopWindow) {
+    double est = 0.0;
+#pragma unroll
+    for (int j = kStopHist; j >= 1; --j) est += hist[(m - j) % kStopHist];
+    est += tn;
+    stop = est <= tol * sqrt(pn2);
+  }
+  hist[m % kStopHist] = tn;
+  return stop;
+}
+
 // Per-sweep control block in device memory.  Written only by the last block
 // of a launch (fixed-order reduction), read by the next launch and the host.
 struct Ctl {
@@ -45,6 +73,7 @@ struct Ctl {
   double gmin;          // Gershgorin result
   int iters;
   int pad[3];
+  double hist[kStopHist];  // ||d_m y_m|| of the latest decided terms, slot m mod kStopHist
 };
 static_assert(sizeof(Ctl) <= 128, "ctl size");
 
@@ -116,7 +145,7 @@ struct LejaArgs {
   double shift2;     // c + gamma xi_{k+1} (term k+2)
   double invg;       // 1 / gamma
   double d0, dk1, dk2;  // d_0 (first launch), d_{k+1}, d_{k+2}
-  double tol2;
+  double tol;        // stopping tolerance (window test above)
   int k;             // terms before this launch
   int nterms;        // terms of this launch
   int max_degree;
@@ -157,6 +186,22 @@ Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint = 0);
 hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // tiling of the four-term kernel: strips of 56*vec output columns, 8 output rows per block
 Tiling make_tiling4(int nx, int ny, int vec_hint = 0);
+// A four-term block with output rows J0 .. J0 + kFourTermRows - 1 (J0 a
+// multiple of kFourTermRows, at most ny - 1) reads grid rows
+// J0 - kFourTermTerms .. J0 + kFourTermRows - 1 + kFourTermTerms: a frame of
+// one row per stage on each side, plus the stencil's own neighbour row.  The
+// row rule wraps a periodic row index once, so on a periodic grid every such
+// row lands inside the grid only if the first block's lowest row is >= -ny
+// and the last block's highest row is <= 2 ny - 1 (true for every ny >= 11,
+// false for ny = 3, 4, 5 and 9).  Grids where it fails run two terms per
+// launch.
+constexpr int kFourTermRows = 8;   // output rows per block
+constexpr int kFourTermTerms = 4;  // Newton terms per launch
+inline bool four_term_rows_fit(int ny, int bc) {
+  if (bc != BC_PERIODIC) return true;  // rows outside a Dirichlet grid are zero or edge rows, never loaded
+  const int j0_last = kFourTermRows * ((ny - 1) / kFourTermRows);
+  return -kFourTermTerms >= -ny && j0_last + kFourTermRows - 1 + kFourTermTerms <= 2 * ny - 1;
+}
 
 // power iteration launch k: w = A(x) / ||x||, stopping test of iteration k
 struct PowerArgs {

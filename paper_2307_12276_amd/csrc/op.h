@@ -94,15 +94,21 @@ struct adl_op {
   int host_wait = 1;        // 1: spin on the mirror when there is one; 0: copy back + synchronise
   std::vector<Plan> plans;  // small cache
   int plan_next = 0;
-  // kernel profiling of the Newton-Leja iteration kernel
+  // kernel profiling of the Newton-Leja iteration kernel: totals, and per
+  // launch kind (ADL_LAUNCH_FIRST, _ONE, _TWO, _FOUR)
   bool prof = false;
   double prof_ms = 0.0, prof_bytes = 0.0;
   long long prof_launches = 0;
+  double kind_ms[4] = {0, 0, 0, 0}, kind_bytes[4] = {0, 0, 0, 0};
+  long long kind_launches[4] = {0, 0, 0, 0}, kind_terms[4] = {0, 0, 0, 0};
   std::vector<hipEvent_t> evs;
 };
 
 
 namespace adl {
+// Records the message of a failing entry point (returned by adl_last_error)
+// and returns code.
+int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 // cached plan of the op (l, alpha, h)
 Plan& get_plan(adl_op* op, int l, double alpha, double h);
 int substeps_for(double alpha, double dt, double rho_max);

@@ -254,17 +254,27 @@ __device__ __forceinline__ void leja_decide(const LejaArgs& A) {
   }
   block_allreduce<10, 8>(v);
   if (v[9] != 0.0) return;  // decided by an earlier launch
+  // Terms up to `done` were decided already: a chunk's closing decision
+  // launch decides the chunk's last launch, and the first launch of the next
+  // chunk is handed the same launch.  Each term enters the window once.
+  const int done = A.ctl->degree;
+  if (A.k_prev + nt <= done) return;
+  // norms of the terms before the decided ones (the window of the test)
+  double hist[kStopHist];
+#pragma unroll
+  for (int i = 0; i < kStopHist; ++i) hist[i] = A.ctl->hist[i];
   int stop = 0, status = 0, degree = A.k_prev + A.nterms_prev;
   double tn2 = 0.0, pn2 = 0.0;
   for (int t = 0; t < nt && !stop; ++t) {
+    const int deg = A.k_prev + t + 1;
+    if (deg <= done) continue;
     tn2 = v[2 * t];
     pn2 = v[2 * t + 1];
-    const int deg = A.k_prev + t + 1;
     if (!isfinite(tn2) || !isfinite(pn2)) {
       stop = 1; status = 2; degree = deg;
     } else if (deg == 1 && v[8] == 0.0) {
       stop = 1; status = 1; degree = 0;
-    } else if (tn2 <= A.tol2 * pn2) {
+    } else if (window_stop(hist, deg, sqrt(tn2), pn2, A.tol)) {
       stop = 1; status = 1; degree = deg;
     } else if (deg >= A.max_degree) {
       stop = 1; status = 3; degree = deg;
@@ -274,6 +284,8 @@ __device__ __forceinline__ void leja_decide(const LejaArgs& A) {
     Ctl* c = A.ctl;
     c->tn2 = tn2;
     c->pn2 = pn2;
+#pragma unroll
+    for (int i = 0; i < kStopHist; ++i) c->hist[i] = hist[i];
     c->degree = degree;
     c->status = status;
     __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -585,6 +597,9 @@ constexpr int kRing4 = 16;                // rows of each LDS ring
 constexpr int kW4 = ADL_WAVES4;           // waves per block
 constexpr int kOW4 = (kR4 + kW4 - 1) / kW4;  // output rows per wave
 static_assert(kQ4 <= kRing4, "ring rows");
+// stage 1 loads rows J0 - kT4 .. J0 + kR4 - 1 + kT4 (the host's periodic
+// row check, four_term_rows_fit, assumes this geometry)
+static_assert(kR4 == kFourTermRows && kT4 == kFourTermTerms, "four-term geometry");
 
 // Field rows kept in LDS for stages 2-4: stage 1 stores the centre row of
 // each field it loads (after the row rule: edge rows for kxx and kyy, zero

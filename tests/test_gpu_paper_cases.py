@@ -66,12 +66,12 @@ def test_paper_case_parity(case, scheme):
 def test_work_precision_exact_in_time(case):
     """Cases I (ring, T = 0.75, one step) and II (spiral 2 with advection and
     the sources of eq. 8, T = 0.85, steps of 1e4 dt_CFL) at 64 x 64, tol 1e-2
-    .. 1e-10, the GPU's own Gershgorin bound: error against the exact
-    solution falls with the tolerance from 1e-3 on, the matvec count never
-    falls, and for tol <= 1e-6 the error stays within 1000 tol.  (tol is the
-    threshold of the stopping rule on one Newton term, not an error bound:
-    with several substeps the sweep can stop while the terms still
-    oscillate; measured factors at 64^2 reach ~600 for Case I.)"""
+    .. 1e-10, the GPU's own Gershgorin bound: tol is the desired accuracy of
+    the solution (Sec. 3), so for tol <= 1e-4 the error against the exact
+    solution stays within 10 tol -- the bound the oracle's stopping rule is
+    pinned to on these problems (tests/test_paper_cases.py, measured up to
+    5 tol) -- the error falls with the tolerance from 1e-3 on (to 5 % at
+    saturation) and the matvec count never falls."""
     w = W.paper_case(case, 64)
     ref = R.exact_solution(w)
     op = make_op(w)
@@ -83,11 +83,11 @@ def test_work_precision_exact_in_time(case):
         rows.append((tol, mv, rel(u, ref)))
     print("\ncase %s, 64^2, %d step(s) of %.3g dt_CFL:" % (case, w.steps, w.dt / w.extra["dt_cfl"]))
     for tol, mv, err in rows:
-        print("  tol %.0e  matvecs %6d  rel. error %.2e" % (tol, mv, err))
+        print("  tol %.0e  matvecs %6d  rel. error %.2e  error / tol %.2f" % (tol, mv, err, err / tol))
     errs = [r[2] for r in rows[1:]]
-    assert all(a > b for a, b in zip(errs, errs[1:])), errs
+    assert all(b <= 1.05 * a for a, b in zip(errs, errs[1:])), errs
     assert all(a[1] <= b[1] for a, b in zip(rows, rows[1:]))
-    assert all(err <= 1000 * tol for tol, _, err in rows if tol <= 1e-6)
+    assert all(err <= 10 * tol for tol, _, err in rows if tol <= 1e-4), rows
 
 
 @pytest.mark.parametrize("case", ["III", "IV"])

@@ -111,3 +111,44 @@ def test_xcd_block_order_is_a_bijection():
         for x in range(min(n, 8)):
             seq = [got[b] for b in range(x, n, 8)]
             assert seq == list(range(seq[0], seq[0] + len(seq)))
+
+
+def test_four_term_rows_stay_inside_periodic_grids():
+    """Row indices of a four-term launch, restated from the kernel: a block
+    with output rows J0 .. J0 + 7 (J0 = 8 b <= ny - 1) computes stage 1 on
+    rows J0 - 3 .. J0 + 10 and loads their neighbours, J0 - 4 .. J0 + 11; a
+    periodic row index is wrapped once (r + ny below 0, r - ny from ny).
+    The host's test for four terms per launch on a periodic grid (lowest row
+    >= -ny, highest row of the last block <= 2 ny - 1) holds exactly where
+    every load stays inside the grid: always from 11 rows up, never at
+    ny = 3, 4, 5 and 9 (which run two terms per launch)."""
+    def rows_inside(ny):
+        for J0 in range(0, ny, 8):
+            for r in range(J0 - 4, J0 + 12):
+                m = r + ny if r < 0 else (r - ny if r >= ny else r)
+                if not 0 <= m < ny:
+                    return False
+        return True
+
+    def host_rule(ny):
+        j0_last = 8 * ((ny - 1) // 8)
+        return -4 >= -ny and j0_last + 8 - 1 + 4 <= 2 * ny - 1
+
+    for ny in range(3, 300):
+        assert rows_inside(ny) == host_rule(ny), ny
+    assert [ny for ny in range(3, 300) if not rows_inside(ny)] == [3, 4, 5, 9]
+
+
+def test_batch_errors_reach_last_error(capfd):
+    """A rejected batch call reports through adl_last_error like every other
+    entry point, and the library prints nothing."""
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.adl_op_set_limits(None, 10, 1.0) == A.EINVAL  # leaves a message of its own
+    rc = L.adl_batch_create(0, None, None, 0, 0, ctypes.byref(h))
+    assert rc == A.EINVAL
+    assert b"nbins" in L.adl_last_error()
+    assert L.adl_batch_set_tile_rows(None, 4) == A.EINVAL
+    assert b"tile rows" in L.adl_last_error()
+    out, err = capfd.readouterr()
+    assert out == "" and err == ""

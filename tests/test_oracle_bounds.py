@@ -86,6 +86,40 @@ def test_node_eigen_and_features():
     assert f[8] == pytest.approx(-3.0)
 
 
+def test_field_features_every_entry():
+    """All nine statistics against a per-node loop over 2 x 2 eigvalsh and
+    math.hypot, on fields built so that every entry differs from the others
+    (max against mean, k_par against k_perp, |a| against its components, hx
+    against hy), with one indefinite node whose negative k_perp is clipped to
+    0 (plus 1e-30)."""
+    ny, nx = 5, 8
+    rng = np.random.default_rng(11)
+    Dxx = rng.uniform(0.5, 3.0, (ny, nx))
+    Dyy = rng.uniform(0.01, 0.2, (ny, nx))
+    Dxy = rng.uniform(-0.05, 0.05, (ny, nx))
+    Dxy[2, 3] = 2.0  # Dxx Dyy < Dxy^2 there: k_perp < 0
+    ax = rng.uniform(-1.0, 1.0, (ny, nx))
+    ay = rng.uniform(-3.0, 3.0, (ny, nx))
+    hx, hy, dt = 0.02, 0.125, 3e-4
+    kpar, kperp, amag = [], [], []
+    for j in range(ny):
+        for i in range(nx):
+            lo, hi = np.linalg.eigvalsh([[Dxx[j, i], Dxy[j, i]], [Dxy[j, i], Dyy[j, i]]])
+            kpar.append(hi)
+            kperp.append(max(lo, 0.0) + 1e-30)
+            amag.append(math.hypot(ax[j, i], ay[j, i]))
+    assert min(kperp) == 1e-30
+    want = [math.log10(max(kpar)), math.log10(sum(kpar) / len(kpar)),
+            math.log10(max(kperp)), math.log10(sum(kperp) / len(kperp)),
+            max(amag), sum(amag) / len(amag), math.log10(hx), math.log10(hy), math.log10(dt)]
+    assert len(set(np.round(want, 6))) == 9
+    got = features.field_features(Dxx, Dxy, Dyy, ax, ay, hx, hy, dt)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-13)
+    # constant advection (scalars) broadcasts over the grid
+    got = features.field_features(Dxx, Dxy, Dyy, 0.6, -0.8, hx, hy, dt)
+    assert got[4] == pytest.approx(1.0, rel=1e-15) and got[5] == pytest.approx(1.0, rel=1e-15)
+
+
 def test_mlp_gradient_finite_differences():
     W0 = mlp.init_params(3)
     X = np.random.default_rng(0).standard_normal((5, 9))

@@ -115,6 +115,48 @@ def test_diagonal_operator_closed_form(l, rho_dt):
     assert st["degrees"][0] < 6.0 * math.sqrt(rho_dt) + 10
 
 
+@pytest.mark.parametrize("l", [0, 1, 2])
+@pytest.mark.parametrize("rho_dt,rho_max", [(1600.0, 1600.0), (1600.0, 400.0), (3000.0, 500.0)])
+def test_tolerance_is_the_accuracy_on_a_diagonal_operator(l, rho_dt, rho_max):
+    """tol as the desired accuracy of the result (Sec. 3): for tol = 1e-4 and
+    1e-6, with one sweep and with K = 4 and 6 substeps (phi_0 chains K
+    sweeps; phi_1 and phi_2 use the substep recursion), the error against
+    the closed form phi_l(lambda dt) v stays within 10 tol, both for a vector
+    spread over the whole spectrum and for one concentrated on its smooth end
+    (where the Newton terms oscillate most).  A one-term stopping test fails
+    this (up to 40 tol on the paper's Case I)."""
+    lam = -np.linspace(0.0, 1.0, 3000) * rho_dt
+    for v in (W.random_vector(3000, 7), np.exp(lam / (0.01 * rho_dt))):
+        ex = phi.phi(l, lam) * v
+        for tol in (1e-4, 1e-6):
+            st = {}
+            p = leja.phi_apply(lambda x: lam * x, l, 1.0, v, -rho_dt, tol, rho_max=rho_max, stats=st)
+            assert st["substeps"] == math.ceil(rho_dt / rho_max)
+            assert np.linalg.norm(p - ex) <= 10 * tol * np.linalg.norm(ex), (tol, st)
+
+
+def test_stopping_window():
+    """The sweep stops at the first degree m >= STOP_WINDOW whose last
+    STOP_WINDOW term norms sum to at most tol ||p_m||: recomputed here from
+    the unstopped term sequence of a diagonal operator."""
+    lam = -np.linspace(0.0, 1.0, 2000) * 900.0
+    v = W.random_vector(2000, 5)
+    d = leja.newton_coefficients(1, -900.0, 1.0)
+    xi = leja.leja_points()
+    c, g = -450.0, 225.0
+    y, p, tn, pn = v.copy(), d[0] * v, [], []
+    for k in range(300):
+        y = (lam * y - (c + g * xi[k]) * y) / g
+        p = p + d[k + 1] * y
+        tn.append(np.linalg.norm(d[k + 1] * y))
+        pn.append(np.linalg.norm(p))
+    for tol in (1e-3, 1e-6, 1e-9):
+        want = next(m for m in range(leja.STOP_WINDOW, 301)
+                    if sum(tn[m - leja.STOP_WINDOW:m]) <= tol * pn[m - 1])
+        _, m, conv = leja.newton_sweep(lambda x: lam * x, v, -900.0, 1.0, d, tol)
+        assert conv and m == want, (tol, m, want)
+
+
 def small_op(bc=O.PERIODIC, n=(9, 7), seed=2, scale=1.0):
     nx, ny = n
     Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=seed, field_advection=True)
@@ -215,14 +257,17 @@ def test_zero_vector_and_zero_operator():
     assert np.allclose(leja.phi_combo(A, v, 2 * v, 0.5, 0.0, 1e-10), 0.5 * (v + v))
 
 
-def test_null_space_vector_converges_in_one_term():
-    """A constant vector is in the periodic null space: phi_l(A dt) c = c / l!."""
+def test_null_space_vector_converges_at_the_first_window():
+    """A constant vector is in the periodic null space: every Newton term
+    after the first vanishes (y_1 = A c / gamma = 0, up to rounding), so the
+    sweep stops as soon as the stopping window is full, with
+    phi_l(A dt) c = c / l!."""
     op = small_op()
     A = lambda x: O.apply(op, x)
     c = np.full(op.shape, 3.0)
     st = {}
     p = leja.phi_apply(A, 1, 0.05, c, -500.0, 1e-10, stats=st)
-    assert st["degrees"] == [1]
+    assert st["degrees"] == [leja.STOP_WINDOW]
     assert np.allclose(p, c, rtol=1e-12)
 
 

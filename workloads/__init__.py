@@ -284,6 +284,22 @@ def roofline_shape(n: int = 4096, seed: int = 0, steps: int = 1, tol: float = 1e
     return w
 
 
+# stream-function seeds of the learned predictor's training samples are the
+# sample indices (learned_sample), 0 .. 9999 for the 10 000-sample set; the
+# evaluation field takes a seed outside that range
+C5_EVAL_SEED = 1_000_001
+
+
+def c5_learned_eval(n: int = 4096, steps: int = 5, tol: float = 1e-8, seed: int = C5_EVAL_SEED) -> Workload:
+    """Evaluation workload of the learned interval: the stream-function
+    recipe (k_par = 1, k_par/k_perp = 1e4, a = (0.2, 0), pulsed source,
+    dt = 100 dt_CFL) on an n x n periodic grid with a stream function no
+    training sample used, FP32 fields, exponential midpoint, tol 1e-8."""
+    w = c3_stream_function(n=n, seed=seed, steps=steps, tol=tol, storage=1, scheme="midpoint")
+    w.name = "learned-eval-stream-%d" % n
+    return w
+
+
 # --------------------------------------------------------------------------
 # the paper's own test problems (Sec. 3)
 # --------------------------------------------------------------------------
