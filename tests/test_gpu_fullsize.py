@@ -178,8 +178,10 @@ def test_learned_interval_4096_fp32_storage():
           "rel err %.2e; FP64 reference %d matvecs; mass defect %.1e / %.1e / %.1e"
           % (tl, info["rho_hat"], info["alpha"], info["gershgorin"], mvl, fbl, el, tp, mvp, ep, mv_ref,
              dl, dp, d_ref))
+    # (the bound's cost is compared in test_gpu_learned.py, away from the
+    # oracle processes this module runs beside the GPU work)
     assert el <= 1e-5 and ep <= 1e-5
-    assert tl < tp
+    assert fbl == 0
     assert max(dl, dp, d_ref) < 1e-10
 
 
