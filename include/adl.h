@@ -202,6 +202,23 @@ int adl_apply(adl_op* op, const double* x, double* y, void* stream);
 int adl_spectral_bound(adl_op* op, int method, int max_iter, double rtol, uint64_t seed,
                        double* alpha_out, int* iters_out, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the Gershgorin interval end of
+ * adl_spectral_bound(ADL_BOUND_GERSHGORIN) -- the same reduction and the
+ * same value as on an FP64 op of these fields -- computed from the caller's
+ * unscaled device fields (Dxx, Dxy, Dyy [ny][nx] FP64; ax, ay fields or both
+ * NULL for the constants ax_c, ay_c; grid and bc as for adl_op_create) with
+ * no op, no workspace and no allocation.  alpha_out: device, one double,
+ * written on `stream` (the call enqueues two kernels and returns without
+ * synchronising).  The reduction's scratch (block partials and a counter,
+ * 8.4 KB) is a static device array of the library, one per GPU, kept until
+ * the process ends; every call on a GPU shares it, so calls that overlap on
+ * one GPU (different streams, no ordering) race.  At most 1024 reduction
+ * blocks, i.e. grids of up to 2^31 points (ADL_EINVAL beyond). */
+int adl_gershgorin_bound_noalloc(int nx, int ny, double hx, double hy, int bc, const double* Dxx,
+                                 const double* Dxy, const double* Dyy, const double* ax, const double* ay,
+                                 double ax_c, double ay_c, double* alpha_out, void* stream);
+
 /* The raw estimate lambda (before the safety factor and the Gershgorin cap)
  * of the op's last power iteration; ADL_EBOUND if none has run. */
 int adl_last_power_estimate(const adl_op* op, double* lambda);

@@ -86,6 +86,7 @@ _SIG = {
     "adl_spectral_bound": (_I, [_P, _I, _I, _D, ctypes.c_uint64, ctypes.POINTER(_D),
                                 ctypes.POINTER(_I), _P]),
     "adl_set_bound": (_I, [_P, _D]),
+    "adl_gershgorin_bound_noalloc": (_I, [_I, _I, _D, _D, _I, _P, _P, _P, _P, _P, _D, _D, _P, _P]),
     "adl_last_power_estimate": (_I, [_P, ctypes.POINTER(_D)]),
     "adl_get_bound": (_I, [_P, ctypes.POINTER(_D)]),
     "adl_leja_phi": (_I, [_P, _I, _D, _P, _P, _D, _I, ctypes.POINTER(Stats), _P]),
@@ -174,6 +175,22 @@ def newton_coefficients(l: int, alpha: float, h: float, n: int):
     out = (ctypes.c_double * n)()
     _check(lib().adl_newton_coefficients(l, alpha, h, n, out))
     return list(out)
+
+
+def gershgorin_bound_noalloc(Dxx, Dxy, Dyy, hx: float, hy: float, bc: int, alpha_out, ax=None, ay=None,
+                             ax_c: float = 0.0, ay_c: float = 0.0, stream=None):
+    """adl_gershgorin_bound_noalloc: the Gershgorin interval end of the
+    unscaled FP64 fields [ny][nx] into alpha_out (device tensor of one FP64
+    value), enqueued on the stream without allocating or synchronising."""
+    import torch
+    ny, nx = Dxx.shape
+    shape = (ny, nx)
+    _check(lib().adl_gershgorin_bound_noalloc(
+        int(nx), int(ny), float(hx), float(hy), int(bc), _ptr(Dxx, torch.float64, shape, "Dxx"),
+        _ptr(Dxy, torch.float64, shape, "Dxy"), _ptr(Dyy, torch.float64, shape, "Dyy"),
+        _ptr(ax, torch.float64, shape, "ax"), _ptr(ay, torch.float64, shape, "ay"), float(ax_c), float(ay_c),
+        _ptr(alpha_out, torch.float64, (1,), "alpha_out"), _stream(stream)))
+    return alpha_out
 
 
 def workspace_bytes(nx: int, ny: int, storage: int = STORAGE_FP64, max_degree: int = 0) -> int:

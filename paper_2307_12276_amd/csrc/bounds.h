@@ -9,11 +9,19 @@
 
 namespace adl {
 
+// Scale factors of unscaled FP64 fields (Dxx, Dxy, Dyy, ax, ay as the
+// caller holds them): the stored form is field * scale, computed here with
+// the same product the field preparation stores.
+struct FieldScale {
+  double xx, xy, yy, ax, ay;
+};
+
 // Gershgorin bound: min over rows of A_ii - sum_{j != i} |A_ij| (one thread
 // per node), as blocks b of nb; the total goes to ctl->gmin and, if given, *gout.
-template <typename TF, bool ADVF>
+// RAW: F points at unscaled FP64 fields, scaled by sc on load.
+template <typename TF, bool ADVF, bool RAW = false>
 __device__ __forceinline__ void gershgorin_blocks(const FieldView& F, double* partials, Ctl* ctl, int nb, int b,
-                                                  double* gout) {
+                                                  double* gout, FieldScale sc = FieldScale{}) {
   const int nx = F.nx, ny = F.ny;
   const bool per = F.bc == BC_PERIODIC;
   const TF* kxx = reinterpret_cast<const TF*>(F.kxx);
@@ -31,17 +39,27 @@ __device__ __forceinline__ void gershgorin_blocks(const FieldView& F, double* pa
     const int iW = i > 0 ? i - 1 : (per ? nx - 1 : i);
     const int jN = j + 1 < ny ? j + 1 : (per ? 0 : j);
     const int jS = j > 0 ? j - 1 : (per ? ny - 1 : j);
-    auto at = [&](const TF* a, int jj, int ii) { return (double)a[(long)jj * nx + ii]; };
-    const double kC = at(kxx, j, i), kE = at(kxx, j, iE), kW = at(kxx, j, iW);
-    const double gC = at(kyy, j, i), gN = at(kyy, jN, i), gS = at(kyy, jS, i);
-    const double mE = hasE ? at(kxy, j, iE) : 0.0, mW = hasW ? at(kxy, j, iW) : 0.0;
-    const double mN = hasN ? at(kxy, jN, i) : 0.0, mS = hasS ? at(kxy, jS, i) : 0.0;
+    auto at = [&](const TF* a, int jj, int ii, double s) {
+      const double v = (double)a[(long)jj * nx + ii];
+      if constexpr (RAW) {
+        // the product rounded on its own, as the field preparation stores it
+        // (not fused into a following addition)
+#pragma clang fp contract(off)
+        return v * s;
+      } else {
+        return v;
+      }
+    };
+    const double kC = at(kxx, j, i, sc.xx), kE = at(kxx, j, iE, sc.xx), kW = at(kxx, j, iW, sc.xx);
+    const double gC = at(kyy, j, i, sc.yy), gN = at(kyy, jN, i, sc.yy), gS = at(kyy, jS, i, sc.yy);
+    const double mE = hasE ? at(kxy, j, iE, sc.xy) : 0.0, mW = hasW ? at(kxy, j, iW, sc.xy) : 0.0;
+    const double mN = hasN ? at(kxy, jN, i, sc.xy) : 0.0, mS = hasS ? at(kxy, jS, i, sc.xy) : 0.0;
     double aE = F.axc, aW = F.axc, aN = F.ayc, aS = F.ayc;
     if constexpr (ADVF) {
-      aE = hasE ? at(fax, j, iE) : 0.0;
-      aW = hasW ? at(fax, j, iW) : 0.0;
-      aN = hasN ? at(fay, jN, i) : 0.0;
-      aS = hasS ? at(fay, jS, i) : 0.0;
+      aE = hasE ? at(fax, j, iE, sc.ax) : 0.0;
+      aW = hasW ? at(fax, j, iW, sc.ax) : 0.0;
+      aN = hasN ? at(fay, jN, i, sc.ay) : 0.0;
+      aS = hasS ? at(fay, jS, i, sc.ay) : 0.0;
     }
     const double fe = 0.5 * (kC + kE), fw = 0.5 * (kC + kW), fn = 0.5 * (gC + gN), fs = 0.5 * (gC + gS);
     const double cen = -(fe + fw + fn + fs);
