@@ -14,7 +14,7 @@ The paper's recipe (Sec. 2, "Leja method" paragraph):
 Readings of what the paper leaves open (all listed in the design notes):
   * Leja points: xi_0 = 2, then xi_k maximises prod_{j<k} |xi - xi_j| over
     [-2, 2]; ties (the first is at k = 3, +-2/sqrt 3) go to the smaller xi.
-  * Stopping (tol is the desired accuracy of the result, Sec. 3): the error
+  * Stopping (tol is the accuracy asked of the result, as Sec. 3 uses it): the error
     of the degree-m interpolant is estimated by the norms of the last
     STOP_WINDOW Newton terms, and the sweep stops at the first m >= STOP_WINDOW
     with

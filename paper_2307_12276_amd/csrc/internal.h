@@ -33,7 +33,7 @@ constexpr int kMaxGrid2 = ADL_MAX_GRID2;
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
 
 // Stopping rule of a Newton-Leja sweep (the paper leaves it open; tol is the
-// desired accuracy of the result, Sec. 3): the truncation error of the
+// accuracy asked of the result, as Sec. 3 uses it): the truncation error of the
 // degree-m interpolant is estimated by the norms of its last kStopWindow
 // terms, and the sweep stops at the first m >= kStopWindow with
 //   ||d_{m-4} y_{m-4}|| + ... + ||d_m y_m|| <= tol ||p_m||

@@ -66,8 +66,8 @@ def test_paper_case_parity(case, scheme):
 def test_work_precision_exact_in_time(case):
     """Cases I (ring, T = 0.75, one step) and II (spiral 2 with advection and
     the sources of eq. 8, T = 0.85, steps of 1e4 dt_CFL) at 64 x 64, tol 1e-2
-    .. 1e-10, the GPU's own Gershgorin bound: tol is the desired accuracy of
-    the solution (Sec. 3), so for tol <= 1e-4 the error against the exact
+    .. 1e-10, the GPU's own Gershgorin bound: tol is the accuracy asked of
+    the solution (as Sec. 3 uses it), so for tol <= 1e-4 the error against the exact
     solution stays within 10 tol -- the bound the oracle's stopping rule is
     pinned to on these problems (tests/test_paper_cases.py, measured up to
     5 tol) -- the error falls with the tolerance from 1e-3 on (to 5 % at

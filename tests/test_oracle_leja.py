@@ -118,7 +118,7 @@ def test_diagonal_operator_closed_form(l, rho_dt):
 @pytest.mark.parametrize("l", [0, 1, 2])
 @pytest.mark.parametrize("rho_dt,rho_max", [(1600.0, 1600.0), (1600.0, 400.0), (3000.0, 500.0)])
 def test_tolerance_is_the_accuracy_on_a_diagonal_operator(l, rho_dt, rho_max):
-    """tol as the desired accuracy of the result (Sec. 3): for tol = 1e-4 and
+    """tol as the accuracy asked of the result (as Sec. 3 uses it): for tol = 1e-4 and
     1e-6, with one sweep and with K = 4 and 6 substeps (phi_0 chains K
     sweeps; phi_1 and phi_2 use the substep recursion), the error against
     the closed form phi_l(lambda dt) v stays within 10 tol, both for a vector

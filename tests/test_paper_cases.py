@@ -88,7 +88,7 @@ def test_exact_case_ii_reference():
 @pytest.mark.parametrize("case,n", [("I", 24), ("I", 64), ("II", 24)])
 def test_oracle_work_precision_cases_i_ii(case, n):
     """Cases I and II, whose solutions are exact in time (Sec. 3, Fig. 3):
-    with tol the desired accuracy, the error against the exact solution stays
+    with tol the accuracy asked of the result, the error against the exact solution stays
     within 10 tol for every tol from 1e-4 to 1e-10, and the matvec count
     rises as tol falls.  Case I at 64^2 is one phi_0 step over the whole
     interval in K = 5 substeps (the chained sweeps share tol), Case II at
