@@ -270,7 +270,8 @@ def chosen_vs_plain(steps=10, tol=1e-9):
              per-bin exponential midpoint steps;
     chosen = FP32 fields, learned interval per bin (field statistics + MLP
              + Gershgorin cap, power-iteration fallback), all bins advanced by
-             one hipGraph launch per step.
+             the batched kernels, every launch covering all bins (eager;
+             the captured-hipGraph replay of the same step is timed too).
     Both at the same tolerance; reported: steps/s of the steps, time to
     solution including the interval estimation, and the relative difference
     of the chosen result from the plain FP64 result (max over bins)."""
@@ -323,17 +324,30 @@ def chosen_vs_plain(steps=10, tol=1e-9):
     fb = 0
     batch.bind(uc, S)
     for n in range(steps):
-        st = batch.midpoint_step(None, None, dt, tol, use_graph=True)
-        mv_c += sum(x["matvecs"] for x in st)
-        fb += sum(x["fallback"] for x in st)
+        st = batch.midpoint_step(None, None, dt, tol, use_graph=False).array
+        mv_c += int(st["matvecs"].sum())
+        fb += int(st["fallback"].sum())
     torch.cuda.synchronize()
     t_steps_c = time.perf_counter() - t0
+    # the same steps replayed as a captured hipGraph (same results; slower
+    # to launch on this runtime), from a copy of the state
+    ug = [dev_tensor(b.u0) for b in bins]
+    batch.bind(ug, S)
+    batch.midpoint_step(None, None, dt, tol, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(steps):
+        batch.midpoint_step(None, None, dt, tol, use_graph=True)
+    torch.cuda.synchronize()
+    t_steps_g = time.perf_counter() - t0
     diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(uc, up))
     res.update({
         "plain": {"steps_per_s": steps / t_steps_p, "bound_s": t_bound_p, "power_iterations": pits,
                   "time_to_solution_s": t_bound_p + t_steps_p, "matvecs": mv_p},
         "chosen": {"steps_per_s": steps / t_steps_c, "bound_s": t_bound_c, "tile_rows": best_rows,
-                   "time_to_solution_s": t_bound_c + t_steps_c, "matvecs": mv_c, "fallbacks": fb},
+                   "time_to_solution_s": t_bound_c + t_steps_c, "matvecs": mv_c, "fallbacks": fb,
+                   "launch": "eager (the step's launches enqueued one by one)",
+                   "graph_steps_per_s": steps / t_steps_g},
         "speedup_steps": t_steps_p / t_steps_c,
         "speedup_time_to_solution": (t_bound_p + t_steps_p) / (t_bound_c + t_steps_c),
         "max_rel_diff_chosen_vs_plain_fp64": diff})
@@ -382,7 +396,7 @@ def profile_bins(steps=4, tile_rows=16, tol=1e-9):
     batch.bind(u, S)
     mv = 0
     for _ in range(steps):
-        mv += sum(x["matvecs"] for x in batch.midpoint_step(None, None, dt, tol))
+        mv += int(batch.midpoint_step(None, None, dt, tol).array["matvecs"].sum())
     torch.cuda.synchronize()
     log("bins: %d steps, %d matvecs, tile rows %d" % (steps, mv, tile_rows))
 

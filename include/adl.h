@@ -284,7 +284,12 @@ int adl_batch_set_term_fusion(adl_batch* batch, int two_terms);
 
 /* Autotuner: times the launches of one step (stage and sweep; u is not
  * modified) for each of the ncand candidate tile heights (host array) and
- * installs the fastest; best_rows / best_ms (host, may be NULL) receive it. */
+ * installs the fastest; best_rows / best_ms (host, may be NULL) receive it.
+ * Results are cached for the life of the process by (GPU architecture,
+ * storage and advection kind, columns per lane, terms per launch, the
+ * candidates, the bins' grid shapes): a later call with the same key, on
+ * this batch or another, installs the cached height and its time without
+ * timing again. */
 int adl_batch_autotune(adl_batch* b, double* const* u, const double* const* S_half, double dt,
                        double tol, const int* candidates, int ncand, int* best_rows,
                        double* best_ms, void* stream);

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -72,7 +73,7 @@ struct BinCtl {
   int stop;
   int status;  // 0 running, 1 converged, 2 non-finite, 3 degree cap
   int degree;
-  int pad;
+  int upd;     // 1: u already advanced by an earlier update launch of this step
   double tn2, pn2;
   double hist[kStopHist];  // term norms of the stopping window (as in Ctl)
 };
@@ -964,14 +965,14 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BinCtl* ctl, int nbins
   }
 }
 
-// u_b += dt p_b for converged bins (one wave per tile)
+// u_b += dt p_b for converged bins not advanced yet (one wave per tile)
 template <int VEC>
 __global__ __launch_bounds__(64 * kBWaves) void batch_update_kernel(BatchArgs A, double* const* u) {
   const int gt = wave_unit();
   if (gt >= A.total_tiles) return;
   const int b = __builtin_amdgcn_readfirstlane(A.tile_bin[gt]);
   const BinDesc& B = A.bins[b];
-  if (!B.active || A.ctl[b].status != 1 || A.ctl[b].degree == 0) return;  // degree 0: p = 0
+  if (!B.active || A.ctl[b].status != 1 || A.ctl[b].upd || A.ctl[b].degree == 0) return;  // degree 0: p = 0
   const double* pb = B.pb[pbuf_index(A.ctl[b].degree, A.two)];
   const int t = gt - B.tile_base;
   const int rb = t / B.ncb, cb = t - rb * B.ncb;
@@ -987,6 +988,30 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_update_kernel(BatchArgs A,
 #pragma unroll
     for (int v = 0; v < VEC; ++v) uu[v] = uu[v] + B.dt * pp[v];
     str<double, VEC>(ub + ro, col0, uu);
+  }
+}
+
+// Before a step's sweep continues past the graph: bins that have converged
+// were advanced by the graph's update launch; mark them so that the update
+// after the continuation leaves them alone.
+__global__ __launch_bounds__(256) void batch_mark_kernel(BinCtl* ctl, int nbins) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nbins && ctl[b].status == 1) ctl[b].upd = 1;
+}
+
+// The bins' outcomes for the host: one wave copies the control blocks into
+// coherent pinned host memory, releases them at system scope, then writes
+// the step's publication number (a device counter it advances), which the
+// host spins on instead of copying the blocks back and synchronising.
+__global__ __launch_bounds__(64) void batch_publish_kernel(const BinCtl* __restrict__ ctl, BinCtl* hbins, int nbins,
+                                                           int* dseq, int* hseq) {
+  const int lane = threadIdx.x;
+  for (int b = lane; b < nbins; b += 64) hbins[b] = ctl[b];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the copies before the number
+  if (lane == 0) {
+    const int s = *dseq + 1;
+    *dseq = s;
+    __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -1015,7 +1040,14 @@ struct adl_batch {
   double* d_partials = nullptr;
   double* d_plans = nullptr;   // nbins x 2 x M
   double** d_uptrs = nullptr;  // nbins
-  BinCtl* h_ctl = nullptr;     // pinned
+  int* d_seq = nullptr;        // publications so far (device counter)
+  // the bins' outcomes as published (coherent pinned host memory): a 64-byte
+  // header whose first int is the publication number, then nbins control
+  // blocks; hmir_dev is its device address
+  unsigned char* hmir = nullptr;
+  unsigned char* hmir_dev = nullptr;
+  int pubs = 0;                // publications enqueued for execution
+  const BinCtl* h_ctl = nullptr;  // the published control blocks (in hmir)
   int total_tiles = 0;
   int total_tiles2 = 0;
   long part_stride = 0;  // doubles per launch parity of the partials
@@ -1057,7 +1089,7 @@ int tiles2_of(int nx, int ny, int vec, int rows) {
 }
 
 struct BLayout {
-  size_t bins, ctl, tile_bin, tile_bin2, partials, plans, uptrs, total;
+  size_t bins, ctl, tile_bin, tile_bin2, partials, plans, uptrs, seq, total;
 };
 
 BLayout blayout(int nbins, long max_tiles, int M) {
@@ -1075,6 +1107,7 @@ BLayout blayout(int nbins, long max_tiles, int M) {
   L.partials = take(sizeof(double) * 2 * 6 * max_tiles);
   L.plans = take(sizeof(double) * 2 * (size_t)M * nbins);
   L.uptrs = take(sizeof(double*) * nbins);
+  L.seq = take(256);
   L.total = o;
   return L;
 }
@@ -1204,6 +1237,43 @@ int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t
   return ADL_OK;
 }
 
+// After a sweep's launches: u_b += dt p_b for the bins converged and not yet
+// advanced, then the outcomes published to the host mirror.
+int enqueue_tail(adl_batch* B, hipStream_t st) {
+  BatchArgs a = base_args(B);
+  if (B->vec == 2)
+    hipLaunchKernelGGL((batch_update_kernel<2>), dim3(blocks_for(B->total_tiles)), dim3(64 * kBWaves), 0, st, a,
+                       B->d_uptrs);
+  else
+    hipLaunchKernelGGL((batch_update_kernel<1>), dim3(blocks_for(B->total_tiles)), dim3(64 * kBWaves), 0, st, a,
+                       B->d_uptrs);
+  hipLaunchKernelGGL(batch_publish_kernel, dim3(1), dim3(64), 0, st, B->d_ctl,
+                     reinterpret_cast<BinCtl*>(B->hmir_dev + 64), B->nbins, B->d_seq,
+                     reinterpret_cast<int*>(B->hmir_dev));
+  BCHK(hipGetLastError());
+  return ADL_OK;
+}
+
+// Waits until publication number `want` has reached the host mirror (the
+// stream is queried every 50 us so that a failed launch ends the wait).
+int await_publication(adl_batch* B, int want, hipStream_t st) {
+  const int* h = reinterpret_cast<const int*>(B->hmir);
+  auto seen = [&] { return __atomic_load_n(h, __ATOMIC_ACQUIRE) == want; };
+  auto next = std::chrono::steady_clock::now() + std::chrono::microseconds(50);
+  while (!seen()) {
+    __builtin_ia32_pause();
+    const auto now = std::chrono::steady_clock::now();
+    if (now < next) continue;
+    next = now + std::chrono::microseconds(50);
+    const hipError_t q = hipStreamQuery(st);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return bfail(ADL_EHIP, hipGetErrorString(q));
+    if (seen()) break;
+    return bfail(ADL_EHIP, "batched step ended without publishing its outcome");
+  }
+  return ADL_OK;
+}
+
 int upload_bins(adl_batch* B, double* const* u, const double* const* S, double dt, double tol, hipStream_t st,
                 bool& changed) {
   changed = false;
@@ -1255,6 +1325,36 @@ int upload_bins(adl_batch* B, double* const* u, const double* const* S, double d
     changed = true;
   }
   (void)st;
+  return ADL_OK;
+}
+
+// Autotune results of this process, by tuning key.
+std::mutex& tune_cache_mu() {
+  static std::mutex m;
+  return m;
+}
+std::map<std::string, std::pair<int, double>>& tune_cache() {
+  static std::map<std::string, std::pair<int, double>> c;
+  return c;
+}
+
+// The tuning key of a batch: the GPU's architecture, the storage and
+// advection kind, the columns per lane, the Newton terms per launch, the
+// candidate heights and the multiset of the bins' grid shapes (nx x ny).
+int autotune_key(const adl_batch* B, const int* candidates, int ncand, std::string& key) {
+  int dev = 0;
+  BCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  BCHK(hipGetDeviceProperties(&prop, dev));
+  std::vector<std::pair<int, int>> shapes;
+  shapes.reserve(B->nbins);
+  for (const adl_op* op : B->ops) shapes.emplace_back(op->nx, op->ny);
+  std::sort(shapes.begin(), shapes.end());
+  key = std::string(prop.gcnArchName) + "|f32=" + std::to_string(B->f32) + "|adv=" + std::to_string((int)B->advf) +
+        "|vec=" + std::to_string(B->vec) + "|two=" + std::to_string(B->two) + "|cand=";
+  for (int c = 0; c < ncand; ++c) key += std::to_string(candidates[c]) + ",";
+  key += "|bins=";
+  for (const auto& sh : shapes) key += std::to_string(sh.first) + "x" + std::to_string(sh.second) + ",";
   return ADL_OK;
 }
 
@@ -1332,23 +1432,36 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
   hipError_t e = hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(B->d_tile_bin2, B->tile_bin2.data(), sizeof(int) * B->total_tiles2, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&B->h_ctl), sizeof(BinCtl) * nbins, hipHostMallocDefault);
+  B->d_seq = reinterpret_cast<int*>(B->ws + L.seq);
+  if (e == hipSuccess) e = hipMemset(B->d_seq, 0, sizeof(int));
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&B->hmir), 64 + sizeof(BinCtl) * nbins,
+                      hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable);
+  if (e == hipSuccess) {
+    std::memset(B->hmir, 0, 64 + sizeof(BinCtl) * nbins);
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&B->hmir_dev), B->hmir, 0);
+  }
   if (e == hipSuccess) e = hipStreamCreate(&B->cap_stream);
   if (e != hipSuccess) {
-    if (B->h_ctl) hipHostFree(B->h_ctl);
+    if (B->hmir) hipHostFree(B->hmir);
     delete B;
     return bfail(ADL_EHIP, hipGetErrorString(e));
   }
+  B->h_ctl = reinterpret_cast<const BinCtl*>(B->hmir + 64);
   *out = B;
   return ADL_OK;
 }
 
 int adl_batch_destroy(adl_batch* B) {
   if (!B) return ADL_OK;
+  if (B->cap_stream) (void)hipStreamSynchronize(B->cap_stream);
   if (B->gexec) hipGraphExecDestroy(B->gexec);
   if (B->graph) hipGraphDestroy(B->graph);
   if (B->cap_stream) hipStreamDestroy(B->cap_stream);
-  if (B->h_ctl) hipHostFree(B->h_ctl);
+  if (B->hmir) {
+    (void)hipDeviceSynchronize();  // no publication of this batch may still be in flight
+    hipHostFree(B->hmir);
+  }
   delete B;
   return ADL_OK;
 }
@@ -1361,6 +1474,7 @@ int adl_batch_set_tile_rows(adl_batch* B, int rows) {
   const int rc = upload_tiles(B);
   if (rc != ADL_OK) return rc;
   BCHK(hipMemcpy(B->d_bins, B->bins.data(), sizeof(BinDesc) * B->nbins, hipMemcpyHostToDevice));
+  BCHK(hipStreamSynchronize(B->cap_stream));
   if (B->gexec) {
     hipGraphExecDestroy(B->gexec);
     B->gexec = nullptr;
@@ -1376,6 +1490,7 @@ int adl_batch_set_term_fusion(adl_batch* B, int two_terms) {
   if (!B || (two_terms != 0 && two_terms != 1)) return bfail(ADL_EINVAL, "two_terms must be 0 or 1");
   if (two_terms == B->two) return ADL_OK;
   B->two = two_terms;
+  BCHK(hipStreamSynchronize(B->cap_stream));
   if (B->gexec) {
     hipGraphExecDestroy(B->gexec);
     B->gexec = nullptr;
@@ -1394,10 +1509,30 @@ int adl_batch_get_tile_rows(const adl_batch* B, int* rows) {
 }
 
 // Project autotuner: time the stage + sweep launches of one step (u is not
-// modified) for each candidate tile height and keep the fastest.
+// modified) for each candidate tile height and keep the fastest.  Results are
+// cached per process by the tuning key (autotune_key): a later call with the
+// same key installs the cached tile height without timing.
 int adl_batch_autotune(adl_batch* B, double* const* u, const double* const* S_half, double dt, double tol,
                        const int* candidates, int ncand, int* best_rows, double* best_ms, void* stream) {
   if (!B || !u || !candidates || ncand < 1) return bfail(ADL_EINVAL, "bad autotune arguments");
+  for (int c = 0; c < ncand; ++c)
+    if (candidates[c] < 1) return bfail(ADL_EINVAL, "tile height candidates must be positive");
+  std::string key;
+  {
+    const int rc = autotune_key(B, candidates, ncand, key);
+    if (rc != ADL_OK) return rc;
+  }
+  {
+    std::lock_guard<std::mutex> g(tune_cache_mu());
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      const int rc = adl_batch_set_tile_rows(B, it->second.first);
+      if (rc != ADL_OK) return rc;
+      if (best_rows) *best_rows = it->second.first;
+      if (best_ms) *best_ms = it->second.second;
+      return ADL_OK;
+    }
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int best = B->rows;
   double bms = INFINITY;
@@ -1431,6 +1566,10 @@ int adl_batch_autotune(adl_batch* B, double* const* u, const double* const* S_ha
   hipEventDestroy(e1);
   int rc = adl_batch_set_tile_rows(B, best);
   if (rc != ADL_OK) return rc;
+  {
+    std::lock_guard<std::mutex> g(tune_cache_mu());
+    tune_cache()[key] = {best, bms};
+  }
   if (best_rows) *best_rows = best;
   if (best_ms) *best_ms = bms;
   return ADL_OK;
@@ -1460,6 +1599,7 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
     if (use_graph) {
       const bool rebuild = !B->gexec || changed || nterms > B->g_launches || B->g_rows != B->rows;
       if (rebuild) {
+        BCHK(hipStreamSynchronize(B->cap_stream));  // the old graph has finished its last replay
         if (B->gexec) hipGraphExecDestroy(B->gexec);
         if (B->graph) hipGraphDestroy(B->graph);
         B->gexec = nullptr;
@@ -1467,6 +1607,7 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
         BCHK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
         int cov = 0;
         rc = enqueue_sweep(B, 0, nterms, true, B->cap_stream, &cov);
+        if (rc == ADL_OK) rc = enqueue_tail(B, B->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
         if (rc != ADL_OK) return rc;
@@ -1490,6 +1631,7 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
       BCHK(hipEventRecord(ev, st));
       BCHK(hipStreamWaitEvent(B->cap_stream, ev, 0));
       BCHK(hipGraphLaunch(B->gexec, B->cap_stream));
+      ++B->pubs;
       BCHK(hipEventRecord(ev, B->cap_stream));
       BCHK(hipStreamWaitEvent(st, ev, 0));
       BCHK(hipEventDestroy(ev));
@@ -1499,30 +1641,30 @@ int adl_batch_midpoint_step(adl_batch* B, double* const* u, const double* const*
       launched = B->gcovered;
     } else {
       rc = enqueue_sweep(B, 0, nterms, true, st, &launched);
+      if (rc == ADL_OK) rc = enqueue_tail(B, st);
       if (rc != ADL_OK) return rc;
+      ++B->pubs;
     }
-    // continue bins that have not stopped yet
+    // the common path ends here: the graph (or the eager launches) advanced
+    // every converged bin and published the outcomes; bins still running
+    // continue (their u is advanced after the continuation)
     while (true) {
-      BCHK(hipMemcpyAsync(B->h_ctl, B->d_ctl, sizeof(BinCtl) * B->nbins, hipMemcpyDeviceToHost, st));
-      BCHK(hipStreamSynchronize(st));
+      rc = await_publication(B, B->pubs, st);
+      if (rc != ADL_OK) return rc;
       bool running = false;
       for (int b = 0; b < B->nbins; ++b)
         if (B->bins[b].active && !B->h_ctl[b].stop) running = true;
       if (!running || launched >= B->max_degree) break;
+      hipLaunchKernelGGL(batch_mark_kernel, dim3((B->nbins + 255) / 256), dim3(256), 0, st, B->d_ctl, B->nbins);
+      BCHK(hipGetLastError());
       const int more = std::min(B->max_degree - launched, std::max(8, launched / 4));
       int cov = 0;
       rc = enqueue_sweep(B, launched, more, false, st, &cov);
+      if (rc == ADL_OK) rc = enqueue_tail(B, st);
       if (rc != ADL_OK) return rc;
+      ++B->pubs;
       launched += cov;
     }
-    BatchArgs a = base_args(B);
-    if (B->vec == 2)
-      hipLaunchKernelGGL((batch_update_kernel<2>), dim3(blocks_for(B->total_tiles)), dim3(64 * kBWaves), 0, st, a,
-                         B->d_uptrs);
-    else
-      hipLaunchKernelGGL((batch_update_kernel<1>), dim3(blocks_for(B->total_tiles)), dim3(64 * kBWaves), 0, st, a,
-                         B->d_uptrs);
-    BCHK(hipGetLastError());
   }
   // per-bin results; bins outside the kernel (substeps, zero operator) and
   // bins that hit the degree cap take the single-op path (substeps allowed)

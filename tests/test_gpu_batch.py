@@ -170,6 +170,17 @@ def test_batch_fallback_bins_and_autotune():
     best, ms = b.autotune(us, Ss, bins[0].dt, bins[0].tol, candidates=(2, 8, 16))
     assert best in (2, 8, 16) and ms > 0
     assert all(torch.equal(u, to_dev(w.u0)) for u, w in zip(us, bins))  # autotune leaves u alone
+    # the result is cached by (architecture, storage, advection, shapes,
+    # candidates): the same key again, on this batch or another one, installs
+    # the cached height and time without timing
+    b.set_tile_rows(4)
+    assert b.autotune(us, Ss, bins[0].dt, bins[0].tol, candidates=(2, 8, 16)) == (best, ms)
+    assert b.get_tile_rows() == best
+    b2 = A.Batch([g for _, g in pairs])
+    assert b2.autotune(us, Ss, bins[0].dt, bins[0].tol, candidates=(2, 8, 16)) == (best, ms)
+    b2.close()
+    _, ms3 = b.autotune(us, Ss, bins[0].dt, bins[0].tol, candidates=(8, 2, 16))  # another key: timed
+    assert ms3 != ms
     stats = b.midpoint_step(us, Ss, bins[0].dt, bins[0].tol)
     assert stats[0]["substeps"] > 1
     for i, (w, (oop, _), u) in enumerate(zip(bins, pairs, us)):
