@@ -377,10 +377,28 @@ def profile_leja(n, mode=1, fp32=False):
     print(json.dumps({"profile_leja": n, "terms": st["matvecs"]}), flush=True)
 
 
+def profile_c2(steps=5):
+    """A few steps of the 512^2 Dirichlet two-stage quadrature workload
+    alone (four Newton terms per launch), for rocprofv3."""
+    import torch
+    import paper_2307_12276_amd as A
+    import workloads as W
+    w = W.c2_dirichlet_circular(n=512, steps=steps)
+    op = make_op(w, A.STORAGE_FP64)
+    op.spectral_bound(A.BOUND_GERSHGORIN)
+    u = dev_tensor(w.u0)
+    srcs = device_sources(w)
+    mv = 0
+    for n in range(steps):
+        mv += gpu_step(op, w, u, n, srcs)["matvecs"]
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_c2": steps, "matvecs": mv}), flush=True)
+
+
 def profile_bins(steps=4, tile_rows=16, tol=1e-9):
     """The chosen form of the 256-bin momentum workload alone (FP32 fields,
-    learned interval, one hipGraph per batched midpoint step) for a few
-    steps, for rocprofv3."""
+    learned interval, eager launches of each batched midpoint step) for a
+    few steps, for rocprofv3."""
     import torch
     import paper_2307_12276_amd as A
     from paper_2307_12276_amd import learned
@@ -692,6 +710,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 512^2, roofline, bins and paper-case legs")
     ap.add_argument("--profile-leja", type=int, default=0, help="run one sweep at this size and exit")
+    ap.add_argument("--profile-c2", type=int, default=0,
+                    help="run this many steps of the 512^2 Dirichlet quadrature workload and exit")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy and exit")
     ap.add_argument("--fp32", action="store_true", help="with --profile-leja: fields stored in FP32")
     ap.add_argument("--profile-bins", action="store_true",
@@ -702,6 +722,9 @@ def main():
     args = ap.parse_args()
     if args.profile_leja:
         profile_leja(args.profile_leja, 0 if args.one_term else (3 if args.frames else 1), args.fp32)
+        return
+    if args.profile_c2:
+        profile_c2(args.profile_c2)
         return
     if args.calibrate_copy:
         calibrate_copy()

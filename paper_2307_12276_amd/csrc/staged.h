@@ -51,15 +51,6 @@ struct RawRow {
   bool zero;
 };
 
-template <typename T, int VEC, int MODE>
-__device__ __forceinline__ void raw_load(const T* __restrict__ a, int r, const FieldView& F, const Strip& g,
-                                         RawRow<VEC>& o) {
-  const int row = map_row_any(r, F.ny, F.bc, MODE, o.zero);
-  const T* rp = a + (long)row * F.nx;
-  ldr<T, VEC>(rp, g.colc, o.c);
-  o.h = ld1<T>(rp, g.hcol);
-}
-
 // Layout of a ring row: [left halo, pad, the strip's 64*VEC values, right
 // halo, pad].  A lane's VEC values start on a 16-byte boundary, so the lane
 // writes and reads them with one aligned access (a layout with the values
@@ -101,35 +92,55 @@ __device__ __forceinline__ void lds_set(double* p, const double (&c)[VEC]) {
   }
 }
 
-template <int VEC>
-__device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<VEC>& x) {
+// A row goes into its ring with the boundary rule already applied, so that
+// a reader needs no select: with Dirichlet boundaries every column outside
+// the grid -- the elements of lanes outside it and the halo elements beyond
+// the edge -- holds the ghost value of the array (zero; for kxx and kyy, whose
+// face averages take the edge value, the value of the nearest edge column).
+// Periodic rows hold the wrapped columns as loaded.  `edges`: the strip has
+// such columns (Dirichlet, and the strip or its halo reaches past an edge).
+template <int VEC, int MODE>
+__device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<VEC>& x, bool edges, int nx) {
   using L = RingRow<VEC>;
   const int lane = threadIdx.x & (kWave - 1);
   double c[VEC];
+  double h;
+  if (x.zero) {  // (wave-uniform, as is `edges`)
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) c[v] = x.zero ? 0.0 : x.c[v];
+    for (int v = 0; v < VEC; ++v) c[v] = 0.0;
+    h = 0.0;
+  } else if (edges) {
+    // outside lanes load a valid column next to the edge (strip_at): the
+    // left ones columns 0 .., the right ones .. nx-1
+    const double edge = g.col0 < 0 ? x.c[0] : x.c[VEC - 1];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) c[v] = g.inside ? x.c[v] : (MODE == MODE_EDGE ? edge : 0.0);
+    const bool hghost = g.lane0 ? g.col0 - 1 < 0 : g.col0 + VEC >= nx;
+    const double hedge = g.lane0 ? c[0] : c[VEC - 1];
+    h = hghost ? (MODE == MODE_EDGE ? hedge : 0.0) : x.h;
+  } else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) c[v] = x.c[v];
+    h = x.h;
+  }
   lds_set<VEC>(row + L::kOwn + lane * VEC, c);
-  if (g.lane0) row[L::kLeft] = x.zero ? 0.0 : x.h;
-  if (g.lane63) row[L::kRight] = x.zero ? 0.0 : x.h;
+  if (g.lane0) row[L::kLeft] = h;
+  if (g.lane63) row[L::kRight] = h;
 }
 
-// Every lane of the wave must execute it: the DPP shifts read the adjacent
-// lanes, and a lane that is switched off hands over zero.  The shifts are
-// therefore taken unconditionally and selected afterwards (a conditional
-// expression around them would run them only on the lanes it selects).
-template <int VEC, int MODE>
-__device__ __forceinline__ void ring_rown(const double* row, const Strip& g, RowN<VEC>& o) {
+// A row and its x-neighbours from a ring (no boundary selects: ring_put
+// stored the ghost values).  Every lane of the wave must execute it: the DPP
+// shifts read the adjacent lanes.
+template <int VEC>
+__device__ __forceinline__ void ring_rown(const double* row, RowN<VEC>& o) {
   using L = RingRow<VEC>;
-  lds_get<VEC>(row + L::kOwn + (threadIdx.x & (kWave - 1)) * VEC, o.c);
-  const double h = row[g.lane0 ? L::kLeft : L::kRight];  // (used by lanes 0 and 63)
-  const double sl = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
-  const double sr = dpp_f64<kDppWaveShl1>(o.c[0]);
-  const double l = g.lane0 ? h : sl;
-  const double r = g.lane63 ? h : sr;
-  const double gl = MODE == MODE_EDGE ? o.c[0] : 0.0;
-  const double gr = MODE == MODE_EDGE ? o.c[VEC - 1] : 0.0;
-  o.l = g.ghostL ? gl : l;
-  o.r = g.ghostR ? gr : r;
+  const int lane = threadIdx.x & (kWave - 1);
+  lds_get<VEC>(row + L::kOwn + lane * VEC, o.c);
+  // both halo elements on every lane (two reads of one address each, so
+  // that each shift's kept value is a register of its own)
+  const double hl = row[L::kLeft], hr = row[L::kRight];
+  o.l = dpp_f64_keep<kDppWaveShr1>(hl, o.c[VEC - 1]);
+  o.r = dpp_f64_keep<kDppWaveShl1>(hr, o.c[0]);
 }
 
 template <int VEC>
@@ -143,7 +154,8 @@ struct Rings {
   static constexpr int kRow = RingRow<VEC>::kLen;
   static constexpr int kArrays = ADVF ? 6 : 4;
   double* base;
-  int r0;  // grid row of slot 0
+  int r0;      // grid row of slot 0
+  bool edges;  // Dirichlet ghost columns in the strip or its halo (ring_put)
   __device__ __forceinline__ double* row(int a, int r) const {
     return base + ((long)a * kSRing + (unsigned)(r - r0) % kSRing) * kRow;
   }
@@ -155,29 +167,46 @@ struct RowSet {
   RawRow<VEC> y, gy, m, k, ax, ay;
 };
 
+// one lane's part of row `row` (already mapped) of an array
+template <typename T, int VEC>
+__device__ __forceinline__ void raw_load_at(const T* __restrict__ a, int row, bool zero, const FieldView& F,
+                                            const Strip& g, RawRow<VEC>& o) {
+  const T* rp = a + (long)row * F.nx;
+  ldr<T, VEC>(rp, g.colc, o.c);
+  o.h = ld1<T>(rp, g.hcol);
+  o.zero = zero;
+}
+
+// grid row r of every input array: the boundary rule on the row index is
+// worked out once for both rules (zero ghost rows for y, kxy, ax', ay'; the
+// edge row for kyy and kxx)
 template <typename TF, typename TY, int VEC, bool ADVF>
 __device__ __forceinline__ void rowset_load(const FieldView& F, const TY* __restrict__ yin, const Strip& g, int r,
                                             RowSet<VEC, ADVF>& s) {
-  raw_load<TY, VEC, MODE_ZERO>(yin, r, F, g, s.y);
-  raw_load<TF, VEC, MODE_EDGE>(reinterpret_cast<const TF*>(F.kyy), r, F, g, s.gy);
-  raw_load<TF, VEC, MODE_ZERO>(reinterpret_cast<const TF*>(F.kxy), r, F, g, s.m);
-  raw_load<TF, VEC, MODE_EDGE>(reinterpret_cast<const TF*>(F.kxx), r, F, g, s.k);
+  bool zero;
+  const int rz = map_row_any(r, F.ny, F.bc, MODE_ZERO, zero);
+  const bool in = r >= 0 && r < F.ny;
+  const int re = (in || F.bc == BC_PERIODIC) ? rz : (r < 0 ? 0 : F.ny - 1);
+  raw_load_at<TY, VEC>(yin, rz, zero, F, g, s.y);
+  raw_load_at<TF, VEC>(reinterpret_cast<const TF*>(F.kyy), re, false, F, g, s.gy);
+  raw_load_at<TF, VEC>(reinterpret_cast<const TF*>(F.kxy), rz, zero, F, g, s.m);
+  raw_load_at<TF, VEC>(reinterpret_cast<const TF*>(F.kxx), re, false, F, g, s.k);
   if constexpr (ADVF) {
-    raw_load<TF, VEC, MODE_ZERO>(reinterpret_cast<const TF*>(F.ax), r, F, g, s.ax);
-    raw_load<TF, VEC, MODE_ZERO>(reinterpret_cast<const TF*>(F.ay), r, F, g, s.ay);
+    raw_load_at<TF, VEC>(reinterpret_cast<const TF*>(F.ax), rz, zero, F, g, s.ax);
+    raw_load_at<TF, VEC>(reinterpret_cast<const TF*>(F.ay), rz, zero, F, g, s.ay);
   }
 }
 
 template <int VEC, bool ADVF>
-__device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF>& R, const Strip& g, int r,
+__device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
                                            const RowSet<VEC, ADVF>& s) {
-  ring_put<VEC>(R.row(0, r), g, s.y);
-  ring_put<VEC>(R.row(1, r), g, s.gy);
-  ring_put<VEC>(R.row(2, r), g, s.m);
-  ring_put<VEC>(R.row(3, r), g, s.k);
+  ring_put<VEC, MODE_ZERO>(R.row(0, r), g, s.y, R.edges, F.nx);
+  ring_put<VEC, MODE_EDGE>(R.row(1, r), g, s.gy, R.edges, F.nx);
+  ring_put<VEC, MODE_ZERO>(R.row(2, r), g, s.m, R.edges, F.nx);
+  ring_put<VEC, MODE_EDGE>(R.row(3, r), g, s.k, R.edges, F.nx);
   if constexpr (ADVF) {
-    ring_put<VEC>(R.row(4, r), g, s.ax);
-    ring_put<VEC>(R.row(5, r), g, s.ay);
+    ring_put<VEC, MODE_ZERO>(R.row(4, r), g, s.ax, R.edges, F.nx);
+    ring_put<VEC, MODE_ZERO>(R.row(5, r), g, s.ay, R.edges, F.nx);
   }
 }
 
@@ -191,11 +220,11 @@ __device__ __forceinline__ void ring_stencil(const Rings<VEC, ADVF>& R, const St
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
     ring_rowc<VEC>(R.row(1, r - 1 + t), gg[t]);
-    ring_rown<VEC, MODE_ZERO>(R.row(2, r - 1 + t), g, m[t]);
+    ring_rown<VEC>(R.row(2, r - 1 + t), m[t]);
     if constexpr (ADVF) ring_rowc<VEC>(R.row(5, r - 1 + t), ay[t]);
   }
-  ring_rown<VEC, MODE_EDGE>(R.row(3, r), g, k);
-  if constexpr (ADVF) ring_rown<VEC, MODE_ZERO>(R.row(4, r), g, ac);
+  ring_rown<VEC>(R.row(3, r), k);
+  if constexpr (ADVF) ring_rown<VEC>(R.row(4, r), ac);
   stencil_point<VEC, ADVF>(um, uc, up, gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc, F.ayc,
                            Ax);
 }
@@ -206,7 +235,7 @@ __device__ __forceinline__ void ring_stage1(const Rings<VEC, ADVF>& R, const Str
                                             Stage1Ep<VEC, kSY1>& ep) {
   RowN<VEC> u[3];
 #pragma unroll
-  for (int t = 0; t < 3; ++t) ring_rown<VEC, MODE_ZERO>(R.row(0, r - 1 + t), g, u[t]);
+  for (int t = 0; t < 3; ++t) ring_rown<VEC>(R.row(0, r - 1 + t), u[t]);
   double Ax[VEC];
   ring_stencil<VEC, ADVF>(R, g, r, F, u[0], u[1], u[2], Ax);
   typename Stage1Ep<VEC, kSY1>::Extra none;
@@ -226,11 +255,19 @@ struct StagedIO {
   double shift, shift2, invg, dk1, dk2;
 };
 
+#ifndef ADL_STAGED_AHEAD
+#define ADL_STAGED_AHEAD 1
+#endif
+// band steps between a row's load and its put into the rings (1 or 2)
+constexpr int kStagedAhead = ADL_STAGED_AHEAD;
+static_assert(kStagedAhead == 1 || kStagedAhead == 2, "load distance");
+
 // One block (kWavesY2 waves) over bands rb0 .. rb1-1 of the strip whose
-// first loaded column is i0: the run's prologue, then per band step the next
-// rows' loads, stage 1, stage 2 and the stores; acc gets the lane's norm sums
-// (term k+1: ||d y||^2, ||p||^2; term k+2: the same).  `stopflag` gates the
-// work after the first loads; every wave executes every barrier.
+// first loaded column is i0: the run's prologue, then per band step the
+// loads of a later step's rows, stage 1, stage 2 and the stores; acc gets
+// the lane's norm sums (term k+1: ||d y||^2, ||p||^2; term k+2: the same).
+// `stopflag` gates the work after the first loads; every wave executes every
+// barrier.
 template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY>& io, double* lds, int i0, int rb0,
                                            int rb1, int stopflag, double (&acc)[4]) {
@@ -251,31 +288,36 @@ __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY
   Rings<VEC, ADVF> R;
   R.base = lds + kSY1 * W;
   R.r0 = J0 - 2;
+  R.edges = F.bc != BC_PERIODIC && (i0 <= 0 || i0 + kWave * VEC >= F.nx);
   const TY* __restrict__ yin = io.yin;
   // prologue: input rows J0-2 .. J0+1, y_{k+1} on J0-1 and J0, then input
-  // rows J0+2 .. J0+5 (the last of them takes the slot of J0-2)
-  RowSet<VEC, ADVF> cur, nxt;
+  // rows J0+2 .. J0+5 (the last of them takes the slot of J0-2); with a load
+  // distance of two steps also the loads of rows J0+6 .. J0+9
+  RowSet<VEC, ADVF> cur, bufA, bufB;
   rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 - 2 + wave, cur);
   const bool live = ep1.go();
   if (live) {
-    rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 2 + wave, nxt);
-    rowset_put<VEC, ADVF>(R, g, J0 - 2 + wave, cur);
+    rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 2 + wave, bufA);
+    if (kStagedAhead == 2 && rb0 + 1 < rb1) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 6 + wave, bufB);
+    rowset_put<VEC, ADVF>(R, g, J0 - 2 + wave, F, cur);
   }
   __syncthreads();
   if (live && wave < 2) ring_stage1<VEC, ADVF>(R, g, J0 - 1 + wave, F, ep1);
   __syncthreads();
-  if (live) rowset_put<VEC, ADVF>(R, g, J0 + 2 + wave, nxt);
+  if (live) rowset_put<VEC, ADVF>(R, g, J0 + 2 + wave, F, bufA);
   __syncthreads();
-#pragma unroll 1
-  for (int rb = rb0; rb < rb1; ++rb) {
+  // one band step (output rows j0 .. j0+3): loads rows of step rb +
+  // kStagedAhead into `ld`, puts the rows of step rb + 1 from `pt`
+  auto band = [&](int rb, RowSet<VEC, ADVF>& ld, RowSet<VEC, ADVF>& pt) {
     const int j0 = rb * kWavesY2;
     const int j = j0 + wave;
     const bool has = j < F.ny;
     const bool more = rb + 1 < rb1;
-    // the next step's input rows and this step's p_k, in flight during the step
+    // the loads of a later step's input rows and this step's p_k, in flight
+    // during the step
     double pk[VEC];
     if (live) {
-      if (more) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 6 + wave, nxt);
+      if (rb + kStagedAhead < rb1) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 2 + 4 * kStagedAhead + wave, ld);
       if (own && has) ldr_s<NT, double, VEC>(io.pin + (long)j * F.nx, g.col0, pk);
       // stage 1: y_{k+1} on row j0+1+wave
       ring_stage1<VEC, ADVF>(R, g, j0 + 1 + wave, F, ep1);
@@ -311,8 +353,22 @@ __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY
     }
     __syncthreads();
     // the next step's rows replace rows j0-1 .. j0+2, read for the last time above
-    if (live && more) rowset_put<VEC, ADVF>(R, g, j0 + 6 + wave, nxt);
+    if (live && more) rowset_put<VEC, ADVF>(R, g, j0 + 6 + wave, F, pt);
     __syncthreads();
+  };
+  if constexpr (kStagedAhead == 1) {
+#pragma unroll 1
+    for (int rb = rb0; rb < rb1; ++rb) band(rb, bufA, bufA);
+  } else {
+    // two buffers take turns, so that no register of a load in flight is
+    // copied (a copy waits for the load)
+    int rb = rb0;
+#pragma unroll 1
+    for (; rb + 1 < rb1; rb += 2) {
+      band(rb, bufA, bufB);
+      band(rb + 1, bufB, bufA);
+    }
+    if (rb < rb1) band(rb, bufA, bufB);
   }
 }
 

@@ -335,7 +335,10 @@ __device__ __forceinline__ bool block_stopped(const Ctl* ctl) {
 // register allocation does not carry its extra state.
 template <typename TF, typename TYI, typename TYO, int VEC, bool ADVF, bool FIRST, bool NT>
 __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T, LejaArgs A) {
-  if (A.decide_only || blockIdx.x == 0) {
+  // XCD-contiguous logical blocks: neighbouring tiles, which share halo
+  // columns and rows, run on one XCD and meet in its L2
+  const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
+  if (L == 0) {
     if (!FIRST) {
       leja_decide(A);
       if (A.decide_only && A.hctl && threadIdx.x == 0) publish_outcome(A);
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T,
     }
     return;
   }
-  const int b = blockIdx.x - 1;
+  const int b = L - 1;
   LejaEp<TYO, VEC, FIRST, NT> ep;
   ep.nx = F.nx;
   ep.yout = reinterpret_cast<TYO*>(A.yout);
@@ -479,11 +482,12 @@ __device__ __forceinline__ bool stage1_own(const FieldView& F, const TY* __restr
 template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ double lds[];
-  if (A.decide_only || blockIdx.x == 0) {
+  const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);  // as in leja_kernel
+  if (L == 0) {
     leja_decide(A);
     return;
   }
-  const int b = blockIdx.x - 1;
+  const int b = L - 1;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   const int W = kWave * VEC;
@@ -750,12 +754,16 @@ __device__ __forceinline__ void stage_t(const FieldView& F, const Strip& g, cons
 template <bool LF, typename TF, typename TY, int VEC, bool ADVF>
 __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
-  if (A.decide_only || blockIdx.x == 0) {
+  // XCD-contiguous logical blocks (row-major: column block fastest): the
+  // blocks above and below a block, which load half of its rows again, run
+  // on the same XCD and find those rows in its L2
+  const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
+  if (L == 0) {
     leja_decide(A);
     return;
   }
   if (block_stopped(A.ctl)) return;  // uniform over the block
-  const int b = blockIdx.x - 1;
+  const int b = L - 1;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   const int W = kWave * VEC;

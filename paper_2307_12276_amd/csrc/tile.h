@@ -36,6 +36,28 @@ __device__ __forceinline__ double dpp_f64(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
+// The same shift where the lane without a source gets zero by the DPP bound
+// control, so no register has to hold an old value (for rows whose edge
+// lanes' neighbours are not used)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_any(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// The same shift where the lane without a source (lane 0 for wave_shr:1,
+// lane 63 for wave_shl:1) keeps `old` instead of zero: passing the halo
+// element as `old` makes the shift deliver it to the edge lane, and no
+// select and no zero register are needed.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_keep(double old, double v) {
+  const long long b = __double_as_longlong(v);
+  const long long o = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 struct Strip {
   int col0;     // first column of this lane (may be >= nx in the last strip)
@@ -256,13 +278,14 @@ struct Stage1Ep {
 };
 
 // y_{k+1} row q of LDS (rounded to the storage type) with its x-neighbours
+// (lanes 0 and 63, the frame, get zero as the missing neighbour)
 template <typename TY, int VEC>
 __device__ __forceinline__ void lds_row_n(const double* lds, int q, RowN<VEC>& o) {
   const double* row = lds + (long)q * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
 #pragma unroll
   for (int v = 0; v < VEC; ++v) o.c[v] = storage_round<TY>(row[v]);
-  o.l = dpp_f64<kDppWaveShr1>(o.c[VEC - 1]);
-  o.r = dpp_f64<kDppWaveShl1>(o.c[0]);
+  o.l = dpp_f64_any<kDppWaveShr1>(o.c[VEC - 1]);
+  o.r = dpp_f64_any<kDppWaveShl1>(o.c[0]);
 }
 
 }  // namespace adl
