@@ -43,11 +43,15 @@ __device__ __forceinline__ int map_row_any(int r, int ny, int bc, int mode, bool
   return 0;
 }
 
-// one lane's part of an input row, as loaded (boundary rule on the row index)
-template <int VEC>
+// one lane's part of an input row, as loaded (boundary rule on the row
+// index), in the array's storage type: FP32 fields are widened only when the
+// row goes into its ring, so that a load stays in flight across the band
+// step it is issued in (widening at the load makes the wave wait for it
+// there)
+template <typename T, int VEC>
 struct RawRow {
-  double c[VEC];
-  double h;
+  T c[VEC];
+  T h;
   bool zero;
 };
 
@@ -99,33 +103,31 @@ __device__ __forceinline__ void lds_set(double* p, const double (&c)[VEC]) {
 // face averages take the edge value, the value of the nearest edge column).
 // Periodic rows hold the wrapped columns as loaded.  `edges`: the strip has
 // such columns (Dirichlet, and the strip or its halo reaches past an edge).
-template <int VEC, int MODE>
-__device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<VEC>& x, bool edges, int nx) {
+// Every lane consumes its loads on every path (selects, no branches; lanes
+// 1 .. 62 write their first value where lanes 0 and 63 write the halo
+// element): a load left unconsumed on some path makes the compiler wait for
+// it, and for everything issued before it, at the next reuse of its register.
+template <int VEC, int MODE, typename T>
+__device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<T, VEC>& x, bool edges, int nx) {
   using L = RingRow<VEC>;
   const int lane = threadIdx.x & (kWave - 1);
+  // outside lanes load a valid column next to the edge (strip_at): the left
+  // ones columns 0 .., the right ones .. nx-1
+  const bool ghostcols = edges && !g.inside;
+  const double edge = (double)(g.col0 < 0 ? x.c[0] : x.c[VEC - 1]);
   double c[VEC];
-  double h;
-  if (x.zero) {  // (wave-uniform, as is `edges`)
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) c[v] = 0.0;
-    h = 0.0;
-  } else if (edges) {
-    // outside lanes load a valid column next to the edge (strip_at): the
-    // left ones columns 0 .., the right ones .. nx-1
-    const double edge = g.col0 < 0 ? x.c[0] : x.c[VEC - 1];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) c[v] = g.inside ? x.c[v] : (MODE == MODE_EDGE ? edge : 0.0);
-    const bool hghost = g.lane0 ? g.col0 - 1 < 0 : g.col0 + VEC >= nx;
-    const double hedge = g.lane0 ? c[0] : c[VEC - 1];
-    h = hghost ? (MODE == MODE_EDGE ? hedge : 0.0) : x.h;
-  } else {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) c[v] = x.c[v];
-    h = x.h;
+  for (int v = 0; v < VEC; ++v) {
+    const double val = ghostcols ? (MODE == MODE_EDGE ? edge : 0.0) : (double)x.c[v];
+    c[v] = x.zero ? 0.0 : val;
   }
+  const bool hghost = edges && (g.lane0 ? g.col0 - 1 < 0 : g.col0 + VEC >= nx);
+  const double hedge = g.lane0 ? c[0] : c[VEC - 1];
+  const double hv = hghost ? (MODE == MODE_EDGE ? hedge : 0.0) : (double)x.h;
+  const double h = x.zero ? 0.0 : hv;
   lds_set<VEC>(row + L::kOwn + lane * VEC, c);
-  if (g.lane0) row[L::kLeft] = h;
-  if (g.lane63) row[L::kRight] = h;
+  const int hoff = g.lane0 ? L::kLeft : (g.lane63 ? L::kRight : L::kOwn + lane * VEC);
+  row[hoff] = (g.lane0 || g.lane63) ? h : c[0];
 }
 
 // A row and its x-neighbours from a ring (no boundary selects: ring_put
@@ -161,19 +163,28 @@ struct Rings {
   }
 };
 
-// the loads of one grid row for every input ring
-template <int VEC, bool ADVF>
+// the loads of one grid row for every input ring (y_k in TY, fields in TF)
+template <typename TF, typename TY, int VEC, bool ADVF>
 struct RowSet {
-  RawRow<VEC> y, gy, m, k, ax, ay;
+  RawRow<TY, VEC> y;
+  RawRow<TF, VEC> gy, m, k, ax, ay;
 };
 
-// one lane's part of row `row` (already mapped) of an array
+// one lane's part of row `row` (already mapped) of an array, unconverted
 template <typename T, int VEC>
 __device__ __forceinline__ void raw_load_at(const T* __restrict__ a, int row, bool zero, const FieldView& F,
-                                            const Strip& g, RawRow<VEC>& o) {
+                                            const Strip& g, RawRow<T, VEC>& o) {
   const T* rp = a + (long)row * F.nx;
-  ldr<T, VEC>(rp, g.colc, o.c);
-  o.h = ld1<T>(rp, g.hcol);
+  const T* ap = at_col(rp, g.colc);
+  if constexpr (VEC == 2) {
+    typedef T t2 __attribute__((ext_vector_type(2)));
+    const t2 v = *reinterpret_cast<const t2*>(ap);
+    o.c[0] = v.x;
+    o.c[1] = v.y;
+  } else {
+    o.c[0] = ap[0];
+  }
+  o.h = *at_col(rp, g.hcol);
   o.zero = zero;
 }
 
@@ -182,7 +193,7 @@ __device__ __forceinline__ void raw_load_at(const T* __restrict__ a, int row, bo
 // edge row for kyy and kxx)
 template <typename TF, typename TY, int VEC, bool ADVF>
 __device__ __forceinline__ void rowset_load(const FieldView& F, const TY* __restrict__ yin, const Strip& g, int r,
-                                            RowSet<VEC, ADVF>& s) {
+                                            RowSet<TF, TY, VEC, ADVF>& s) {
   bool zero;
   const int rz = map_row_any(r, F.ny, F.bc, MODE_ZERO, zero);
   const bool in = r >= 0 && r < F.ny;
@@ -197,9 +208,9 @@ __device__ __forceinline__ void rowset_load(const FieldView& F, const TY* __rest
   }
 }
 
-template <int VEC, bool ADVF>
+template <typename TF, typename TY, int VEC, bool ADVF>
 __device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
-                                           const RowSet<VEC, ADVF>& s) {
+                                           const RowSet<TF, TY, VEC, ADVF>& s) {
   ring_put<VEC, MODE_ZERO>(R.row(0, r), g, s.y, R.edges, F.nx);
   ring_put<VEC, MODE_EDGE>(R.row(1, r), g, s.gy, R.edges, F.nx);
   ring_put<VEC, MODE_ZERO>(R.row(2, r), g, s.m, R.edges, F.nx);
@@ -255,121 +266,140 @@ struct StagedIO {
   double shift, shift2, invg, dk1, dk2;
 };
 
-#ifndef ADL_STAGED_AHEAD
-#define ADL_STAGED_AHEAD 1
-#endif
-// band steps between a row's load and its put into the rings (1 or 2)
-constexpr int kStagedAhead = ADL_STAGED_AHEAD;
-static_assert(kStagedAhead == 1 || kStagedAhead == 2, "load distance");
+// Stores of the staged pass: through a buffer resource for the row (base
+// and length in scalar registers), and a lane that must not store passes an
+// offset past the row's end, which the hardware drops.  The stores then need
+// no branch around them: a branch that some waves skip leaves the wait
+// counters of the two paths apart, and the compiler then waits for every
+// load in flight (the next rows' prefetch included) before the first use of
+// any of them.  NT sets the non-temporal hint.
+constexpr int kDropOffset = 0x40000000;  // past the end of any row (rows < 1 GiB)
+
+template <bool NT, typename T, int VEC>
+__device__ __forceinline__ void row_store(T* rowp, int nx, int voff, const double (&c)[VEC]) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(rowp, 0, nx * (int)sizeof(T), 0x00020000);
+  constexpr int aux = NT ? 2 : 0;
+  if constexpr (sizeof(T) == 8 && VEC == 2) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    d2 v;
+    v.x = c[0];
+    v.y = c[1];
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, 0, aux);
+  } else if constexpr (sizeof(T) == 8) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, c[0]), r, voff, 0, aux);
+  } else if constexpr (VEC == 2) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    f2 v;
+    v.x = (float)c[0];
+    v.y = (float)c[1];
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, aux);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)c[0]), r, voff, 0, aux);
+  }
+}
 
 // One block (kWavesY2 waves) over bands rb0 .. rb1-1 of the strip whose
 // first loaded column is i0: the run's prologue, then per band step the
-// loads of a later step's rows, stage 1, stage 2 and the stores; acc gets
+// loads of the next step's rows, stage 1, stage 2 and the stores; acc gets
 // the lane's norm sums (term k+1: ||d y||^2, ||p||^2; term k+2: the same).
-// `stopflag` gates the work after the first loads; every wave executes every
-// barrier.
+// `stopflag` set: the wave only keeps the block's barrier count.
+//
+// The memory operations of a step are laid out for the in-order wait
+// counter: p_k is issued first and the next step's rows after it, all
+// unconditionally (rows past the grid and lanes outside it read valid
+// elements they do not use; the last step, which loads no rows, is a copy
+// of its own), so that stage 2's wait for p_k leaves the rows in flight
+// until they go into the rings at the end of the step.
 template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
 __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY>& io, double* lds, int i0, int rb0,
                                            int rb1, int stopflag, double (&acc)[4]) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   const int W = kWave * VEC;
+  Stage1Ep<VEC, kSY1> ep1;
+  ep1.stopflag = stopflag;
+  if (!ep1.go()) {
+    // prologue and band steps: three barriers each
+    for (int rb = rb0 - 1; rb < rb1; ++rb) {
+      __syncthreads();
+      __syncthreads();
+      __syncthreads();
+    }
+    return;
+  }
   const Strip g = strip_at<VEC>(F, i0);
   const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
   const int J0 = rb0 * kWavesY2;
-  Stage1Ep<VEC, kSY1> ep1;
   ep1.lds = lds;
   ep1.r0 = J0 - 1;
   ep1.ny = F.ny;
   ep1.per = F.bc == BC_PERIODIC;
   ep1.shift = io.shift;
   ep1.invg = io.invg;
-  ep1.stopflag = stopflag;
   Rings<VEC, ADVF> R;
   R.base = lds + kSY1 * W;
   R.r0 = J0 - 2;
   R.edges = F.bc != BC_PERIODIC && (i0 <= 0 || i0 + kWave * VEC >= F.nx);
   const TY* __restrict__ yin = io.yin;
+  const int ocol = g.col0 * (int)sizeof(TY), ocolp = g.col0 * 8;
   // prologue: input rows J0-2 .. J0+1, y_{k+1} on J0-1 and J0, then input
-  // rows J0+2 .. J0+5 (the last of them takes the slot of J0-2); with a load
-  // distance of two steps also the loads of rows J0+6 .. J0+9
-  RowSet<VEC, ADVF> cur, bufA, bufB;
+  // rows J0+2 .. J0+5 (the last of them takes the slot of J0-2)
+  RowSet<TF, TY, VEC, ADVF> cur, nxt;
   rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 - 2 + wave, cur);
-  const bool live = ep1.go();
-  if (live) {
-    rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 2 + wave, bufA);
-    if (kStagedAhead == 2 && rb0 + 1 < rb1) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 6 + wave, bufB);
-    rowset_put<VEC, ADVF>(R, g, J0 - 2 + wave, F, cur);
-  }
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 2 + wave, nxt);
+  rowset_put<TF, TY, VEC, ADVF>(R, g, J0 - 2 + wave, F, cur);
   __syncthreads();
-  if (live && wave < 2) ring_stage1<VEC, ADVF>(R, g, J0 - 1 + wave, F, ep1);
+  if (wave < 2) ring_stage1<VEC, ADVF>(R, g, J0 - 1 + wave, F, ep1);
   __syncthreads();
-  if (live) rowset_put<VEC, ADVF>(R, g, J0 + 2 + wave, F, bufA);
+  rowset_put<TF, TY, VEC, ADVF>(R, g, J0 + 2 + wave, F, nxt);
   __syncthreads();
-  // one band step (output rows j0 .. j0+3): loads rows of step rb +
-  // kStagedAhead into `ld`, puts the rows of step rb + 1 from `pt`
-  auto band = [&](int rb, RowSet<VEC, ADVF>& ld, RowSet<VEC, ADVF>& pt) {
+  // one band step (output rows j0 .. j0+3); LAST: the run's last step
+  auto band = [&]<bool LAST>(int rb) {
     const int j0 = rb * kWavesY2;
     const int j = j0 + wave;
-    const bool has = j < F.ny;
-    const bool more = rb + 1 < rb1;
-    // the loads of a later step's input rows and this step's p_k, in flight
-    // during the step
+    const bool keep = own && j < F.ny;
     double pk[VEC];
-    if (live) {
-      if (rb + kStagedAhead < rb1) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 2 + 4 * kStagedAhead + wave, ld);
-      if (own && has) ldr_s<NT, double, VEC>(io.pin + (long)j * F.nx, g.col0, pk);
-      // stage 1: y_{k+1} on row j0+1+wave
-      ring_stage1<VEC, ADVF>(R, g, j0 + 1 + wave, F, ep1);
-    }
+    ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
+    if constexpr (!LAST) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 6 + wave, nxt);
+    // stage 1: y_{k+1} on row j0+1+wave
+    ring_stage1<VEC, ADVF>(R, g, j0 + 1 + wave, F, ep1);
     __syncthreads();
-    if (live && has) {
-      // stage 2: y_{k+2} on row j
-      RowN<VEC> u[3];
+    // stage 2: y_{k+2} on row j (rows past the grid are computed and dropped)
+    RowN<VEC> u[3];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(lds, (unsigned)(j - 1 + t - ep1.r0) % kSY1, u[t]);
-      double Ax[VEC];
-      ring_stencil<VEC, ADVF>(R, g, j, F, u[0], u[1], u[2], Ax);
-      if (own) {
-        const long ro = (long)j * F.nx;
-        const double* y1row = lds + (long)((unsigned)(j - ep1.r0) % kSY1) * W + lane * VEC;
-        double y2[VEC], pm[VEC], p2[VEC];
+    for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(lds, (unsigned)(j - 1 + t - ep1.r0) % kSY1, u[t]);
+    double Ax[VEC];
+    ring_stencil<VEC, ADVF>(R, g, j, F, u[0], u[1], u[2], Ax);
+    const long ro = (long)min(j, F.ny - 1) * F.nx;
+    double y1[VEC], y2[VEC], pm[VEC], p2[VEC];
+    lds_get<VEC>(lds + (long)((unsigned)(j - ep1.r0) % kSY1) * W + lane * VEC, y1);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const double t1 = io.dk1 * y1row[v];
-          pm[v] = pk[v] + t1;
-          y2[v] = (Ax[v] - io.shift2 * u[1].c[v]) * io.invg;
-          const double t2 = io.dk2 * y2[v];
-          p2[v] = pm[v] + t2;
-          acc[0] += t1 * t1;
-          acc[1] += pm[v] * pm[v];
-          acc[2] += t2 * t2;
-          acc[3] += p2[v] * p2[v];
-        }
-        str_s<NT, TY, VEC>(io.yout + ro, g.col0, y2);
-        str_s<NT, double, VEC>(io.pmid + ro, g.col0, pm);
-        str_s<NT, double, VEC>(io.p + ro, g.col0, p2);
-      }
+    for (int v = 0; v < VEC; ++v) {
+      const double t1 = io.dk1 * y1[v];
+      pm[v] = pk[v] + t1;
+      y2[v] = (Ax[v] - io.shift2 * u[1].c[v]) * io.invg;
+      const double t2 = io.dk2 * y2[v];
+      p2[v] = pm[v] + t2;
+      acc[0] += keep ? t1 * t1 : 0.0;
+      acc[1] += keep ? pm[v] * pm[v] : 0.0;
+      acc[2] += keep ? t2 * t2 : 0.0;
+      acc[3] += keep ? p2[v] * p2[v] : 0.0;
     }
+    row_store<NT, TY, VEC>(io.yout + ro, F.nx, keep ? ocol : kDropOffset, y2);
+    row_store<NT, double, VEC>(io.pmid + ro, F.nx, keep ? ocolp : kDropOffset, pm);
+    row_store<NT, double, VEC>(io.p + ro, F.nx, keep ? ocolp : kDropOffset, p2);
     __syncthreads();
     // the next step's rows replace rows j0-1 .. j0+2, read for the last time above
-    if (live && more) rowset_put<VEC, ADVF>(R, g, j0 + 6 + wave, F, pt);
+    if constexpr (!LAST) rowset_put<TF, TY, VEC, ADVF>(R, g, j0 + 6 + wave, F, nxt);
     __syncthreads();
   };
-  if constexpr (kStagedAhead == 1) {
 #pragma unroll 1
-    for (int rb = rb0; rb < rb1; ++rb) band(rb, bufA, bufA);
-  } else {
-    // two buffers take turns, so that no register of a load in flight is
-    // copied (a copy waits for the load)
-    int rb = rb0;
-#pragma unroll 1
-    for (; rb + 1 < rb1; rb += 2) {
-      band(rb, bufA, bufB);
-      band(rb + 1, bufB, bufA);
-    }
-    if (rb < rb1) band(rb, bufA, bufB);
-  }
+  for (int rb = rb0; rb < rb1 - 1; ++rb) band.template operator()<false>(rb);
+  if (rb1 > rb0) band.template operator()<true>(rb1 - 1);
 }
 
 // dynamic LDS of a staged block
