@@ -139,11 +139,11 @@ LEG_KERNELS = {0: ("one-term", "leja_kernel"),
 
 
 def run_roofline_leg(w, storage, mode=1):
-    """One midpoint step of the stream-function field at n x n: the
-    Newton-Leja kernels' dispatch-timed bandwidth on a working set far beyond
-    the caches, with one term per launch (mode 0), two with the kernel the
-    library picks at this size (mode 1: input rows staged in LDS) or two with
-    the register-frame kernel (mode 3)."""
+    """Midpoint steps of the stream-function field at n x n (two warm-up
+    steps, three timed): the Newton-Leja kernels' dispatch-timed bandwidth on
+    a working set far beyond the caches, with one term per launch (mode 0),
+    two with the kernel the library picks at this size (mode 1: input rows
+    staged in LDS) or two with the register-frame kernel (mode 3)."""
     import torch
     import paper_2307_12276_amd as A
     n = w.nx
@@ -152,13 +152,16 @@ def run_roofline_leg(w, storage, mode=1):
     op.spectral_bound(A.BOUND_GERSHGORIN)
     u = dev_tensor(w.u0)
     srcs = device_sources(w)
-    gpu_step(op, w, u, 0, srcs)  # warm-up (plan, predicted degree)
+    for k in range(2):  # warm-up (plan, predicted degree, first touch of every sweep buffer)
+        gpu_step(op, w, u, k, srcs)
     torch.cuda.synchronize()
     op.profile(True)
     t0 = time.perf_counter()
-    st = gpu_step(op, w, u, 1, srcs)
+    timed = 3
+    for k in range(2, 2 + timed):
+        st = gpu_step(op, w, u, k, srcs)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = (time.perf_counter() - t0) / timed
     ms, launches, nbytes = op.profile_read()
     op.profile(False)
     avg_ms, per_launch, achieved = kernel_roofline(ms, launches, nbytes)

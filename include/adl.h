@@ -154,15 +154,17 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
  * default) computes four terms per launch on grids below 2^20 points
  * (mode 4's form, y_{k+1} .. y_{k+3} kept on chip) and, on larger grids,
  * terms k+1 and k+2 in one launch, keeping y_{k+1} on chip (read y_k, the
- * fields and p_k once, write y_{k+2}, p_{k+1}, p_{k+2}) with the input rows
+ * fields and p_k once, write y_{k+2} and p_{k+2}) with the input rows
  * staged in LDS (without non-temporal hints, also below 2^20 points: one-row
  * frames in registers); mode = 2 and mode = 3
  * force the LDS-staged and the register-frame form; mode = 4 computes four
- * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames; p_{k+1}
- * .. p_{k+4} written), on grids below 2^20 points without non-temporal hints
- * and, on a periodic grid, ny >= 4 other than 5 and 9 (a block's rows wrap
- * once; ADL_EINVAL otherwise; mode 1 then runs two terms per launch);
- * mode = 0 launches one kernel per term.  Results
+ * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames), on
+ * grids swept without non-temporal hints and, on a periodic grid, ny >= 4
+ * other than 5 and 9 (a block's rows wrap once; ADL_EINVAL otherwise; mode 1
+ * then runs two terms per launch); mode = 0 launches one kernel per term.
+ * A fused launch stores y and p of its last term only; when the sweep stops
+ * at an earlier term of a launch, the launch is run again on its inputs to
+ * store p of that term (the same arithmetic, so the same values).  Results
  * agree to rounding (the block partial sums of the norms are grouped
  * differently).  ADL_EINVAL for other values. */
 int adl_op_set_term_fusion(adl_op* op, int mode);
@@ -172,7 +174,7 @@ int adl_op_set_term_fusion(adl_op* op, int mode);
  * non-temporal, so that on grids far beyond the caches the rows re-read by
  * neighbouring tiles stay in L2; mode = 0 uses ordinary loads and stores;
  * mode = -1 (the default) chooses 1 when the sweep's working set (fields,
- * the input vector, two y and four p buffers) exceeds 512 MiB.  Results are
+ * the input vector, three y and three p buffers) exceeds 512 MiB.  Results are
  * identical in every mode.  ADL_EINVAL for other values. */
 int adl_op_set_streaming(adl_op* op, int mode);
 

@@ -74,6 +74,8 @@ struct BinCtl {
   int status;  // 0 running, 1 converged, 2 non-finite, 3 degree cap
   int degree;
   int upd;     // 1: u already advanced by an earlier update launch of this step
+  int inner;   // the decided term is the first of a two-term launch (its p is not stored)
+  int launch;  // launch index of the decided term
   double tn2, pn2;
   double hist[kStopHist];  // term norms of the stopping window (as in Ctl)
 };
@@ -183,6 +185,8 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
     for (int i = 0; i < kStopHist; ++i) c->hist[i] = hist[i];
     c->degree = degree;
     c->status = status;
+    c->inner = two && degree == A.kprev + 1;
+    c->launch = A.L - 1;
     __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   return stop != 0;
@@ -247,7 +251,8 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_leja_kernel(BatchArgs A, i
 // down its rows with every vertical window in registers -- input rows r ..
 // r+2 of y_k, rows r-1 .. r+2 of kyy and kxy (ay'), rows r .. r+1 of kxx
 // (ax'), y_{k+1} on rows r-1 .. r+1 -- computing y_{k+1} of row r+1 and then
-// y_{k+2} of row r; p_{k+1} and p_{k+2} as for a single operator.  Each step
+// y_{k+2} of row r; p_{k+1} and p_{k+2} as for a single operator (p_{k+2}
+// stored; the update launch rebuilds p_{k+1} of a bin that stopped there).  Each step
 // first issues the loads of the next step's new input row (and of its p_k
 // row), so that their latency hides behind the step's arithmetic, and every
 // input element of the tile is loaded once.  The x-neighbours of y_{k+1} come
@@ -777,7 +782,8 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
     in.ay = rsrc_of(uni(F.ay));
   }
   const Rsrc yout = rsrc_of(uni(((A.L + 1) & 1) ? B.y1 : B.y0));
-  const Rsrc pmid = rsrc_of(uni(B.pb[pbuf_index(k + 1, A.two)]));
+  // (p_{k+1} is not stored: a bin that stops at term k+1 is advanced by
+  // p_{k+2} - d_{k+2} y_{k+2}, both stored, in the update launch)
   const Rsrc pout = rsrc_of(uni(B.pb[pbuf_index(k + 2, A.two)]));
   // (a second term past the bin's degree cap is computed with the last plan
   // entries and discarded by the decision at the cap)
@@ -878,7 +884,6 @@ __device__ __forceinline__ void batch_term2(const BatchArgs& A, const BinDesc& B
         }
         const int so = r * F.nx * 8;
         bstore<VEC>(yout, lo.o8, so, y2);
-        bstore<VEC>(pmid, lo.o8, so, pm);
         bstore<VEC>(pout, lo.o8, so, p2);
       }
     }
@@ -965,15 +970,24 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BinCtl* ctl, int nbins
   }
 }
 
-// u_b += dt p_b for converged bins not advanced yet (one wave per tile)
+// u_b += dt p_b for converged bins not advanced yet (one wave per tile).  A
+// bin that stopped at the first term m of a two-term launch is advanced by
+// p_m = p_{m+1} - d_{m+1} y_{m+1}: that launch stored p and y of term m+1
+// only, and no later launch of the sweep wrote those buffers of the bin (the
+// launch beside the decision writes the other y buffer and the other p pair).
 template <int VEC>
 __global__ __launch_bounds__(64 * kBWaves) void batch_update_kernel(BatchArgs A, double* const* u) {
   const int gt = wave_unit();
   if (gt >= A.total_tiles) return;
   const int b = __builtin_amdgcn_readfirstlane(A.tile_bin[gt]);
   const BinDesc& B = A.bins[b];
-  if (!B.active || A.ctl[b].status != 1 || A.ctl[b].upd || A.ctl[b].degree == 0) return;  // degree 0: p = 0
-  const double* pb = B.pb[pbuf_index(A.ctl[b].degree, A.two)];
+  const BinCtl& c = A.ctl[b];
+  if (!B.active || c.status != 1 || c.upd || c.degree == 0) return;  // degree 0: p = 0
+  const int m = c.degree;
+  const bool inner = c.inner != 0;
+  const double* pb = B.pb[pbuf_index(inner ? m + 1 : m, A.two)];
+  const double* yb = reinterpret_cast<const double*>(((c.launch + 1) & 1) ? B.y1 : B.y0);
+  const double dm = inner ? B.d[min(m + 1, B.max_degree)] : 0.0;
   const int t = gt - B.tile_base;
   const int rb = t / B.ncb, cb = t - rb * B.ncb;
   const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
@@ -985,6 +999,12 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_update_kernel(BatchArgs A,
     double uu[VEC], pp[VEC];
     ldr<double, VEC>(ub + ro, col0, uu);
     ldr<double, VEC>(pb + ro, col0, pp);
+    if (inner) {
+      double yy[VEC];
+      ldr<double, VEC>(yb + ro, col0, yy);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) pp[v] = pp[v] - dm * yy[v];
+    }
 #pragma unroll
     for (int v = 0; v < VEC; ++v) uu[v] = uu[v] + B.dt * pp[v];
     str<double, VEC>(ub + ro, col0, uu);

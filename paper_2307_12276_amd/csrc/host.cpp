@@ -205,11 +205,9 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
   size_t kxx, kxy, kyy, ax, ay, y0, y1, p, p2, p3, p4, w1, w2, yacc, tmp, tmp2, partials, ctl, total;
-  size_t p58;  // p5 .. p8 (four-term launches), or kNone
 };
-constexpr size_t kNone = ~(size_t)0;
-// four Newton terms per launch on grids below this many points (each launch
-// then needs eight p buffers; the grid's vectors stay in the caches) ...
+// four Newton terms per launch on grids below this many points (the grid's
+// vectors stay in the caches) ...
 constexpr long kFourTermMaxPoints = 1L << 20;
 // ... which is also the default there: measured on MI355X (FP64, steps/s of
 // the two-stage quadrature, two terms per launch -> four, LDS rows accessed
@@ -254,7 +252,6 @@ static WsLayout ws_layout(int nx, int ny, int storage) {
   L.p2 = take(n * 8);
   L.p3 = take(n * 8);
   L.p4 = take(n * 8);
-  L.p58 = (long)n < kFourTermMaxPoints ? take(4 * align_up(n * 8)) : kNone;
   L.partials = take(2 * 6 * max_partial_blocks(nx, ny) * 8);
   L.ctl = take(4 * 128);
   L.total = o;
@@ -394,20 +391,21 @@ Plan& adl::get_plan(adl_op* op, int l, double alpha, double h) {
   return P;
 }
 
-// Algorithmic HBM bytes of one Newton-Leja launch of n terms: read y_k, the
-// three tensor fields (+ two advection fields), p_k (not at k = 0), w2 (when
-// the augmented column enters); write y of the last term and p of each term.
-static double leja_bytes(const adl_op* op, int k, int n, bool with_w2) {
+// Algorithmic HBM bytes of one Newton-Leja launch (any number of terms):
+// read y_k, the three tensor fields (+ two advection fields), p_k (not at
+// k = 0), w2 (when the augmented column enters); write y and p of the
+// launch's last term.
+static double leja_bytes(const adl_op* op, int k, bool with_w2) {
   const double fs = op->f.f32 ? 4.0 : 8.0;
   const double ys = op->storage == ADL_STORAGE_FP32_FIELDS_Y ? 4.0 : 8.0;
-  double b = (k == 0 ? 8.0 : ys) + 3.0 * fs + (k == 0 ? 0.0 : 8.0) + (with_w2 ? 8.0 : 0.0) + ys + 8.0 * n;
+  double b = (k == 0 ? 8.0 : ys) + 3.0 * fs + (k == 0 ? 0.0 : 8.0) + (with_w2 ? 8.0 : 0.0) + ys + 8.0;
   if (op->f.ax) b += 2.0 * fs;
   return b * (double)op->n;
 }
 
 // Whether the Newton-Leja launches use non-temporal hints on the vectors
 // they read or write once: by default when the sweep's working set (fields,
-// v, two y and four p buffers) exceeds twice the 256 MiB Infinity Cache, so
+// v, three y and three p buffers) exceeds twice the 256 MiB Infinity Cache, so
 // that each launch streams through it anyway.  Below that the hint evicts
 // lines the next launch would find in cache (measured on MI355X: 10 % slower
 // launches at 512^2 and at 2048^2, 335 MB; 4-10 % faster at 2896^2 and
@@ -418,18 +416,18 @@ static int streaming_on(const adl_op* op) {
   if (op->streaming >= 0) return op->streaming;
   const double fs = op->f.f32 ? 4.0 : 8.0;
   const double ys = op->storage == ADL_STORAGE_FP32_FIELDS_Y ? 4.0 : 8.0;
-  const double per_pt = (op->f.ax ? 5.0 : 3.0) * fs + 8.0 + 2.0 * ys + 4.0 * 8.0;
+  const double per_pt = (op->f.ax ? 5.0 : 3.0) * fs + 8.0 + 3.0 * ys + 3.0 * 8.0;
   return per_pt * (double)op->n > kStreamMinBytes ? 1 : 0;
 }
 
-// Whether the op can run four Newton terms per launch: its workspace has the
-// eight p buffers, a launch's 12 partial rows fit a partials slot, the sweep
-// runs without non-temporal hints (the four-term kernel has none), and a
-// periodic grid has enough rows for the kernel's one-wrap row rule.
+// Whether the op can run four Newton terms per launch: a launch's 12 partial
+// rows fit a partials slot, the sweep runs without non-temporal hints (the
+// four-term kernel has none), and a periodic grid has enough rows for the
+// kernel's one-wrap row rule.
 static bool four_terms_ok(const adl_op* op) {
   const long nb = std::max(op->t4.nblocks, op->t41.nblocks);
   if (!four_term_rows_fit(op->ny, op->bc)) return false;
-  return op->p5 && 12L * nb <= op->slot_stride && !streaming_on(op);
+  return 12L * nb <= op->slot_stride && !streaming_on(op);
 }
 
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
@@ -441,12 +439,17 @@ static bool four_terms_ok(const adl_op* op) {
 // launch's block 0 takes the stopping decision of the previous launch's terms
 // from its block partials; a one-block launch at the end of every chunk
 // decides the chunk's last launch, and the host reads the outcome once per
-// chunk.  p of the terms of launch L goes to the set L mod 2 of S buffers
-// (S = 4 with four-term launches, else 2; the last term always to the set's
-// last buffer), so a launch never overwrites a p that the decision it runs
-// beside may pick.  The buffers are p_out and 2S - 1 workspace buffers,
-// arranged so that the predicted degree ends in p_out; otherwise the result
-// is copied there.
+// chunk.
+//
+// A launch stores y and p of its last term only (the norms of every term go
+// into its partials).  Launch L reads y from buffer L mod 3 and p from p
+// buffer (L - 1) mod 3 and writes buffers (L + 1) mod 3 and L mod 3: the
+// launch that runs beside the decision of launch L writes neither of launch
+// L's inputs, and every launch after it skips its work, so when the sweep
+// stops at a term inside launch L (not its last), a replay of launch L on its
+// intact inputs stores p of that term, bitwise what launch L computed.  The
+// p buffers are p_out and two workspace vectors, arranged so that the
+// predicted degree ends in p_out; otherwise the result is copied there.
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
                  double tol, int maxdeg, hipStream_t st, SweepOut& out) {
   if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;
@@ -458,7 +461,6 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const bool fuse = op->fuse_terms != 0;
   const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n < kFourTermMaxPoints)) &&
                     four_terms_ok(op);
-  const int S = four ? 4 : 2;  // p buffers per launch (two sets)
   // first chunk: the last degree of this plan plus one (the degree moves by
   // about one from step to step; one launch too many costs its work, one too
   // few a second chunk and host round trip); the first sweep of a plan
@@ -494,31 +496,33 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     const int t = kcov == 0 ? predicted : kcov + std::max(8, kcov / 4);
     return t > maxdeg ? maxdeg : t;
   };
-  // slot of term j among the 2S p buffers: set L mod 2 of launch L, its last
-  // term in the set's last buffer and the earlier ones just before it
-  auto slot_of_term = [&](int j) -> int {
+  // launch index of term j (terms kL+1 .. kL+nL in launch L)
+  auto launch_of_term = [&](int j) -> int {
     int kcov = 0, L = 0, target = next_target(0);
     while (true) {
       if (kcov >= target) target = next_target(kcov);
       const int n = plan_terms(kcov, target);
-      if (j <= kcov + n) return S * (L & 1) + (S - 1) - (kcov + n - j);
+      if (j <= kcov + n) return L;
       kcov += n;
       ++L;
     }
   };
-  double* pbuf[8];
+  // buffers: y in ybuf[L mod 3] (the third one a workspace vector), p in
+  // pbuf[L mod 3], p_out at the predicted degree's launch
+  void* ybuf3[3];
+  double* pbuf[3];
   {
-    const int want = slot_of_term(std::max(mexp, 1));
-    double* ws[8] = {op->p, op->p2, op->p3, op->p4, op->p5, op->p6, op->p7, op->p8};
+    double* ws[4] = {op->p, op->p2, op->p3, op->p4};
     int wi = 0;
-    for (int s = 0; s < 2 * S; ++s) {
-      if (s == want) {
-        pbuf[s] = p_out;
-      } else {
-        if (ws[wi] == p_out) ++wi;
-        pbuf[s] = ws[wi++];
-      }
-    }
+    auto take_ws = [&]() {
+      if (ws[wi] == p_out) ++wi;
+      return ws[wi++];
+    };
+    ybuf3[0] = op->ybuf[0];
+    ybuf3[1] = op->ybuf[1];
+    ybuf3[2] = take_ws();
+    const int want = launch_of_term(std::max(mexp, 1)) % 3;
+    for (int i = 0; i < 3; ++i) pbuf[i] = i == want ? p_out : take_ws();
   }
   LejaArgs a{};
   a.invg = P.invg;
@@ -558,14 +562,12 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.k = kcov;
       a.nterms = n;
       a.first = kcov == 0;
-      a.yin = kcov == 0 ? (const void*)v : op->ybuf[L & 1];
-      a.yout = op->ybuf[(L + 1) & 1];
+      a.yin = kcov == 0 ? (const void*)v : ybuf3[L % 3];
+      a.yout = ybuf3[(L + 1) % 3];
       a.yin_f32 = (kcov > 0) && ys32;
-      a.pin = kcov == 0 ? nullptr : pbuf[S * ((L + 1) & 1) + S - 1];
-      a.p = pbuf[S * (L & 1) + S - 1];
-      a.pmid = n >= 2 ? pbuf[S * (L & 1) + S - n] : nullptr;
-      a.pmid2 = n == 4 ? pbuf[S * (L & 1) + S - 3] : nullptr;
-      a.pmid3 = n == 4 ? pbuf[S * (L & 1) + S - 2] : nullptr;
+      a.pin = kcov == 0 ? nullptr : pbuf[(L + 2) % 3];
+      a.p = pbuf[L % 3];
+      a.pmid = a.pmid2 = a.pmid3 = nullptr;
       a.w2 = (kcov == 0 && w2 && P.s[0] != 0.0) ? w2 : nullptr;
       a.w2c = P.s[kcov] * w2scale;
       a.shift = P.shift[kcov];
@@ -629,7 +631,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         if (stopped && past) break;
         float ms = 0.0f;
         HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * (l - L0)], op->evs[2 * (l - L0) + 1]));
-        const double b = leja_bytes(op, lk[l], ln[l], lk[l] == 0 && w2 != nullptr && P.s[0] != 0.0);
+        const double b = leja_bytes(op, lk[l], lk[l] == 0 && w2 != nullptr && P.s[0] != 0.0);
         op->prof_ms += ms;
         op->prof_launches += 1;
         op->prof_bytes += b;
@@ -651,7 +653,46 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     if (out.degree == 0) {
       HIPCHK(launch_fill(op->n, p_out, 0.0, st));
     } else {
-      double* res = pbuf[slot_of_term(out.degree)];
+      const int m = out.degree;
+      const int Ls = launch_of_term(m);
+      double* res = pbuf[Ls % 3];
+      if (m != lk[Ls] + ln[Ls]) {
+        // the sweep stopped inside launch Ls: replay it on its inputs (y in
+        // ybuf3[Ls mod 3], p in pbuf[(Ls + 2) mod 3], both intact) storing p
+        // of term m only, into p_out unless p_out holds its p input
+        const double* pin = pbuf[(Ls + 2) % 3];
+        double* dst = pin == p_out ? pbuf[Ls % 3] : p_out;
+        const int k = lk[Ls], n = ln[Ls], t = m - k;
+        a.ev_start = a.ev_stop = nullptr;
+        a.k = k;
+        a.nterms = n;
+        a.first = 0;
+        a.w2 = nullptr;
+        a.yin = ybuf3[Ls % 3];
+        a.yout = nullptr;
+        a.yin_f32 = ys32;
+        a.pin = pin;
+        a.p = n == t ? dst : nullptr;
+        a.pmid = t == 1 ? dst : nullptr;
+        a.pmid2 = t == 2 ? dst : nullptr;
+        a.pmid3 = t == 3 ? dst : nullptr;
+        a.shift = P.shift[k];
+        a.shift2 = n >= 2 ? P.shift[k + 1] : 0.0;
+        a.shift3 = n == 4 ? P.shift[k + 2] : 0.0;
+        a.shift4 = n == 4 ? P.shift[k + 3] : 0.0;
+        a.dk1 = P.d[k + 1];
+        a.dk2 = n >= 2 ? P.d[k + 2] : 0.0;
+        a.dk3 = n == 4 ? P.d[k + 3] : 0.0;
+        a.dk4 = n == 4 ? P.d[k + 4] : 0.0;
+        a.lds_fields = n == 4;
+        a.decide_only = 0;
+        a.replay = 1;
+        a.hctl = nullptr;
+        if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
+        else HIPCHK(launch_leja2_step(op->f, T2, a, st));
+        a.replay = 0;
+        res = dst;
+      }
       if (res != p_out) HIPCHK(launch_axpby(op->n, p_out, 1.0, res, 0.0, nullptr, st));
     }
   }
@@ -877,13 +918,6 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->p2 = reinterpret_cast<double*>(base + L.p2);
   op->p3 = reinterpret_cast<double*>(base + L.p3);
   op->p4 = reinterpret_cast<double*>(base + L.p4);
-  if (L.p58 != kNone) {
-    const size_t st = align_up((size_t)nx * ny * 8);
-    op->p5 = reinterpret_cast<double*>(base + L.p58);
-    op->p6 = reinterpret_cast<double*>(base + L.p58 + st);
-    op->p7 = reinterpret_cast<double*>(base + L.p58 + 2 * st);
-    op->p8 = reinterpret_cast<double*>(base + L.p58 + 3 * st);
-  }
   op->slot_stride = 6 * (long)max_partial_blocks(nx, ny);
   op->partials = reinterpret_cast<double*>(base + L.partials);
   op->ctl = reinterpret_cast<Ctl*>(base + L.ctl);
@@ -995,7 +1029,7 @@ int adl_op_set_term_fusion(adl_op* op, int mode) {
   RETCHK(check_op(op));
   if (mode < 0 || mode > 4) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2, 3 or 4");
   if (mode == 4 && !four_terms_ok(op))
-    return fail(ADL_EINVAL, "four terms per launch need a grid below 2^20 points, no non-temporal hints and, "
+    return fail(ADL_EINVAL, "four terms per launch need a sweep without non-temporal hints and, "
                             "on a periodic grid, ny >= 4 other than 5 and 9");
   op->fuse_terms = mode;
   return ADL_OK;

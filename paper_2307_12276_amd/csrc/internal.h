@@ -135,10 +135,11 @@ hipError_t launch_apply2(const FieldView& f, const Tiling& t, const double* x, d
 // launch's terms (taken by block 0).
 struct LejaArgs {
   const void* yin;   // y_k (double at k = 0, else the y storage type)
-  void* yout;        // y of the launch's last term
+  void* yout;        // y of the launch's last term, or null (not stored: a replay)
   const double* pin; // p_k (k >= 1; FP64)
-  double* p;         // p of the launch's last term (a different buffer from pin)
-  double* pmid;      // two-term launch: p_{k+1}; four-term launch: p_{k+1}
+  double* p;         // p of the launch's last term (a different buffer from pin), or
+                     // null (not stored: a replay of a launch whose earlier term is the result)
+  double* pmid;      // two-term launch: p_{k+1}; four-term launch: p_{k+1}; null: not stored
   const double* w2;  // augmented column (first term only), or null
   double w2c;        // s_0 / h
   double shift;      // c + gamma xi_k   (term k+1)
@@ -175,6 +176,10 @@ struct LejaArgs {
   double* pmid2;
   double* pmid3;
   int lds_fields;    // four-term launch: stage 1 keeps the field rows in LDS for stages 2-4
+  // Replay of a launch of a finished sweep, to store p of one of its earlier
+  // terms (the result, when the sweep stopped inside the launch): the same
+  // arithmetic on the same y_k and p_k, no stop flag, no decision, no partials
+  int replay;
 };
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // two-term launch (terms k+1, k+2; k >= 1) on the two-term tiling

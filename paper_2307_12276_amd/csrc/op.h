@@ -76,13 +76,9 @@ struct adl_op {
   double* yacc = nullptr;
   double* tmp = nullptr;
   double* tmp2 = nullptr;
-  double* p2 = nullptr;     // Newton polynomial buffers of a sweep (with the caller's p_out)
+  double* p2 = nullptr;     // a sweep's third y buffer and its p buffers (with p and the caller's p_out)
   double* p3 = nullptr;
   double* p4 = nullptr;
-  double* p5 = nullptr;     // four-term launches (grids below 2^20 points only): four more
-  double* p6 = nullptr;
-  double* p7 = nullptr;
-  double* p8 = nullptr;
   long slot_stride = 0;     // doubles per partials slot
   double* partials = nullptr;
   Ctl* ctl = nullptr;

@@ -259,10 +259,10 @@ __device__ __forceinline__ void ring_stage1(const Rings<VEC, ADVF>& R, const Str
 template <typename TY>
 struct StagedIO {
   const TY* yin;
-  TY* yout;
+  TY* yout;          // or null: not stored
   const double* pin;
-  double* pmid;
-  double* p;
+  double* pmid;      // or null: not stored
+  double* p;         // or null: not stored
   double shift, shift2, invg, dk1, dk2;
 };
 
@@ -346,6 +346,12 @@ __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY
   R.edges = F.bc != BC_PERIODIC && (i0 <= 0 || i0 + kWave * VEC >= F.nx);
   const TY* __restrict__ yin = io.yin;
   const int ocol = g.col0 * (int)sizeof(TY), ocolp = g.col0 * 8;
+  // outputs that are not stored: the lanes' offsets drop the stores (and the
+  // row's base comes from another array, so no address is formed from null)
+  const bool sy = io.yout != nullptr, sm = io.pmid != nullptr, sp = io.p != nullptr;
+  TY* const yo = sy ? io.yout : const_cast<TY*>(yin);
+  double* const pmo = sm ? io.pmid : const_cast<double*>(io.pin);
+  double* const po = sp ? io.p : const_cast<double*>(io.pin);
   // prologue: input rows J0-2 .. J0+1, y_{k+1} on J0-1 and J0, then input
   // rows J0+2 .. J0+5 (the last of them takes the slot of J0-2)
   RowSet<TF, TY, VEC, ADVF> cur, nxt;
@@ -389,9 +395,9 @@ __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY
       acc[2] += keep ? t2 * t2 : 0.0;
       acc[3] += keep ? p2[v] * p2[v] : 0.0;
     }
-    row_store<NT, TY, VEC>(io.yout + ro, F.nx, keep ? ocol : kDropOffset, y2);
-    row_store<NT, double, VEC>(io.pmid + ro, F.nx, keep ? ocolp : kDropOffset, pm);
-    row_store<NT, double, VEC>(io.p + ro, F.nx, keep ? ocolp : kDropOffset, p2);
+    row_store<NT, TY, VEC>(yo + ro, F.nx, keep && sy ? ocol : kDropOffset, y2);
+    row_store<NT, double, VEC>(pmo + ro, F.nx, keep && sm ? ocolp : kDropOffset, pm);
+    row_store<NT, double, VEC>(po + ro, F.nx, keep && sp ? ocolp : kDropOffset, p2);
     __syncthreads();
     // the next step's rows replace rows j0-1 .. j0+2, read for the last time above
     if constexpr (!LAST) rowset_put<TF, TY, VEC, ADVF>(R, g, j0 + 6 + wave, F, nxt);

@@ -377,10 +377,11 @@ __global__ __launch_bounds__(kTileBlock) void leja_kernel(FieldView F, Tiling T,
 // coefficients and p_k of its own row in registers; the one-row frame above is already in the
 // ring and one wave adds the frame row below.  After a block barrier, stage 2
 // computes y_{k+2} from the ring (x-neighbours by the same DPP shifts) and
-// updates p twice: p_{k+1} = p_k + d_{k+1} y_{k+1} (written: it is the result
-// if term k+1 is the last) and p_{k+2} = p_{k+1} + d_{k+2} y_{k+2}.  Per point
-// and pair of terms: read y_k, the fields and p_k, write y_{k+2}, p_{k+1} and
-// p_{k+2} (64 B in FP64 instead of 2 x 56 B).  Frame positions outside a
+// updates p twice: p_{k+1} = p_k + d_{k+1} y_{k+1} and p_{k+2} = p_{k+1} +
+// d_{k+2} y_{k+2}.  Per point and pair of terms: read y_k, the fields and
+// p_k, write y_{k+2} and p_{k+2} (56 B in FP64 instead of 2 x 56 B); p_{k+1}
+// is stored only by a replay of the launch (A.replay), when the sweep
+// stopped at term k+1.  Frame positions outside a
 // Dirichlet grid hold zero; periodic frames are computed from wrapped loads.
 // Stage 2 reads y_{k+1} from LDS rounded to the y storage type, exactly as
 // the one-term kernel would read it back; p and the norms use it unrounded.
@@ -484,7 +485,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
   extern __shared__ double lds[];
   const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);  // as in leja_kernel
   if (L == 0) {
-    leja_decide(A);
+    if (!A.replay) leja_decide(A);
     return;
   }
   const int b = L - 1;
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
   ep1.per = F.bc == BC_PERIODIC;
   ep1.shift = A.shift;
   ep1.invg = A.invg;
-  ep1.stopflag = __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ep1.stopflag = A.replay ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // term k+1: ||d y||^2, ||p||^2; term k+2: the same
   bool live = true;
   const int cb = b % T.ncb;
@@ -546,16 +547,16 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
           acc[2] += t2 * t2;
           acc[3] += p2[v] * p2[v];
         }
-        str_s<NT, TY, VEC>(yout + ro, g.col0, y2);
-        str_s<NT, double, VEC>(A.pmid + ro, g.col0, pm);
-        str_s<NT, double, VEC>(A.p + ro, g.col0, p2);
+        if (yout) str_s<NT, TY, VEC>(yout + ro, g.col0, y2);
+        if (A.pmid) str_s<NT, double, VEC>(A.pmid + ro, g.col0, pm);
+        if (A.p) str_s<NT, double, VEC>(A.p + ro, g.col0, p2);
       }
     }
     __syncthreads();
   }
   // block partials: term k+1 at (0, 1, 2), term k+2 at (3, 4, 5)
   block_allreduce<4, 4>(acc);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !A.replay) {
     double* part = A.partials + (long)A.slot * A.slot_stride;
     const int nb = T.nblocks;
     part[0L * nb + b] = acc[0];
@@ -584,8 +585,9 @@ __global__ __launch_bounds__(kTileBlock2) void leja2_kernel(FieldView F, Tiling 
 // per block) measured slower on every grid once the LDS rows were accessed
 // 16 bytes per lane, and the host no longer picks it.  Each wave keeps p of
 // its output rows in registers and updates it after every stage:
-// p_{k+t} = p_{k+t-1} + d_{k+t} y_{k+t}, written for t = 1, 2, 3 (one of them
-// is the result if the sweep stops there) and 4, with y_{k+4}.  Rows and
+// p_{k+t} = p_{k+t-1} + d_{k+t} y_{k+t}; p_{k+4} is written with y_{k+4}, and
+// p_{k+t} for t < 4 only by a replay of the launch (A.replay), when the
+// sweep stopped at term k+t.  Rows and
 // columns outside a Dirichlet grid hold zero at every stage; periodic ones are
 // computed from wrapped field rows.  Stages read y from LDS rounded to the y
 // storage type, as a one-term launch reads it back from memory; p and the
@@ -759,10 +761,10 @@ __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling 
   // on the same XCD and find those rows in its L2
   const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
   if (L == 0) {
-    leja_decide(A);
+    if (!A.replay) leja_decide(A);
     return;
   }
-  if (block_stopped(A.ctl)) return;  // uniform over the block
+  if (!A.replay && block_stopped(A.ctl)) return;  // uniform over the block
   const int b = L - 1;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
@@ -803,7 +805,7 @@ __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling 
           tn += tv * tv;
           pn += pk[h][v] * pk[h][v];
         }
-        str_s<false, double, VEC>(dst + (long)jo[h] * F.nx, g.col0, pk[h]);
+        if (dst) str_s<false, double, VEC>(dst + (long)jo[h] * F.nx, g.col0, pk[h]);
       }
     }
   };
@@ -856,13 +858,13 @@ __global__ __launch_bounds__(kWave * kW4) void leja4_kernel(FieldView F, Tiling 
         acc[6] += tv * tv;
         acc[7] += pk[h][v] * pk[h][v];
       }
-      str_s<false, TY, VEC>(yout + ro, g.col0, yt);
-      str_s<false, double, VEC>(A.p + ro, g.col0, pk[h]);
+      if (yout) str_s<false, TY, VEC>(yout + ro, g.col0, yt);
+      if (A.p) str_s<false, double, VEC>(A.p + ro, g.col0, pk[h]);
     }
   }
   // block partials: term t at rows 3t (||d y||^2), 3t + 1 (||p||^2), 3t + 2 (0)
   block_allreduce<8, 8>(acc);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !A.replay) {
     double* part = A.partials + (long)A.slot * A.slot_stride;
     const int nb = T.nblocks;
 #pragma unroll
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja2s_kernel(FieldView F, Tiling
   extern __shared__ double lds[];
   const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
   if (L == 0) {
-    leja_decide(A);
+    if (!A.replay) leja_decide(A);
     return;
   }
   const int b = L - 1;
@@ -898,12 +900,12 @@ __global__ __launch_bounds__(kTileBlock2) void leja2s_kernel(FieldView F, Tiling
   io.dk1 = A.dk1;
   io.dk2 = A.dk2;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  staged_run<TF, TY, VEC, ADVF, NT>(F, io, lds, cb * (kWave - 2) * VEC - VEC, rb0, rb1,
-                                    __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                    acc);
+  staged_run<TF, TY, VEC, ADVF, NT>(
+      F, io, lds, cb * (kWave - 2) * VEC - VEC, rb0, rb1,
+      A.replay ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), acc);
   // block partials: term k+1 at (0, 1, 2), term k+2 at (3, 4, 5)
   block_allreduce<4, 4>(acc);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !A.replay) {
     double* part = A.partials + (long)A.slot * A.slot_stride;
     const int nb = T.nblocks;
     part[0L * nb + b] = acc[0];
@@ -1236,13 +1238,12 @@ hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs
     return hipErrorInvalidValue;
   if (t.rows != kR4 || t.bands != 1 || t.nblocks != t.ncb * t.nrb) return hipErrorInvalidValue;
   if (!a.decide_only) {
-    // p_k is read while the four p outputs are written: all distinct
+    // p_k is read while the stored p outputs (at least one) are written: all distinct
     const double* o[5] = {a.pin, a.pmid, a.pmid2, a.pmid3, a.p};
-    for (int i = 0; i < 5; ++i) {
-      if (o[i] == nullptr) return hipErrorInvalidValue;
+    if (a.pin == nullptr || (!a.pmid && !a.pmid2 && !a.pmid3 && !a.p)) return hipErrorInvalidValue;
+    for (int i = 1; i < 5; ++i)
       for (int j = 0; j < i; ++j)
-        if (o[i] == o[j]) return hipErrorInvalidValue;
-    }
+        if (o[i] != nullptr && o[i] == o[j]) return hipErrorInvalidValue;
   }
   ADL_DISPATCH_TILE(t, f, {
     if (f.f32) {
@@ -1258,8 +1259,9 @@ hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs
 
 hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
   if (a.first || a.k < 1 || a.nterms != 2 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32) return hipErrorInvalidValue;
-  if (!a.decide_only && (a.pin == nullptr || a.p == nullptr || a.pmid == nullptr || a.pin == a.p ||
-                         a.pin == a.pmid || a.p == a.pmid))
+  // p_k is read while the stored p outputs (at least one) are written: all distinct
+  if (!a.decide_only && (a.pin == nullptr || (a.p == nullptr && a.pmid == nullptr) || a.pin == a.p ||
+                         a.pin == a.pmid || (a.p != nullptr && a.p == a.pmid)))
     return hipErrorInvalidValue;
   ADL_DISPATCH_TILE(t, f, {
     if (a.stream) {

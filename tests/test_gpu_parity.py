@@ -364,14 +364,19 @@ def test_default_mode_runs_four_terms_on_mid_grids():
     assert rel(res[1][0], res[0][0]) < max(1e-13, 4e-15 * m)
 
 
-def test_four_term_mode_needs_a_small_grid():
-    """Mode 4 is refused where the workspace has no room for its eight p
-    buffers (2^20 points and more)."""
+def test_four_term_mode_needs_a_sweep_without_hints():
+    """Mode 4 is refused while the op's sweeps carry non-temporal hints (the
+    four-term kernel has no hinted form) and accepted without them, also at
+    2^20 points (a fused launch stores only its last term's y and p, so the
+    workspace needs no extra buffers for it)."""
     nx = ny = 1024
     z = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
     op = A.Op(z + 1.0, z, z + 1.0, 1.0 / nx, 1.0 / ny, A.BC_PERIODIC, A.STORAGE_FP64)
-    with pytest.raises(A.AdlError, match="2\\^20"):
+    op.set_streaming(1)
+    with pytest.raises(A.AdlError, match="non-temporal"):
         op.set_term_fusion(4)
+    op.set_streaming(0)
+    op.set_term_fusion(4)
     op.set_term_fusion(1)
 
 
