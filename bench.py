@@ -12,16 +12,16 @@ beyond L2 and the 256 MB Infinity Cache.  Operator setup, the Gershgorin
 bound and the source arrays of every step are on the device before timing.
 
 Prints one JSON line.  `value` = time steps per second on one GPU.
-`roofline` = the dominant kernel, the two-term Newton-Leja launch
-(leja2s_kernel: input rows staged in LDS): 56 B per point and Newton term
+`roofline` = the dominant kernel, the three-term Newton-Leja launch
+(leja3s_kernel: input rows staged in LDS): 56 B per point and Newton term
 (read y, three tensor fields and p, write y and p, FP64) times the terms of
 a launch, over the launch's average duration from HIP events on its own
 dispatches, against 8 TB/s; `traffic` = the HBM bytes per launch measured by
 rocprofv3 counters (profiles/).  `cpu_baseline` = the FP64 NumPy oracle,
 single-threaded, on a bounded sample of the same workload.  Extra legs: the
-512^2 two-stage quadrature workload, one- and two-term kernels at 4096^2, four
-terms per launch at 640^2, the 256-bin momentum workload (chosen vs plain),
-the paper's Cases I-IV.
+512^2 two-stage quadrature workload, one-, two- and three-term kernels at
+4096^2, four terms per launch at 640^2, the 256-bin momentum workload
+(chosen vs plain), the paper's Cases I-IV.
 """
 import os
 
@@ -85,7 +85,7 @@ def device_sources(w):
 
 
 KERNEL_SOURCES = ("device.h", "internal.h", "stencil.hip", "tile.h", "staged.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja2s_kernel_stream4096_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja3s_kernel_stream4096_traffic.txt")
 TRAFFIC_KEY = "traffic_bytes_per_launch_stream4096"
 BYTES_PER_TERM_FP64 = 56.0  # read y, Dxx, Dxy, Dyy, p; write y, p (FP64, constant advection)
 
@@ -133,17 +133,26 @@ def kernel_roofline(op_ms, launches, nbytes):
     return avg_ms, per_launch, achieved
 
 
+KIND_KERNELS = {"two": "leja2s_kernel (two Newton terms per launch, input rows staged in LDS, non-temporal "
+                        "hints on the vectors read or written once)",
+                "three": "leja3s_kernel (three Newton terms per launch, input rows staged in LDS, non-temporal "
+                         "hints on the vectors read or written once)",
+                "four": "leja4_kernel (four Newton terms per launch)"}
+
 LEG_KERNELS = {0: ("one-term", "leja_kernel"),
-               1: ("two-term", "leja2s_kernel (input rows staged in LDS) + leja_kernel (first term)"),
-               3: ("two-term, register frames", "leja2_kernel + leja_kernel (first term)")}
+               1: ("three-term (the default)", "leja3s_kernel (input rows staged in LDS) + leja_kernel (first term)"),
+               2: ("two-term", "leja2s_kernel (input rows staged in LDS) + leja_kernel (first term)"),
+               3: ("two-term, register frames", "leja2_kernel + leja_kernel (first term)"),
+}
 
 
 def run_roofline_leg(w, storage, mode=1):
     """Midpoint steps of the stream-function field at n x n (two warm-up
     steps, three timed): the Newton-Leja kernels' dispatch-timed bandwidth on
     a working set far beyond the caches, with one term per launch (mode 0),
-    two with the kernel the library picks at this size (mode 1: input rows
-    staged in LDS) or two with the register-frame kernel (mode 3)."""
+    the library's choice at this size (mode 1: three terms per launch, input
+    rows staged in LDS), two with staged rows (mode 2) or two with register
+    frames (mode 3)."""
     import torch
     import paper_2307_12276_amd as A
     n = w.nx
@@ -170,7 +179,7 @@ def run_roofline_leg(w, storage, mode=1):
            "launches_of": LEG_KERNELS[mode][0],
            "nx": n, "ny": n, "kernel": LEG_KERNELS[mode][1],
            "launches": launches, "bytes_per_launch": per_launch, "avg_kernel_us": avg_ms * 1e3,
-           "us_per_term": ms * 1e3 / max(terms + 1, 1),
+           "us_per_term": ms * 1e3 / (timed * max(terms + 1, 1)),
            "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
            "matvecs_per_step": st["matvecs"], "step_ms": wall * 1e3}
     del op
@@ -658,19 +667,22 @@ def headline(args):
         op.midpoint_step(u, S[n], w.dt, w.tol)
     torch.cuda.synchronize()
     el_prof = time.perf_counter() - t1
-    kinds = {k: op.profile_read_kind(getattr(A, "LAUNCH_" + k.upper())) for k in ("first", "one", "two", "four")}
+    kinds = {k: op.profile_read_kind(getattr(A, "LAUNCH_" + k.upper()))
+             for k in ("first", "one", "two", "three", "four")}
     op.profile_read()
     op.profile(False)
-    ms2, n2, fused2, terms2 = kinds["two"]
+    # the dominant launch kind (the most kernel time): three terms per launch
+    dom = max(("two", "three", "four"), key=lambda k: kinds[k][0])
+    ms2, n2, fused2, terms2 = kinds[dom]
     N = w.nx * w.ny
     avg_s = ms2 / max(n2, 1) * 1e-3
     alg = BYTES_PER_TERM_FP64 * N * terms2 / max(n2, 1)
     achieved = alg / avg_s / 1e9 if n2 else 0.0
     traffic = measured_traffic()
     value = args.steps / el
-    log("headline: %d steps in %.3fs: %.2f steps/s, %.1f matvecs/step; two-term launches %.1f us avg over %d "
+    log("headline: %d steps in %.3fs: %.2f steps/s, %.1f matvecs/step; %s-term launches %.1f us avg over %d "
         "(%.2f terms each): %.0f GB/s by 56 B/pt/term (%.1f%% of 8 TB/s)"
-        % (args.steps, el, value, mv / args.steps, avg_s * 1e6, n2, terms2 / max(n2, 1), achieved,
+        % (args.steps, el, value, mv / args.steps, dom, avg_s * 1e6, n2, terms2 / max(n2, 1), achieved,
            100 * achieved / HBM_PEAK_GBS))
     out = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
@@ -684,16 +696,15 @@ def headline(args):
                    "matvecs_per_step": mv / args.steps, "matvecs_per_s": mv / el, "setup_s": setup_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "leja2s_kernel (two Newton terms per launch, input rows staged in LDS, "
-                               "non-temporal hints on the vectors read or written once)",
+                     "kernel": KIND_KERNELS[dom],
                      "bytes_per_launch": alg, "bytes_rule": "56 B per point and Newton term (FP64) x %d points "
                                                            "x %.2f terms per launch" % (N, terms2 / max(n2, 1)),
                      "avg_kernel_us": avg_s * 1e6, "launches": n2,
                      "fused_bytes_per_launch": fused2 / max(n2, 1),
-                     "timing": "HIP events on each two-term dispatch, second pass of %d steps (%.3fs)"
-                               % (args.steps, el_prof),
-                     "traffic_source": "profiles/leja2s_kernel_stream4096_traffic.txt (rocprofv3 FETCH_SIZE and "
-                                       "WRITE_SIZE per dispatch, scaled by a 1 GiB copy), bytes per launch"},
+                     "timing": "HIP events on each %s-term dispatch, second pass of %d steps (%.3fs)"
+                               % (dom, args.steps, el_prof),
+                     "traffic_source": "profiles/%s (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, "
+                                       "scaled by a 1 GiB copy), bytes per launch" % os.path.basename(TRAFFIC_FILE)},
         "launch_kinds": {k: {"launches": v[1], "avg_us": 1e3 * v[0] / v[1] if v[1] else None, "terms": v[3]}
                          for k, v in kinds.items()},
     }
@@ -768,8 +779,8 @@ def main():
         t0 = time.time()
         rw = W.roofline_shape(n=4096)
         log("roofline leg: 4096^2 fields built in %.1fs" % (time.time() - t0))
-        for storage, mode in ((A.STORAGE_FP64, 0), (A.STORAGE_FP64, 1), (A.STORAGE_FP64, 3),
-                              (A.STORAGE_FP32_FIELDS, 1)):
+        for storage, mode in ((A.STORAGE_FP64, 0), (A.STORAGE_FP64, 2), (A.STORAGE_FP64, 3),
+                              (A.STORAGE_FP64, 1), (A.STORAGE_FP32_FIELDS, 2), (A.STORAGE_FP32_FIELDS, 1)):
             legs.append(run_roofline_leg(rw, storage, mode))
             log("roofline leg %s %s: %.1f us/launch, %.1f us/term, %.0f GB/s (%.1f%% of 8 TB/s)" % (
                 legs[-1]["storage"], legs[-1]["launches_of"], legs[-1]["avg_kernel_us"],

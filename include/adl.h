@@ -135,10 +135,10 @@ int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, doub
 
 /* The same counters split by launch kind (read before adl_op_profile_read,
  * which resets them): ADL_LAUNCH_FIRST = the first term of a sweep (y_0 = v,
- * the augmented column), ADL_LAUNCH_ONE / _TWO / _FOUR = launches of one, two
- * or four later terms.  terms (may be NULL) = Newton terms those launches
- * computed.  ADL_EINVAL for another kind. */
-enum { ADL_LAUNCH_FIRST = 0, ADL_LAUNCH_ONE = 1, ADL_LAUNCH_TWO = 2, ADL_LAUNCH_FOUR = 3 };
+ * the augmented column), ADL_LAUNCH_ONE / _TWO / _THREE / _FOUR = launches of
+ * one, two, three or four later terms.  terms (may be NULL) = Newton terms
+ * those launches computed.  ADL_EINVAL for another kind. */
+enum { ADL_LAUNCH_FIRST = 0, ADL_LAUNCH_ONE = 1, ADL_LAUNCH_TWO = 2, ADL_LAUNCH_FOUR = 3, ADL_LAUNCH_THREE = 4 };
 int adl_op_profile_read_kind(const adl_op* op, int kind, double* kernel_ms, long long* launches,
                              double* bytes, long long* terms);
 
@@ -161,7 +161,10 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
  * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames), on
  * grids swept without non-temporal hints and, on a periodic grid, ny >= 4
  * other than 5 and 9 (a block's rows wrap once; ADL_EINVAL otherwise; mode 1
- * then runs two terms per launch); mode = 0 launches one kernel per term.
+ * then runs two terms per launch); mode = 5 computes three terms per launch
+ * with the input rows staged in LDS (y_{k+1}, y_{k+2} kept in LDS), on grids
+ * whose two-term tiling has two columns per lane (ADL_EINVAL otherwise);
+ * mode = 0 launches one kernel per term.
  * A fused launch stores y and p of its last term only; when the sweep stops
  * at an earlier term of a launch, the launch is run again on its inputs to
  * store p of that term (the same arithmetic, so the same values).  Results

@@ -20,7 +20,7 @@ BC_PERIODIC, BC_DIRICHLET = 0, 1
 STORAGE_FP64, STORAGE_FP32_FIELDS, STORAGE_FP32_FIELDS_Y = 0, 1, 2
 BOUND_GERSHGORIN, BOUND_POWER = 0, 1
 QUAD2_AUGMENTED, QUAD2_TWO_SWEEP = 0, 1
-LAUNCH_FIRST, LAUNCH_ONE, LAUNCH_TWO, LAUNCH_FOUR = 0, 1, 2, 3
+LAUNCH_FIRST, LAUNCH_ONE, LAUNCH_TWO, LAUNCH_FOUR, LAUNCH_THREE = 0, 1, 2, 3, 4
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_CACHE_PER_ROW = 9155, 9, 3, 201
 
 _ERRNAMES = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EBOUND: "EBOUND", ENAN: "ENAN",
@@ -271,8 +271,9 @@ class Op:
         _check(lib().adl_op_set_tiling(self.handle, int(rows), int(cols_per_lane)))
 
     def set_term_fusion(self, mode=True):
-        """Newton terms per launch: True/1 two (kernel chosen by the tiling),
-        2 two with LDS-staged rows, 3 two with register frames, False/0 one."""
+        """Newton terms per launch: True/1 the library's choice (four below
+        2^20 points, else two), 2 two with LDS-staged rows, 3 two with
+        register frames, 4 four, 5 three with LDS-staged rows, False/0 one."""
         m = int(mode) if not isinstance(mode, bool) else int(mode)
         _check(lib().adl_op_set_term_fusion(self.handle, m))
 
@@ -300,7 +301,7 @@ class Op:
 
     def profile_read_kind(self, kind: int):
         """(kernel ms, launches, algorithmic bytes, Newton terms) of the timed
-        Leja launches of one kind (LAUNCH_FIRST / _ONE / _TWO / _FOUR); call
+        Leja launches of one kind (LAUNCH_FIRST / _ONE / _TWO / _THREE / _FOUR); call
         before profile_read, which resets the counters."""
         ms = ctypes.c_double()
         n = ctypes.c_longlong()

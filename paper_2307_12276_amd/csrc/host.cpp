@@ -214,6 +214,9 @@ constexpr long kFourTermMaxPoints = 1L << 20;
 // 16 bytes per lane, chunks ending on their targets): 256^2 +7 %, 384^2
 // +15 %, 512^2 +14 %, 640^2 +44 %, 896^2 +31 %, 1000^2 +11 %
 
+// rows of block partials per slot: three per term of a launch of up to four
+constexpr int kSlotRows = 12;
+
 static size_t max_partial_blocks(int nx, int ny) {
   // stencil launches: at most max(kMaxGrid, number of strips) blocks (one
   // column per lane and 62 output columns per strip in the two-term kernel:
@@ -252,7 +255,7 @@ static WsLayout ws_layout(int nx, int ny, int storage) {
   L.p2 = take(n * 8);
   L.p3 = take(n * 8);
   L.p4 = take(n * 8);
-  L.partials = take(2 * 6 * max_partial_blocks(nx, ny) * 8);
+  L.partials = take(2 * kSlotRows * max_partial_blocks(nx, ny) * 8);
   L.ctl = take(4 * 128);
   L.total = o;
   return L;
@@ -430,6 +433,15 @@ static bool four_terms_ok(const adl_op* op) {
   return 12L * nb <= op->slot_stride && !streaming_on(op);
 }
 
+// Whether the op can run three Newton terms per launch (LDS-staged) on
+// vectors whose tiling has `vec` columns per lane: the three-term tiling has
+// two columns per lane (its stage 3 is then valid on the tiling's output
+// lanes), the vectors allow it, and a launch's 9 partial rows fit a partials
+// slot.
+static bool three_terms_ok(const adl_op* op, int vec) {
+  return vec == 2 && op->t3.vec == 2 && 9L * op->t3.nblocks <= op->slot_stride;
+}
+
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
 //
@@ -461,6 +473,12 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const bool fuse = op->fuse_terms != 0;
   const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n < kFourTermMaxPoints)) &&
                     four_terms_ok(op);
+  // three terms per launch (LDS-staged) from kStagedMinPoints up by default
+  // (4096^2 FP64 headline steps: 140 steps/s with two terms per launch, 185
+  // with three), or forced by mode 5
+  const bool three = !four && three_terms_ok(op, T.vec) &&
+                     (op->fuse_terms == 5 || (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints));
+  const Tiling& T3 = op->t3;
   // first chunk: the last degree of this plan plus one (the degree moves by
   // about one from step to step; one launch too many costs its work, one too
   // few a second chunk and host round trip); the first sweep of a plan
@@ -487,6 +505,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     };
     const int lim = four ? std::min(target, maxdeg) : maxdeg;
     if (four && kcov + 4 <= lim && !aug(4)) return 4;
+    if (three && kcov + 3 <= lim && !aug(3)) return 3;
     const bool two = fuse && kcov + 2 <= lim && !aug(2);
     return two ? 2 : 1;
   };
@@ -537,7 +556,8 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   // where the staged kernel's prologue and extra barrier do not pay (measured
   // per launch, staged / frames: 512^2 1.14, 768^2 0.93-1.05, 1024^2
   // 0.87-0.92, 1536^2 0.78-0.86, 2048^2 0.84-0.89)
-  a.staged = op->fuse_terms == 2 || (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints);
+  a.staged = op->fuse_terms == 2 || op->fuse_terms == 5 ||
+             (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints);
   a.partials = op->partials;
   a.slot_stride = op->slot_stride;
   a.ctl = op->ctl;
@@ -572,11 +592,11 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.w2c = P.s[kcov] * w2scale;
       a.shift = P.shift[kcov];
       a.shift2 = n >= 2 ? P.shift[kcov + 1] : 0.0;
-      a.shift3 = n == 4 ? P.shift[kcov + 2] : 0.0;
+      a.shift3 = n >= 3 ? P.shift[kcov + 2] : 0.0;
       a.shift4 = n == 4 ? P.shift[kcov + 3] : 0.0;
       a.dk1 = P.d[kcov + 1];
       a.dk2 = n >= 2 ? P.d[kcov + 2] : 0.0;
-      a.dk3 = n == 4 ? P.d[kcov + 3] : 0.0;
+      a.dk3 = n >= 3 ? P.d[kcov + 3] : 0.0;
       a.dk4 = n == 4 ? P.d[kcov + 4] : 0.0;
       // four-term launch: field rows kept in LDS (faster than reading them
       // again on every grid measured, 256^2 to 1000^2, once the LDS rows were
@@ -589,11 +609,12 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.slot_prev = prev_slot;
       a.decide_only = 0;
       if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
+      else if (n == 3) HIPCHK(launch_leja3_step(op->f, T3, a, st));
       else if (n == 2) HIPCHK(launch_leja2_step(op->f, T2, a, st));
       else HIPCHK(launch_leja_step(op->f, T, a, st));
       lk.push_back(kcov);
       ln.push_back(n);
-      prev_nb = n == 4 ? T4.nblocks : (n == 2 ? T2.nblocks : T.nblocks);
+      prev_nb = n == 4 ? T4.nblocks : n == 3 ? T3.nblocks : n == 2 ? T2.nblocks : T.nblocks;
       prev_k = kcov;
       prev_n = n;
       prev_slot = L & 1;
@@ -635,8 +656,11 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         op->prof_ms += ms;
         op->prof_launches += 1;
         op->prof_bytes += b;
-        const int kind = lk[l] == 0 ? ADL_LAUNCH_FIRST : (ln[l] == 4 ? ADL_LAUNCH_FOUR
-                                                          : (ln[l] == 2 ? ADL_LAUNCH_TWO : ADL_LAUNCH_ONE));
+        const int kind = lk[l] == 0  ? ADL_LAUNCH_FIRST
+                         : ln[l] == 4 ? ADL_LAUNCH_FOUR
+                         : ln[l] == 3 ? ADL_LAUNCH_THREE
+                         : ln[l] == 2 ? ADL_LAUNCH_TWO
+                                      : ADL_LAUNCH_ONE;
         op->kind_ms[kind] += ms;
         op->kind_launches[kind] += 1;
         op->kind_bytes[kind] += b;
@@ -678,17 +702,18 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         a.pmid3 = t == 3 ? dst : nullptr;
         a.shift = P.shift[k];
         a.shift2 = n >= 2 ? P.shift[k + 1] : 0.0;
-        a.shift3 = n == 4 ? P.shift[k + 2] : 0.0;
+        a.shift3 = n >= 3 ? P.shift[k + 2] : 0.0;
         a.shift4 = n == 4 ? P.shift[k + 3] : 0.0;
         a.dk1 = P.d[k + 1];
         a.dk2 = n >= 2 ? P.d[k + 2] : 0.0;
-        a.dk3 = n == 4 ? P.d[k + 3] : 0.0;
+        a.dk3 = n >= 3 ? P.d[k + 3] : 0.0;
         a.dk4 = n == 4 ? P.d[k + 4] : 0.0;
         a.lds_fields = n == 4;
         a.decide_only = 0;
         a.replay = 1;
         a.hctl = nullptr;
         if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
+        else if (n == 3) HIPCHK(launch_leja3_step(op->f, T3, a, st));
         else HIPCHK(launch_leja2_step(op->f, T2, a, st));
         a.replay = 0;
         res = dst;
@@ -905,6 +930,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->t1 = make_tiling(nx, ny, 0, 1);
   op->t2 = make_tiling2(nx, ny, 0);
   op->t21 = make_tiling2(nx, ny, 0, 1);
+  op->t3 = make_tiling2(nx, ny, 0, 0, kMaxGrid3);
   op->t4 = make_tiling4(nx, ny);
   op->t41 = make_tiling4(nx, ny, 1);
   op->ybuf[0] = base + L.y0;
@@ -918,7 +944,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->p2 = reinterpret_cast<double*>(base + L.p2);
   op->p3 = reinterpret_cast<double*>(base + L.p3);
   op->p4 = reinterpret_cast<double*>(base + L.p4);
-  op->slot_stride = 6 * (long)max_partial_blocks(nx, ny);
+  op->slot_stride = kSlotRows * (long)max_partial_blocks(nx, ny);
   op->partials = reinterpret_cast<double*>(base + L.partials);
   op->ctl = reinterpret_cast<Ctl*>(base + L.ctl);
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&op->host_ctl), 4 * sizeof(Ctl), hipHostMallocDefault);
@@ -977,7 +1003,7 @@ static void profile_reset(adl_op* op) {
   op->prof_ms = 0.0;
   op->prof_bytes = 0.0;
   op->prof_launches = 0;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     op->kind_ms[k] = op->kind_bytes[k] = 0.0;
     op->kind_launches[k] = op->kind_terms[k] = 0;
   }
@@ -1002,7 +1028,7 @@ int adl_op_profile_read(adl_op* op, double* kernel_ms, long long* launches, doub
 int adl_op_profile_read_kind(const adl_op* op, int kind, double* kernel_ms, long long* launches, double* bytes,
                              long long* terms) {
   RETCHK(check_op(op));
-  if (kind < ADL_LAUNCH_FIRST || kind > ADL_LAUNCH_FOUR) return fail(ADL_EINVAL, "bad launch kind %d", kind);
+  if (kind < ADL_LAUNCH_FIRST || kind > ADL_LAUNCH_THREE) return fail(ADL_EINVAL, "bad launch kind %d", kind);
   if (kernel_ms) *kernel_ms = op->kind_ms[kind];
   if (launches) *launches = op->kind_launches[kind];
   if (bytes) *bytes = op->kind_bytes[kind];
@@ -1020,6 +1046,7 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
   op->t1 = make_tiling(op->nx, op->ny, rows, 1);
   op->t2 = make_tiling2(op->nx, op->ny, rows, cols_per_lane);
   op->t21 = make_tiling2(op->nx, op->ny, rows, 1);
+  op->t3 = make_tiling2(op->nx, op->ny, rows, cols_per_lane, kMaxGrid3);
   op->t4 = make_tiling4(op->nx, op->ny, cols_per_lane);
   op->t41 = make_tiling4(op->nx, op->ny, 1);
   return ADL_OK;
@@ -1027,7 +1054,9 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
 
 int adl_op_set_term_fusion(adl_op* op, int mode) {
   RETCHK(check_op(op));
-  if (mode < 0 || mode > 4) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2, 3 or 4");
+  if (mode < 0 || mode > 5) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2, 3, 4 or 5");
+  if (mode == 5 && !three_terms_ok(op, 2))
+    return fail(ADL_EINVAL, "three terms per launch need a grid whose two-term tiling has two columns per lane");
   if (mode == 4 && !four_terms_ok(op))
     return fail(ADL_EINVAL, "four terms per launch need a sweep without non-temporal hints and, "
                             "on a periodic grid, ny >= 4 other than 5 and 9");

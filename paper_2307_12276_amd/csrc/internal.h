@@ -23,12 +23,21 @@ constexpr int kBlock = 256;             // elementwise and reduction kernels
 #ifndef ADL_MAX_GRID2
 #define ADL_MAX_GRID2 4096
 #endif
+#ifndef ADL_MAX_GRID3
+#define ADL_MAX_GRID3 1536
+#endif
 constexpr int kWavesY = ADL_WAVES_Y;     // stencil blocks: waves stacked in y (one strip)
 constexpr int kTileBlock = kWave * kWavesY;
 constexpr int kMaxGrid = ADL_MAX_GRID;   // blocks of a stencil launch (tiles walked per block)
 constexpr int kWavesY2 = ADL_WAVES_Y2;   // two-term kernel: waves (= output rows) per block
 constexpr int kTileBlock2 = kWave * kWavesY2;
 constexpr int kMaxGrid2 = ADL_MAX_GRID2;
+// three-term launches (LDS-staged, three blocks per CU): fewer blocks with
+// longer runs of bands, so that the run's prologue (two stages on four rows
+// above the run) is spread over more output rows (measured at 4096^2 FP64,
+// the headline's steps: 4096 blocks 211 us per launch, 2304 201 us, 1536
+// 194 us)
+constexpr int kMaxGrid3 = ADL_MAX_GRID3;
 
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
 
@@ -185,7 +194,11 @@ hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs&
 // two-term launch (terms k+1, k+2; k >= 1) on the two-term tiling
 hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // tiling of the two-term kernel: strips of 62*vec output columns, bands of kWavesY*rows rows
-Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint = 0);
+Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint = 0, int max_blocks = kMaxGrid2);
+// three-term launch (terms k+1 .. k+3; k >= 1) with the input rows staged in
+// LDS, on a two-term tiling with two columns per lane; the launch's block
+// partials take 9 x nblocks values of its slot
+hipError_t launch_leja3_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // four-term launch (terms k+1 .. k+4; k >= 1) on the four-term tiling; the
 // launch's block partials take 12 x nblocks values of its slot
 hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);

@@ -47,6 +47,7 @@ struct adl_op {
   Tiling t1{};  // one column per lane: used when a caller's vector is not 16-byte aligned
   Tiling t2{};  // two-term Newton-Leja kernel (two columns per lane when nx is even)
   Tiling t21{}; // two-term kernel, one column per lane
+  Tiling t3{};  // three-term kernel: the two-term tiling with fewer, longer runs (kMaxGrid3)
   Tiling t4{};  // four-term Newton-Leja kernel (two columns per lane when nx is even)
   Tiling t41{}; // four-term kernel, one column per lane
   int fuse_terms = 1;  // 0 one Newton term per launch, 1 two (kernel by tiling), 2 two (LDS-staged), 3 two (frames),
@@ -91,12 +92,12 @@ struct adl_op {
   std::vector<Plan> plans;  // small cache
   int plan_next = 0;
   // kernel profiling of the Newton-Leja iteration kernel: totals, and per
-  // launch kind (ADL_LAUNCH_FIRST, _ONE, _TWO, _FOUR)
+  // launch kind (ADL_LAUNCH_FIRST, _ONE, _TWO, _FOUR, _THREE)
   bool prof = false;
   double prof_ms = 0.0, prof_bytes = 0.0;
   long long prof_launches = 0;
-  double kind_ms[4] = {0, 0, 0, 0}, kind_bytes[4] = {0, 0, 0, 0};
-  long long kind_launches[4] = {0, 0, 0, 0}, kind_terms[4] = {0, 0, 0, 0};
+  double kind_ms[5] = {0, 0, 0, 0, 0}, kind_bytes[5] = {0, 0, 0, 0, 0};
+  long long kind_launches[5] = {0, 0, 0, 0, 0}, kind_terms[5] = {0, 0, 0, 0, 0};
   std::vector<hipEvent_t> evs;
 };
 

@@ -150,16 +150,17 @@ __device__ __forceinline__ void ring_rowc(const double* row, RowC<VEC>& o) {
   lds_get<VEC>(row + RingRow<VEC>::kOwn + (threadIdx.x & (kWave - 1)) * VEC, o.c);
 }
 
-// the input rings of a block: y_k, kyy, kxy, kxx (+ ax', ay'), kSRing rows each
-template <int VEC, bool ADVF>
+// the input rings of a block: y_k, kyy, kxy, kxx (+ ax', ay'), NR rows each
+template <int VEC, bool ADVF, int NR = kSRing>
 struct Rings {
   static constexpr int kRow = RingRow<VEC>::kLen;
   static constexpr int kArrays = ADVF ? 6 : 4;
+  static constexpr int kRows = NR;
   double* base;
   int r0;      // grid row of slot 0
   bool edges;  // Dirichlet ghost columns in the strip or its halo (ring_put)
   __device__ __forceinline__ double* row(int a, int r) const {
-    return base + ((long)a * kSRing + (unsigned)(r - r0) % kSRing) * kRow;
+    return base + ((long)a * NR + (unsigned)(r - r0) % NR) * kRow;
   }
 };
 
@@ -208,8 +209,8 @@ __device__ __forceinline__ void rowset_load(const FieldView& F, const TY* __rest
   }
 }
 
-template <typename TF, typename TY, int VEC, bool ADVF>
-__device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
+template <typename TF, typename TY, int VEC, bool ADVF, int NR>
+__device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r, const FieldView& F,
                                            const RowSet<TF, TY, VEC, ADVF>& s) {
   ring_put<VEC, MODE_ZERO>(R.row(0, r), g, s.y, R.edges, F.nx);
   ring_put<VEC, MODE_EDGE>(R.row(1, r), g, s.gy, R.edges, F.nx);
@@ -222,8 +223,8 @@ __device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF>& R, const Stri
 }
 
 // (A x) at row r from the rings, x = y_k (ring 0) or the rows u[] given
-template <int VEC, bool ADVF>
-__device__ __forceinline__ void ring_stencil(const Rings<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
+template <int VEC, bool ADVF, int NR>
+__device__ __forceinline__ void ring_stencil(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r, const FieldView& F,
                                              const RowN<VEC>& um, const RowN<VEC>& uc, const RowN<VEC>& up,
                                              double (&Ax)[VEC]) {
   RowN<VEC> m[3], k, ac;
@@ -241,15 +242,15 @@ __device__ __forceinline__ void ring_stencil(const Rings<VEC, ADVF>& R, const St
 }
 
 // stage 1 of row r: y_{k+1} into the y_{k+1} ring (ghost rule of Stage1Ep)
-template <int VEC, bool ADVF>
-__device__ __forceinline__ void ring_stage1(const Rings<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
-                                            Stage1Ep<VEC, kSY1>& ep) {
+template <int VEC, bool ADVF, int NR, int NY>
+__device__ __forceinline__ void ring_stage1(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r, const FieldView& F,
+                                            Stage1Ep<VEC, NY>& ep) {
   RowN<VEC> u[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) ring_rown<VEC>(R.row(0, r - 1 + t), u[t]);
   double Ax[VEC];
   ring_stencil<VEC, ADVF>(R, g, r, F, u[0], u[1], u[2], Ax);
-  typename Stage1Ep<VEC, kSY1>::Extra none;
+  typename Stage1Ep<VEC, NY>::Extra none;
   ep.finish(r, g, Ax, u[1].c, none);
 }
 
@@ -406,6 +407,188 @@ __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY
 #pragma unroll 1
   for (int rb = rb0; rb < rb1 - 1; ++rb) band.template operator()<false>(rb);
   if (rb1 > rb0) band.template operator()<true>(rb1 - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Three Newton-Leja terms per launch with the input rows staged in LDS (the
+// pass of leja3s_kernel): the march of staged_run with one more stage.  Per
+// band step (output rows j0 .. j0+3, one per wave) stage 1 computes y_{k+1}
+// on rows j0+2 .. j0+5 from the input rings into the Y1 ring, stage 2
+// y_{k+2} on rows j0+1 .. j0+4 from Y1 into the Y2 ring, and stage 3
+// y_{k+3} on the output rows from Y2; the output row's p is advanced by the
+// three terms, p_{k+t} = p_{k+t-1} + d_{k+t} y_{k+t}, with y_{k+1} and
+// y_{k+2} of that row read back (unrounded) from Y1 and Y2.  Per point and
+// three terms the launch reads y_k, the fields and p_k once and writes
+// y_{k+3} and p_{k+3}: 56 B in FP64 instead of 3 x 56 B.
+//
+// Columns: stage t is valid one column further in from each end of the
+// strip than stage t-1 (stage 1 on all 64*VEC columns, thanks to the halo
+// elements); with two columns per lane, stage 3 is valid on lanes 1 .. 62,
+// the output lanes of the two-term tiling, which the three-term launch
+// shares.
+//
+// Rings: the input rings hold rows j0-1 .. j0+6 at a step's start (stage 1
+// reads y_k on j0+1 .. j0+6, stage 3 the fields on j0-1 .. j0+4), and the
+// step's loads of rows j0+7 .. j0+10 replace j0-1 .. j0+2 after stage 3;
+// Y1 holds rows j0 .. j0+5 while stage 2 and the p update read it, Y2 rows
+// j0-1 .. j0+4 while stage 3 and the p update read it.
+constexpr int kS3Ring = 8;
+constexpr int kS3Y = 6;
+
+template <typename TY>
+struct Staged3IO {
+  const TY* yin;
+  TY* yout;           // or null: not stored
+  const double* pin;
+  double* p1;         // p_{k+1}, or null: not stored
+  double* p2;         // p_{k+2}, or null
+  double* p;          // p_{k+3}, or null
+  double shift, shift2, shift3, invg, dk1, dk2, dk3;
+};
+
+// y_{k+t} (t >= 2) at row r: the stencil of the y_{k+t-1} ring rows r-1 .. r+1
+// (rounded to the y storage type, as a one-term launch reads y back) with the
+// field rows of the input rings; returns A y and the centre row (rounded)
+template <typename TY, int VEC, bool ADVF, int NR>
+__device__ __forceinline__ void ring_stage_from_y(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r,
+                                                  const FieldView& F, const double* ylds, int yr0, double (&Ax)[VEC],
+                                                  double (&uc)[VEC]) {
+  RowN<VEC> u[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(ylds, (unsigned)(r - 1 + t - yr0) % kS3Y, u[t]);
+  ring_stencil<VEC, ADVF>(R, g, r, F, u[0], u[1], u[2], Ax);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) uc[v] = u[1].c[v];
+}
+
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
+__device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<TY>& io, double* lds, int i0, int rb0,
+                                            int rb1, int stopflag, double (&acc)[6]) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int W = kWave * VEC;
+  Stage1Ep<VEC, kS3Y> e1, e2;
+  e1.stopflag = stopflag;
+  if (!e1.go()) {
+    // prologue and band steps: four barriers each
+    for (int rb = rb0 - 1; rb < rb1; ++rb) {
+      __syncthreads();
+      __syncthreads();
+      __syncthreads();
+      __syncthreads();
+    }
+    return;
+  }
+  const Strip g = strip_at<VEC>(F, i0);
+  const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
+  const int J0 = rb0 * kWavesY2;
+  e1.lds = lds;
+  e1.r0 = J0 - 2;
+  e1.ny = F.ny;
+  e1.per = F.bc == BC_PERIODIC;
+  e1.shift = io.shift;
+  e1.invg = io.invg;
+  e2 = e1;
+  e2.lds = lds + kS3Y * W;
+  e2.r0 = J0 - 1;
+  e2.shift = io.shift2;
+  Rings<VEC, ADVF, kS3Ring> R;
+  R.base = lds + 2 * kS3Y * W;
+  R.r0 = J0 - 3;
+  R.edges = F.bc != BC_PERIODIC && (i0 <= 0 || i0 + kWave * VEC >= F.nx);
+  const TY* __restrict__ yin = io.yin;
+  const int ocol = g.col0 * (int)sizeof(TY), ocolp = g.col0 * 8;
+  // outputs that are not stored: the lanes' offsets drop the stores (and the
+  // row's base comes from another array, so no address is formed from null)
+  const bool sy = io.yout != nullptr, s1 = io.p1 != nullptr, s2 = io.p2 != nullptr, sp = io.p != nullptr;
+  TY* const yo = sy ? io.yout : const_cast<TY*>(yin);
+  double* const p1o = s1 ? io.p1 : const_cast<double*>(io.pin);
+  double* const p2o = s2 ? io.p2 : const_cast<double*>(io.pin);
+  double* const po = sp ? io.p : const_cast<double*>(io.pin);
+  // prologue: input rows J0-3 .. J0+4 into the rings, y_{k+1} on J0-2 ..
+  // J0+1, y_{k+2} on J0-1 and J0, then input rows J0+5, J0+6 into the slots
+  // of J0-3, J0-2 (waves 2 and 3 load rows they do not put)
+  RowSet<TF, TY, VEC, ADVF> cur, nxt, ex;
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 - 3 + wave, cur);
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 1 + wave, nxt);
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 5 + wave, ex);
+  rowset_put<TF, TY, VEC, ADVF>(R, g, J0 - 3 + wave, F, cur);
+  rowset_put<TF, TY, VEC, ADVF>(R, g, J0 + 1 + wave, F, nxt);
+  __syncthreads();
+  ring_stage1<VEC, ADVF>(R, g, J0 - 2 + wave, F, e1);
+  __syncthreads();
+  if (wave < 2) {
+    double Ax[VEC], uc[VEC];
+    ring_stage_from_y<TY, VEC, ADVF>(R, g, J0 - 1 + wave, F, e1.lds, e1.r0, Ax, uc);
+    typename Stage1Ep<VEC, kS3Y>::Extra none;
+    e2.finish(J0 - 1 + wave, g, Ax, uc, none);
+  }
+  __syncthreads();
+  if (wave < 2) rowset_put<TF, TY, VEC, ADVF>(R, g, J0 + 5 + wave, F, ex);
+  __syncthreads();
+  // one band step (output rows j0 .. j0+3); LAST: the run's last step
+  auto band = [&]<bool LAST>(int rb) {
+    const int j0 = rb * kWavesY2;
+    const int j = j0 + wave;
+    const bool keep = own && j < F.ny;
+    double pk[VEC];
+    ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
+    if constexpr (!LAST) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 7 + wave, nxt);
+    // stage 1: y_{k+1} on row j0+2+wave
+    ring_stage1<VEC, ADVF>(R, g, j0 + 2 + wave, F, e1);
+    __syncthreads();
+    // stage 2: y_{k+2} on row j0+1+wave
+    {
+      double Ax[VEC], uc[VEC];
+      ring_stage_from_y<TY, VEC, ADVF>(R, g, j0 + 1 + wave, F, e1.lds, e1.r0, Ax, uc);
+      typename Stage1Ep<VEC, kS3Y>::Extra none;
+      e2.finish(j0 + 1 + wave, g, Ax, uc, none);
+    }
+    __syncthreads();
+    // stage 3: y_{k+3} on row j (rows past the grid are computed and dropped)
+    double Ax[VEC], uc[VEC];
+    ring_stage_from_y<TY, VEC, ADVF>(R, g, j, F, e2.lds, e2.r0, Ax, uc);
+    double y1[VEC], y2[VEC];
+    lds_get<VEC>(e1.lds + (long)((unsigned)(j - e1.r0) % kS3Y) * W + lane * VEC, y1);
+    lds_get<VEC>(e2.lds + (long)((unsigned)(j - e2.r0) % kS3Y) * W + lane * VEC, y2);
+    const long ro = (long)min(j, F.ny - 1) * F.nx;
+    double y3[VEC], pa[VEC], pb[VEC], pc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const double t1 = io.dk1 * y1[v];
+      pa[v] = pk[v] + t1;
+      const double t2 = io.dk2 * y2[v];
+      pb[v] = pa[v] + t2;
+      y3[v] = (Ax[v] - io.shift3 * uc[v]) * io.invg;
+      const double t3 = io.dk3 * y3[v];
+      pc[v] = pb[v] + t3;
+      acc[0] += keep ? t1 * t1 : 0.0;
+      acc[1] += keep ? pa[v] * pa[v] : 0.0;
+      acc[2] += keep ? t2 * t2 : 0.0;
+      acc[3] += keep ? pb[v] * pb[v] : 0.0;
+      acc[4] += keep ? t3 * t3 : 0.0;
+      acc[5] += keep ? pc[v] * pc[v] : 0.0;
+    }
+    row_store<NT, TY, VEC>(yo + ro, F.nx, keep && sy ? ocol : kDropOffset, y3);
+    row_store<NT, double, VEC>(p1o + ro, F.nx, keep && s1 ? ocolp : kDropOffset, pa);
+    row_store<NT, double, VEC>(p2o + ro, F.nx, keep && s2 ? ocolp : kDropOffset, pb);
+    row_store<NT, double, VEC>(po + ro, F.nx, keep && sp ? ocolp : kDropOffset, pc);
+    __syncthreads();
+    // the next step's rows replace rows j0-1 .. j0+2, read for the last time by stage 3
+    if constexpr (!LAST) rowset_put<TF, TY, VEC, ADVF>(R, g, j0 + 7 + wave, F, nxt);
+    __syncthreads();
+  };
+#pragma unroll 1
+  for (int rb = rb0; rb < rb1 - 1; ++rb) band.template operator()<false>(rb);
+  if (rb1 > rb0) band.template operator()<true>(rb1 - 1);
+}
+
+// dynamic LDS of a three-term staged block
+template <int VEC, bool ADVF>
+constexpr size_t staged3_lds_bytes() {
+  return ((size_t)2 * kS3Y * kWave * VEC +
+          (size_t)Rings<VEC, ADVF, kS3Ring>::kArrays * kS3Ring * Rings<VEC, ADVF, kS3Ring>::kRow) *
+         sizeof(double);
 }
 
 // dynamic LDS of a staged block

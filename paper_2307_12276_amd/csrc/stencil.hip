@@ -917,6 +917,54 @@ __global__ __launch_bounds__(kTileBlock2) void leja2s_kernel(FieldView F, Tiling
   }
 }
 
+// Three Newton terms per launch (k >= 1) with the input rows staged in LDS
+// (staged3_run in staged.h), on the two-term tiling with two columns per
+// lane: the strips, bands and runs of leja2s_kernel.
+template <typename TF, typename TY, bool ADVF, bool NT>
+__global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling T, LejaArgs A) {
+  extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
+  constexpr int VEC = 2;
+  const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
+  if (L == 0) {
+    if (!A.replay) leja_decide(A);
+    return;
+  }
+  const int b = L - 1;
+  const int cb = b % T.ncb;
+  const int rb0 = (b / T.ncb) * T.bands;
+  const int rb1 = min(rb0 + T.bands, T.nrb);
+  Staged3IO<TY> io;
+  io.yin = reinterpret_cast<const TY*>(A.yin);
+  io.yout = reinterpret_cast<TY*>(A.yout);
+  io.pin = A.pin;
+  io.p1 = A.pmid;
+  io.p2 = A.pmid2;
+  io.p = A.p;
+  io.shift = A.shift;
+  io.shift2 = A.shift2;
+  io.shift3 = A.shift3;
+  io.invg = A.invg;
+  io.dk1 = A.dk1;
+  io.dk2 = A.dk2;
+  io.dk3 = A.dk3;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  staged3_run<TF, TY, VEC, ADVF, NT>(
+      F, io, lds, cb * (kWave - 2) * VEC - VEC, rb0, rb1,
+      A.replay ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), acc);
+  // block partials: term t (0, 1, 2) at rows 3t (||d y||^2), 3t + 1 (||p||^2), 3t + 2 (0)
+  block_allreduce<6, 6>(acc);
+  if (threadIdx.x == 0 && !A.replay) {
+    double* part = A.partials + (long)A.slot * A.slot_stride;
+    const int nb = T.nblocks;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      part[(3L * t) * nb + b] = acc[2 * t];
+      part[(3L * t + 1) * nb + b] = acc[2 * t + 1];
+      part[(3L * t + 2) * nb + b] = 0.0;
+    }
+  }
+}
+
 // Power iteration term: w_{k+1} = A(w_k) / lambda_k, lambda_k = ||w_k|| from
 // the partials of the launch that wrote w_k.
 template <int VEC>
@@ -1077,7 +1125,7 @@ Tiling make_tiling(int nx, int ny, int rows_hint, int vec_hint) {
   return t;
 }
 
-Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint) {
+Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint, int max_blocks) {
   Tiling t;
   const bool two = nx % 2 == 0 && nx >= 2 * kWave;
   t.vec = (vec_hint == 1 || !two) ? 1 : 2;
@@ -1086,7 +1134,7 @@ Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint) {
   (void)rows_hint;  // one output row per wave
   t.rows = 1;
   t.nrb = (ny + kWavesY2 - 1) / kWavesY2;
-  const long per_strip = kMaxGrid2 / t.ncb > 0 ? kMaxGrid2 / t.ncb : 1;
+  const long per_strip = max_blocks / t.ncb > 0 ? max_blocks / t.ncb : 1;
   t.bands = (int)((t.nrb + per_strip - 1) / per_strip);
   t.nblocks = t.ncb * ((t.nrb + t.bands - 1) / t.bands);
   return t;
@@ -1254,6 +1302,53 @@ hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs
       else leja4_launch<double, double, VEC, ADVF>(f, t, a, st);
     }
   });
+  return hipGetLastError();
+}
+
+template <typename TF, typename TY, bool ADVF, bool NT>
+static void leja3s_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock2);
+  const size_t lds = staged3_lds_bytes<2, ADVF>();
+  if (a.ev_start)
+    hipExtLaunchKernelGGL((leja3s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
+  else
+    hipLaunchKernelGGL((leja3s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, f, t, a);
+}
+
+template <typename TF, typename TY, bool NT>
+static void leja3s_dispatch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if (f.ax) leja3s_launch<TF, TY, true, NT>(f, t, a, st);
+  else leja3s_launch<TF, TY, false, NT>(f, t, a, st);
+}
+
+hipError_t launch_leja3_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if (a.first || a.k < 1 || a.nterms != 3 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || t.vec != 2)
+    return hipErrorInvalidValue;
+  if (!a.decide_only) {
+    // p_k is read while the stored p outputs (at least one) are written: all distinct
+    const double* o[4] = {a.pin, a.pmid, a.pmid2, a.p};
+    if (a.pin == nullptr || (!a.pmid && !a.pmid2 && !a.p)) return hipErrorInvalidValue;
+    for (int i = 1; i < 4; ++i)
+      for (int j = 0; j < i; ++j)
+        if (o[i] != nullptr && o[i] == o[j]) return hipErrorInvalidValue;
+  }
+  if (a.stream) {
+    if (f.f32) {
+      if (a.ystore_f32) leja3s_dispatch<float, float, true>(f, t, a, st);
+      else leja3s_dispatch<float, double, true>(f, t, a, st);
+    } else {
+      if (a.ystore_f32) leja3s_dispatch<double, float, true>(f, t, a, st);
+      else leja3s_dispatch<double, double, true>(f, t, a, st);
+    }
+  } else {
+    if (f.f32) {
+      if (a.ystore_f32) leja3s_dispatch<float, float, false>(f, t, a, st);
+      else leja3s_dispatch<float, double, false>(f, t, a, st);
+    } else {
+      if (a.ystore_f32) leja3s_dispatch<double, float, false>(f, t, a, st);
+      else leja3s_dispatch<double, double, false>(f, t, a, st);
+    }
+  }
   return hipGetLastError();
 }
 

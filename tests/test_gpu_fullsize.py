@@ -185,30 +185,31 @@ def test_learned_interval_4096_fp32_storage():
     assert max(dl, dp, d_ref) < 1e-10
 
 
-def test_two_term_kernels_at_4096_match_one_term_launches():
+def test_multi_term_kernels_at_4096_match_one_term_launches():
     """The 4096^2 stream-function field of the bench's roofline legs (FP64,
-    a working set beyond the caches, so the library picks the LDS-staged
-    two-term kernel with non-temporal hints): one phi_1 sweep with one term
-    per launch, with the staged kernel and with the register-frame kernel.
-    Same degree, and the same polynomial up to the grouping of the norm
-    partial sums (the one-term path equals the oracle at smaller sizes)."""
+    a working set beyond the caches, so the launches carry non-temporal
+    hints): one phi_1 sweep with one term per launch, with the staged and
+    the register-frame two-term kernels and with the staged three-term
+    kernel.  Same degree, and the same polynomial up to the grouping of the
+    norm partial sums (the one-term path equals the oracle at smaller
+    sizes)."""
     w = W.roofline_shape(n=4096)
     op = make_op(w, A.STORAGE_FP64)
     op.spectral_bound(A.BOUND_GERSHGORIN)
     v = to_dev(w.u0)
     outs, degs = {}, {}
-    for mode in (0, 1, 3):
+    for mode in (0, 2, 3, 5):
         op.set_term_fusion(mode)
         out = torch.empty_like(v)
         st = op.leja_phi(1, w.dt, v, out, w.tol)
         outs[mode] = out
         degs[mode] = st["max_degree"]
-    r1 = float((outs[1] - outs[0]).norm() / outs[0].norm())
-    r3 = float((outs[3] - outs[0]).norm() / outs[0].norm())
-    print("4096^2 phi_1 sweep: degrees %s, staged vs one-term %.2e, frames vs one-term %.2e, staged vs frames %s"
-          % (degs, r1, r3, "bitwise" if torch.equal(outs[1], outs[3]) else "differ"))
-    assert degs[0] == degs[1] == degs[3]
-    assert r1 < 1e-13 and r3 < 1e-13
+    r = {m: float((outs[m] - outs[0]).norm() / outs[0].norm()) for m in (2, 3, 5)}
+    print("4096^2 phi_1 sweep: degrees %s, against one term per launch: two-term staged %.2e, frames %.2e, "
+          "three-term staged %.2e; two-term staged vs frames %s"
+          % (degs, r[2], r[3], r[5], "bitwise" if torch.equal(outs[2], outs[3]) else "differ"))
+    assert degs[0] == degs[2] == degs[3] == degs[5]
+    assert max(r.values()) < 1e-13
     del op
     torch.cuda.empty_cache()
 
@@ -225,15 +226,16 @@ def sweep_and_step_1024(storage, mode):
 @pytest.mark.timeout(1800)
 @pytest.mark.parametrize("storage", [A.STORAGE_FP64, A.STORAGE_FP32_FIELDS])
 def test_sweeps_from_2pow20_points_match_oracle(oracle, storage):
-    """2^20 points (1024^2): the default mode runs two Newton terms per
-    launch with LDS-staged rows (leja2s_kernel; mode 2 forces it, mode 3 the
-    register-frame kernel): the phi_1 sweep and one two-stage step equal the
-    oracle (on the FP32-rounded fields for storage 1) to 1e-10 with the same
-    matvec count, in every two-term mode."""
+    """2^20 points (1024^2): the default mode runs three Newton terms per
+    launch with LDS-staged rows (leja3s_kernel; mode 5 forces it), mode 2
+    two terms with LDS-staged rows (leja2s_kernel), mode 3 two with register
+    frames: the phi_1 sweep and one two-stage step equal the oracle (on the
+    FP32-rounded fields for storage 1) to 1e-10 with the same matvec count,
+    in every mode."""
     f32 = storage == A.STORAGE_FP32_FIELDS
     po, alpha, mvo, Ko = oracle("sweep1024_f32" if f32 else "sweep1024")
     uo, alpha_q, mvq = oracle("quad1024_f32" if f32 else "quad1024")
-    for mode in (1, 2, 3):
+    for mode in (1, 2, 3, 5):
         w, op = sweep_and_step_1024(storage, mode)
         op.set_bound(alpha)
         v = to_dev(w.u0 + 1e-3 * W.random_vector(w.u0.shape, 21))
@@ -241,13 +243,15 @@ def test_sweeps_from_2pow20_points_match_oracle(oracle, storage):
         op.profile(True)
         st = op.leja_phi(1, w.dt, v, out, w.tol)
         _, n2, _, _ = op.profile_read_kind(A.LAUNCH_TWO)
+        _, n3, _, _ = op.profile_read_kind(A.LAUNCH_THREE)
         _, n4, _, _ = op.profile_read_kind(A.LAUNCH_FOUR)
         op.profile(False)
         e = rel(to_np(out), po)
-        print("1024^2 storage %d mode %d: phi_1 %d matvecs (oracle %d), two-term launches %d, rel diff %.2e"
-              % (storage, mode, st["matvecs"], mvo, n2, e))
+        print("1024^2 storage %d mode %d: phi_1 %d matvecs (oracle %d), two-/three-term launches %d/%d, "
+              "rel diff %.2e" % (storage, mode, st["matvecs"], mvo, n2, n3, e))
         assert st["matvecs"] == mvo and st["substeps"] == Ko
-        assert n2 > 0 and n4 == 0
+        assert (n3 > 0) if mode in (1, 5) else (n2 > 0 and n3 == 0)
+        assert n4 == 0
         assert e < 1e-10
         S1, S2 = (to_dev(a) for a in w.stage_sources(0))
         u = to_dev(w.u0)
@@ -265,7 +269,7 @@ def test_sweeps_from_2pow20_points_match_oracle(oracle, storage):
 def test_roofline_4096_step_matches_oracle(oracle):
     """The benchmark's headline workload (4096^2 stream-function field,
     FP64, exponential midpoint, tol 1e-10) in the launch configuration the
-    benchmark times (default mode: LDS-staged two-term launches with
+    benchmark times (default mode: LDS-staged three-term launches with
     non-temporal hints): one step equals the oracle to 1e-10 with the same
     matvec count."""
     w = W.roofline_shape(n=4096, steps=1)
@@ -275,13 +279,13 @@ def test_roofline_4096_step_matches_oracle(oracle):
     u = to_dev(w.u0)
     op.profile(True)
     st = op.midpoint_step(u, to_dev(w.stage_sources(0)[0]), w.dt, w.tol)
-    _, n2, _, t2 = op.profile_read_kind(A.LAUNCH_TWO)
+    _, n3, _, t3 = op.profile_read_kind(A.LAUNCH_THREE)
     op.profile(False)
     e = rel(to_np(u), uo)
-    print("4096^2 FP64 midpoint step: %d matvecs (oracle %d), %d two-term launches, rel diff %.2e"
-          % (st["matvecs"], mvo[0], n2, e))
+    print("4096^2 FP64 midpoint step: %d matvecs (oracle %d), %d three-term launches, rel diff %.2e"
+          % (st["matvecs"], mvo[0], n3, e))
     assert st["matvecs"] == mvo[0]
-    assert n2 > 0 and 2 * n2 == t2
+    assert n3 > 0 and 3 * n3 == t3
     assert e < 1e-10
     del op
     torch.cuda.empty_cache()
