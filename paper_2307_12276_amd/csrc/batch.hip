@@ -74,8 +74,8 @@ struct BinCtl {
   int status;  // 0 running, 1 converged, 2 non-finite, 3 degree cap
   int degree;
   int upd;     // 1: u already advanced by an earlier update launch of this step
-  int inner;   // the decided term is the first of a two-term launch (its p is not stored)
-  int launch;  // launch index of the decided term
+  int inner;   // the stopping term is the first of a two-term launch (its p is not stored)
+  int launch;  // launch index of the stopping term (kNoLaunch until the bin stops)
   double tn2, pn2;
   double hist[kStopHist];  // term norms of the stopping window (as in Ctl)
 };
@@ -93,6 +93,7 @@ struct BatchArgs {
   int k;                 // terms before this launch
   int kprev, nprev;      // the previous launch: terms before it, its terms (1 or 2)
   int two;               // p buffers in pairs per launch (two-term sweeps)
+  int advance;           // tiles of a stopped bin advance u in its due launch (0: timing runs leave u alone)
 };
 
 // Launch geometry of the tile kernels: kBWaves independent waves per block,
@@ -112,6 +113,69 @@ inline unsigned blocks_for(long units) { return (unsigned)((units + kBWaves - 1)
 // one-term sweeps alternate by degree
 __device__ __forceinline__ int pbuf_index(int m, int two) {
   return two ? 2 * ((m >> 1) & 1) + (m & 1) : (m & 1);
+}
+
+// BinCtl::launch before any decision: far from every launch index, so that a
+// tile that reads the stop flag set beside it in its own launch, together
+// with an older value of `launch`, never takes the update as due
+constexpr int kNoLaunch = -1000000;
+
+// The update u_b += dt p_m of a bin that stopped at term m with status 1,
+// over rows j0 .. j1-1 and columns c0 .. c1-1 of the bin (a tile's own
+// points; one lane per VEC columns).  A bin that stopped at the first term
+// m of a two-term launch is advanced by p_m = p_{m+1} - d_{m+1} y_{m+1}: that
+// launch stored p and y of term m+1 only, and no later launch of the sweep
+// wrote those buffers of the bin (the launch beside the decision writes the
+// other y buffer and the other p pair, and every later one skips the bin).
+template <int VEC>
+__device__ __forceinline__ void bin_update_rect(const BatchArgs& A, const BinDesc& B, const BinCtl& c,
+                                                double* __restrict__ ub, int j0, int j1, int c0, int c1) {
+  const int m = c.degree;
+  const bool inner = c.inner != 0;
+  const double* __restrict__ pb = B.pb[pbuf_index(inner ? m + 1 : m, A.two)];
+  const double* __restrict__ yb = reinterpret_cast<const double*>(((c.launch + 1) & 1) ? B.y1 : B.y0);
+  const double dm = inner ? B.d[min(m + 1, B.max_degree)] : 0.0;
+  const double dt = B.dt;
+  const int nx = B.f.nx;
+  const int col0 = c0 + (int)(threadIdx.x & 63) * VEC;
+  if (col0 >= c1) return;
+  // rows in groups of four, every load of a group issued before its stores
+  // (u, p and y are distinct arrays)
+  constexpr int G = 4;
+  for (int j = j0; j < j1; j += G) {
+    double uu[G][VEC], pp[G][VEC], yy[G][VEC];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const long ro = (long)min(j + q, j1 - 1) * nx;
+      ldr<double, VEC>(ub + ro, col0, uu[q]);
+      ldr<double, VEC>(pb + ro, col0, pp[q]);
+      if (inner) {
+        ldr<double, VEC>(yb + ro, col0, yy[q]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) yy[q][v] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      if (j + q < j1) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double pv = inner ? pp[q][v] - dm * yy[q][v] : pp[q][v];
+          uu[q][v] = uu[q][v] + dt * pv;
+        }
+        str<double, VEC>(ub + (long)(j + q) * nx, col0, uu[q]);
+      }
+    }
+  }
+}
+
+// A tile of a stopped bin in term launch A.L: the bin's update is due in the
+// launch after the one whose decision stopped it (launch c.launch + 2), done
+// there by the bin's tiles; the tail's update launch advances the bins whose
+// due launch did not run.
+__device__ __forceinline__ bool update_due(const BatchArgs& A, const BinCtl& c) {
+  return A.advance && c.status == 1 && !c.upd && c.degree > 0 && A.L == c.launch + 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -185,8 +249,15 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
     for (int i = 0; i < kStopHist; ++i) c->hist[i] = hist[i];
     c->degree = degree;
     c->status = status;
-    c->inner = two && degree == A.kprev + 1;
-    c->launch = A.L - 1;
+    // recorded only by the decision that stops the bin: a tile that reads
+    // the stop flag set beside it in this launch, with `launch` as it was
+    // before, then sees kNoLaunch (never a due launch), not the value of an
+    // earlier, non-stopping decision, which would make the current launch
+    // look due and advance u twice
+    if (stop) {
+      c->inner = two && degree == A.kprev + 1;
+      c->launch = A.L - 1;
+    }
     __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   return stop != 0;
@@ -241,7 +312,17 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_leja_kernel(BatchArgs A, i
   const int b = __builtin_amdgcn_readfirstlane(A.tile_bin[gt]);
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
-  if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    const BinCtl& c = A.ctl[b];
+    if (!FIRST && update_due(A, c)) {
+      const int t = gt - B.tile_base;
+      const int rb = t / B.ncb, cb = t - rb * B.ncb;
+      const int j0 = rb * B.rows, c0 = cb * kWave * VEC;
+      bin_update_rect<VEC>(A, B, c, const_cast<double*>(B.u), j0, min(j0 + B.rows, B.f.ny), c0,
+                           min(c0 + kWave * VEC, B.f.nx));
+    }
+    return;
+  }
   if (A.k >= B.max_degree) return;
   batch_term<TF, VEC, ADVF, FIRST>(A, B, gt - B.tile_base);
 }
@@ -947,7 +1028,19 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_leja2_kernel(BatchArgs A, 
   const int b = __builtin_amdgcn_readfirstlane(A.tile_bin2[gt]);
   const BinDesc& B = A.bins[b];
   if (!B.active) return;
-  if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    const BinCtl& c = A.ctl[b];
+    if (update_due(A, c)) {
+      // the two-term tile's own points: rows j0 .. j0+rows-1, the strip's
+      // 62*VEC output columns
+      const int t = gt - B.tile_base2;
+      const int rb = t / B.ncb2, cb = t - rb * B.ncb2;
+      const int j0 = rb * B.rows, c0 = cb * (kWave - 2) * VEC;
+      bin_update_rect<VEC>(A, B, c, const_cast<double*>(B.u), j0, min(j0 + B.rows, B.f.ny), c0,
+                           min(c0 + (kWave - 2) * VEC, B.f.nx));
+    }
+    return;
+  }
   if (A.k >= B.max_degree) return;
   batch_term2<TF, VEC, ADVF>(A, B, gt - B.tile_base2);
 }
@@ -966,6 +1059,7 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BinCtl* ctl, int nbins
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < nbins) {
     BinCtl c{};
+    c.launch = kNoLaunch;
     ctl[b] = c;
   }
 }
@@ -975,6 +1069,8 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(BinCtl* ctl, int nbins
 // p_m = p_{m+1} - d_{m+1} y_{m+1}: that launch stored p and y of term m+1
 // only, and no later launch of the sweep wrote those buffers of the bin (the
 // launch beside the decision writes the other y buffer and the other p pair).
+// A.L = the number of term launches the sweep has enqueued; a bin whose due
+// launch (c.launch + 2) is among them was advanced there.
 template <int VEC>
 __global__ __launch_bounds__(64 * kBWaves) void batch_update_kernel(BatchArgs A, double* const* u) {
   const int gt = wave_unit();
@@ -983,32 +1079,12 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_update_kernel(BatchArgs A,
   const BinDesc& B = A.bins[b];
   const BinCtl& c = A.ctl[b];
   if (!B.active || c.status != 1 || c.upd || c.degree == 0) return;  // degree 0: p = 0
-  const int m = c.degree;
-  const bool inner = c.inner != 0;
-  const double* pb = B.pb[pbuf_index(inner ? m + 1 : m, A.two)];
-  const double* yb = reinterpret_cast<const double*>(((c.launch + 1) & 1) ? B.y1 : B.y0);
-  const double dm = inner ? B.d[min(m + 1, B.max_degree)] : 0.0;
+  if (c.launch + 2 < A.L) return;                                      // advanced in its due launch
   const int t = gt - B.tile_base;
   const int rb = t / B.ncb, cb = t - rb * B.ncb;
   const int j0 = rb * B.rows, j1 = min(j0 + B.rows, B.f.ny);
-  const int col0 = (cb * kWave + (threadIdx.x & 63)) * VEC;
-  if (col0 >= B.f.nx) return;
-  double* ub = u[b];
-  for (int j = j0; j < j1; ++j) {
-    const long ro = (long)j * B.f.nx;
-    double uu[VEC], pp[VEC];
-    ldr<double, VEC>(ub + ro, col0, uu);
-    ldr<double, VEC>(pb + ro, col0, pp);
-    if (inner) {
-      double yy[VEC];
-      ldr<double, VEC>(yb + ro, col0, yy);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) pp[v] = pp[v] - dm * yy[v];
-    }
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) uu[v] = uu[v] + B.dt * pp[v];
-    str<double, VEC>(ub + ro, col0, uu);
-  }
+  const int c0 = cb * kWave * VEC;
+  bin_update_rect<VEC>(A, B, c, u[b], j0, j1, c0, min(c0 + kWave * VEC, B.f.nx));
 }
 
 // Before a step's sweep continues past the graph: bins that have converged
@@ -1210,9 +1286,12 @@ BatchArgs base_args(const adl_batch* B) {
 // first when with_stage), then the decision of the last launch.  The first
 // term is a launch of its own; later launches take two terms while the batch
 // fuses terms and the second stays within the degree cap.  `covered` returns
-// the number of terms enqueued (nterms, or one more).
-int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t st, int* covered = nullptr) {
+// the number of terms enqueued (nterms, or one more).  advance = false (the
+// autotuner's timing runs): no tile advances u.
+int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t st, int* covered = nullptr,
+                  bool advance = true) {
   BatchArgs a = base_args(B);
+  a.advance = advance ? 1 : 0;
   if (with_stage) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((B->nbins + 255) / 256), dim3(256), 0, st, B->d_ctl, B->nbins);
     dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
@@ -1261,6 +1340,7 @@ int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t
 // advanced, then the outcomes published to the host mirror.
 int enqueue_tail(adl_batch* B, hipStream_t st) {
   BatchArgs a = base_args(B);
+  a.L = B->sL;
   if (B->vec == 2)
     hipLaunchKernelGGL((batch_update_kernel<2>), dim3(blocks_for(B->total_tiles)), dim3(64 * kBWaves), 0, st, a,
                        B->d_uptrs);
@@ -1569,7 +1649,7 @@ int adl_batch_autotune(adl_batch* B, double* const* u, const double* const* S_ha
     float ms_min = INFINITY;
     for (int rep = 0; rep < 3; ++rep) {
       BCHK(hipEventRecord(e0, st));
-      rc = enqueue_sweep(B, 0, nterms, true, st);
+      rc = enqueue_sweep(B, 0, nterms, true, st, nullptr, false);
       if (rc != ADL_OK) return rc;
       BCHK(hipEventRecord(e1, st));
       BCHK(hipEventSynchronize(e1));

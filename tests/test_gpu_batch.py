@@ -212,3 +212,34 @@ def test_batch_full_config_sampled_bins():
         assert stats[i]["matvecs"] == st["matvecs"]
         assert rel(to_np(us[i]), ref) < 1e-10, i
     assert all(s["status"] == 0 for s in stats)
+
+
+def test_batch_all_bins_equal_single_op_steps():
+    """The chosen form on the 256-bin workload (FP32 fields, learned
+    intervals, two terms per launch, eager launches): three batched steps
+    equal, bin by bin, the same steps taken by each bin's own operator (same
+    fields, same intervals; the single-op path equals the oracle).  Every bin
+    is advanced exactly once per step, whichever launch its update falls in
+    (a bin is advanced by its tiles in the launch after the one whose
+    decision stopped it, or by the step's last launch)."""
+    from paper_2307_12276_amd import learned
+    bins = W.c4_bins()
+    dt = bins[0].dt
+    tol = 1e-9
+    Ss = [to_dev(w.S(0)) for w in bins]
+    ops = [A.Op(to_dev(w.Dxx), to_dev(w.Dxy), to_dev(w.Dyy), w.hx, w.hy, w.bc, A.STORAGE_FP32_FIELDS,
+                ax_c=w.ax_c, ay_c=w.ay_c) for w in bins]
+    b = A.Batch(ops)
+    b.learned_bound(dt, torch.from_numpy(learned.load()).cuda(),
+                    torch.empty(72 * len(ops), dtype=torch.float32, device="cuda"))
+    ub = [to_dev(w.u0) for w in bins]
+    us = [to_dev(w.u0) for w in bins]
+    b.bind(ub, Ss)
+    for step in range(3):
+        st = b.midpoint_step(None, None, dt, tol, use_graph=False).array
+        for op, u, S in zip(ops, us, Ss):
+            op.midpoint_step(u, S, dt, tol)
+        d = [float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y)) for x, y in zip(ub, us)]
+        worst = int(np.argmax(d))
+        print("step %d: max rel diff %.2e (bin %d, %d matvecs)" % (step, d[worst], worst, int(st["matvecs"][worst])))
+        assert max(d) < 1e-12, (step, worst, d[worst])
