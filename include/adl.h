@@ -152,19 +152,22 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
 
 /* Newton terms per launch of a sweep (Sec. 2 recurrence): mode = 1 (the
  * default) computes four terms per launch on grids below 2^20 points
- * (mode 4's form, y_{k+1} .. y_{k+3} kept on chip) and, on larger grids,
- * terms k+1 and k+2 in one launch, keeping y_{k+1} on chip (read y_k, the
- * fields and p_k once, write y_{k+2} and p_{k+2}) with the input rows
- * staged in LDS (without non-temporal hints, also below 2^20 points: one-row
- * frames in registers); mode = 2 and mode = 3
- * force the LDS-staged and the register-frame form; mode = 4 computes four
+ * (mode 4's form, y_{k+1} .. y_{k+3} kept on chip) and, from 2^20 points
+ * on, three (mode 5's form: read y_k, the fields and p_k once, write y_{k+3}
+ * and p_{k+3}); where those forms do not apply it computes terms k+1 and
+ * k+2 in one launch, keeping y_{k+1} on chip, with the input rows staged in
+ * LDS from 2^20 points on and one-row frames in registers below;
+ * mode = 2 and mode = 3
+ * force the two-term LDS-staged and register-frame forms; mode = 4 computes four
  * terms per launch (y_{k+1} .. y_{k+3} kept in LDS, three-row frames), on
  * grids swept without non-temporal hints and, on a periodic grid, ny >= 4
  * other than 5 and 9 (a block's rows wrap once; ADL_EINVAL otherwise; mode 1
  * then runs two terms per launch); mode = 5 computes three terms per launch
  * with the input rows staged in LDS (y_{k+1}, y_{k+2} kept in LDS), on grids
  * whose two-term tiling has two columns per lane (ADL_EINVAL otherwise);
- * mode = 0 launches one kernel per term.
+ * mode = 6 computes four terms per launch with the input rows staged in LDS
+ * (y_{k+1} .. y_{k+3} kept in LDS; nx even and at least 128, ADL_EINVAL
+ * otherwise); mode = 0 launches one kernel per term.
  * A fused launch stores y and p of its last term only; when the sweep stops
  * at an earlier term of a launch, the launch is run again on its inputs to
  * store p of that term (the same arithmetic, so the same values).  Results

@@ -272,8 +272,9 @@ class Op:
 
     def set_term_fusion(self, mode=True):
         """Newton terms per launch: True/1 the library's choice (four below
-        2^20 points, else two), 2 two with LDS-staged rows, 3 two with
-        register frames, 4 four, 5 three with LDS-staged rows, False/0 one."""
+        2^20 points, else three), 2 two with LDS-staged rows, 3 two with
+        register frames, 4 four, 5 three with LDS-staged rows, 6 four with
+        LDS-staged rows, False/0 one."""
         m = int(mode) if not isinstance(mode, bool) else int(mode)
         _check(lib().adl_op_set_term_fusion(self.handle, m))
 

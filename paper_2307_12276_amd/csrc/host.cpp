@@ -441,6 +441,11 @@ static bool four_terms_ok(const adl_op* op) {
 static bool three_terms_ok(const adl_op* op, int vec) {
   return vec == 2 && op->t3.vec == 2 && 9L * op->t3.nblocks <= op->slot_stride;
 }
+// the same for four terms per launch with LDS-staged rows (stage 4 valid on
+// lanes 2 .. 61 of the tiling's strips with two columns per lane)
+static bool four_staged_ok(const adl_op* op, int vec) {
+  return vec == 2 && op->t4s.vec == 2 && 12L * op->t4s.nblocks <= op->slot_stride;
+}
 
 // p_out = g(A) v (top block of the augmented form when w2 != null; the
 // augmented column enters with coefficient s_k * w2scale).
@@ -471,14 +476,17 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   const Tiling& T2 = T.vec == op->t2.vec ? op->t2 : op->t21;
   const Tiling& T4 = T.vec == op->t4.vec ? op->t4 : op->t41;
   const bool fuse = op->fuse_terms != 0;
-  const bool four = (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n < kFourTermMaxPoints)) &&
+  // four terms per launch with LDS-staged rows (mode 6)
+  const bool fours = op->fuse_terms == 6 && four_staged_ok(op, T.vec);
+  const bool four = !fours && (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n < kFourTermMaxPoints)) &&
                     four_terms_ok(op);
   // three terms per launch (LDS-staged) from kStagedMinPoints up by default
   // (4096^2 FP64 headline steps: 140 steps/s with two terms per launch, 185
   // with three), or forced by mode 5
-  const bool three = !four && three_terms_ok(op, T.vec) &&
+  const bool three = !four && !fours && three_terms_ok(op, T.vec) &&
                      (op->fuse_terms == 5 || (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints));
   const Tiling& T3 = op->t3;
+  const Tiling& T4s = op->t4s;
   // first chunk: the last degree of this plan plus one (the degree moves by
   // about one from step to step; one launch too many costs its work, one too
   // few a second chunk and host round trip); the first sweep of a plan
@@ -505,6 +513,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     };
     const int lim = four ? std::min(target, maxdeg) : maxdeg;
     if (four && kcov + 4 <= lim && !aug(4)) return 4;
+    if (fours && kcov + 4 <= maxdeg && !aug(4)) return 4;
     if (three && kcov + 3 <= lim && !aug(3)) return 3;
     const bool two = fuse && kcov + 2 <= lim && !aug(2);
     return two ? 2 : 1;
@@ -556,7 +565,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   // where the staged kernel's prologue and extra barrier do not pay (measured
   // per launch, staged / frames: 512^2 1.14, 768^2 0.93-1.05, 1024^2
   // 0.87-0.92, 1536^2 0.78-0.86, 2048^2 0.84-0.89)
-  a.staged = op->fuse_terms == 2 || op->fuse_terms == 5 ||
+  a.staged = op->fuse_terms == 2 || op->fuse_terms == 5 || op->fuse_terms == 6 ||
              (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints);
   a.partials = op->partials;
   a.slot_stride = op->slot_stride;
@@ -608,13 +617,14 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.nterms_prev = prev_n;
       a.slot_prev = prev_slot;
       a.decide_only = 0;
-      if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
+      if (n == 4 && fours) HIPCHK(launch_leja4s_step(op->f, T4s, a, st));
+      else if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
       else if (n == 3) HIPCHK(launch_leja3_step(op->f, T3, a, st));
       else if (n == 2) HIPCHK(launch_leja2_step(op->f, T2, a, st));
       else HIPCHK(launch_leja_step(op->f, T, a, st));
       lk.push_back(kcov);
       ln.push_back(n);
-      prev_nb = n == 4 ? T4.nblocks : n == 3 ? T3.nblocks : n == 2 ? T2.nblocks : T.nblocks;
+      prev_nb = n == 4 ? (fours ? T4s.nblocks : T4.nblocks) : n == 3 ? T3.nblocks : n == 2 ? T2.nblocks : T.nblocks;
       prev_k = kcov;
       prev_n = n;
       prev_slot = L & 1;
@@ -712,7 +722,8 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         a.decide_only = 0;
         a.replay = 1;
         a.hctl = nullptr;
-        if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
+        if (n == 4 && fours) HIPCHK(launch_leja4s_step(op->f, T4s, a, st));
+        else if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
         else if (n == 3) HIPCHK(launch_leja3_step(op->f, T3, a, st));
         else HIPCHK(launch_leja2_step(op->f, T2, a, st));
         a.replay = 0;
@@ -931,6 +942,7 @@ int adl_op_create(int nx, int ny, double hx, double hy, int bc, int storage, con
   op->t2 = make_tiling2(nx, ny, 0);
   op->t21 = make_tiling2(nx, ny, 0, 1);
   op->t3 = make_tiling2(nx, ny, 0, 0, kMaxGrid3);
+  op->t4s = make_tiling2(nx, ny, 0, 0, kMaxGrid3, 2);
   op->t4 = make_tiling4(nx, ny);
   op->t41 = make_tiling4(nx, ny, 1);
   op->ybuf[0] = base + L.y0;
@@ -1047,6 +1059,7 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
   op->t2 = make_tiling2(op->nx, op->ny, rows, cols_per_lane);
   op->t21 = make_tiling2(op->nx, op->ny, rows, 1);
   op->t3 = make_tiling2(op->nx, op->ny, rows, cols_per_lane, kMaxGrid3);
+  op->t4s = make_tiling2(op->nx, op->ny, rows, cols_per_lane, kMaxGrid3, 2);
   op->t4 = make_tiling4(op->nx, op->ny, cols_per_lane);
   op->t41 = make_tiling4(op->nx, op->ny, 1);
   return ADL_OK;
@@ -1054,7 +1067,9 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane) {
 
 int adl_op_set_term_fusion(adl_op* op, int mode) {
   RETCHK(check_op(op));
-  if (mode < 0 || mode > 5) return fail(ADL_EINVAL, "term fusion mode must be 0, 1, 2, 3, 4 or 5");
+  if (mode < 0 || mode > 6) return fail(ADL_EINVAL, "term fusion mode must be 0 .. 6");
+  if (mode == 6 && !four_staged_ok(op, 2))
+    return fail(ADL_EINVAL, "four staged terms per launch need a grid whose tiling has two columns per lane");
   if (mode == 5 && !three_terms_ok(op, 2))
     return fail(ADL_EINVAL, "three terms per launch need a grid whose two-term tiling has two columns per lane");
   if (mode == 4 && !four_terms_ok(op))

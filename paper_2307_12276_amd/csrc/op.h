@@ -48,6 +48,7 @@ struct adl_op {
   Tiling t2{};  // two-term Newton-Leja kernel (two columns per lane when nx is even)
   Tiling t21{}; // two-term kernel, one column per lane
   Tiling t3{};  // three-term kernel: the two-term tiling with fewer, longer runs (kMaxGrid3)
+  Tiling t4s{}; // four-term staged kernel: strips of 60*VEC output columns, kMaxGrid3 blocks
   Tiling t4{};  // four-term Newton-Leja kernel (two columns per lane when nx is even)
   Tiling t41{}; // four-term kernel, one column per lane
   int fuse_terms = 1;  // 0 one Newton term per launch, 1 two (kernel by tiling), 2 two (LDS-staged), 3 two (frames),

@@ -107,24 +107,39 @@ __device__ __forceinline__ void lds_set(double* p, const double (&c)[VEC]) {
 // 1 .. 62 write their first value where lanes 0 and 63 write the halo
 // element): a load left unconsumed on some path makes the compiler wait for
 // it, and for everything issued before it, at the next reuse of its register.
+// acc + (kept ? s : 0) for km = 1 or 0 (kept or not): one FMA with the same
+// value as a select and an add (1 * s + acc rounds once, as s + acc does;
+// 0 * s adds +0), where the 64-bit select alone takes two instructions
+__device__ __forceinline__ double acc_kept(double acc, double km, double s) { return __builtin_fma(km, s, acc); }
+
 template <int VEC, int MODE, typename T>
 __device__ __forceinline__ void ring_put(double* row, const Strip& g, const RawRow<T, VEC>& x, bool edges, int nx) {
   using L = RingRow<VEC>;
   const int lane = threadIdx.x & (kWave - 1);
   // outside lanes load a valid column next to the edge (strip_at): the left
   // ones columns 0 .., the right ones .. nx-1
-  const bool ghostcols = edges && !g.inside;
-  const double edge = (double)(g.col0 < 0 ? x.c[0] : x.c[VEC - 1]);
-  double c[VEC];
+  double c[VEC], h;
+  if (edges || x.zero) {
+    // wave-uniform: a ghost row, or a strip with Dirichlet ghost columns (the
+    // empty asm keeps the compiler from turning the branch into selects)
+    __asm__ volatile("");
+    const bool ghostcols = edges && !g.inside;
+    const double edge = (double)(g.col0 < 0 ? x.c[0] : x.c[VEC - 1]);
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) {
-    const double val = ghostcols ? (MODE == MODE_EDGE ? edge : 0.0) : (double)x.c[v];
-    c[v] = x.zero ? 0.0 : val;
+    for (int v = 0; v < VEC; ++v) {
+      const double val = ghostcols ? (MODE == MODE_EDGE ? edge : 0.0) : (double)x.c[v];
+      c[v] = x.zero ? 0.0 : val;
+    }
+    const bool hghost = edges && (g.lane0 ? g.col0 - 1 < 0 : g.col0 + VEC >= nx);
+    const double hedge = g.lane0 ? c[0] : c[VEC - 1];
+    const double hv = hghost ? (MODE == MODE_EDGE ? hedge : 0.0) : (double)x.h;
+    h = x.zero ? 0.0 : hv;
+  } else {
+    // the row as loaded (both paths consume every loaded register)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) c[v] = (double)x.c[v];
+    h = (double)x.h;
   }
-  const bool hghost = edges && (g.lane0 ? g.col0 - 1 < 0 : g.col0 + VEC >= nx);
-  const double hedge = g.lane0 ? c[0] : c[VEC - 1];
-  const double hv = hghost ? (MODE == MODE_EDGE ? hedge : 0.0) : (double)x.h;
-  const double h = x.zero ? 0.0 : hv;
   lds_set<VEC>(row + L::kOwn + lane * VEC, c);
   const int hoff = g.lane0 ? L::kLeft : (g.lane63 ? L::kRight : L::kOwn + lane * VEC);
   row[hoff] = (g.lane0 || g.lane63) ? h : c[0];
@@ -209,8 +224,8 @@ __device__ __forceinline__ void rowset_load(const FieldView& F, const TY* __rest
   }
 }
 
-template <typename TF, typename TY, int VEC, bool ADVF, int NR>
-__device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r, const FieldView& F,
+template <typename TF, typename TY, int VEC, bool ADVF, class RG>
+__device__ __forceinline__ void rowset_put(const RG& R, const Strip& g, int r, const FieldView& F,
                                            const RowSet<TF, TY, VEC, ADVF>& s) {
   ring_put<VEC, MODE_ZERO>(R.row(0, r), g, s.y, R.edges, F.nx);
   ring_put<VEC, MODE_EDGE>(R.row(1, r), g, s.gy, R.edges, F.nx);
@@ -223,8 +238,8 @@ __device__ __forceinline__ void rowset_put(const Rings<VEC, ADVF, NR>& R, const 
 }
 
 // (A x) at row r from the rings, x = y_k (ring 0) or the rows u[] given
-template <int VEC, bool ADVF, int NR>
-__device__ __forceinline__ void ring_stencil(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r, const FieldView& F,
+template <int VEC, bool ADVF, class RG>
+__device__ __forceinline__ void ring_stencil(const RG& R, const Strip& g, int r, const FieldView& F,
                                              const RowN<VEC>& um, const RowN<VEC>& uc, const RowN<VEC>& up,
                                              double (&Ax)[VEC]) {
   RowN<VEC> m[3], k, ac;
@@ -242,8 +257,8 @@ __device__ __forceinline__ void ring_stencil(const Rings<VEC, ADVF, NR>& R, cons
 }
 
 // stage 1 of row r: y_{k+1} into the y_{k+1} ring (ghost rule of Stage1Ep)
-template <int VEC, bool ADVF, int NR, int NY>
-__device__ __forceinline__ void ring_stage1(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r, const FieldView& F,
+template <int VEC, bool ADVF, class RG, int NY>
+__device__ __forceinline__ void ring_stage1(const RG& R, const Strip& g, int r, const FieldView& F,
                                             Stage1Ep<VEC, NY>& ep) {
   RowN<VEC> u[3];
 #pragma unroll
@@ -369,6 +384,7 @@ __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY
     const int j0 = rb * kWavesY2;
     const int j = j0 + wave;
     const bool keep = own && j < F.ny;
+    const double km = keep ? 1.0 : 0.0;
     double pk[VEC];
     ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
     if constexpr (!LAST) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 6 + wave, nxt);
@@ -391,10 +407,10 @@ __device__ __forceinline__ void staged_run(const FieldView& F, const StagedIO<TY
       y2[v] = (Ax[v] - io.shift2 * u[1].c[v]) * io.invg;
       const double t2 = io.dk2 * y2[v];
       p2[v] = pm[v] + t2;
-      acc[0] += keep ? t1 * t1 : 0.0;
-      acc[1] += keep ? pm[v] * pm[v] : 0.0;
-      acc[2] += keep ? t2 * t2 : 0.0;
-      acc[3] += keep ? p2[v] * p2[v] : 0.0;
+      acc[0] = acc_kept(acc[0], km, t1 * t1);
+      acc[1] = acc_kept(acc[1], km, pm[v] * pm[v]);
+      acc[2] = acc_kept(acc[2], km, t2 * t2);
+      acc[3] = acc_kept(acc[3], km, p2[v] * p2[v]);
     }
     row_store<NT, TY, VEC>(yo + ro, F.nx, keep && sy ? ocol : kDropOffset, y2);
     row_store<NT, double, VEC>(pmo + ro, F.nx, keep && sm ? ocolp : kDropOffset, pm);
@@ -449,13 +465,12 @@ struct Staged3IO {
 // y_{k+t} (t >= 2) at row r: the stencil of the y_{k+t-1} ring rows r-1 .. r+1
 // (rounded to the y storage type, as a one-term launch reads y back) with the
 // field rows of the input rings; returns A y and the centre row (rounded)
-template <typename TY, int VEC, bool ADVF, int NR>
-__device__ __forceinline__ void ring_stage_from_y(const Rings<VEC, ADVF, NR>& R, const Strip& g, int r,
-                                                  const FieldView& F, const double* ylds, int yr0, double (&Ax)[VEC],
-                                                  double (&uc)[VEC]) {
+template <typename TY, int VEC, bool ADVF, int NYR = kS3Y, class RG>
+__device__ __forceinline__ void ring_stage_from_y(const RG& R, const Strip& g, int r, const FieldView& F,
+                                                  const double* ylds, int yr0, double (&Ax)[VEC], double (&uc)[VEC]) {
   RowN<VEC> u[3];
 #pragma unroll
-  for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(ylds, (unsigned)(r - 1 + t - yr0) % kS3Y, u[t]);
+  for (int t = 0; t < 3; ++t) lds_row_n<TY, VEC>(ylds, (unsigned)(r - 1 + t - yr0) % NYR, u[t]);
   ring_stencil<VEC, ADVF>(R, g, r, F, u[0], u[1], u[2], Ax);
 #pragma unroll
   for (int v = 0; v < VEC; ++v) uc[v] = u[1].c[v];
@@ -531,6 +546,7 @@ __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<
     const int j0 = rb * kWavesY2;
     const int j = j0 + wave;
     const bool keep = own && j < F.ny;
+    const double km = keep ? 1.0 : 0.0;
     double pk[VEC];
     ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
     if constexpr (!LAST) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 7 + wave, nxt);
@@ -562,12 +578,12 @@ __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<
       y3[v] = (Ax[v] - io.shift3 * uc[v]) * io.invg;
       const double t3 = io.dk3 * y3[v];
       pc[v] = pb[v] + t3;
-      acc[0] += keep ? t1 * t1 : 0.0;
-      acc[1] += keep ? pa[v] * pa[v] : 0.0;
-      acc[2] += keep ? t2 * t2 : 0.0;
-      acc[3] += keep ? pb[v] * pb[v] : 0.0;
-      acc[4] += keep ? t3 * t3 : 0.0;
-      acc[5] += keep ? pc[v] * pc[v] : 0.0;
+      acc[0] = acc_kept(acc[0], km, t1 * t1);
+      acc[1] = acc_kept(acc[1], km, pa[v] * pa[v]);
+      acc[2] = acc_kept(acc[2], km, t2 * t2);
+      acc[3] = acc_kept(acc[3], km, pb[v] * pb[v]);
+      acc[4] = acc_kept(acc[4], km, t3 * t3);
+      acc[5] = acc_kept(acc[5], km, pc[v] * pc[v]);
     }
     row_store<NT, TY, VEC>(yo + ro, F.nx, keep && sy ? ocol : kDropOffset, y3);
     row_store<NT, double, VEC>(p1o + ro, F.nx, keep && s1 ? ocolp : kDropOffset, pa);
@@ -581,6 +597,250 @@ __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<
 #pragma unroll 1
   for (int rb = rb0; rb < rb1 - 1; ++rb) band.template operator()<false>(rb);
   if (rb1 > rb0) band.template operator()<true>(rb1 - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Four Newton-Leja terms per launch with the input rows staged in LDS (the
+// pass of leja4s_kernel): the march of staged3_run with a fourth stage.  Per
+// band step (output rows j0 .. j0+3) stage t computes y_{k+t} on rows
+// j0+4-t .. j0+7-t; stage 4 is the output row, whose p advances by the four
+// terms with y_{k+1} .. y_{k+3} of that row read back from the Y rings.
+// Stage 4 is valid on lanes 2 .. 61 with two columns per lane (the strips
+// have 60*VEC output columns).  Each input array keeps only the rows its
+// readers need (RingsV): y_k rows j0+2 .. j0+7 (stage 1), kyy and kxy rows
+// j0-1 .. j0+7 (three-row stencil terms of stages 4 .. 1), kxx rows
+// j0 .. j0+7 (centre rows; j0+7 arrived with the previous step's loads);
+// the step's loads of rows j0+8 .. j0+11 replace the oldest rows of each
+// ring after stage 4.  Y1 holds rows j0 .. j0+6, Y2 and Y3 six rows each:
+// 52.8 KB per FP64 block, three blocks per CU.
+// ---------------------------------------------------------------------------
+constexpr int kS4Y1 = 7, kS4Y = 6;
+
+// input rings with a row count per array: y_k, kyy, kxy, kxx (+ ax', ay')
+template <int VEC, bool ADVF>
+struct RingsV {
+  static constexpr int kRow = RingRow<VEC>::kLen;
+  static constexpr int kArrays = ADVF ? 6 : 4;
+  static constexpr int nr(int a) { return a == 0 ? 6 : (a == 1 || a == 2) ? 9 : a == 3 ? 8 : a == 4 ? 8 : 9; }
+  static constexpr int off(int a) { return a == 0 ? 0 : off(a - 1) + nr(a - 1); }
+  static constexpr int kRows = off(kArrays);
+  double* base;
+  int r0;      // grid row of slot 0 (every ring)
+  bool edges;  // Dirichlet ghost columns in the strip or its halo (ring_put)
+  __device__ __forceinline__ double* row(int a, int r) const {
+    return base + ((long)off(a) + (unsigned)(r - r0) % nr(a)) * kRow;
+  }
+};
+
+template <typename TY>
+struct Staged4IO {
+  const TY* yin;
+  TY* yout;           // or null: not stored
+  const double* pin;
+  double* p1;         // p_{k+1} .. p_{k+3}, or null: not stored
+  double* p2;
+  double* p3;
+  double* p;          // p_{k+4}, or null
+  double shift, shift2, shift3, shift4, invg, dk1, dk2, dk3, dk4;
+};
+
+// y_{k+t} (t >= 2) at row r of the run's prologue: the stencil of the Y ring
+// rows r-1 .. r+1 (rounded to the storage type) with the field rows read
+// from memory, into the ring of ep
+template <typename TF, typename TY, int VEC, bool ADVF, int NYR, int NO>
+__device__ __forceinline__ void prologue_stage_g(const FieldView& F, const Strip& g, int r, const double* ylds,
+                                                 int yr0, Stage1Ep<VEC, NO>& ep) {
+  const TF* __restrict__ kxx = reinterpret_cast<const TF*>(F.kxx);
+  const TF* __restrict__ kxy = reinterpret_cast<const TF*>(F.kxy);
+  const TF* __restrict__ kyy = reinterpret_cast<const TF*>(F.kyy);
+  const TF* __restrict__ fax = reinterpret_cast<const TF*>(F.ax);
+  const TF* __restrict__ fay = reinterpret_cast<const TF*>(F.ay);
+  RowN<VEC> u[3], m[3], k, ac;
+  RowC<VEC> gg[3], ay[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    row_c<TF, VEC, MODE_EDGE>(kyy, r - 1 + t, F, g, gg[t]);
+    row_n<TF, VEC, MODE_ZERO>(kxy, r - 1 + t, F, g, m[t]);
+    if constexpr (ADVF) row_c<TF, VEC, MODE_ZERO>(fay, r - 1 + t, F, g, ay[t]);
+    lds_row_n<TY, VEC>(ylds, (unsigned)(r - 1 + t - yr0) % NYR, u[t]);
+  }
+  row_n<TF, VEC, MODE_EDGE>(kxx, r, F, g, k);
+  if constexpr (ADVF) row_n<TF, VEC, MODE_ZERO>(fax, r, F, g, ac);
+  double Ax[VEC];
+  stencil_point<VEC, ADVF>(u[0], u[1], u[2], gg[0], gg[1], gg[2], m[0], m[1], m[2], k, ac, ay[0], ay[2], F.axc,
+                           F.ayc, Ax);
+  typename Stage1Ep<VEC, NO>::Extra none;
+  ep.finish(r, g, Ax, u[1].c, none);
+}
+
+// the input arrays of a loaded row set that go into their rings (the run's
+// prologue: y_k from row J0+2, kxx from row J0 on)
+template <typename TF, typename TY, int VEC, bool ADVF>
+__device__ __forceinline__ void rowset_put_from(const RingsV<VEC, ADVF>& R, const Strip& g, int r, const FieldView& F,
+                                                const RowSet<TF, TY, VEC, ADVF>& s, int ymin, int kmin) {
+  if (r >= ymin) ring_put<VEC, MODE_ZERO>(R.row(0, r), g, s.y, R.edges, F.nx);
+  ring_put<VEC, MODE_EDGE>(R.row(1, r), g, s.gy, R.edges, F.nx);
+  ring_put<VEC, MODE_ZERO>(R.row(2, r), g, s.m, R.edges, F.nx);
+  if (r >= kmin) ring_put<VEC, MODE_EDGE>(R.row(3, r), g, s.k, R.edges, F.nx);
+  if constexpr (ADVF) {
+    if (r >= kmin) ring_put<VEC, MODE_ZERO>(R.row(4, r), g, s.ax, R.edges, F.nx);
+    ring_put<VEC, MODE_ZERO>(R.row(5, r), g, s.ay, R.edges, F.nx);
+  }
+}
+
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
+__device__ __forceinline__ void staged4_run(const FieldView& F, const Staged4IO<TY>& io, double* lds, int i0, int rb0,
+                                            int rb1, int stopflag, double (&acc)[8]) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int W = kWave * VEC;
+  Stage1Ep<VEC, kS4Y1> e1;
+  Stage1Ep<VEC, kS4Y> e2, e3;
+  e1.stopflag = stopflag;
+  if (!e1.go()) {
+    // prologue and band steps: four and five barriers
+    __syncthreads();
+    __syncthreads();
+    __syncthreads();
+    __syncthreads();
+    for (int rb = rb0; rb < rb1; ++rb) {
+      __syncthreads();
+      __syncthreads();
+      __syncthreads();
+      __syncthreads();
+      __syncthreads();
+    }
+    return;
+  }
+  const Strip g = strip_at<VEC>(F, i0);
+  const bool own = lane >= 2 && lane <= kWave - 3 && g.inside;
+  const int J0 = rb0 * kWavesY2;
+  e1.lds = lds;
+  e1.r0 = J0 - 3;
+  e1.ny = F.ny;
+  e1.per = F.bc == BC_PERIODIC;
+  e1.shift = io.shift;
+  e1.invg = io.invg;
+  e2.lds = lds + kS4Y1 * W;
+  e2.r0 = J0 - 2;
+  e2.ny = F.ny;
+  e2.per = e1.per;
+  e2.shift = io.shift2;
+  e2.invg = io.invg;
+  e2.stopflag = 0;
+  e3 = e2;
+  e3.lds = lds + (kS4Y1 + kS4Y) * W;
+  e3.r0 = J0 - 1;
+  e3.shift = io.shift3;
+  RingsV<VEC, ADVF> R;
+  R.base = lds + (kS4Y1 + 2 * kS4Y) * W;
+  R.r0 = J0 - 1;
+  R.edges = F.bc != BC_PERIODIC && (i0 <= 0 || i0 + kWave * VEC >= F.nx);
+  const TY* __restrict__ yin = io.yin;
+  const int ocol = g.col0 * (int)sizeof(TY), ocolp = g.col0 * 8;
+  const bool sy = io.yout != nullptr, s1 = io.p1 != nullptr, s2 = io.p2 != nullptr, s3 = io.p3 != nullptr,
+             sp = io.p != nullptr;
+  TY* const yo = sy ? io.yout : const_cast<TY*>(yin);
+  double* const p1o = s1 ? io.p1 : const_cast<double*>(io.pin);
+  double* const p2o = s2 ? io.p2 : const_cast<double*>(io.pin);
+  double* const p3o = s3 ? io.p3 : const_cast<double*>(io.pin);
+  double* const po = sp ? io.p : const_cast<double*>(io.pin);
+  // prologue: y_{k+1} on rows J0-3 .. J0+2, y_{k+2} on J0-2 .. J0+1, y_{k+3}
+  // on J0-1 and J0, from memory (cache hits of the rows the blocks above
+  // read); meanwhile the input rows J0-1 .. J0+7 go into the rings
+  RowSet<TF, TY, VEC, ADVF> ra, rb, rc;
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 - 1 + wave, ra);
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 3 + wave, rb);
+  rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 7 + wave, rc);
+  stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, e1, g, J0 - 3 + wave);
+  if (wave < 2) stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, e1, g, J0 + 1 + wave);
+  __syncthreads();
+  prologue_stage_g<TF, TY, VEC, ADVF, kS4Y1>(F, g, J0 - 2 + wave, e1.lds, e1.r0, e2);
+  __syncthreads();
+  if (wave < 2) prologue_stage_g<TF, TY, VEC, ADVF, kS4Y>(F, g, J0 - 1 + wave, e2.lds, e2.r0, e3);
+  rowset_put_from<TF, TY, VEC, ADVF>(R, g, J0 - 1 + wave, F, ra, J0 + 2, J0);
+  rowset_put_from<TF, TY, VEC, ADVF>(R, g, J0 + 3 + wave, F, rb, J0 + 2, J0);
+  if (wave == 0) rowset_put_from<TF, TY, VEC, ADVF>(R, g, J0 + 7, F, rc, J0 + 2, J0);
+  __syncthreads();
+  __syncthreads();
+  // one band step (output rows j0 .. j0+3); LAST: the run's last step
+  RowSet<TF, TY, VEC, ADVF> nxt;
+  auto band = [&]<bool LAST>(int rb) {
+    const int j0 = rb * kWavesY2;
+    const int j = j0 + wave;
+    const bool keep = own && j < F.ny;
+    const double km = keep ? 1.0 : 0.0;
+    double pk[VEC];
+    ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
+    if constexpr (!LAST) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 8 + wave, nxt);
+    // stage 1: y_{k+1} on row j0+3+wave
+    ring_stage1<VEC, ADVF>(R, g, j0 + 3 + wave, F, e1);
+    __syncthreads();
+    // stage 2: y_{k+2} on row j0+2+wave
+    {
+      double Ax[VEC], uc[VEC];
+      ring_stage_from_y<TY, VEC, ADVF, kS4Y1>(R, g, j0 + 2 + wave, F, e1.lds, e1.r0, Ax, uc);
+      typename Stage1Ep<VEC, kS4Y>::Extra none;
+      e2.finish(j0 + 2 + wave, g, Ax, uc, none);
+    }
+    __syncthreads();
+    // stage 3: y_{k+3} on row j0+1+wave
+    {
+      double Ax[VEC], uc[VEC];
+      ring_stage_from_y<TY, VEC, ADVF, kS4Y>(R, g, j0 + 1 + wave, F, e2.lds, e2.r0, Ax, uc);
+      typename Stage1Ep<VEC, kS4Y>::Extra none;
+      e3.finish(j0 + 1 + wave, g, Ax, uc, none);
+    }
+    __syncthreads();
+    // stage 4: y_{k+4} on row j (rows past the grid are computed and dropped)
+    double Ax[VEC], uc[VEC];
+    ring_stage_from_y<TY, VEC, ADVF, kS4Y>(R, g, j, F, e3.lds, e3.r0, Ax, uc);
+    double y1[VEC], y2[VEC], y3[VEC];
+    lds_get<VEC>(e1.lds + (long)((unsigned)(j - e1.r0) % kS4Y1) * W + lane * VEC, y1);
+    lds_get<VEC>(e2.lds + (long)((unsigned)(j - e2.r0) % kS4Y) * W + lane * VEC, y2);
+    lds_get<VEC>(e3.lds + (long)((unsigned)(j - e3.r0) % kS4Y) * W + lane * VEC, y3);
+    const long ro = (long)min(j, F.ny - 1) * F.nx;
+    double y4[VEC], pa[VEC], pb[VEC], pc[VEC], pd[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const double t1 = io.dk1 * y1[v];
+      pa[v] = pk[v] + t1;
+      const double t2 = io.dk2 * y2[v];
+      pb[v] = pa[v] + t2;
+      const double t3 = io.dk3 * y3[v];
+      pc[v] = pb[v] + t3;
+      y4[v] = (Ax[v] - io.shift4 * uc[v]) * io.invg;
+      const double t4 = io.dk4 * y4[v];
+      pd[v] = pc[v] + t4;
+      acc[0] = acc_kept(acc[0], km, t1 * t1);
+      acc[1] = acc_kept(acc[1], km, pa[v] * pa[v]);
+      acc[2] = acc_kept(acc[2], km, t2 * t2);
+      acc[3] = acc_kept(acc[3], km, pb[v] * pb[v]);
+      acc[4] = acc_kept(acc[4], km, t3 * t3);
+      acc[5] = acc_kept(acc[5], km, pc[v] * pc[v]);
+      acc[6] = acc_kept(acc[6], km, t4 * t4);
+      acc[7] = acc_kept(acc[7], km, pd[v] * pd[v]);
+    }
+    row_store<NT, TY, VEC>(yo + ro, F.nx, keep && sy ? ocol : kDropOffset, y4);
+    row_store<NT, double, VEC>(p1o + ro, F.nx, keep && s1 ? ocolp : kDropOffset, pa);
+    row_store<NT, double, VEC>(p2o + ro, F.nx, keep && s2 ? ocolp : kDropOffset, pb);
+    row_store<NT, double, VEC>(p3o + ro, F.nx, keep && s3 ? ocolp : kDropOffset, pc);
+    row_store<NT, double, VEC>(po + ro, F.nx, keep && sp ? ocolp : kDropOffset, pd);
+    __syncthreads();
+    // the next step's rows replace each ring's oldest rows, read for the last time above
+    if constexpr (!LAST) rowset_put<TF, TY, VEC, ADVF>(R, g, j0 + 8 + wave, F, nxt);
+    __syncthreads();
+  };
+#pragma unroll 1
+  for (int rb = rb0; rb < rb1 - 1; ++rb) band.template operator()<false>(rb);
+  if (rb1 > rb0) band.template operator()<true>(rb1 - 1);
+}
+
+// dynamic LDS of a four-term staged block
+template <int VEC, bool ADVF>
+constexpr size_t staged4_lds_bytes() {
+  return ((size_t)(kS4Y1 + 2 * kS4Y) * kWave * VEC + (size_t)RingsV<VEC, ADVF>::kRows * RingsV<VEC, ADVF>::kRow) *
+         sizeof(double);
 }
 
 // dynamic LDS of a three-term staged block

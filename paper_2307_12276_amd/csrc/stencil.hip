@@ -41,8 +41,7 @@ namespace adl {
 // the rest); every thread receives the totals.
 // ---------------------------------------------------------------------------
 template <int NA, int NS>
-__device__ __forceinline__ void block_allreduce(double (&v)[NA]) {
-  __shared__ double sh[NA * 16];
+__device__ __forceinline__ void block_allreduce_at(double (&v)[NA], double* sh) {
 #pragma unroll
   for (int k = 0; k < NA; ++k) {
 #pragma unroll
@@ -64,6 +63,12 @@ __device__ __forceinline__ void block_allreduce(double (&v)[NA]) {
     for (int w = 1; w < nw; ++w) s = (k < NS) ? s + sh[w * NA + k] : nanmax(s, sh[w * NA + k]);
     v[k] = s;
   }
+}
+// the same with a static LDS array (sh: NA * 16 doubles)
+template <int NA, int NS>
+__device__ __forceinline__ void block_allreduce(double (&v)[NA]) {
+  __shared__ double sh[NA * 16];
+  block_allreduce_at<NA, NS>(v, sh);
 }
 
 // Totals of the block partials written by an earlier launch: part[k * nb + b].
@@ -221,7 +226,11 @@ struct LejaEp {
 // k_prev+nterms_prev, in order) from its block partials, taken by one block
 // (fixed-order totals) and recorded in the control block unless an earlier
 // launch has already stopped the sweep.
-__device__ __forceinline__ void leja_decide(const LejaArgs& A) {
+// (dsh: a kernel's dynamic LDS for the reduction (160 doubles), or null for
+// a static array; the four-term staged kernel passes its rings, so that it
+// holds no static LDS and three blocks fit a CU)
+template <bool DYN = false>
+__device__ __forceinline__ void leja_decide(const LejaArgs& A, double* dsh = nullptr) {
   // the stop flag travels with the partial sums (a max-reduced value), so its
   // load and the partial loads are in flight together
   const double* part = A.partials + (long)A.slot_prev * A.slot_stride;
@@ -252,7 +261,8 @@ __device__ __forceinline__ void leja_decide(const LejaArgs& A) {
     }
     any = true;
   }
-  block_allreduce<10, 8>(v);
+  if constexpr (DYN) block_allreduce_at<10, 8>(v, dsh);
+  else block_allreduce<10, 8>(v);
   if (v[9] != 0.0) return;  // decided by an earlier launch
   // Terms up to `done` were decided already: a chunk's closing decision
   // launch decides the chunk's last launch, and the first launch of the next
@@ -965,6 +975,59 @@ __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling
   }
 }
 
+// Four Newton terms per launch (k >= 1) with the input rows staged in LDS
+// (staged4_run in staged.h), on its own tiling of strips of 60*VEC output
+// columns with two columns per lane.  No static LDS (the block reductions
+// use the dynamic rings), so that three blocks share a CU.
+template <typename TF, typename TY, bool ADVF, bool NT>
+__global__ __launch_bounds__(kTileBlock2) void leja4s_kernel(FieldView F, Tiling T, LejaArgs A) {
+  extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
+  constexpr int VEC = 2;
+  const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
+  if (L == 0) {
+    if (!A.replay) leja_decide<true>(A, lds);
+    return;
+  }
+  const int b = L - 1;
+  const int cb = b % T.ncb;
+  const int rb0 = (b / T.ncb) * T.bands;
+  const int rb1 = min(rb0 + T.bands, T.nrb);
+  Staged4IO<TY> io;
+  io.yin = reinterpret_cast<const TY*>(A.yin);
+  io.yout = reinterpret_cast<TY*>(A.yout);
+  io.pin = A.pin;
+  io.p1 = A.pmid;
+  io.p2 = A.pmid2;
+  io.p3 = A.pmid3;
+  io.p = A.p;
+  io.shift = A.shift;
+  io.shift2 = A.shift2;
+  io.shift3 = A.shift3;
+  io.shift4 = A.shift4;
+  io.invg = A.invg;
+  io.dk1 = A.dk1;
+  io.dk2 = A.dk2;
+  io.dk3 = A.dk3;
+  io.dk4 = A.dk4;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  staged4_run<TF, TY, VEC, ADVF, NT>(
+      F, io, lds, cb * (kWave - 4) * VEC - 2 * VEC, rb0, rb1,
+      A.replay ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), acc);
+  // block partials: term t (0 .. 3) at rows 3t (||d y||^2), 3t + 1 (||p||^2), 3t + 2 (0)
+  __syncthreads();  // (the rings are free again: the reduction's scratch)
+  block_allreduce_at<8, 8>(acc, lds);
+  if (threadIdx.x == 0 && !A.replay) {
+    double* part = A.partials + (long)A.slot * A.slot_stride;
+    const int nb = T.nblocks;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      part[(3L * t) * nb + b] = acc[2 * t];
+      part[(3L * t + 1) * nb + b] = acc[2 * t + 1];
+      part[(3L * t + 2) * nb + b] = 0.0;
+    }
+  }
+}
+
 // Power iteration term: w_{k+1} = A(w_k) / lambda_k, lambda_k = ||w_k|| from
 // the partials of the launch that wrote w_k.
 template <int VEC>
@@ -1125,11 +1188,11 @@ Tiling make_tiling(int nx, int ny, int rows_hint, int vec_hint) {
   return t;
 }
 
-Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint, int max_blocks) {
+Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint, int max_blocks, int frame) {
   Tiling t;
   const bool two = nx % 2 == 0 && nx >= 2 * kWave;
   t.vec = (vec_hint == 1 || !two) ? 1 : 2;
-  const int wo = (kWave - 2) * t.vec;  // output columns of a strip
+  const int wo = (kWave - 2 * frame) * t.vec;  // output columns of a strip
   t.ncb = (nx + wo - 1) / wo;
   (void)rows_hint;  // one output row per wave
   t.rows = 1;
@@ -1347,6 +1410,53 @@ hipError_t launch_leja3_step(const FieldView& f, const Tiling& t, const LejaArgs
     } else {
       if (a.ystore_f32) leja3s_dispatch<double, float, false>(f, t, a, st);
       else leja3s_dispatch<double, double, false>(f, t, a, st);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename TF, typename TY, bool ADVF, bool NT>
+static void leja4s_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock2);
+  const size_t lds = staged4_lds_bytes<2, ADVF>();
+  if (a.ev_start)
+    hipExtLaunchKernelGGL((leja4s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
+  else
+    hipLaunchKernelGGL((leja4s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, f, t, a);
+}
+
+template <typename TF, typename TY, bool NT>
+static void leja4s_dispatch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if (f.ax) leja4s_launch<TF, TY, true, NT>(f, t, a, st);
+  else leja4s_launch<TF, TY, false, NT>(f, t, a, st);
+}
+
+hipError_t launch_leja4s_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if (a.first || a.k < 1 || a.nterms != 4 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || t.vec != 2)
+    return hipErrorInvalidValue;
+  if (!a.decide_only) {
+    // p_k is read while the stored p outputs (at least one) are written: all distinct
+    const double* o[5] = {a.pin, a.pmid, a.pmid2, a.pmid3, a.p};
+    if (a.pin == nullptr || (!a.pmid && !a.pmid2 && !a.pmid3 && !a.p)) return hipErrorInvalidValue;
+    for (int i = 1; i < 5; ++i)
+      for (int j = 0; j < i; ++j)
+        if (o[i] != nullptr && o[i] == o[j]) return hipErrorInvalidValue;
+  }
+  if (a.stream) {
+    if (f.f32) {
+      if (a.ystore_f32) leja4s_dispatch<float, float, true>(f, t, a, st);
+      else leja4s_dispatch<float, double, true>(f, t, a, st);
+    } else {
+      if (a.ystore_f32) leja4s_dispatch<double, float, true>(f, t, a, st);
+      else leja4s_dispatch<double, double, true>(f, t, a, st);
+    }
+  } else {
+    if (f.f32) {
+      if (a.ystore_f32) leja4s_dispatch<float, float, false>(f, t, a, st);
+      else leja4s_dispatch<float, double, false>(f, t, a, st);
+    } else {
+      if (a.ystore_f32) leja4s_dispatch<double, float, false>(f, t, a, st);
+      else leja4s_dispatch<double, double, false>(f, t, a, st);
     }
   }
   return hipGetLastError();

@@ -270,10 +270,19 @@ struct Stage1Ep {
   __device__ __forceinline__ void load(int, const Strip&, Extra&) {}
   __device__ __forceinline__ void finish(int r, const Strip& g, const double (&Ax)[VEC], const double (&xc)[VEC],
                                          const Extra&) {
-    const bool ghost = !per && (!g.inside || r < 0 || r >= ny);
     double* row = lds + (long)((unsigned)(r - r0) % NR) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
+    double y[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) row[v] = ghost ? 0.0 : (Ax[v] - shift * xc[v]) * invg;
+    for (int v = 0; v < VEC; ++v) y[v] = (Ax[v] - shift * xc[v]) * invg;
+    if (!per) {
+      // uniform branch: only Dirichlet rows and columns have ghost entries
+      __asm__ volatile("");
+      const bool ghost = !g.inside || r < 0 || r >= ny;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) y[v] = ghost ? 0.0 : y[v];
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) row[v] = y[v];
   }
 };
 

@@ -339,12 +339,13 @@ def test_four_term_launches_match_one_term_launches(nx, ny, bc, storage):
     assert eq < (max(1e-13, 4e-15 * mq) if mq == quads[1][1] else 1e-10), eq
 
 
+@pytest.mark.parametrize("mode,terms", [(5, 3), (6, 4)])
 @pytest.mark.parametrize("nx,ny", [(128, 128), (130, 70), (300, 129), (250, 7), (200, 200), (256, 9), (512, 33)])
 @pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
 @pytest.mark.parametrize("storage", [0, 1, 2])
-def test_three_term_launches_match_one_term_launches(nx, ny, bc, storage):
-    """Three Newton terms per launch with LDS-staged rows (y_{k+1}, y_{k+2}
-    kept in LDS rings, on the two-term tiling) give the one-term result: the
+def test_staged_multi_term_launches_match_one_term_launches(mode, terms, nx, ny, bc, storage):
+    """Three (mode 5) or four (mode 6) Newton terms per launch with LDS-staged
+    rows (the intermediate y kept in LDS rings) give the one-term result: the
     same degree wherever the sweep stops inside a launch (a replay of the
     launch stores p of that term), the same polynomial up to the grouping of
     the norm partial sums; the phi_1 + phi_2 sweep of the augmented form too;
@@ -359,8 +360,9 @@ def test_three_term_launches_match_one_term_launches(nx, ny, bc, storage):
     v = to_dev(v0)
     outs, degs, quads, n3s = [], [], [], []
     mults = (40.0, 300.0, 2000.0)
-    for mode in (0, 5):
-        gop.set_term_fusion(mode)
+    kind = A.LAUNCH_THREE if terms == 3 else A.LAUNCH_FOUR
+    for m in (0, mode):
+        gop.set_term_fusion(m)
         o, d = [], []
         gop.profile(True)
         for mult in mults:
@@ -368,7 +370,7 @@ def test_three_term_launches_match_one_term_launches(nx, ny, bc, storage):
             st = gop.leja_phi(1, mult / abs(alpha), v, out, 1e-10)
             o.append(to_np(out))
             d.append(st["max_degree"])
-        _, n3, _, t3 = gop.profile_read_kind(A.LAUNCH_THREE)
+        _, n3, _, t3 = gop.profile_read_kind(kind)
         gop.profile(False)
         n3s.append((n3, t3))
         outs.append(o)
@@ -377,15 +379,15 @@ def test_three_term_launches_match_one_term_launches(nx, ny, bc, storage):
         S = torch.full_like(v, 0.5)
         qs = gop.quad2_step(u, S, 2.0 * S, 1.0 / 3.0, 2.0 / 3.0, 300.0 / abs(alpha), 1e-10)
         quads.append((to_np(u), qs["matvecs"]))
-    assert n3s[0][0] == 0 and n3s[1][0] > 0 and n3s[1][1] == 3 * n3s[1][0], n3s
+    assert n3s[0][0] == 0 and n3s[1][0] > 0 and n3s[1][1] == terms * n3s[1][0], n3s
     assert degs[0] == degs[1], degs
     errs = [rel(b, a) for a, b in zip(outs[0], outs[1])]
-    print("degrees %s, three-term vs one-term %s" % (degs[0], ["%.1e" % e for e in errs]))
+    print("degrees %s, %d-term vs one-term %s" % (degs[0], terms, ["%.1e" % e for e in errs]))
     for e, m in zip(errs, degs[0]):
         assert e < max(1e-13, 4e-15 * m), (e, m)
     eq = rel(quads[1][0], quads[0][0])
     mq = quads[0][1]
-    print("quad2 step: matvecs %d / %d, three-term vs one-term %.1e" % (mq, quads[1][1], eq))
+    print("quad2 step: matvecs %d / %d, %d-term vs one-term %.1e" % (mq, quads[1][1], terms, eq))
     assert eq < (max(1e-13, 4e-15 * mq) if mq == quads[1][1] else 1e-10), eq
     for mult, o, d in zip(mults, outs[1], degs[1]):
         ost = {}
@@ -398,14 +400,15 @@ def test_three_term_launches_match_one_term_launches(nx, ny, bc, storage):
 
 
 @pytest.mark.parametrize("nx,ny", [(33, 45), (64, 64), (257, 33)])
-def test_three_term_mode_needs_two_columns_per_lane(nx, ny):
-    """Mode 5 needs the two-term tiling with two columns per lane (nx even
-    and at least 128): other widths are refused with ADL_EINVAL."""
+def test_staged_multi_term_modes_need_two_columns_per_lane(nx, ny):
+    """Modes 5 and 6 need tilings with two columns per lane (nx even and at
+    least 128): other widths are refused with ADL_EINVAL."""
     z = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
     op = A.Op(z + 1.0, z, z + 1.0, 1.0 / nx, 1.0 / ny, A.BC_PERIODIC, A.STORAGE_FP64)
-    with pytest.raises(A.AdlError) as e:
-        op.set_term_fusion(5)
-    assert e.value.code == A.EINVAL
+    for mode in (5, 6):
+        with pytest.raises(A.AdlError) as e:
+            op.set_term_fusion(mode)
+        assert e.value.code == A.EINVAL
 
 
 def test_default_mode_runs_four_terms_on_mid_grids():
@@ -573,7 +576,7 @@ def test_periodic_few_rows_sweeps_match_oracle(nx, ny):
         assert e.value.code == A.EINVAL
     st = {}
     ref = leja.phi_apply(lambda x: O.apply(oop, x), 1, dt, v0, alpha, 1e-10, stats=st)
-    modes = (1, 0, 2, 3) + ((4,) if four else ()) + ((5,) if nx % 2 == 0 and nx >= 128 else ())
+    modes = (1, 0, 2, 3) + ((4,) if four else ()) + ((5, 6) if nx % 2 == 0 and nx >= 128 else ())
     for mode in modes:
         gop.set_term_fusion(mode)
         out = torch.empty_like(v)
