@@ -284,11 +284,18 @@ int adl_batch_destroy(adl_batch* b);
 int adl_batch_set_tile_rows(adl_batch* b, int rows);
 int adl_batch_get_tile_rows(const adl_batch* b, int* rows);
 
-/* Newton terms per launch of the batched sweep: two_terms = 1 (the default)
- * computes terms k+1 and k+2 of every running bin in one launch after the
- * first term (one wave per tile marches down its rows with y_{k+1} in LDS);
- * 0 launches one kernel per term.  ADL_EINVAL for other values. */
-int adl_batch_set_term_fusion(adl_batch* batch, int two_terms);
+/* Newton terms per launch of the batched sweep (Sec. 2 recurrence): mode = 3
+ * (the default when every bin has nx even and >= 128) computes terms k+1 ..
+ * k+3 of every running bin in one launch, the first three included, blocks
+ * of four waves marching runs of 4 * tile_rows rows of a strip of one bin
+ * with the input rows staged in LDS (a launch stores y of its last two terms,
+ * the second-to-last in FP32, and p of the last; a bin that stops at an
+ * earlier term is advanced by p_m rebuilt from them); mode = 1 (the default
+ * otherwise) computes terms k+1 and k+2 in one launch after a launch of the
+ * first term alone (one wave per tile marches down its rows with y_{k+1} in
+ * registers); mode = 0 launches one kernel per term.  ADL_EINVAL for other
+ * values, and for mode 3 when a bin is narrower or odd. */
+int adl_batch_set_term_fusion(adl_batch* batch, int mode);
 
 /* Autotuner: times the launches of one step (stage and sweep; u is not
  * modified) for each of the ncand candidate tile heights (host array) and

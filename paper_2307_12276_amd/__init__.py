@@ -458,9 +458,12 @@ class Batch:
         _check(lib().adl_batch_get_tile_rows(self.handle, ctypes.byref(r)))
         return r.value
 
-    def set_term_fusion(self, two_terms: bool = True):
-        """Newton terms per batched launch after the first: two (default) or one."""
-        _check(lib().adl_batch_set_term_fusion(self.handle, int(bool(two_terms))))
+    def set_term_fusion(self, mode=True):
+        """Newton terms per batched launch: 3 three with LDS-staged blocks
+        (the default when every bin has nx even and >= 128), True/1 two after
+        a launch of the first term alone (the default otherwise), False/0 one."""
+        m = int(mode) if not isinstance(mode, bool) else int(mode)
+        _check(lib().adl_batch_set_term_fusion(self.handle, m))
 
     def autotune(self, us, S_halfs, dt: float, tol: float, candidates=(8, 16, 32), stream=None):
         up, sp = self._ptr_arrays(us, S_halfs)

@@ -11,7 +11,8 @@
 //              p_{b,k+1} = p_{b,k} + d_{b,k+1} y_{k+1},
 //              for every bin still running, with the bin's own plan; after
 //              the first term two terms per launch by default (y_{k+1} kept
-//              in registers)
+//              in registers), or three with the input rows staged in LDS
+//              (blocks of four waves march runs of one strip of a bin)
 //   finalize   the decision of the last term, one wave per bin
 //   update     u_b += dt p_b for converged bins
 // The stopping decision lags one launch behind the work, as for a single
@@ -66,6 +67,11 @@ struct BinDesc {
   int ncb2;       // strips of 62*VEC output columns (two-term tiles)
   int ntiles2;
   int tile_base2;
+  int ncb3;       // three-term blocks: strips of 124 output columns,
+  int bands3;     // runs of bands3 bands of four rows,
+  int nblocks3;   // ncb3 x runs blocks from block_base3 on
+  int block_base3;
+  float* y2b[2];   // three-term launches: y of the second-to-last term of launch L (FP32) in y2b[L & 1]
   int active;     // 0: the bin is advanced by the single-op path instead
 };
 
@@ -74,7 +80,7 @@ struct BinCtl {
   int status;  // 0 running, 1 converged, 2 non-finite, 3 degree cap
   int degree;
   int upd;     // 1: u already advanced by an earlier update launch of this step
-  int inner;   // the stopping term is the first of a two-term launch (its p is not stored)
+  int inner;   // terms of the stopping launch after the stopping term (their p alone is stored)
   int launch;  // launch index of the stopping term (kNoLaunch until the bin stops)
   double tn2, pn2;
   double hist[kStopHist];  // term norms of the stopping window (as in Ctl)
@@ -84,15 +90,18 @@ struct BatchArgs {
   const BinDesc* bins;
   const int* tile_bin;   // global one-term tile -> bin
   const int* tile_bin2;  // global two-term tile -> bin
+  const int* block_bin3;  // global three-term block -> bin
   BinCtl* ctl;
   double* partials;      // 2 launch parities x tiles x 6
   int total_tiles;
   int total_tiles2;
+  int total_blocks3;
   long part_stride;      // doubles per parity
   int L;                 // launch index within the sweep
   int k;                 // terms before this launch
   int kprev, nprev;      // the previous launch: terms before it, its terms (1 or 2)
   int two;               // p buffers in pairs per launch (two-term sweeps)
+  int three;             // three-term sweeps: p of launch L's last term in pb[(L & 1) ? 0 : 1]
   int advance;           // tiles of a stopped bin advance u in its due launch (0: timing runs leave u alone)
 };
 
@@ -114,6 +123,10 @@ inline unsigned blocks_for(long units) { return (unsigned)((units + kBWaves - 1)
 __device__ __forceinline__ int pbuf_index(int m, int two) {
   return two ? 2 * ((m >> 1) & 1) + (m & 1) : (m & 1);
 }
+// three-term sweeps: the p buffer launch L writes (its last term's p; the
+// first launch writes pb[1], as pbuf_index(1, .) gives) and the one it reads
+__device__ __forceinline__ int pbuf_out3(int L) { return (L & 1) ? 0 : 1; }
+__device__ __forceinline__ int pbuf_in3(int L) { return (L & 1) ? 1 : 0; }
 
 // BinCtl::launch before any decision: far from every launch index, so that a
 // tile that reads the stop flag set beside it in its own launch, together
@@ -122,38 +135,50 @@ constexpr int kNoLaunch = -1000000;
 
 // The update u_b += dt p_m of a bin that stopped at term m with status 1,
 // over rows j0 .. j1-1 and columns c0 .. c1-1 of the bin (a tile's own
-// points; one lane per VEC columns).  A bin that stopped at the first term
-// m of a two-term launch is advanced by p_m = p_{m+1} - d_{m+1} y_{m+1}: that
-// launch stored p and y of term m+1 only, and no later launch of the sweep
-// wrote those buffers of the bin (the launch beside the decision writes the
-// other y buffer and the other p pair, and every later one skips the bin).
+// points; one lane per VEC columns).  A bin that stopped at an earlier term m
+// of a fused launch is advanced by p_m = p_last - d_last y_last (- d_{m+1}
+// y_{m+1} when the launch ran two terms past m, three-term sweeps): that
+// launch stored p and y of its last term (and, with three terms, y of the one
+// before, in FP32: the term d_{m+1} y_{m+1} is of the order of tol |p| at a
+// stop, so its rounding moves p_m by ~1e-7 tol |p|), and no later launch of
+// the sweep wrote those buffers of the bin (the launch beside the decision
+// writes the other y buffers and the other p buffers, and every later one
+// skips the bin).
 template <int VEC>
 __device__ __forceinline__ void bin_update_rect(const BatchArgs& A, const BinDesc& B, const BinCtl& c,
                                                 double* __restrict__ ub, int j0, int j1, int c0, int c1) {
   const int m = c.degree;
-  const bool inner = c.inner != 0;
-  const double* __restrict__ pb = B.pb[pbuf_index(inner ? m + 1 : m, A.two)];
+  const int back = c.inner;
+  const double* __restrict__ pb = B.pb[A.three ? pbuf_out3(c.launch) : pbuf_index(m + back, A.two)];
   const double* __restrict__ yb = reinterpret_cast<const double*>(((c.launch + 1) & 1) ? B.y1 : B.y0);
-  const double dm = inner ? B.d[min(m + 1, B.max_degree)] : 0.0;
+  const float* __restrict__ yb2 = B.y2b[c.launch & 1];
+  const double dm = back > 0 ? B.d[min(m + back, B.max_degree)] : 0.0;
+  const double dm2 = back > 1 ? B.d[min(m + 1, B.max_degree)] : 0.0;
   const double dt = B.dt;
   const int nx = B.f.nx;
   const int col0 = c0 + (int)(threadIdx.x & 63) * VEC;
   if (col0 >= c1) return;
   // rows in groups of four, every load of a group issued before its stores
-  // (u, p and y are distinct arrays)
+  // (u, p and the y are distinct arrays)
   constexpr int G = 4;
   for (int j = j0; j < j1; j += G) {
-    double uu[G][VEC], pp[G][VEC], yy[G][VEC];
+    double uu[G][VEC], pp[G][VEC], yy[G][VEC], zz[G][VEC];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
       const long ro = (long)min(j + q, j1 - 1) * nx;
       ldr<double, VEC>(ub + ro, col0, uu[q]);
       ldr<double, VEC>(pb + ro, col0, pp[q]);
-      if (inner) {
+      if (back > 0) {
         ldr<double, VEC>(yb + ro, col0, yy[q]);
       } else {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) yy[q][v] = 0.0;
+      }
+      if (back > 1) {
+        ldr<float, VEC>(yb2 + ro, col0, zz[q]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) zz[q][v] = 0.0;
       }
     }
 #pragma unroll
@@ -161,7 +186,9 @@ __device__ __forceinline__ void bin_update_rect(const BatchArgs& A, const BinDes
       if (j + q < j1) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-          const double pv = inner ? pp[q][v] - dm * yy[q][v] : pp[q][v];
+          double pv = pp[q][v];
+          if (back > 0) pv = pv - dm * yy[q][v];
+          if (back > 1) pv = pv - dm2 * zz[q][v];
           uu[q][v] = uu[q][v] + dt * pv;
         }
         str<double, VEC>(ub + (long)(j + q) * nx, col0, uu[q]);
@@ -194,26 +221,31 @@ __device__ __forceinline__ void wave_sum3(double (&v)[3]) {
 // kprev+2 after a two-term launch, in order), from that launch's tile
 // partials (whole wave; fixed order).
 __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B, int b, bool record) {
-  const bool two = A.nprev == 2;
-  const int base = two ? B.tile_base2 : B.tile_base;
-  const int nt = two ? B.ntiles2 : B.ntiles;
+  const int nterms = A.nprev;
+  const bool two = nterms == 2, three = nterms == 3;
+  const int base = three ? B.block_base3 : two ? B.tile_base2 : B.tile_base;
+  const int nt = three ? B.nblocks3 : two ? B.ntiles2 : B.ntiles;
   const double* part = A.partials + (long)((A.L - 1) & 1) * A.part_stride + (long)base * 6;
+  // a unit's partials: ||d y||^2 and ||p||^2 of its terms at (0, 1), (3, 4)
+  // and, after a three-term launch, (2, 5); after a one-term launch entry 2
+  // is max |y_0| (the first term's zero check)
   double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   bool any = false;
   for (int t = threadIdx.x & 63; t < nt; t += 64) {
     tot[0] += part[t * 6 + 0];
     tot[1] += part[t * 6 + 1];
-    tot[2] = any ? nanmax(tot[2], part[t * 6 + 2]) : part[t * 6 + 2];
+    tot[2] = three ? tot[2] + part[t * 6 + 2] : (any ? nanmax(tot[2], part[t * 6 + 2]) : part[t * 6 + 2]);
     tot[3] += part[t * 6 + 3];
     tot[4] += part[t * 6 + 4];
+    tot[5] += part[t * 6 + 5];
     any = true;
   }
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
+  for (int q = 0; q < 6; ++q) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const double t = __shfl_xor(tot[q], o);
-      tot[q] = q == 2 ? nanmax(tot[q], t) : tot[q] + t;
+      tot[q] = (q == 2 && !three) ? nanmax(tot[q], t) : tot[q] + t;
     }
   }
   BinCtl* c = A.ctl + b;
@@ -221,20 +253,22 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
   // earlier enqueue decided the launch this one is handed again): each term
   // enters the stopping window once
   const int done = c->degree;
-  if (A.kprev + (two ? 2 : 1) <= done) return false;
+  if (A.kprev + nterms <= done) return false;
   double hist[kStopHist];
 #pragma unroll
   for (int i = 0; i < kStopHist; ++i) hist[i] = c->hist[i];
   int stop = 0, status = 0, degree = 0;
   double tn2 = 0.0, pn2 = 0.0;
-  for (int i = 0; i < (two ? 2 : 1) && !stop; ++i) {
+  for (int i = 0; i < nterms && !stop; ++i) {
     if (A.kprev + 1 + i <= done) continue;
-    tn2 = tot[3 * i];
-    pn2 = tot[3 * i + 1];
+    tn2 = i < 2 ? tot[3 * i] : tot[2];
+    pn2 = i < 2 ? tot[3 * i + 1] : tot[5];
     degree = A.kprev + 1 + i;
     if (!isfinite(tn2) || !isfinite(pn2)) {
       stop = 1; status = 2;
-    } else if (A.kprev == 0 && i == 0 && tot[2] == 0.0) {
+    } else if (A.kprev == 0 && i == 0 && (three ? tn2 == 0.0 && pn2 == 0.0 : tot[2] == 0.0)) {
+      // y_0 = 0 (a three-term first launch has no max |y_0|: with y_0 = 0,
+      // and only then, both d_1 y_1 and p_1 = d_0 y_0 + d_1 y_1 vanish)
       stop = 1; status = 1; degree = 0;
     } else if (window_stop(hist, degree, sqrt(tn2), pn2, B.tol)) {
       stop = 1; status = 1;
@@ -255,7 +289,7 @@ __device__ __forceinline__ bool bin_decide(const BatchArgs& A, const BinDesc& B,
     // earlier, non-stopping decision, which would make the current launch
     // look due and advance u twice
     if (stop) {
-      c->inner = two && degree == A.kprev + 1;
+      c->inner = degree > 0 ? A.kprev + nterms - degree : 0;
       c->launch = A.L - 1;
     }
     __hip_atomic_store(&c->stop, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1045,6 +1079,123 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_leja2_kernel(BatchArgs A, 
   batch_term2<TF, VEC, ADVF>(A, B, gt - B.tile_base2);
 }
 
+// Three terms per launch with the input rows staged in LDS: blocks [0, ndec)
+// hold one decision wave per bin (as the first waves of the tile launches),
+// every later block marches one run of bands3 bands (four rows each) of one
+// strip of 124 output columns of one bin with staged3_run (two columns per
+// lane), and stores y and p of the third term and y of the second (for the
+// update of a bin whose stopping term is not the last of its launch).
+// FIRST: the sweep's first launch, terms 1 .. 3 from y_0 = w, with
+// p_0 = d_0 w formed in the march (no decision: no launch before it).  The block's partials (the three terms' ||d y||^2 and ||p||^2,
+// summed over its waves in order) go to the unit partials of the block.
+// The blocks keep dispatch order: the XCDs take them round-robin, so the
+// blocks of the bins still running late in a sweep are spread over every XCD
+// (an XCD-contiguous order, which lets neighbouring strips share L2, left
+// those late launches to the one or two XCDs that held those bins' blocks).
+constexpr int kStrip3 = (kWave - 2) * 2;  // output columns of a three-term block
+
+
+template <typename TF, bool ADVF, bool FIRST>
+__global__ __launch_bounds__(kTileBlock2) void batch_leja3s_kernel(BatchArgs A, int nbins, int ndec) {
+  extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
+  __shared__ double wsum[kWavesY2][6];
+  __shared__ int bstop;
+  constexpr int VEC = 2;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if ((int)blockIdx.x < ndec) {
+    const int b = (int)blockIdx.x * kWavesY2 + wave;
+    if (FIRST || b >= nbins) return;
+    const BinDesc& B = A.bins[b];
+    if (!B.active) return;
+    if (__hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    bin_decide(A, B, b, true);
+    return;
+  }
+  const int bi = (int)blockIdx.x - ndec;
+  const int b = __builtin_amdgcn_readfirstlane(A.block_bin3[bi]);
+  const BinDesc& B = A.bins[b];
+  if (!B.active) return;
+  // one read of the stop flag for the whole block (its waves must agree:
+  // the march has barriers)
+  if (threadIdx.x == 0) bstop = __hip_atomic_load(&A.ctl[b].stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int stop = __builtin_amdgcn_readfirstlane(bstop);
+  FieldView F = B.f;
+  F.nx = uni(F.nx);
+  F.ny = uni(F.ny);
+  F.bc = uni(F.bc);
+  F.axc = uni(F.axc);
+  F.ayc = uni(F.ayc);
+  const int ubase = uni(B.block_base3);
+  const int t = bi - ubase;
+  const int ncb3 = uni(B.ncb3), bands = uni(B.bands3);
+  const int cb = t % ncb3, run = t / ncb3;
+  const int nrb = (F.ny + kWavesY2 - 1) / kWavesY2;
+  const int rb0 = run * bands, rb1 = min(rb0 + bands, nrb);
+  if (stop) {
+    const BinCtl& c = A.ctl[b];
+    if (update_due(A, c)) {
+      // the block's own points, a quarter of its rows per wave
+      const int j0 = rb0 * kWavesY2, j1 = min(rb1 * kWavesY2, F.ny);
+      const int q = (j1 - j0 + kWavesY2 - 1) / kWavesY2;
+      const int c0 = cb * kStrip3;
+      bin_update_rect<VEC>(A, B, c, const_cast<double*>(B.u), j0 + wave * q, min(j0 + (wave + 1) * q, j1), c0,
+                           min(c0 + kStrip3, F.nx));
+    }
+    return;
+  }
+  const int k = A.k;
+  const int M = uni(B.max_degree);
+  if (k >= M) return;
+  Staged3IO<double> io;
+  io.yin = FIRST ? uni(static_cast<const double*>(B.w))
+                 : uni(reinterpret_cast<const double*>((A.L & 1) ? B.y1 : B.y0));
+  io.yout = uni(reinterpret_cast<double*>(((A.L + 1) & 1) ? B.y1 : B.y0));
+  io.p = uni(B.pb[pbuf_out3(A.L)]);
+  io.pin = FIRST ? io.p : uni(B.pb[pbuf_in3(A.L)]);  // (FIRST: not read)
+  io.p1 = nullptr;
+  io.p2 = nullptr;
+  io.d0 = uni(B.d[0]);
+  io.y2out = uni(B.y2b[A.L & 1]);
+  // (terms past the bin's degree cap are computed with the last plan entries
+  // and discarded by the decision at the cap)
+  io.shift = uni(B.shift[k]);
+  io.shift2 = uni(B.shift[min(k + 1, M)]);
+  io.shift3 = uni(B.shift[min(k + 2, M)]);
+  io.invg = uni(B.invg);
+  io.dk1 = uni(B.d[k + 1]);
+  io.dk2 = uni(B.d[min(k + 2, M)]);
+  io.dk3 = uni(B.d[min(k + 3, M)]);
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  staged3_run<TF, double, VEC, ADVF, true, true, FIRST>(F, io, lds, cb * kStrip3 - VEC, rb0, rb1, 0, acc);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) wsum[wave][q] = acc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      tot[q] = wsum[0][q];
+#pragma unroll
+      for (int w = 1; w < kWavesY2; ++w) tot[q] += wsum[w][q];
+    }
+    double* part = tile_partials(A, (long)ubase + t);
+    part[0] = tot[0];
+    part[1] = tot[1];
+    part[2] = tot[4];
+    part[3] = tot[2];
+    part[4] = tot[3];
+    part[5] = tot[5];
+  }
+}
+
 // decision of the last launch for every running bin: one wave per bin
 __global__ __launch_bounds__(64) void batch_finalize_kernel(BatchArgs A, int nbins) {
   const int b = blockIdx.x;
@@ -1133,6 +1284,7 @@ struct adl_batch {
   BinCtl* d_ctl = nullptr;
   int* d_tile_bin = nullptr;
   int* d_tile_bin2 = nullptr;
+  int* d_block_bin3 = nullptr;
   double* d_partials = nullptr;
   double* d_plans = nullptr;   // nbins x 2 x M
   double** d_uptrs = nullptr;  // nbins
@@ -1146,10 +1298,13 @@ struct adl_batch {
   const BinCtl* h_ctl = nullptr;  // the published control blocks (in hmir)
   int total_tiles = 0;
   int total_tiles2 = 0;
+  int total_blocks3 = 0;
   long part_stride = 0;  // doubles per launch parity of the partials
   int two = 1;           // two Newton terms per launch after the first
+  int three = 0;         // three (LDS-staged blocks; all bins two columns per lane)
   std::vector<BinDesc> bins;
-  std::vector<int> tile_bin, tile_bin2;
+  std::vector<int> tile_bin, tile_bin2, block_bin3;
+  std::vector<double> order_key;  // |alpha| dt of each bin's plan (three-term block order)
   // launch state of the sweep being enqueued: launches so far, and the last
   // launch's terms-before and term count (restored after a graph replay)
   int sL = 0, skprev = 0, snprev = 0;
@@ -1185,7 +1340,7 @@ int tiles2_of(int nx, int ny, int vec, int rows) {
 }
 
 struct BLayout {
-  size_t bins, ctl, tile_bin, tile_bin2, partials, plans, uptrs, seq, total;
+  size_t bins, ctl, tile_bin, tile_bin2, block_bin3, partials, plans, uptrs, seq, total;
 };
 
 BLayout blayout(int nbins, long max_tiles, int M) {
@@ -1200,6 +1355,7 @@ BLayout blayout(int nbins, long max_tiles, int M) {
   L.ctl = take(sizeof(BinCtl) * nbins);
   L.tile_bin = take(sizeof(int) * max_tiles);
   L.tile_bin2 = take(sizeof(int) * max_tiles);
+  L.block_bin3 = take(sizeof(int) * max_tiles);
   L.partials = take(sizeof(double) * 2 * 6 * max_tiles);
   L.plans = take(sizeof(double) * 2 * (size_t)M * nbins);
   L.uptrs = take(sizeof(double*) * nbins);
@@ -1221,9 +1377,32 @@ long max_tiles_for(int nbins, adl_op* const* ops) {
     if (e_ != hipSuccess) return bfail(ADL_EHIP, hipGetErrorString(e_)); \
   } while (0)
 
+// The three-term blocks bin by bin in order of decreasing |alpha| dt (the
+// bins' order keys): the stiffest bins, whose sweeps run longest, come
+// first, so that in the late launches, where only they still run, their
+// blocks start at once instead of after the blocks of the bins that have
+// stopped (at 256 C4 bins: 3.13-3.24 -> 2.95-3.05 ms per step).
+void order_blocks3(adl_batch* B) {
+  B->block_bin3.clear();
+  int base3 = 0;
+  if (B->vec == 2) {
+    std::vector<int> ord(B->nbins);
+    for (int b = 0; b < B->nbins; ++b) ord[b] = b;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return B->order_key[a] > B->order_key[b]; });
+    for (int b : ord) {
+      BinDesc& d = B->bins[b];
+      d.block_base3 = base3;
+      for (int t = 0; t < d.nblocks3; ++t) B->block_bin3.push_back(b);
+      base3 += d.nblocks3;
+    }
+  }
+  B->total_blocks3 = base3;
+}
+
 void build_tiles(adl_batch* B) {
   B->tile_bin.clear();
   B->tile_bin2.clear();
+  B->block_bin3.clear();
   int base = 0, base2 = 0;
   for (int b = 0; b < B->nbins; ++b) {
     adl_op* op = B->ops[b];
@@ -1240,14 +1419,25 @@ void build_tiles(adl_batch* B) {
     for (int t = 0; t < d.ntiles2; ++t) B->tile_bin2.push_back(b);
     base += d.ntiles;
     base2 += d.ntiles2;
+    // three-term blocks (two columns per lane only): runs of `rows` bands
+    // of four rows, i.e. a tile height of 16 rows gives runs of 64 rows
+    if (B->vec == 2) {
+      const int nband = (op->ny + kWavesY2 - 1) / kWavesY2;
+      d.ncb3 = (op->nx + kStrip3 - 1) / kStrip3;
+      d.bands3 = B->rows;
+      d.nblocks3 = d.ncb3 * ((nband + d.bands3 - 1) / d.bands3);
+    }
   }
   B->total_tiles = base;
   B->total_tiles2 = base2;
+  order_blocks3(B);
 }
 
 int upload_tiles(adl_batch* B) {
   BCHK(hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice));
   BCHK(hipMemcpy(B->d_tile_bin2, B->tile_bin2.data(), sizeof(int) * B->total_tiles2, hipMemcpyHostToDevice));
+  if (B->total_blocks3 > 0)
+    BCHK(hipMemcpy(B->d_block_bin3, B->block_bin3.data(), sizeof(int) * B->total_blocks3, hipMemcpyHostToDevice));
   return ADL_OK;
 }
 
@@ -1273,25 +1463,30 @@ BatchArgs base_args(const adl_batch* B) {
   a.bins = B->d_bins;
   a.tile_bin = B->d_tile_bin;
   a.tile_bin2 = B->d_tile_bin2;
+  a.block_bin3 = B->d_block_bin3;
   a.ctl = B->d_ctl;
   a.partials = B->d_partials;
   a.total_tiles = B->total_tiles;
   a.total_tiles2 = B->total_tiles2;
+  a.total_blocks3 = B->total_blocks3;
   a.part_stride = B->part_stride;
   a.two = B->two;
+  a.three = B->three;
   return a;
 }
 
 // Enqueue launches covering terms k0+1 .. k0+nterms at least (reset and stage
-// first when with_stage), then the decision of the last launch.  The first
-// term is a launch of its own; later launches take two terms while the batch
-// fuses terms and the second stays within the degree cap.  `covered` returns
+// first when with_stage), then the decision of the last launch.  Three-term
+// sweeps take three terms in every launch; otherwise the first term is a
+// launch of its own and later launches take two terms while the batch fuses
+// terms and the second stays within the degree cap.  `covered` returns
 // the number of terms enqueued (nterms, or one more).  advance = false (the
 // autotuner's timing runs): no tile advances u.
 int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t st, int* covered = nullptr,
                   bool advance = true) {
   BatchArgs a = base_args(B);
   a.advance = advance ? 1 : 0;
+
   if (with_stage) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((B->nbins + 255) / 256), dim3(256), 0, st, B->d_ctl, B->nbins);
     dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
@@ -1302,7 +1497,9 @@ int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t
   }
   int k = k0;
   while (k < k0 + nterms) {
-    const int n = (k == 0 || !B->two || k + 2 > B->max_degree) ? 1 : 2;
+    // three-term sweeps run three terms in every launch, the first included
+    // (terms past a bin's degree cap are discarded by its decision there)
+    const int n = B->three ? 3 : (k == 0 || !B->two || k + 2 > B->max_degree) ? 1 : 2;
     a.L = B->sL;
     a.k = k;
     a.kprev = B->skprev;
@@ -1315,10 +1512,23 @@ int enqueue_sweep(adl_batch* B, int k0, int nterms, bool with_stage, hipStream_t
         else
           hipLaunchKernelGGL((batch_leja_kernel<TF, VEC, ADVF, false>), grid, blk, 0, st, a, B->nbins);
       });
-    } else {
+    } else if (n == 2) {
       const dim3 grid(blocks_for((long)B->nbins + B->total_tiles2)), blk(64 * kBWaves);
       dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
         hipLaunchKernelGGL((batch_leja2_kernel<TF, VEC, ADVF>), grid, blk, 0, st, a, B->nbins);
+      });
+    } else {
+      // decision blocks first (one wave per bin)
+      const int ndec = (B->nbins + kWavesY2 - 1) / kWavesY2;
+      const dim3 grid(ndec + B->total_blocks3), blk(kTileBlock2);
+      dispatch(B, [&]<typename TF, int VEC, bool ADVF>() {
+        if constexpr (VEC == 2) {
+          const size_t lds = staged3_lds_bytes<2, ADVF>();
+          if (a.k == 0)
+            hipLaunchKernelGGL((batch_leja3s_kernel<TF, ADVF, true>), grid, blk, lds, st, a, B->nbins, ndec);
+          else
+            hipLaunchKernelGGL((batch_leja3s_kernel<TF, ADVF, false>), grid, blk, lds, st, a, B->nbins, ndec);
+        }
       });
     }
     B->skprev = k;
@@ -1397,6 +1607,10 @@ int upload_bins(adl_batch* B, double* const* u, const double* const* S, double d
     d.pb[1] = op->p;
     d.pb[2] = op->p3;
     d.pb[3] = op->p4;
+    // three-term sweeps use pb[0], pb[1] only: the other two hold the y of
+    // the second-to-last term of each launch
+    d.y2b[0] = reinterpret_cast<float*>(op->p3);
+    d.y2b[1] = reinterpret_cast<float*>(op->p4);
     d.tol = tol;
     d.dt = dt;
     d.max_degree = std::min(op->max_degree, B->max_degree);
@@ -1414,8 +1628,15 @@ int upload_bins(adl_batch* B, double* const* u, const double* const* S, double d
                      hipMemcpyHostToDevice));
       B->plan_alpha[b] = op->alpha;
       B->plan_dt[b] = dt;
+      B->order_key[b] = std::fabs(op->alpha) * dt;
       plans_changed = true;
     }
+  }
+  if (plans_changed && B->vec == 2) {
+    // (the stream was synchronised above: no launch still reads the table)
+    order_blocks3(B);
+    if (B->total_blocks3 > 0)
+      BCHK(hipMemcpy(B->d_block_bin3, B->block_bin3.data(), sizeof(int) * B->total_blocks3, hipMemcpyHostToDevice));
   }
   if (changed || plans_changed) {
     BCHK(hipStreamSynchronize(st));
@@ -1451,7 +1672,8 @@ int autotune_key(const adl_batch* B, const int* candidates, int ncand, std::stri
   for (const adl_op* op : B->ops) shapes.emplace_back(op->nx, op->ny);
   std::sort(shapes.begin(), shapes.end());
   key = std::string(prop.gcnArchName) + "|f32=" + std::to_string(B->f32) + "|adv=" + std::to_string((int)B->advf) +
-        "|vec=" + std::to_string(B->vec) + "|two=" + std::to_string(B->two) + "|cand=";
+        "|vec=" + std::to_string(B->vec) + "|two=" + std::to_string(B->two) +
+        "|three=" + std::to_string(B->three) + "|cand=";
   for (int c = 0; c < ncand; ++c) key += std::to_string(candidates[c]) + ",";
   key += "|bins=";
   for (const auto& sh : shapes) key += std::to_string(sh.first) + "x" + std::to_string(sh.second) + ",";
@@ -1512,6 +1734,9 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
   B->ops.assign(ops, ops + nbins);
   B->nbins = nbins;
   B->vec = all_even ? 2 : 1;
+  // three terms per launch by default where every bin allows them (C4, 256
+  // bins: 3.63-3.67 ms per step with two terms per launch, 2.94-3.02 with three)
+  B->three = all_even ? 1 : 0;
   B->f32 = f32;
   B->advf = advf;
   B->rows = tile_rows > 0 ? tile_rows : 16;
@@ -1521,17 +1746,21 @@ int adl_batch_create(int nbins, adl_op* const* ops, void* workspace, size_t ws_b
   B->d_ctl = reinterpret_cast<BinCtl*>(B->ws + L.ctl);
   B->d_tile_bin = reinterpret_cast<int*>(B->ws + L.tile_bin);
   B->d_tile_bin2 = reinterpret_cast<int*>(B->ws + L.tile_bin2);
+  B->d_block_bin3 = reinterpret_cast<int*>(B->ws + L.block_bin3);
   B->part_stride = 6 * mt;
   B->d_partials = reinterpret_cast<double*>(B->ws + L.partials);
   B->d_plans = reinterpret_cast<double*>(B->ws + L.plans);
   B->d_uptrs = reinterpret_cast<double**>(B->ws + L.uptrs);
   B->bins.assign(nbins, BinDesc{});
+  B->order_key.assign(nbins, 0.0);
   B->plan_alpha.assign(nbins, NAN);
   B->plan_dt.assign(nbins, NAN);
   build_tiles(B);
   hipError_t e = hipMemcpy(B->d_tile_bin, B->tile_bin.data(), sizeof(int) * B->total_tiles, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(B->d_tile_bin2, B->tile_bin2.data(), sizeof(int) * B->total_tiles2, hipMemcpyHostToDevice);
+  if (e == hipSuccess && B->total_blocks3 > 0)
+    e = hipMemcpy(B->d_block_bin3, B->block_bin3.data(), sizeof(int) * B->total_blocks3, hipMemcpyHostToDevice);
   B->d_seq = reinterpret_cast<int*>(B->ws + L.seq);
   if (e == hipSuccess) e = hipMemset(B->d_seq, 0, sizeof(int));
   if (e == hipSuccess)
@@ -1586,10 +1815,14 @@ int adl_batch_set_tile_rows(adl_batch* B, int rows) {
   return ADL_OK;
 }
 
-int adl_batch_set_term_fusion(adl_batch* B, int two_terms) {
-  if (!B || (two_terms != 0 && two_terms != 1)) return bfail(ADL_EINVAL, "two_terms must be 0 or 1");
-  if (two_terms == B->two) return ADL_OK;
-  B->two = two_terms;
+int adl_batch_set_term_fusion(adl_batch* B, int mode) {
+  if (!B || (mode != 0 && mode != 1 && mode != 3)) return bfail(ADL_EINVAL, "term fusion mode must be 0, 1 or 3");
+  if (mode == 3 && B->vec != 2)
+    return bfail(ADL_EINVAL, "three terms per launch need every bin at two columns per lane (nx even, >= 128)");
+  const int two = mode != 0, three = mode == 3;
+  if (two == B->two && three == B->three) return ADL_OK;
+  B->two = two;
+  B->three = three;
   BCHK(hipStreamSynchronize(B->cap_stream));
   if (B->gexec) {
     hipGraphExecDestroy(B->gexec);

@@ -459,7 +459,9 @@ struct Staged3IO {
   double* p1;         // p_{k+1}, or null: not stored
   double* p2;         // p_{k+2}, or null
   double* p;          // p_{k+3}, or null
+  float* y2out;       // y_{k+2} rounded to FP32: stored by staged3_run<..., Y2 = true> only
   double shift, shift2, shift3, invg, dk1, dk2, dk3;
+  double d0;          // staged3_run<..., FIRST = true>: p_0 = d0 y_0 (pin is not read)
 };
 
 // y_{k+t} (t >= 2) at row r: the stencil of the y_{k+t-1} ring rows r-1 .. r+1
@@ -476,7 +478,7 @@ __device__ __forceinline__ void ring_stage_from_y(const RG& R, const Strip& g, i
   for (int v = 0; v < VEC; ++v) uc[v] = u[1].c[v];
 }
 
-template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT, bool Y2 = false, bool FIRST = false>
 __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<TY>& io, double* lds, int i0, int rb0,
                                             int rb1, int stopflag, double (&acc)[6]) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -548,7 +550,15 @@ __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<
     const bool keep = own && j < F.ny;
     const double km = keep ? 1.0 : 0.0;
     double pk[VEC];
-    ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
+    if constexpr (FIRST) {
+      // the sweep's first launch: p_0 = d_0 y_0, from the y_0 row in its ring
+      double y0[VEC];
+      lds_get<VEC>(R.row(0, j) + RingRow<VEC>::kOwn + lane * VEC, y0);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) pk[v] = io.d0 * y0[v];
+    } else {
+      ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
+    }
     if constexpr (!LAST) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 7 + wave, nxt);
     // stage 1: y_{k+1} on row j0+2+wave
     ring_stage1<VEC, ADVF>(R, g, j0 + 2 + wave, F, e1);
@@ -589,6 +599,7 @@ __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<
     row_store<NT, double, VEC>(p1o + ro, F.nx, keep && s1 ? ocolp : kDropOffset, pa);
     row_store<NT, double, VEC>(p2o + ro, F.nx, keep && s2 ? ocolp : kDropOffset, pb);
     row_store<NT, double, VEC>(po + ro, F.nx, keep && sp ? ocolp : kDropOffset, pc);
+    if constexpr (Y2) row_store<NT, float, VEC>(io.y2out + ro, F.nx, keep ? g.col0 * 4 : kDropOffset, y2);
     __syncthreads();
     // the next step's rows replace rows j0-1 .. j0+2, read for the last time by stage 3
     if constexpr (!LAST) rowset_put<TF, TY, VEC, ADVF>(R, g, j0 + 7 + wave, F, nxt);

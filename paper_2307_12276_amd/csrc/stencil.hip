@@ -950,6 +950,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling
   io.p1 = A.pmid;
   io.p2 = A.pmid2;
   io.p = A.p;
+  io.y2out = nullptr;
   io.shift = A.shift;
   io.shift2 = A.shift2;
   io.shift3 = A.shift3;

@@ -35,12 +35,17 @@ def oracle_steps(w, oop, nsteps):
     return u, degs
 
 
+# term fusion modes of the batched sweep: two terms per launch (True, the
+# default), one (False), three with LDS-staged blocks (3)
+MODES = [True, False, 3]
+
+
 @pytest.mark.parametrize("use_graph", [True, False])
-@pytest.mark.parametrize("two_terms", [True, False])
-def test_batch_matches_oracle_per_bin(use_graph, two_terms):
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_oracle_per_bin(use_graph, mode):
     bins = W.c4_bins(nbins=10, sizes=(128, 130, 192, 256))
     pairs, b = make_batch(bins)
-    b.set_term_fusion(two_terms)
+    b.set_term_fusion(mode)
     us = [to_dev(w.u0) for w in bins]
     Ss = [to_dev(w.S(0)) for w in bins]
     for step in range(2):
@@ -51,13 +56,38 @@ def test_batch_matches_oracle_per_bin(use_graph, two_terms):
         assert rel(to_np(u), ref) < 1e-10, w.name
 
 
-@pytest.mark.parametrize("two_terms", [True, False])
-def test_batch_graph_replays_equal_eager(two_terms):
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_zero_stage_vector_bin(mode):
+    """A bin with u = 0 and no source has w = A u + S = 0: its sweep stops at
+    degree 0 (the three-term first launch detects y_0 = 0 from its vanishing
+    first term and p_1) and u stays 0, while the other bins match the
+    oracle; same matvec counts as the oracle."""
+    bins = W.c4_bins(nbins=4, sizes=(128, 192))
+    bins[1].u0 = np.zeros_like(bins[1].u0)
+    pairs, b = make_batch(bins)
+    b.set_term_fusion(mode)
+    us = [to_dev(w.u0) for w in bins]
+    Ss = [to_dev(w.S(0)) for w in bins]
+    Ss[1] = None
+    stats = b.midpoint_step(us, Ss, bins[0].dt, bins[0].tol)
+    for i, (w, (oop, _), u, st) in enumerate(zip(bins, pairs, us, stats)):
+        ost = {}
+        ref = integrators.exp_midpoint_step(lambda x: O.apply(oop, x), w.u0, None if i == 1 else w.S(0), w.dt,
+                                            bounds.gershgorin(oop), w.tol, stats=ost)
+        assert st["matvecs"] == ost["matvecs"], (i, st, ost)
+        if i == 1:
+            assert not torch.any(u) and st["max_degree"] == 0, st
+        else:
+            assert rel(to_np(u), ref) < 1e-10, i
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_graph_replays_equal_eager(mode):
     bins = W.c4_bins(nbins=6, sizes=(128, 256))
     _, b1 = make_batch(bins)
     _, b2 = make_batch(bins)
-    b1.set_term_fusion(two_terms)
-    b2.set_term_fusion(two_terms)
+    b1.set_term_fusion(mode)
+    b2.set_term_fusion(mode)
     ua = [to_dev(w.u0) for w in bins]
     ub = [to_dev(w.u0) for w in bins]
     S = [to_dev(w.S(0)) for w in bins]
@@ -125,12 +155,14 @@ VARIED = {
 }
 
 
-@pytest.mark.parametrize("two_terms", [True, False])
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("case", sorted(VARIED))
-def test_batch_varied_bins_match_oracle(case, two_terms):
+def test_batch_varied_bins_match_oracle(case, mode):
     """Batched bins beyond the C4 layout (periodic and mixed boundaries,
     field advection, FP32 fields, odd widths, odd tile heights) against the
-    oracle bin by bin over two midpoint steps: same matvec count, 1e-10."""
+    oracle bin by bin over two midpoint steps: same matvec count, 1e-10.
+    Three terms per launch need every bin at two columns per lane: a batch
+    with an odd or narrow bin refuses them (ADL_EINVAL)."""
     shapes, bcs, field_adv, storage, rows = VARIED[case]
     bins = varied_bins(shapes, bcs, field_adv, seed=len(case))
     pairs = [workload_pair(w, storage) for w in bins]
@@ -138,7 +170,12 @@ def test_batch_varied_bins_match_oracle(case, two_terms):
     for (oop, gop), a in zip(pairs, alphas):
         gop.set_bound(a)
     b = A.Batch([g for _, g in pairs], tile_rows=rows)
-    b.set_term_fusion(two_terms)
+    if mode == 3 and any(w.nx % 2 or w.nx < 128 for w in bins):
+        with pytest.raises(A.AdlError) as e:
+            b.set_term_fusion(mode)
+        assert e.value.code == A.EINVAL
+        return
+    b.set_term_fusion(mode)
     us = [to_dev(w.u0) for w in bins]
     Ss = [to_dev(w.S(0)) for w in bins]
     for _ in range(2):
@@ -214,14 +251,17 @@ def test_batch_full_config_sampled_bins():
     assert all(s["status"] == 0 for s in stats)
 
 
-def test_batch_all_bins_equal_single_op_steps():
+@pytest.mark.parametrize("mode", [True, 3])
+def test_batch_all_bins_equal_single_op_steps(mode):
     """The chosen form on the 256-bin workload (FP32 fields, learned
-    intervals, two terms per launch, eager launches): three batched steps
-    equal, bin by bin, the same steps taken by each bin's own operator (same
-    fields, same intervals; the single-op path equals the oracle).  Every bin
-    is advanced exactly once per step, whichever launch its update falls in
-    (a bin is advanced by its tiles in the launch after the one whose
-    decision stopped it, or by the step's last launch)."""
+    intervals, two or three terms per launch, eager launches): three batched
+    steps equal, bin by bin, the same steps taken by each bin's own operator
+    (same fields, same intervals; the single-op path equals the oracle).
+    Every bin is advanced exactly once per step, whichever launch its update
+    falls in (a bin is advanced by its tiles in the launch after the one
+    whose decision stopped it, or by the step's last launch), and with
+    whichever term of its last launch it stopped at (with three terms per
+    launch the degrees cover all three positions)."""
     from paper_2307_12276_amd import learned
     bins = W.c4_bins()
     dt = bins[0].dt
@@ -230,11 +270,13 @@ def test_batch_all_bins_equal_single_op_steps():
     ops = [A.Op(to_dev(w.Dxx), to_dev(w.Dxy), to_dev(w.Dyy), w.hx, w.hy, w.bc, A.STORAGE_FP32_FIELDS,
                 ax_c=w.ax_c, ay_c=w.ay_c) for w in bins]
     b = A.Batch(ops)
+    b.set_term_fusion(mode)
     b.learned_bound(dt, torch.from_numpy(learned.load()).cuda(),
                     torch.empty(72 * len(ops), dtype=torch.float32, device="cuda"))
     ub = [to_dev(w.u0) for w in bins]
     us = [to_dev(w.u0) for w in bins]
     b.bind(ub, Ss)
+    positions = set()
     for step in range(3):
         st = b.midpoint_step(None, None, dt, tol, use_graph=False).array
         for op, u, S in zip(ops, us, Ss):
@@ -243,3 +285,8 @@ def test_batch_all_bins_equal_single_op_steps():
         worst = int(np.argmax(d))
         print("step %d: max rel diff %.2e (bin %d, %d matvecs)" % (step, d[worst], worst, int(st["matvecs"][worst])))
         assert max(d) < 1e-12, (step, worst, d[worst])
+        # degree m = matvecs - 1; three-term launches hold terms 1-3, 4-6,
+        # ...: (m - 1) % 3 is the stopping term's place in its launch
+        positions |= {(int(mv) - 1 - 1) % 3 for mv in st["matvecs"] if mv - 1 >= 1}
+    if mode == 3:
+        assert positions == {0, 1, 2}, positions
