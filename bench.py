@@ -114,7 +114,7 @@ def traffic_record():
 
 
 def measured_traffic():
-    """HBM bytes per two-term Newton-Leja launch of the 4096^2 workload from
+    """HBM bytes per three-term Newton-Leja launch of the 4096^2 workload from
     the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the
     kernel sources have changed since those counters were taken."""
     kv = traffic_record()
