@@ -227,11 +227,12 @@ def sweep_and_step_1024(storage, mode):
 @pytest.mark.parametrize("storage", [A.STORAGE_FP64, A.STORAGE_FP32_FIELDS])
 def test_sweeps_from_2pow20_points_match_oracle(oracle, storage):
     """2^20 points (1024^2): the default mode runs three Newton terms per
-    launch with LDS-staged rows (leja3s_kernel; mode 5 forces it), mode 2
-    two terms with LDS-staged rows (leja2s_kernel), mode 3 two with register
-    frames: the phi_1 sweep and one two-stage step equal the oracle (on the
-    FP32-rounded fields for storage 1) to 1e-10 with the same matvec count,
-    in every mode."""
+    launch with LDS-staged rows (leja3s_kernel; mode 5 forces it), mode 6
+    four with LDS-staged rows (leja4s_kernel), mode 2 two terms with
+    LDS-staged rows (leja2s_kernel), mode 3 two with register frames: the
+    phi_1 sweep and one two-stage step equal the oracle (on the FP32-rounded
+    fields for storage 1) to 1e-10 with the same matvec count, in every
+    mode."""
     f32 = storage == A.STORAGE_FP32_FIELDS
     po, alpha, mvo, Ko = oracle("sweep1024_f32" if f32 else "sweep1024")
     uo, alpha_q, mvq = oracle("quad1024_f32" if f32 else "quad1024")
