@@ -1167,7 +1167,8 @@ __global__ __launch_bounds__(kTileBlock2) void batch_leja3s_kernel(BatchArgs A, 
   io.dk2 = uni(B.d[min(k + 2, M)]);
   io.dk3 = uni(B.d[min(k + 3, M)]);
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  staged3_run<TF, double, VEC, ADVF, true, true, FIRST>(F, io, lds, cb * kStrip3 - VEC, rb0, rb1, 0, acc);
+  double amax = 0.0;  // (the decision tests y_0 = 0 from the first term and p_1)
+  staged3_run<TF, double, VEC, ADVF, true, true, FIRST>(F, io, lds, cb * kStrip3 - VEC, rb0, rb1, 0, acc, amax);
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
 #pragma unroll

@@ -504,13 +504,17 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   // launch for the remainder), so that a sweep stopping at the predicted
   // degree computes no terms past it
   auto plan_terms = [&](int kcov, int target) {
-    if (kcov == 0) return 1;
     auto aug = [&](int n) {  // the augmented column enters one of terms kcov+1 .. kcov+n
       if (!w2) return false;
       for (int i = 0; i < n; ++i)
         if (P.s[kcov + i] != 0.0) return true;
       return false;
     };
+    // the first launch: terms 1 .. 3 from y_0 = v in the three-term form
+    // (FP64 Newton vectors, no augmented column in them), else term 1 alone
+    // (4096^2 headline steps of 72 terms: 24 launches instead of 1 + 24 and
+    // a replay)
+    if (kcov == 0) return (three && !ys32 && 3 <= maxdeg && !aug(3)) ? 3 : 1;
     const int lim = four ? std::min(target, maxdeg) : maxdeg;
     if (four && kcov + 4 <= lim && !aug(4)) return 4;
     if (fours && kcov + 4 <= maxdeg && !aug(4)) return 4;
@@ -518,6 +522,11 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
     const bool two = fuse && kcov + 2 <= lim && !aug(2);
     return two ? 2 : 1;
   };
+  // three terms per launch from the first one: the first chunk covers the
+  // last degree itself, rounded up to whole launches (one term more would
+  // cost a whole launch whenever the last degree ends a launch: 4096^2
+  // headline steps of degree 72, 24 launches instead of 25)
+  if (P.last_degree > 0 && plan_terms(0, maxdeg) == 3) predicted = std::min(P.last_degree, maxdeg);
   // the chunk targets: the first chunk ends at the predicted degree, each
   // later one max(8, kcov / 4) terms on, capped at the degree limit
   auto next_target = [&](int kcov) {
@@ -694,17 +703,18 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         // the sweep stopped inside launch Ls: replay it on its inputs (y in
         // ybuf3[Ls mod 3], p in pbuf[(Ls + 2) mod 3], both intact) storing p
         // of term m only, into p_out unless p_out holds its p input
-        const double* pin = pbuf[(Ls + 2) % 3];
-        double* dst = pin == p_out ? pbuf[Ls % 3] : p_out;
+        // (the first launch: y_0 = v, no p input)
         const int k = lk[Ls], n = ln[Ls], t = m - k;
+        const double* pin = k == 0 ? nullptr : pbuf[(Ls + 2) % 3];
+        double* dst = pin == p_out ? pbuf[Ls % 3] : p_out;
         a.ev_start = a.ev_stop = nullptr;
         a.k = k;
         a.nterms = n;
-        a.first = 0;
+        a.first = k == 0;
         a.w2 = nullptr;
-        a.yin = ybuf3[Ls % 3];
+        a.yin = k == 0 ? (const void*)v : ybuf3[Ls % 3];
         a.yout = nullptr;
-        a.yin_f32 = ys32;
+        a.yin_f32 = k > 0 && ys32;
         a.pin = pin;
         a.p = n == t ? dst : nullptr;
         a.pmid = t == 1 ? dst : nullptr;

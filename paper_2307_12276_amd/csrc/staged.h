@@ -480,7 +480,7 @@ __device__ __forceinline__ void ring_stage_from_y(const RG& R, const Strip& g, i
 
 template <typename TF, typename TY, int VEC, bool ADVF, bool NT, bool Y2 = false, bool FIRST = false>
 __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<TY>& io, double* lds, int i0, int rb0,
-                                            int rb1, int stopflag, double (&acc)[6]) {
+                                            int rb1, int stopflag, double (&acc)[6], double& amax) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   const int W = kWave * VEC;
@@ -551,11 +551,15 @@ __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<
     const double km = keep ? 1.0 : 0.0;
     double pk[VEC];
     if constexpr (FIRST) {
-      // the sweep's first launch: p_0 = d_0 y_0, from the y_0 row in its ring
+      // the sweep's first launch: p_0 = d_0 y_0, from the y_0 row in its
+      // ring; amax = max |y_0| over the kept points (the zero-vector test)
       double y0[VEC];
       lds_get<VEC>(R.row(0, j) + RingRow<VEC>::kOwn + lane * VEC, y0);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) pk[v] = io.d0 * y0[v];
+      for (int v = 0; v < VEC; ++v) {
+        pk[v] = io.d0 * y0[v];
+        amax = keep ? nanmax(amax, fabs(y0[v])) : amax;
+      }
     } else {
       ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
     }

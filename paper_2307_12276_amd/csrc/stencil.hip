@@ -30,6 +30,8 @@
 #include "bounds.h"
 #include "staged.h"
 
+#include <type_traits>
+
 #include <hip/hip_ext.h>
 
 #include <cmath>
@@ -930,13 +932,21 @@ __global__ __launch_bounds__(kTileBlock2) void leja2s_kernel(FieldView F, Tiling
 // Three Newton terms per launch (k >= 1) with the input rows staged in LDS
 // (staged3_run in staged.h), on the two-term tiling with two columns per
 // lane: the strips, bands and runs of leja2s_kernel.
-template <typename TF, typename TY, bool ADVF, bool NT>
+template <typename TF, typename TY, bool ADVF, bool NT, bool FIRST>
 __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
   constexpr int VEC = 2;
   const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
   if (L == 0) {
-    if (!A.replay) leja_decide(A);
+    if (FIRST) {
+      // a new sweep: clear the control block (no block of this launch reads it)
+      if (!A.replay && threadIdx.x == 0) {
+        Ctl c{};
+        *A.ctl = c;
+      }
+    } else if (!A.replay) {
+      leja_decide(A);
+    }
     return;
   }
   const int b = L - 1;
@@ -946,7 +956,9 @@ __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling
   Staged3IO<TY> io;
   io.yin = reinterpret_cast<const TY*>(A.yin);
   io.yout = reinterpret_cast<TY*>(A.yout);
-  io.pin = A.pin;
+  // (the first launch reads no p_k: p_0 = d_0 y_0 is formed in the march;
+  // its pin is only the base of the stores it drops)
+  io.pin = FIRST ? reinterpret_cast<const double*>(A.yin) : A.pin;
   io.p1 = A.pmid;
   io.p2 = A.pmid2;
   io.p = A.p;
@@ -958,12 +970,16 @@ __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling
   io.dk1 = A.dk1;
   io.dk2 = A.dk2;
   io.dk3 = A.dk3;
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  staged3_run<TF, TY, VEC, ADVF, NT>(
+  io.d0 = A.d0;
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double (&acc6)[6] = *reinterpret_cast<double(*)[6]>(acc);
+  staged3_run<TF, TY, VEC, ADVF, NT, false, FIRST>(
       F, io, lds, cb * (kWave - 2) * VEC - VEC, rb0, rb1,
-      A.replay ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), acc);
-  // block partials: term t (0, 1, 2) at rows 3t (||d y||^2), 3t + 1 (||p||^2), 3t + 2 (0)
-  block_allreduce<6, 6>(acc);
+      (FIRST || A.replay) ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), acc6,
+      acc[6]);
+  // block partials: term t (0, 1, 2) at rows 3t (||d y||^2), 3t + 1 (||p||^2),
+  // 3t + 2 (0; for the first term of a first launch max |y_0|, the zero test)
+  block_allreduce<7, 6>(acc);
   if (threadIdx.x == 0 && !A.replay) {
     double* part = A.partials + (long)A.slot * A.slot_stride;
     const int nb = T.nblocks;
@@ -971,7 +987,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling
     for (int t = 0; t < 3; ++t) {
       part[(3L * t) * nb + b] = acc[2 * t];
       part[(3L * t + 1) * nb + b] = acc[2 * t + 1];
-      part[(3L * t + 2) * nb + b] = 0.0;
+      part[(3L * t + 2) * nb + b] = t == 0 ? acc[6] : 0.0;
     }
   }
 }
@@ -1369,14 +1385,26 @@ hipError_t launch_leja4_step(const FieldView& f, const Tiling& t, const LejaArgs
   return hipGetLastError();
 }
 
-template <typename TF, typename TY, bool ADVF, bool NT>
-static void leja3s_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+template <typename TF, typename TY, bool ADVF, bool NT, bool FIRST>
+static void leja3s_launch_k(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
   const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock2);
   const size_t lds = staged3_lds_bytes<2, ADVF>();
   if (a.ev_start)
-    hipExtLaunchKernelGGL((leja3s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
+    hipExtLaunchKernelGGL((leja3s_kernel<TF, TY, ADVF, NT, FIRST>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f,
+                          t, a);
   else
-    hipLaunchKernelGGL((leja3s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, f, t, a);
+    hipLaunchKernelGGL((leja3s_kernel<TF, TY, ADVF, NT, FIRST>), grid, blk, lds, st, f, t, a);
+}
+
+template <typename TF, typename TY, bool ADVF, bool NT>
+static void leja3s_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if constexpr (std::is_same_v<TY, double>) {
+    if (a.first) {
+      leja3s_launch_k<TF, TY, ADVF, NT, true>(f, t, a, st);
+      return;
+    }
+  }
+  leja3s_launch_k<TF, TY, ADVF, NT, false>(f, t, a, st);
 }
 
 template <typename TF, typename TY, bool NT>
@@ -1386,12 +1414,14 @@ static void leja3s_dispatch(const FieldView& f, const Tiling& t, const LejaArgs&
 }
 
 hipError_t launch_leja3_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  if (a.first || a.k < 1 || a.nterms != 3 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || t.vec != 2)
+  if (a.nterms != 3 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || t.vec != 2) return hipErrorInvalidValue;
+  // the first launch (terms 1 .. 3 from y_0 = v, FP64 Newton vectors only) or a later one
+  if (a.first ? (a.k != 0 || a.ystore_f32 || a.decide_only || a.pin != nullptr) : a.k < 1)
     return hipErrorInvalidValue;
   if (!a.decide_only) {
     // p_k is read while the stored p outputs (at least one) are written: all distinct
     const double* o[4] = {a.pin, a.pmid, a.pmid2, a.p};
-    if (a.pin == nullptr || (!a.pmid && !a.pmid2 && !a.p)) return hipErrorInvalidValue;
+    if ((!a.first && a.pin == nullptr) || (!a.pmid && !a.pmid2 && !a.p)) return hipErrorInvalidValue;
     for (int i = 1; i < 4; ++i)
       for (int j = 0; j < i; ++j)
         if (o[i] != nullptr && o[i] == o[j]) return hipErrorInvalidValue;

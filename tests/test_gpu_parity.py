@@ -176,11 +176,17 @@ def test_gauss_quad2_and_time_dependent_source():
     assert rel(to_np(ug), u) < 1e-10
 
 
-def test_zero_vector_degree_zero():
-    w = W.c1_periodic_constant(n=64)
+@pytest.mark.parametrize("n,mode", [(64, 1), (128, 5), (128, 6)])
+def test_zero_vector_degree_zero(n, mode):
+    """v = 0 gives 0 with degree 0 (no matvec), whichever launch holds the
+    first term: a one-term launch (mode 1 at 64^2), or the first launch of
+    three (mode 5, which also runs terms 2 and 3 there) or of one then four
+    (mode 6)."""
+    w = W.c1_periodic_constant(n=n)
     oop, gop = workload_pair(w)
     gop.set_bound(-1000.0)
-    z = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    gop.set_term_fusion(mode)
+    z = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     out = torch.full_like(z, 7.0)
     st = gop.leja_phi(1, 1e-3, z, out, 1e-10)
     assert st["matvecs"] == 0 and float(out.abs().max()) == 0.0
