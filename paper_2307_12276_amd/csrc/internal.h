@@ -197,9 +197,10 @@ hipError_t launch_leja2_step(const FieldView& f, const Tiling& t, const LejaArgs
 // (frame: lanes at each strip end whose outputs are not stored -- 1 for the
 // two- and three-term kernels, 2 for the four-term staged kernel)
 Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint = 0, int max_blocks = kMaxGrid2, int frame = 1);
-// three-term launch (terms k+1 .. k+3; k >= 1) with the input rows staged in
-// LDS, on a two-term tiling with two columns per lane; the launch's block
-// partials take 9 x nblocks values of its slot
+// three-term launch (terms k+1 .. k+3; k = 0 with a.first: y_0 = v, FP64
+// Newton vectors, no augmented column) with the input rows staged in LDS, on
+// a two-term tiling with two columns per lane; the launch's block partials
+// take 9 x nblocks values of its slot
 hipError_t launch_leja3_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // four-term launch (terms k+1 .. k+4; k >= 1) with the input rows staged in
 // LDS, on a tiling of strips of 60*VEC output columns with two columns per

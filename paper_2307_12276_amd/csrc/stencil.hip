@@ -929,9 +929,13 @@ __global__ __launch_bounds__(kTileBlock2) void leja2s_kernel(FieldView F, Tiling
   }
 }
 
-// Three Newton terms per launch (k >= 1) with the input rows staged in LDS
-// (staged3_run in staged.h), on the two-term tiling with two columns per
-// lane: the strips, bands and runs of leja2s_kernel.
+// Three Newton terms per launch with the input rows staged in LDS
+// (staged3_run in staged.h), on its own tiling of strips of 62*VEC output
+// columns with two columns per lane (the strips of leja2s_kernel, fewer and
+// longer runs).  FIRST: the sweep's first launch, terms 1 .. 3 from y_0 = v
+// in FP64 (no augmented column among them): block 0 clears the control
+// block instead of deciding, p_0 = d_0 y_0 is formed in the march, and the
+// first term's third partial row holds max |y_0| (the zero-vector test).
 template <typename TF, typename TY, bool ADVF, bool NT, bool FIRST>
 __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
