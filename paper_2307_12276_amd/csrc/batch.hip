@@ -1093,6 +1093,10 @@ __global__ __launch_bounds__(64 * kBWaves) void batch_leja2_kernel(BatchArgs A, 
 // (an XCD-contiguous order, which lets neighbouring strips share L2, left
 // those late launches to the one or two XCDs that held those bins' blocks).
 constexpr int kStrip3 = (kWave - 2) * 2;  // output columns of a three-term block
+// whether a bin's three-term blocks are whole-width strips: Dirichlet bins
+// of 128 columns, whose ghost columns on both sides stand in for the frame
+// lanes (one strip instead of two, half the work of such bins)
+__host__ __device__ inline bool whole_strip(int bc, int nx) { return bc != BC_PERIODIC && nx == 2 * kWave; }
 
 
 template <typename TF, bool ADVF, bool FIRST>
@@ -1132,15 +1136,16 @@ __global__ __launch_bounds__(kTileBlock2) void batch_leja3s_kernel(BatchArgs A, 
   const int cb = t % ncb3, run = t / ncb3;
   const int nrb = (F.ny + kWavesY2 - 1) / kWavesY2;
   const int rb0 = run * bands, rb1 = min(rb0 + bands, nrb);
+  // a Dirichlet bin 128 columns wide is one strip of all 64 lanes
+  const bool whole = whole_strip(F.bc, F.nx);
+  const int c0 = whole ? 0 : cb * kStrip3, c1 = whole ? F.nx : min(c0 + kStrip3, F.nx);
   if (stop) {
     const BinCtl& c = A.ctl[b];
     if (update_due(A, c)) {
       // the block's own points, a quarter of its rows per wave
       const int j0 = rb0 * kWavesY2, j1 = min(rb1 * kWavesY2, F.ny);
       const int q = (j1 - j0 + kWavesY2 - 1) / kWavesY2;
-      const int c0 = cb * kStrip3;
-      bin_update_rect<VEC>(A, B, c, const_cast<double*>(B.u), j0 + wave * q, min(j0 + (wave + 1) * q, j1), c0,
-                           min(c0 + kStrip3, F.nx));
+      bin_update_rect<VEC>(A, B, c, const_cast<double*>(B.u), j0 + wave * q, min(j0 + (wave + 1) * q, j1), c0, c1);
     }
     return;
   }
@@ -1168,7 +1173,8 @@ __global__ __launch_bounds__(kTileBlock2) void batch_leja3s_kernel(BatchArgs A, 
   io.dk3 = uni(B.d[min(k + 3, M)]);
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double amax = 0.0;  // (the decision tests y_0 = 0 from the first term and p_1)
-  staged3_run<TF, double, VEC, ADVF, true, true, FIRST>(F, io, lds, cb * kStrip3 - VEC, rb0, rb1, 0, acc, amax);
+  staged3_run<TF, double, VEC, ADVF, true, true, FIRST>(F, io, lds, whole ? 0 : c0 - VEC, rb0, rb1, 0, acc, amax,
+                                                        whole);
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
 #pragma unroll
@@ -1424,7 +1430,7 @@ void build_tiles(adl_batch* B) {
     // of four rows, i.e. a tile height of 16 rows gives runs of 64 rows
     if (B->vec == 2) {
       const int nband = (op->ny + kWavesY2 - 1) / kWavesY2;
-      d.ncb3 = (op->nx + kStrip3 - 1) / kStrip3;
+      d.ncb3 = whole_strip(op->bc, op->nx) ? 1 : (op->nx + kStrip3 - 1) / kStrip3;
       d.bands3 = B->rows;
       d.nblocks3 = d.ncb3 * ((nband + d.bands3 - 1) / d.bands3);
     }

@@ -480,7 +480,8 @@ __device__ __forceinline__ void ring_stage_from_y(const RG& R, const Strip& g, i
 
 template <typename TF, typename TY, int VEC, bool ADVF, bool NT, bool Y2 = false, bool FIRST = false>
 __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<TY>& io, double* lds, int i0, int rb0,
-                                            int rb1, int stopflag, double (&acc)[6], double& amax) {
+                                            int rb1, int stopflag, double (&acc)[6], double& amax,
+                                            bool whole = false) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   const int W = kWave * VEC;
@@ -497,7 +498,11 @@ __device__ __forceinline__ void staged3_run(const FieldView& F, const Staged3IO<
     return;
   }
   const Strip g = strip_at<VEC>(F, i0);
-  const bool own = lane >= 1 && lane <= kWave - 2 && g.inside;
+  // whole: the strip is the whole width of a Dirichlet grid (i0 = 0, nx =
+  // 128): the neighbours beyond both ends are ghost columns, which the
+  // rings and the DPP shifts supply as such, so every lane's three terms are
+  // valid
+  const bool own = (whole || (lane >= 1 && lane <= kWave - 2)) && g.inside;
   const int J0 = rb0 * kWavesY2;
   e1.lds = lds;
   e1.r0 = J0 - 2;
