@@ -152,6 +152,8 @@ VARIED = {
     "dirichlet-field-adv-fp32-vec2": ([(128, 45), (130, 70), (256, 19)], [O.DIRICHLET] * 3, True, 1, 7),
     "mixed-bc-const-adv-fp32-vec2": ([(128, 37), (256, 20), (192, 9)], [O.PERIODIC, O.DIRICHLET, O.PERIODIC],
                                      False, 1, 3),
+    "periodic-field-adv-fp64-vec2": ([(128, 40), (256, 33), (192, 17)], [O.PERIODIC] * 3, True, 0, 5),
+    "dirichlet-whole-strip-fp64-vec2": ([(128, 64), (128, 23), (384, 30)], [O.DIRICHLET] * 3, False, 0, 4),
 }
 
 
