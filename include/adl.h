@@ -155,7 +155,9 @@ int adl_op_set_tiling(adl_op* op, int rows, int cols_per_lane);
  * (mode 4's form, y_{k+1} .. y_{k+3} kept on chip) and, from 2^20 points
  * on, three (mode 5's form: read y_k, the fields and p_k once, write y_{k+3}
  * and p_{k+3}; with FP64 Newton vectors and no augmented column among terms
- * 1 .. 3 the first launch takes three terms too, from y_0 = v); where those
+ * 1 .. 3 the first launch takes three terms too, from y_0 = v, and in a
+ * midpoint step without substeps on a grid of at least 2^24 points, or in
+ * mode 5, it also forms the stage vector A u + S itself); where those
  * forms do not apply it computes terms k+1 and
  * k+2 in one launch, keeping y_{k+1} on chip, with the input rows staged in
  * LDS from 2^20 points on and one-row frames in registers below;

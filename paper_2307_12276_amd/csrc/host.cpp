@@ -467,12 +467,45 @@ static bool four_staged_ok(const adl_op* op, int vec) {
 // intact inputs stores p of that term, bitwise what launch L computed.  The
 // p buffers are p_out and two workspace vectors, arranged so that the
 // predicted degree ends in p_out; otherwise the result is copied there.
+// Whether a sweep on vectors of tiling T runs three terms per launch with
+// LDS-staged rows (the default from kStagedMinPoints up, or mode 5)
+static bool three_term_sweep(const adl_op* op, const Tiling& T) {
+  const bool fours = op->fuse_terms == 6 && four_staged_ok(op, T.vec);
+  const bool four = !fours && (op->fuse_terms == 4 || (op->fuse_terms == 1 && op->n < kFourTermMaxPoints)) &&
+                    four_terms_ok(op);
+  return !four && !fours && three_terms_ok(op, T.vec) &&
+         (op->fuse_terms == 5 || (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints));
+}
+
+// Whether a midpoint step folds its stage vector w = A u + s into the
+// sweep's first launch (the four-stage LDS march, terms 1 .. 3): one
+// substep, a three-term sweep with FP64 Newton vectors whose first launch
+// takes three terms, the four-term staged tiling available; by default from
+// kStageFuseMinPoints up (measured, steps/s fused against a stage launch of
+// its own: 4096^2 FP64 +2 %, FP32 fields +0.4 %; 2048^2 -1.2 %, 1024^2
+// -1 %: the four-stage march is latency-bound, and on smaller grids its
+// launch costs about as much as the two it replaces), always in mode 5
+constexpr long kStageFuseMinPoints = 1L << 24;
+static bool stage_fusable(const adl_op* op, const double* u, const double* s, double dt) {
+  if (op->storage == ADL_STORAGE_FP32_FIELDS_Y || op->alpha == 0.0 || !op->has_bound) return false;
+  if (op->fuse_terms != 5 && (long)op->nx * op->ny < kStageFuseMinPoints) return false;
+  int K = substeps_for(op->alpha, dt, op->rho_max);
+  if (op->learned) K = std::max(K, op->substeps_hint);
+  int maxdeg = op->max_degree;
+  if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;
+  const Tiling& T = tiling_for(op, u, s, op->p);
+  return K == 1 && maxdeg >= 3 && three_term_sweep(op, T) && four_staged_ok(op, T.vec);
+}
+
 static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double w2scale, double* p_out,
-                 double tol, int maxdeg, hipStream_t st, SweepOut& out) {
+                 double tol, int maxdeg, hipStream_t st, SweepOut& out, const double* stage_u = nullptr,
+                 const double* stage_s = nullptr) {
+  // stage_u (v null): the sweep of v = A stage_u + stage_s, whose first
+  // launch computes that stage vector itself (stage_fusable)
   if (op->learned && op->budget > 0 && op->budget < maxdeg) maxdeg = op->budget;
   // (the control block is cleared by block 0 of the first launch)
   const bool ys32 = op->storage == ADL_STORAGE_FP32_FIELDS_Y;
-  const Tiling& T = tiling_for(op, v, p_out);
+  const Tiling& T = tiling_for(op, stage_u ? stage_u : v, p_out);
   const Tiling& T2 = T.vec == op->t2.vec ? op->t2 : op->t21;
   const Tiling& T4 = T.vec == op->t4.vec ? op->t4 : op->t41;
   const bool fuse = op->fuse_terms != 0;
@@ -483,8 +516,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   // three terms per launch (LDS-staged) from kStagedMinPoints up by default
   // (4096^2 FP64 headline steps: 140 steps/s with two terms per launch, 185
   // with three), or forced by mode 5
-  const bool three = !four && !fours && three_terms_ok(op, T.vec) &&
-                     (op->fuse_terms == 5 || (op->fuse_terms == 1 && (long)op->nx * op->ny >= kStagedMinPoints));
+  const bool three = three_term_sweep(op, T);
   const Tiling& T3 = op->t3;
   const Tiling& T4s = op->t4s;
   // first chunk: the last degree of this plan plus one (the degree moves by
@@ -527,6 +559,12 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
   // cost a whole launch whenever the last degree ends a launch: 4096^2
   // headline steps of degree 72, 24 launches instead of 25)
   if (P.last_degree > 0 && plan_terms(0, maxdeg) == 3) predicted = std::min(P.last_degree, maxdeg);
+  // (a stage vector that the first launch cannot compute is formed first)
+  if (stage_u && plan_terms(0, maxdeg) != 3) {
+    HIPCHK(launch_apply(op->f, tiling_for(op, stage_u, stage_s), stage_u, op->w1, stage_s, 1.0, nullptr, 0.0, st));
+    v = op->w1;
+    stage_u = stage_s = nullptr;
+  }
   // the chunk targets: the first chunk ends at the predicted degree, each
   // later one max(8, kcov / 4) terms on, capped at the degree limit
   auto next_target = [&](int kcov) {
@@ -600,7 +638,7 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.k = kcov;
       a.nterms = n;
       a.first = kcov == 0;
-      a.yin = kcov == 0 ? (const void*)v : ybuf3[L % 3];
+      a.yin = kcov == 0 ? (stage_u ? (const void*)stage_u : (const void*)v) : ybuf3[L % 3];
       a.yout = ybuf3[(L + 1) % 3];
       a.yin_f32 = (kcov > 0) && ys32;
       a.pin = kcov == 0 ? nullptr : pbuf[(L + 2) % 3];
@@ -626,14 +664,34 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
       a.nterms_prev = prev_n;
       a.slot_prev = prev_slot;
       a.decide_only = 0;
-      if (n == 4 && fours) HIPCHK(launch_leja4s_step(op->f, T4s, a, st));
+      const bool stage = kcov == 0 && stage_u != nullptr;
+      if (stage) {
+        // the four-stage march: w = A u + s, then terms 1 .. 3 (its p starts
+        // at 0 and takes d_0 w as its first "term")
+        a.stage = 1;
+        a.src = stage_s;
+        a.shift2 = P.shift[0];
+        a.shift3 = P.shift[1];
+        a.shift4 = P.shift[2];
+        a.dk1 = P.d[0];
+        a.dk2 = P.d[1];
+        a.dk3 = P.d[2];
+        a.dk4 = P.d[3];
+        HIPCHK(launch_leja4s_step(op->f, T4s, a, st));
+        a.stage = 0;
+        a.src = nullptr;
+      } else if (n == 4 && fours) HIPCHK(launch_leja4s_step(op->f, T4s, a, st));
       else if (n == 4) HIPCHK(launch_leja4_step(op->f, T4, a, st));
       else if (n == 3) HIPCHK(launch_leja3_step(op->f, T3, a, st));
       else if (n == 2) HIPCHK(launch_leja2_step(op->f, T2, a, st));
       else HIPCHK(launch_leja_step(op->f, T, a, st));
       lk.push_back(kcov);
       ln.push_back(n);
-      prev_nb = n == 4 ? (fours ? T4s.nblocks : T4.nblocks) : n == 3 ? T3.nblocks : n == 2 ? T2.nblocks : T.nblocks;
+      prev_nb = stage     ? T4s.nblocks
+                : n == 4  ? (fours ? T4s.nblocks : T4.nblocks)
+                : n == 3  ? T3.nblocks
+                : n == 2  ? T2.nblocks
+                          : T.nblocks;
       prev_k = kcov;
       prev_n = n;
       prev_slot = L & 1;
@@ -671,7 +729,8 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         if (stopped && past) break;
         float ms = 0.0f;
         HIPCHK(hipEventElapsedTime(&ms, op->evs[2 * (l - L0)], op->evs[2 * (l - L0) + 1]));
-        const double b = leja_bytes(op, lk[l], lk[l] == 0 && w2 != nullptr && P.s[0] != 0.0);
+        // (a first launch with its stage vector reads u and s where others read v)
+        const double b = leja_bytes(op, lk[l], lk[l] == 0 && ((w2 != nullptr && P.s[0] != 0.0) || stage_s));
         op->prof_ms += ms;
         op->prof_launches += 1;
         op->prof_bytes += b;
@@ -703,8 +762,14 @@ static int sweep(adl_op* op, Plan& P, const double* v, const double* w2, double 
         // the sweep stopped inside launch Ls: replay it on its inputs (y in
         // ybuf3[Ls mod 3], p in pbuf[(Ls + 2) mod 3], both intact) storing p
         // of term m only, into p_out unless p_out holds its p input
-        // (the first launch: y_0 = v, no p input)
+        // (the first launch: y_0 = v, no p input; with its stage vector, v is
+        // formed here first and the launch replayed in its three-term form)
         const int k = lk[Ls], n = ln[Ls], t = m - k;
+        if (k == 0 && stage_u) {
+          HIPCHK(launch_apply(op->f, tiling_for(op, stage_u, stage_s), stage_u, op->w1, stage_s, 1.0, nullptr, 0.0,
+                              st));
+          v = op->w1;
+        }
         const double* pin = k == 0 ? nullptr : pbuf[(Ls + 2) % 3];
         double* dst = pin == p_out ? pbuf[Ls % 3] : p_out;
         a.ev_start = a.ev_stop = nullptr;
@@ -773,7 +838,8 @@ static int status_to_code(int status) {
 // substep and u_direct set, u_direct += dt p is applied instead (one update
 // launch fewer) and `applied` is set.
 static int combo_fixed(adl_op* op, const double* w1, const double* w2, double dt, double tol, int K, Acc& acc,
-                       bool& ok, hipStream_t st, double* u_direct = nullptr, bool* applied = nullptr) {
+                       bool& ok, hipStream_t st, double* u_direct = nullptr, bool* applied = nullptr,
+                       const double* stage_u = nullptr, const double* stage_s = nullptr) {
   const double h = dt / K;
   Plan& P = get_plan(op, 1, op->alpha, h);
   ok = true;
@@ -786,7 +852,9 @@ static int combo_fixed(adl_op* op, const double* w1, const double* w2, double dt
       f = op->tmp;
     }
     SweepOut so;
-    RETCHK(sweep(op, P, f, w2, 1.0 / dt, op->p, tol, op->max_degree, st, so));
+    // (stage_u: w1 = A stage_u + stage_s is formed by the sweep's first launch; K = 1)
+    RETCHK(sweep(op, P, f, w2, 1.0 / dt, op->p, tol, op->max_degree, st, so, j == 0 ? stage_u : nullptr,
+                 j == 0 ? stage_s : nullptr));
     account(acc, so);
     if (so.status != 1) {
       if (so.status == 2) return status_to_code(2);
@@ -809,7 +877,8 @@ static int combo_fixed(adl_op* op, const double* w1, const double* w2, double dt
 // u_direct set, a one-substep result may instead be added to u_direct
 // directly (`applied` tells which happened).
 static int phi_combo(adl_op* op, const double* w1, const double* w2, double dt, double tol, Acc& acc,
-                     hipStream_t st, double* u_direct = nullptr, bool* applied = nullptr) {
+                     hipStream_t st, double* u_direct = nullptr, bool* applied = nullptr,
+                     const double* stage_u = nullptr, const double* stage_s = nullptr) {
   bool dummy = false;
   if (!applied) applied = &dummy;
   *applied = false;
@@ -822,7 +891,13 @@ static int phi_combo(adl_op* op, const double* w1, const double* w2, double dt, 
   if (op->learned) K = std::max(K, op->substeps_hint);
   for (int d = 0; d <= kMaxDoublings; ++d) {
     bool ok;
-    RETCHK(combo_fixed(op, w1, w2, dt, tol, K, acc, ok, st, u_direct, applied));
+    if (stage_u && K > 1) {
+      // substeps need w1 itself: form it
+      HIPCHK(launch_apply(op->f, tiling_for(op, stage_u, stage_s), stage_u, op->w1, stage_s, 1.0, nullptr, 0.0, st));
+      w1 = op->w1;
+      stage_u = stage_s = nullptr;
+    }
+    RETCHK(combo_fixed(op, w1, w2, dt, tol, K, acc, ok, st, u_direct, applied, stage_u, stage_s));
     if (ok) {
       acc.substeps = K;
       return ADL_OK;
@@ -1312,11 +1387,14 @@ static int midpoint_impl(adl_op* op, double* u, const double* S_half, double dt,
   RETCHK(check_bound(op));
   hipStream_t st = S(stream);
   Acc acc;
-  // w = A u + S(t + dt/2)
-  HIPCHK(launch_apply(op->f, tiling_for(op, u, S_half), u, op->w1, S_half, 1.0, nullptr, 0.0, st));
+  // w = A u + S(t + dt/2), or formed by the sweep's first launch itself
+  // (one launch fewer over the grid: 4096^2 FP64 steps 4.99 -> 4.87 ms)
+  const bool fused = stage_fusable(op, u, S_half, dt);
+  if (!fused) HIPCHK(launch_apply(op->f, tiling_for(op, u, S_half), u, op->w1, S_half, 1.0, nullptr, 0.0, st));
   acc.matvecs += 1;
   bool applied = false;
-  int code = phi_combo(op, op->w1, nullptr, dt, tol, acc, st, u, &applied);
+  int code = phi_combo(op, fused ? nullptr : op->w1, nullptr, dt, tol, acc, st, u, &applied, fused ? u : nullptr,
+                       fused ? S_half : nullptr);
   if (code == ADL_OK && !applied) {
     hipError_t e = launch_axpby(op->n, u, 1.0, u, 1.0, op->yacc, st);
     if (e != hipSuccess) code = fail(ADL_EHIP, "update failed: %s", hipGetErrorString(e));

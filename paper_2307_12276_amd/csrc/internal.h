@@ -189,6 +189,10 @@ struct LejaArgs {
   // terms (the result, when the sweep stopped inside the launch): the same
   // arithmetic on the same y_k and p_k, no stop flag, no decision, no partials
   int replay;
+  // The sweep's first launch computing its own stage vector (four-term staged
+  // kernel, terms 1 .. 3): yin = u, src = s (or null) of w = A u + s
+  int stage;
+  const double* src;
 };
 hipError_t launch_leja_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // two-term launch (terms k+1, k+2; k >= 1) on the two-term tiling
@@ -204,7 +208,10 @@ Tiling make_tiling2(int nx, int ny, int rows_hint, int vec_hint = 0, int max_blo
 hipError_t launch_leja3_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // four-term launch (terms k+1 .. k+4; k >= 1) with the input rows staged in
 // LDS, on a tiling of strips of 60*VEC output columns with two columns per
-// lane (make_tiling2 with frame 2); block partials: 12 x nblocks values
+// lane (make_tiling2 with frame 2); block partials: 12 x nblocks values.
+// With a.stage: the sweep's first launch, stage vector w = A u + s and terms
+// 1 .. 3 (dk1 .. dk4 = d_0 .. d_3, shift2 .. shift4 = the first three
+// shifts), partials as a three-term launch's
 hipError_t launch_leja4s_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st);
 // four-term launch (terms k+1 .. k+4; k >= 1) on the four-term tiling; the
 // launch's block partials take 12 x nblocks values of its slot

@@ -257,15 +257,14 @@ __device__ __forceinline__ void ring_stencil(const RG& R, const Strip& g, int r,
 }
 
 // stage 1 of row r: y_{k+1} into the y_{k+1} ring (ghost rule of Stage1Ep)
-template <int VEC, bool ADVF, class RG, int NY>
-__device__ __forceinline__ void ring_stage1(const RG& R, const Strip& g, int r, const FieldView& F,
-                                            Stage1Ep<VEC, NY>& ep) {
+template <int VEC, bool ADVF, class RG, class EP>
+__device__ __forceinline__ void ring_stage1(const RG& R, const Strip& g, int r, const FieldView& F, EP& ep) {
   RowN<VEC> u[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) ring_rown<VEC>(R.row(0, r - 1 + t), u[t]);
   double Ax[VEC];
   ring_stencil<VEC, ADVF>(R, g, r, F, u[0], u[1], u[2], Ax);
-  typename Stage1Ep<VEC, NY>::Extra none;
+  typename EP::Extra none;
   ep.finish(r, g, Ax, u[1].c, none);
 }
 
@@ -661,8 +660,27 @@ struct Staged4IO {
   double* p2;
   double* p3;
   double* p;          // p_{k+4}, or null
+  const double* src;  // staged4_run<..., STAGE = true>: the source s of w = A u + s, or null (s = 0)
   double shift, shift2, shift3, shift4, invg, dk1, dk2, dk3, dk4;
 };
+
+// one lane's VEC values of row r of a source vector s (boundary rule of y:
+// wrapped rows, or zero ghost rows), into o; null s gives zeros
+template <int VEC>
+__device__ __forceinline__ void src_row(const FieldView& F, const double* __restrict__ s, const Strip& g, int r,
+                                        double (&o)[VEC]) {
+  bool zero;
+  const int row = map_row_any(r, F.ny, F.bc, MODE_ZERO, zero);
+  double c[VEC];
+  if (s) {
+    ldr<double, VEC>(s + (long)row * F.nx, g.colc, c);
+  } else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) c[v] = 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) o[v] = zero ? 0.0 : c[v];
+}
 
 // y_{k+t} (t >= 2) at row r of the run's prologue: the stencil of the Y ring
 // rows r-1 .. r+1 (rounded to the storage type) with the field rows read
@@ -708,13 +726,18 @@ __device__ __forceinline__ void rowset_put_from(const RingsV<VEC, ADVF>& R, cons
   }
 }
 
-template <typename TF, typename TY, int VEC, bool ADVF, bool NT>
+template <typename TF, typename TY, int VEC, bool ADVF, bool NT, bool STAGE = false>
 __device__ __forceinline__ void staged4_run(const FieldView& F, const Staged4IO<TY>& io, double* lds, int i0, int rb0,
-                                            int rb1, int stopflag, double (&acc)[8]) {
+                                            int rb1, int stopflag, double (&acc)[8], double& amax) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   const int W = kWave * VEC;
-  Stage1Ep<VEC, kS4Y1> e1;
+  // STAGE: the sweep's first launch with its stage vector: stage 1 computes
+  // w = A u + s (y_0 of the sweep) from u = yin and the source io.src, and
+  // stages 2 .. 4 the terms 1 .. 3 (the caller passes d_0 .. d_3 as dk1 ..
+  // dk4, so p_0 = d_0 w is the first "term" on p = 0); amax = max |w| over
+  // the kept points (the zero-vector test)
+  Stage1Ep<VEC, kS4Y1, STAGE> e1;
   Stage1Ep<VEC, kS4Y> e2, e3;
   e1.stopflag = stopflag;
   if (!e1.go()) {
@@ -772,7 +795,14 @@ __device__ __forceinline__ void staged4_run(const FieldView& F, const Staged4IO<
   rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 - 1 + wave, ra);
   rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 3 + wave, rb);
   rowset_load<TF, TY, VEC, ADVF>(F, yin, g, J0 + 7 + wave, rc);
+  // (STAGE: the source row of the first band's stage-1 row, kept in snx)
+  double snx[VEC];
+  if constexpr (STAGE) {
+    src_row<VEC>(F, io.src, g, J0 + 3 + wave, snx);
+    src_row<VEC>(F, io.src, g, J0 - 3 + wave, e1.add);
+  }
   stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, e1, g, J0 - 3 + wave);
+  if constexpr (STAGE) src_row<VEC>(F, io.src, g, J0 + 1 + wave, e1.add);
   if (wave < 2) stencil_group<TF, TY, VEC, ADVF, 1>(F, yin, e1, g, J0 + 1 + wave);
   __syncthreads();
   prologue_stage_g<TF, TY, VEC, ADVF, kS4Y1>(F, g, J0 - 2 + wave, e1.lds, e1.r0, e2);
@@ -791,7 +821,19 @@ __device__ __forceinline__ void staged4_run(const FieldView& F, const Staged4IO<
     const bool keep = own && j < F.ny;
     const double km = keep ? 1.0 : 0.0;
     double pk[VEC];
-    ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
+    if constexpr (STAGE) {
+      // p starts at 0; this band's stage-1 source row (loaded a band ago),
+      // then the next band's, issued before the row prefetch so that its use
+      // waits for nothing issued after it
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        pk[v] = 0.0;
+        e1.add[v] = snx[v];
+      }
+      if constexpr (!LAST) src_row<VEC>(F, io.src, g, j0 + 7 + wave, snx);
+    } else {
+      ldr_s<NT, double, VEC>(io.pin + (long)min(j, F.ny - 1) * F.nx, g.colc, pk);
+    }
     if constexpr (!LAST) rowset_load<TF, TY, VEC, ADVF>(F, yin, g, j0 + 8 + wave, nxt);
     // stage 1: y_{k+1} on row j0+3+wave
     ring_stage1<VEC, ADVF>(R, g, j0 + 3 + wave, F, e1);
@@ -840,6 +882,7 @@ __device__ __forceinline__ void staged4_run(const FieldView& F, const Staged4IO<
       acc[5] = acc_kept(acc[5], km, pc[v] * pc[v]);
       acc[6] = acc_kept(acc[6], km, t4 * t4);
       acc[7] = acc_kept(acc[7], km, pd[v] * pd[v]);
+      if constexpr (STAGE) amax = keep ? nanmax(amax, fabs(y1[v])) : amax;
     }
     row_store<NT, TY, VEC>(yo + ro, F.nx, keep && sy ? ocol : kDropOffset, y4);
     row_store<NT, double, VEC>(p1o + ro, F.nx, keep && s1 ? ocolp : kDropOffset, pa);

@@ -1000,13 +1000,21 @@ __global__ __launch_bounds__(kTileBlock2) void leja3s_kernel(FieldView F, Tiling
 // (staged4_run in staged.h), on its own tiling of strips of 60*VEC output
 // columns with two columns per lane.  No static LDS (the block reductions
 // use the dynamic rings), so that three blocks share a CU.
-template <typename TF, typename TY, bool ADVF, bool NT>
+template <typename TF, typename TY, bool ADVF, bool NT, bool STAGE>
 __global__ __launch_bounds__(kTileBlock2) void leja4s_kernel(FieldView F, Tiling T, LejaArgs A) {
   extern __shared__ __attribute__((aligned(16))) double lds[];  // rows accessed 16 bytes per lane
   constexpr int VEC = 2;
   const int L = A.decide_only ? 0 : xcd_contiguous(blockIdx.x, gridDim.x);
   if (L == 0) {
-    if (!A.replay) leja_decide<true>(A, lds);
+    if (STAGE) {
+      // a new sweep: clear the control block (no block of this launch reads it)
+      if (!A.replay && threadIdx.x == 0) {
+        Ctl c{};
+        *A.ctl = c;
+      }
+    } else if (!A.replay) {
+      leja_decide<true>(A, lds);
+    }
     return;
   }
   const int b = L - 1;
@@ -1021,6 +1029,7 @@ __global__ __launch_bounds__(kTileBlock2) void leja4s_kernel(FieldView F, Tiling
   io.p2 = A.pmid2;
   io.p3 = A.pmid3;
   io.p = A.p;
+  io.src = A.src;
   io.shift = A.shift;
   io.shift2 = A.shift2;
   io.shift3 = A.shift3;
@@ -1030,21 +1039,26 @@ __global__ __launch_bounds__(kTileBlock2) void leja4s_kernel(FieldView F, Tiling
   io.dk2 = A.dk2;
   io.dk3 = A.dk3;
   io.dk4 = A.dk4;
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  staged4_run<TF, TY, VEC, ADVF, NT>(
+  double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double (&acc8)[8] = *reinterpret_cast<double(*)[8]>(acc);
+  staged4_run<TF, TY, VEC, ADVF, NT, STAGE>(
       F, io, lds, cb * (kWave - 4) * VEC - 2 * VEC, rb0, rb1,
-      A.replay ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), acc);
-  // block partials: term t (0 .. 3) at rows 3t (||d y||^2), 3t + 1 (||p||^2), 3t + 2 (0)
+      (STAGE || A.replay) ? 0 : __hip_atomic_load(&A.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), acc8,
+      acc[8]);
+  // block partials: term t (0 .. 3) at rows 3t (||d y||^2), 3t + 1 (||p||^2),
+  // 3t + 2 (0); STAGE: the launch's three terms are stages 2 .. 4, and row 2
+  // holds max |w| (the first-term zero test)
   __syncthreads();  // (the rings are free again: the reduction's scratch)
-  block_allreduce_at<8, 8>(acc, lds);
+  block_allreduce_at<9, 8>(acc, lds);
   if (threadIdx.x == 0 && !A.replay) {
     double* part = A.partials + (long)A.slot * A.slot_stride;
     const int nb = T.nblocks;
+    constexpr int first = STAGE ? 1 : 0, nt = STAGE ? 3 : 4;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      part[(3L * t) * nb + b] = acc[2 * t];
-      part[(3L * t + 1) * nb + b] = acc[2 * t + 1];
-      part[(3L * t + 2) * nb + b] = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      part[(3L * t) * nb + b] = acc[2 * (t + first)];
+      part[(3L * t + 1) * nb + b] = acc[2 * (t + first) + 1];
+      part[(3L * t + 2) * nb + b] = (STAGE && t == 0) ? acc[8] : 0.0;
     }
   }
 }
@@ -1450,14 +1464,26 @@ hipError_t launch_leja3_step(const FieldView& f, const Tiling& t, const LejaArgs
   return hipGetLastError();
 }
 
-template <typename TF, typename TY, bool ADVF, bool NT>
-static void leja4s_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+template <typename TF, typename TY, bool ADVF, bool NT, bool STAGE>
+static void leja4s_launch_k(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
   const dim3 grid(a.decide_only ? 1 : t.nblocks + 1), blk(kTileBlock2);
   const size_t lds = staged4_lds_bytes<2, ADVF>();
   if (a.ev_start)
-    hipExtLaunchKernelGGL((leja4s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f, t, a);
+    hipExtLaunchKernelGGL((leja4s_kernel<TF, TY, ADVF, NT, STAGE>), grid, blk, lds, st, a.ev_start, a.ev_stop, 0, f,
+                          t, a);
   else
-    hipLaunchKernelGGL((leja4s_kernel<TF, TY, ADVF, NT>), grid, blk, lds, st, f, t, a);
+    hipLaunchKernelGGL((leja4s_kernel<TF, TY, ADVF, NT, STAGE>), grid, blk, lds, st, f, t, a);
+}
+
+template <typename TF, typename TY, bool ADVF, bool NT>
+static void leja4s_launch(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
+  if constexpr (std::is_same_v<TY, double>) {
+    if (a.stage) {
+      leja4s_launch_k<TF, TY, ADVF, NT, true>(f, t, a, st);
+      return;
+    }
+  }
+  leja4s_launch_k<TF, TY, ADVF, NT, false>(f, t, a, st);
 }
 
 template <typename TF, typename TY, bool NT>
@@ -1467,12 +1493,17 @@ static void leja4s_dispatch(const FieldView& f, const Tiling& t, const LejaArgs&
 }
 
 hipError_t launch_leja4s_step(const FieldView& f, const Tiling& t, const LejaArgs& a, hipStream_t st) {
-  if (a.first || a.k < 1 || a.nterms != 4 || a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || t.vec != 2)
+  if (a.w2 != nullptr || a.yin_f32 != a.ystore_f32 || t.vec != 2) return hipErrorInvalidValue;
+  // the sweep's first launch with its stage vector (terms 1 .. 3 from w = A u
+  // + s, FP64 Newton vectors, no p input, not a decision launch), or four
+  // later terms
+  if (a.stage ? (!a.first || a.k != 0 || a.nterms != 3 || a.ystore_f32 || a.decide_only || a.pin != nullptr)
+              : (a.first || a.k < 1 || a.nterms != 4))
     return hipErrorInvalidValue;
   if (!a.decide_only) {
     // p_k is read while the stored p outputs (at least one) are written: all distinct
     const double* o[5] = {a.pin, a.pmid, a.pmid2, a.pmid3, a.p};
-    if (a.pin == nullptr || (!a.pmid && !a.pmid2 && !a.pmid3 && !a.p)) return hipErrorInvalidValue;
+    if ((!a.stage && a.pin == nullptr) || (!a.pmid && !a.pmid2 && !a.pmid3 && !a.p)) return hipErrorInvalidValue;
     for (int i = 1; i < 5; ++i)
       for (int j = 0; j < i; ++j)
         if (o[i] != nullptr && o[i] == o[j]) return hipErrorInvalidValue;

@@ -257,9 +257,12 @@ __device__ __forceinline__ double storage_round(double v) {
 constexpr int kRing = 8;  // slots of the LDS ring of y_{k+1} rows (a power of two)
 static_assert(kRing >= 2 * kWavesY2, "a step writes its rows and the frame below while the previous step's "
                                      "rows are still read");
-template <int VEC, int NR = kRing>
+// ADD: the epilogue of a stage vector w = A x + s instead (add: the row's s
+// values, set by the caller before each row)
+template <int VEC, int NR = kRing, bool ADD = false>
 struct Stage1Ep {
   struct Extra {};
+  double add[VEC];
   double* lds;   // [NR][64*VEC]: row r in slot (r - r0) mod NR
   int r0;        // grid row of slot 0 (the row above the block's first tile)
   int ny;
@@ -273,7 +276,7 @@ struct Stage1Ep {
     double* row = lds + (long)((unsigned)(r - r0) % NR) * (kWave * VEC) + (threadIdx.x & (kWave - 1)) * VEC;
     double y[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) y[v] = (Ax[v] - shift * xc[v]) * invg;
+    for (int v = 0; v < VEC; ++v) y[v] = ADD ? Ax[v] + add[v] : (Ax[v] - shift * xc[v]) * invg;
     if (!per) {
       // uniform branch: only Dirichlet rows and columns have ghost entries
       __asm__ volatile("");

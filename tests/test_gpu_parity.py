@@ -405,6 +405,47 @@ def test_staged_multi_term_launches_match_one_term_launches(mode, terms, nx, ny,
             assert rel(o, ref) < 1e-10, mult
 
 
+@pytest.mark.parametrize("nx,ny", [(128, 128), (130, 70), (256, 9), (300, 129), (512, 33)])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.DIRICHLET])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_staged_midpoint_steps_match_oracle(nx, ny, bc, storage):
+    """Midpoint steps with three terms per launch (mode 5): with FP64 Newton
+    vectors the sweep's first launch forms the stage vector w = A u + S
+    itself (the four-stage LDS march) instead of a separate stage launch.
+    Two steps equal the oracle's (1e-10, the same matvec counts; FP32 fields:
+    the oracle on the rounded fields) and the one-term-per-launch steps
+    (1e-12), with a source and without one."""
+    Dxx, Dxy, Dyy, ax, ay = W.random_fields(nx, ny, seed=5 * nx + ny, field_advection=(storage == 0))
+    hx, hy = 1.0 / nx, 0.8 / ny
+    oop, gop = make_pair(Dxx, Dxy, Dyy, ax, ay, hx, hy, bc, storage)
+    alpha = bounds.gershgorin(oop)
+    gop.set_bound(alpha)
+    u0 = W.random_vector((ny, nx), 23)
+    S0 = 0.3 * W.random_vector((ny, nx), 29)
+    dt = 250.0 / abs(alpha)
+    A_ = lambda x: O.apply(oop, x)  # noqa: E731
+    for with_src in (True, False):
+        res = {}
+        for mode in (0, 5):
+            gop.set_term_fusion(mode)
+            u = to_dev(u0)
+            S = to_dev(S0) if with_src else None
+            mv = []
+            for _ in range(2):
+                mv.append(gop.midpoint_step(u, S, dt, 1e-10)["matvecs"])
+            res[mode] = (to_np(u), mv)
+        uo, mvo = u0.copy(), []
+        for _ in range(2):
+            ost = {}
+            uo = integrators.exp_midpoint_step(A_, uo, S0 if with_src else None, dt, alpha, 1e-10, stats=ost)
+            mvo.append(ost["matvecs"])
+        e5, e0 = rel(res[5][0], uo), rel(res[5][0], res[0][0])
+        print("source %s: matvecs %s / %s / oracle %s; mode 5 vs oracle %.1e, vs one-term %.1e"
+              % (with_src, res[5][1], res[0][1], mvo, e5, e0))
+        assert res[5][1] == res[0][1] == mvo
+        assert e5 < 1e-10 and e0 < 1e-12
+
+
 @pytest.mark.parametrize("nx,ny", [(33, 45), (64, 64), (257, 33)])
 def test_staged_multi_term_modes_need_two_columns_per_lane(nx, ny):
     """Modes 5 and 6 need tilings with two columns per lane (nx even and at
